@@ -1,0 +1,170 @@
+"""Hybrid AB-GMRES and BA-GMRES (Algorithms 1 and 2), oracle in FP64.
+
+Given a forward projector A: R^n -> R^m, an unmatched backprojector
+B: R^m -> R^n and data b, the method runs the Arnoldi process on M = AB
+(AB mode, eq. (5)) or M = BA (BA mode, eq. (4)), and at every iteration k
+
+  1. forms q = M w_k and orthogonalises it against W_k (eq. (8));
+  2. chooses lam_k and solves the regularised projected problem (eq. (12));
+  3. forms x_k = x_0 + B W_k y_k (AB) or x_0 + W_k y_k (BA) (eq. (13));
+  4. forms the residual r_k = b - A x_k (AB) or B(b - A x_k) (BA);
+  5. applies the stopping rule (Sec. 3.2).
+
+The paper's loop orthogonalises one basis vector at a time (modified
+Gram-Schmidt).  The GPU path uses classical Gram-Schmidt with one
+re-orthogonalisation pass (CGS2); in exact arithmetic both give the same
+W_{k+1} and H_k, so the oracle offers both ("mgs", "cgs2").
+
+Readings of points the paper leaves open:
+  * x_0 = 0 unless given (u_0 = 0 in Algorithm 1).
+  * Breakdown when h_{k+1,k} <= 1e-14 ||M w_k||: h_{k+1,k} is set to 0, the
+    k-th iterate is formed and the run ends.
+  * rho_k = ||b - A x_k|| (the data residual) is what the discrepancy
+    principle and residual-norm stagnation test, in both modes.  The printed
+    DP inequality is reversed; the run stops at the first k with
+    rho_k <= tau ||e||.  RNS stops at the first k with
+    |rho_{k-1} - rho_k| / rho_{k-1} < eps, with rho_0 = ||b - A x_0||.
+  * The returned x is x_k at the stopping iteration (or at K).
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, field
+
+import numpy as np
+
+from . import smallsolve as ss
+
+STATUS_KMAX = 1
+STATUS_STOP_DP = 2
+STATUS_STOP_RNS = 4
+STATUS_BREAKDOWN = 8
+STATUS_NONFINITE = 16
+STATUS_STOP_LEARNED = 32
+
+BREAKDOWN_TOL = 1e-14
+
+
+@dataclass
+class Result:
+    x: np.ndarray
+    iters: int
+    status: int
+    lam: list = field(default_factory=list)        # lam_k, k = 1..iters
+    rho: list = field(default_factory=list)        # rho_k, k = 0..iters
+    rho_hat: list = field(default_factory=list)    # projected residual, k = 1..iters
+    sigma: np.ndarray | None = None                # singular values of H_iters
+    H: np.ndarray | None = None                    # (iters+1) x iters
+    W: np.ndarray | None = None                    # (iters+1) x len basis (rows)
+    beta: float = 0.0
+    xs: list = field(default_factory=list)         # x_k history when requested
+    Mw_norms: list = field(default_factory=list)
+
+
+def hybrid_gmres(A, B, b, mode: str = "AB", K: int = 30, rule: str = "gcv",
+                 lam: float = 0.0, stop: str | None = None, tau: float = 1.01,
+                 noise_norm: float | None = None, rns_eps: float = 1e-3,
+                 x0=None, ortho: str = "cgs2", keep_x: bool = False,
+                 keep_basis: bool = False) -> Result:
+    """Run hybrid AB- or BA-GMRES for at most K iterations.
+
+    A, B     -- callables on flat FP64 vectors (R^n -> R^m and R^m -> R^n)
+    rule     -- lambda rule: "none", "fixed" (uses lam), "gcv", "dp", "lcurve"
+    stop     -- None (run K iterations), "dp" or "rns"
+    """
+    b = np.asarray(b, dtype=np.float64).reshape(-1)
+    if x0 is None:
+        # x_0 = B u_0 with u_0 = 0
+        n = np.asarray(B(np.zeros_like(b))).size
+        x0 = np.zeros(n)
+    x0 = np.asarray(x0, dtype=np.float64).reshape(-1)
+    Ax0 = np.asarray(A(x0)).reshape(-1)
+    res0 = b - Ax0
+    if mode == "AB":
+        r0 = res0
+    elif mode == "BA":
+        r0 = np.asarray(B(res0)).reshape(-1)
+    else:
+        raise ValueError(mode)
+    rho0 = float(np.linalg.norm(res0))
+    beta = float(np.linalg.norm(r0))
+    out = Result(x=x0.copy(), iters=0, status=0, rho=[rho0], beta=beta)
+    if not np.all(np.isfinite(b)) or not math.isfinite(beta):
+        out.status = STATUS_NONFINITE
+        return out
+    if beta == 0.0:
+        out.status = STATUS_BREAKDOWN
+        return out
+    if (rule == "dp" or stop == "dp") and noise_norm is None:
+        raise ValueError("the discrepancy principle needs ||e||")
+    target = None if noise_norm is None else tau * noise_norm
+
+    W = [r0 / beta]
+    H = np.zeros((K + 1, K))
+    status = STATUS_KMAX
+    k_done = 0
+    x = x0.copy()
+    for k in range(1, K + 1):
+        w = W[k - 1]
+        if mode == "AB":
+            q = np.asarray(A(np.asarray(B(w)).reshape(-1))).reshape(-1)
+        else:
+            q = np.asarray(B(np.asarray(A(w)).reshape(-1))).reshape(-1)
+        mw = float(np.linalg.norm(q))
+        out.Mw_norms.append(mw)
+        if ortho == "cgs2":
+            Wk = np.stack(W)                  # k x len
+            h = Wk @ q
+            q = q - Wk.T @ h
+            c = Wk @ q
+            q = q - Wk.T @ c
+            H[:k, k - 1] = h + c
+        elif ortho == "mgs":
+            for i in range(k):
+                H[i, k - 1] = float(np.dot(q, W[i]))
+                q = q - H[i, k - 1] * W[i]
+        else:
+            raise ValueError(ortho)
+        hk = float(np.linalg.norm(q))
+        broke = hk <= BREAKDOWN_TOL * mw
+        if broke:
+            H[k, k - 1] = 0.0
+        else:
+            H[k, k - 1] = hk
+            W.append(q / hk)
+        Hk = H[:k + 1, :k]
+        sol = ss.solve_projected(Hk, beta, rule, lam_fixed=lam, dp_target=target)
+        y = sol["y"]
+        Wk = np.stack(W[:k])
+        if mode == "AB":
+            x = x0 + np.asarray(B(Wk.T @ y)).reshape(-1)
+        else:
+            x = x0 + Wk.T @ y
+        rk = b - np.asarray(A(x)).reshape(-1)
+        rho = float(np.linalg.norm(rk))
+        out.lam.append(sol["lam"])
+        out.rho.append(rho)
+        out.rho_hat.append(sol["rho_hat"])
+        out.sigma = sol["sigma"]
+        if keep_x:
+            out.xs.append(x.copy())
+        k_done = k
+        if not (np.all(np.isfinite(x)) and math.isfinite(rho)):
+            status = STATUS_NONFINITE
+            break
+        if broke:
+            status = STATUS_BREAKDOWN
+            break
+        if stop == "dp" and rho <= target:
+            status = STATUS_STOP_DP
+            break
+        if stop == "rns" and abs(out.rho[-2] - rho) / out.rho[-2] < rns_eps:
+            status = STATUS_STOP_RNS
+            break
+    out.x = x
+    out.iters = k_done
+    out.status = status
+    out.H = H[:k_done + 1, :k_done].copy()
+    if keep_basis:
+        out.W = np.stack(W)
+    return out

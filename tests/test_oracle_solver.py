@@ -1,0 +1,298 @@
+"""Pins for the oracle's hybrid AB-/BA-GMRES (Algorithms 1 and 2).
+
+* the Arnoldi relation M W_k = W_{k+1} H_k (eq. (8)) and orthonormality;
+* brute force: the iterate as the minimiser over the Krylov space written
+  out in 50-digit arithmetic (mpmath), independent of any Arnoldi process;
+* the matched-pair statements of Sec. 3: AB-GMRES = LSQR, BA-GMRES = LSMR,
+  hybrid BA-GMRES = hybrid LSMR, hybrid AB-GMRES != hybrid LSQR;
+* the full-dimension limits of Sec. 3 (closed forms);
+* invariance under a global scale of B; breakdown and non-finite handling;
+* the paper's qualitative claims (semi-convergence of plain AB-GMRES, and
+  stabilisation by the hybrid method) on seeded C1-shaped problems.
+"""
+import math
+
+import mpmath
+import numpy as np
+import pytest
+
+import synth
+from oracle import solver as sv
+from oracle.geometry import Par2D
+from oracle.operators import Par2DOps
+
+pytestmark = pytest.mark.usefixtures("oracle_lib")
+
+mpmath.mp.dps = 50
+
+
+def c1_problem(idx=0, n=64, na=90, nd=91, eta=0.01):
+    g = Par2D(n, n, na, nd)
+    ops = Par2DOps(g)
+    x, _ = synth.phantom2d(0, idx, n)
+    bt = ops.A(x).reshape(-1)
+    b, en = synth.add_relative_noise(bt, synth.noise_direction(0, idx, g.m), eta)
+    return ops, x.reshape(-1), b, en
+
+
+# ----------------------------------------------------------- Arnoldi ------
+
+@pytest.mark.parametrize("mode", ["AB", "BA"])
+@pytest.mark.parametrize("ortho", ["cgs2", "mgs"])
+def test_arnoldi_relation_and_orthonormality_c1(mode, ortho):
+    ops, x, b, en = c1_problem()
+    r = sv.hybrid_gmres(ops.A, ops.B, b, mode=mode, K=30, rule="gcv", ortho=ortho, keep_basis=True)
+    W, H = r.W, r.H
+    k = r.iters
+    if mode == "AB":
+        MW = np.stack([ops.A(ops.B(w)) for w in W[:k]])
+    else:
+        MW = np.stack([ops.B(ops.A(w)) for w in W[:k]])
+    rel = np.linalg.norm(MW - H.T @ W[:k + 1]) / np.linalg.norm(MW)
+    assert rel < 1e-12
+    orth = np.linalg.norm(W @ W.T - np.eye(k + 1))
+    assert orth < (1e-12 if ortho == "cgs2" else 1e-6), orth
+
+
+def test_arnoldi_relation_c2_shape_first_iterations():
+    n, na, nd = 512, 720, 725
+    g = Par2D(n, n, na, nd)
+    ops = Par2DOps(g)
+    x, _ = synth.phantom2d(1, 0, n)
+    bt = ops.A(x).reshape(-1)
+    b, _ = synth.add_relative_noise(bt, synth.noise_direction(1, 0, g.m), 0.005)
+    r = sv.hybrid_gmres(ops.A, ops.B, b, mode="AB", K=4, rule="gcv", keep_basis=True)
+    W, H = r.W, r.H
+    MW = np.stack([ops.A(ops.B(w)) for w in W[:4]])
+    assert np.linalg.norm(MW - H.T @ W[:5]) / np.linalg.norm(MW) < 1e-12
+    assert np.linalg.norm(W @ W.T - np.eye(5)) < 1e-12
+
+
+def test_cgs2_and_mgs_give_the_same_iterates():
+    ops, x, b, en = c1_problem(idx=1)
+    for mode in ("AB", "BA"):
+        a = sv.hybrid_gmres(ops.A, ops.B, b, mode=mode, K=20, rule="gcv", ortho="cgs2")
+        m = sv.hybrid_gmres(ops.A, ops.B, b, mode=mode, K=20, rule="gcv", ortho="mgs")
+        assert np.linalg.norm(a.x - m.x) < 1e-8 * np.linalg.norm(a.x)
+        np.testing.assert_allclose(a.lam, m.lam, rtol=1e-6)
+
+
+# ---------------------------------------------------- brute force ---------
+
+def mp_mat(a):
+    return mpmath.matrix(np.asarray(a, dtype=np.float64).tolist())
+
+
+def mp_orth(cols):
+    """Orthonormal basis (Gram-Schmidt twice, 50 digits) of the given columns."""
+    basis = []
+    for c in cols:
+        v = c.copy()
+        for _ in range(2):
+            for q in basis:
+                v = v - (q.T * v)[0] * q
+        nv = mpmath.norm(v)
+        basis.append(v / nv)
+    Q = mpmath.matrix(basis[0].rows, len(basis))
+    for j, q in enumerate(basis):
+        for i in range(q.rows):
+            Q[i, j] = q[i]
+    return Q
+
+
+def krylov_basis(M, v, k):
+    cols = [v]
+    for _ in range(k - 1):
+        cols.append(M * cols[-1])
+    return mp_orth(cols)
+
+
+def mp_regls(G, r, lam):
+    """argmin_c ||G c - r||^2 + lam^2 ||c||^2 via the normal equations (50 digits)."""
+    k = G.cols
+    N = G.T * G + (lam ** 2) * mpmath.eye(k)
+    return mpmath.lu_solve(N, G.T * r)
+
+
+def to_np(v):
+    return np.array([float(v[i]) for i in range(v.rows)])
+
+
+def tiny_ops(nx=5, ny=5, na=6, nd=7):
+    g = Par2D(nx, ny, na, nd)
+    ops = Par2DOps(g)
+    return ops, ops.explicit("A"), ops.explicit("B"), ops.explicit("At")
+
+
+@pytest.mark.parametrize("mode", ["AB", "BA"])
+@pytest.mark.parametrize("lam", [0.0, 0.05, 0.7])
+def test_iterate_is_krylov_minimiser_brute_force(mode, lam):
+    ops, Am, Bm, _ = tiny_ops()
+    r = np.random.default_rng(4)
+    b = Am @ r.uniform(size=Am.shape[1]) + 0.05 * r.standard_normal(Am.shape[0])
+    x0 = 0.1 * r.standard_normal(Am.shape[1])
+    A_, B_ = mp_mat(Am), mp_mat(Bm)
+    bb, xx0 = mp_mat(b[:, None]), mp_mat(x0[:, None])
+    rule = "none" if lam == 0.0 else "fixed"
+    for k in (1, 2, 4, 8):
+        o = sv.hybrid_gmres(lambda v: Am @ v, lambda v: Bm @ v, b, mode=mode, K=k,
+                            rule=rule, lam=lam, x0=x0)
+        if mode == "AB":
+            M = A_ * B_
+            r0 = bb - A_ * xx0
+        else:
+            M = B_ * A_
+            r0 = B_ * (bb - A_ * xx0)
+        Q = krylov_basis(M, r0, k)
+        c = mp_regls(M * Q, r0, mpmath.mpf(lam))
+        z = Q * c
+        xbf = xx0 + (B_ * z if mode == "AB" else z)
+        ref = to_np(xbf)
+        assert np.linalg.norm(o.x - ref) <= 1e-10 * np.linalg.norm(ref), (mode, lam, k)
+
+
+def test_matched_ab_gmres_is_lsqr_and_ba_gmres_is_lsmr():
+    # With B = A^T: AB-GMRES iterates minimise ||Ax - b|| over K_k(A^T A, A^T b)
+    # (LSQR) and BA-GMRES iterates minimise ||A^T(Ax - b)|| (LSMR).
+    ops, Am, _, Atm = tiny_ops(6, 6, 5, 9)
+    r = np.random.default_rng(8)
+    b = r.standard_normal(Am.shape[0])
+    A_, At_ = mp_mat(Am), mp_mat(Atm)
+    bb = mp_mat(b[:, None])
+    for k in (1, 3, 6):
+        Q = krylov_basis(At_ * A_, At_ * bb, k)
+        lsqr = to_np(Q * mp_regls(A_ * Q, bb, 0))
+        lsmr = to_np(Q * mp_regls(At_ * A_ * Q, At_ * bb, 0))
+        ab = sv.hybrid_gmres(lambda v: Am @ v, lambda v: Atm @ v, b, mode="AB", K=k, rule="none")
+        ba = sv.hybrid_gmres(lambda v: Am @ v, lambda v: Atm @ v, b, mode="BA", K=k, rule="none")
+        assert np.linalg.norm(ab.x - lsqr) < 1e-10 * np.linalg.norm(lsqr)
+        assert np.linalg.norm(ba.x - lsmr) < 1e-10 * np.linalg.norm(lsmr)
+
+
+def test_matched_hybrid_ba_is_hybrid_lsmr_but_hybrid_ab_is_not_hybrid_lsqr():
+    ops, Am, _, Atm = tiny_ops(6, 6, 5, 9)
+    r = np.random.default_rng(9)
+    b = r.standard_normal(Am.shape[0])
+    A_, At_ = mp_mat(Am), mp_mat(Atm)
+    bb = mp_mat(b[:, None])
+    lam = 0.8
+    for k in (2, 4, 7):
+        Q = krylov_basis(At_ * A_, At_ * bb, k)
+        h_lsmr = to_np(Q * mp_regls(At_ * A_ * Q, At_ * bb, mpmath.mpf(lam)))
+        h_lsqr = to_np(Q * mp_regls(A_ * Q, bb, mpmath.mpf(lam)))
+        ba = sv.hybrid_gmres(lambda v: Am @ v, lambda v: Atm @ v, b, mode="BA", K=k,
+                             rule="fixed", lam=lam)
+        ab = sv.hybrid_gmres(lambda v: Am @ v, lambda v: Atm @ v, b, mode="AB", K=k,
+                             rule="fixed", lam=lam)
+        assert np.linalg.norm(ba.x - h_lsmr) < 1e-10 * np.linalg.norm(h_lsmr)
+        assert np.linalg.norm(ab.x - h_lsqr) > 1e-3 * np.linalg.norm(h_lsqr)
+
+
+def test_full_dimension_limits():
+    lam = 0.3
+    # BA, m >= n, k = n
+    ops, Am, Bm, _ = tiny_ops(4, 4, 6, 7)
+    m, n = Am.shape
+    assert m >= n
+    r = np.random.default_rng(12)
+    b = r.standard_normal(m)
+    BA = Bm @ Am
+    ref = np.linalg.solve(BA.T @ BA + lam ** 2 * np.eye(n), BA.T @ (Bm @ b))
+    o = sv.hybrid_gmres(lambda v: Am @ v, lambda v: Bm @ v, b, mode="BA", K=n, rule="fixed", lam=lam)
+    assert o.iters == n
+    assert np.linalg.norm(o.x - ref) < 1e-9 * np.linalg.norm(ref)
+    # AB, n >= m, k = m (every bin sees the image, so AB is nonsingular and
+    # the Arnoldi process does not break down before k = m)
+    ops, Am, Bm, _ = tiny_ops(6, 6, 3, 6)
+    m, n = Am.shape
+    assert n >= m
+    b = r.standard_normal(m)
+    AB = Am @ Bm
+    ref = Bm @ np.linalg.solve(AB.T @ AB + lam ** 2 * np.eye(m), AB.T @ b)
+    o = sv.hybrid_gmres(lambda v: Am @ v, lambda v: Bm @ v, b, mode="AB", K=m, rule="fixed", lam=lam)
+    assert o.iters == m
+    assert np.linalg.norm(o.x - ref) < 1e-9 * np.linalg.norm(ref)
+
+
+@pytest.mark.parametrize("mode", ["AB", "BA"])
+@pytest.mark.parametrize("rule", ["gcv", "none"])
+def test_invariant_to_global_scale_of_B(mode, rule):
+    ops, x, b, en = c1_problem(idx=2)
+    K = 15
+    a = sv.hybrid_gmres(ops.A, ops.B, b, mode=mode, K=K, rule=rule)
+    s = sv.hybrid_gmres(ops.A, lambda v: 3.5 * ops.B(v), b, mode=mode, K=K, rule=rule)
+    # GCV is flat at its minimum, so lam is fixed only to ~sqrt(eps) relative
+    tol = 1e-8 if rule == "gcv" else 1e-10
+    assert np.linalg.norm(a.x - s.x) < tol * np.linalg.norm(a.x)
+
+
+# ------------------------------------------------------ failure paths -----
+
+def test_zero_data_is_breakdown_with_x0():
+    ops, x, b, en = c1_problem()
+    o = sv.hybrid_gmres(ops.A, ops.B, np.zeros_like(b), mode="AB", K=5, rule="gcv")
+    assert o.status == sv.STATUS_BREAKDOWN and o.iters == 0 and np.all(o.x == 0)
+
+
+def test_invariant_subspace_breaks_down_at_its_dimension():
+    # A = I, B = diag(1..6): AB is diagonal, and b in the span of 3 of its
+    # eigenvectors generates a 3-dimensional Krylov space.
+    Am = np.eye(6)
+    Bm = np.diag(np.arange(1.0, 7.0))
+    b = np.array([1.0, -2.0, 0.5, 0, 0, 0])
+    for mode in ("AB", "BA"):
+        o = sv.hybrid_gmres(lambda v: Am @ v, lambda v: Bm @ v, b, mode=mode, K=6, rule="none")
+        assert o.status == sv.STATUS_BREAKDOWN and o.iters == 3
+        # the invariant subspace contains the exact solution
+        ref = np.linalg.solve(Am, b)
+        assert np.linalg.norm(o.x - ref) < 1e-12 * np.linalg.norm(ref)
+
+
+def test_nonfinite_data_is_flagged():
+    ops, x, b, en = c1_problem()
+    b = b.copy()
+    b[17] = np.nan
+    o = sv.hybrid_gmres(ops.A, ops.B, b, mode="AB", K=5, rule="gcv")
+    assert o.status == sv.STATUS_NONFINITE and o.iters == 0
+
+
+def test_discrepancy_stop_fires_at_first_crossing():
+    ops, x, b, en = c1_problem(idx=3)
+    o = sv.hybrid_gmres(ops.A, ops.B, b, mode="AB", K=60, rule="gcv", stop="dp", noise_norm=en)
+    assert o.status == sv.STATUS_STOP_DP
+    t = 1.01 * en
+    assert o.rho[o.iters] <= t and all(r > t for r in o.rho[:o.iters])
+
+
+def test_residual_stagnation_stop():
+    ops, x, b, en = c1_problem(idx=4)
+    o = sv.hybrid_gmres(ops.A, ops.B, b, mode="BA", K=80, rule="gcv", stop="rns", rns_eps=1e-3)
+    assert o.status == sv.STATUS_STOP_RNS
+    rel = [abs(o.rho[j - 1] - o.rho[j]) / o.rho[j - 1] for j in range(1, o.iters + 1)]
+    assert rel[-1] < 1e-3 and all(v >= 1e-3 for v in rel[:-1])
+
+
+def test_ab_projected_residual_equals_data_residual():
+    # In AB mode ||b - A x_k|| = ||beta e_1 - H_k y_k|| by eq. (8).
+    ops, x, b, en = c1_problem(idx=5)
+    o = sv.hybrid_gmres(ops.A, ops.B, b, mode="AB", K=30, rule="gcv")
+    np.testing.assert_allclose(o.rho[1:], o.rho_hat, rtol=1e-9)
+
+
+# ------------------------------------------------- paper's claims ---------
+
+def test_semi_convergence_and_hybrid_stabilisation():
+    # Sec. 2 (semi-convergence) and Sec. 4: plain AB-GMRES reaches its best
+    # error before K and then degrades; hybrid GCV ends no worse than plain.
+    worse, total = 0, 0
+    for idx in range(4):
+        ops, x, b, en = c1_problem(idx=idx)
+        K = 30
+        p = sv.hybrid_gmres(ops.A, ops.B, b, mode="AB", K=K, rule="none", keep_x=True)
+        h = sv.hybrid_gmres(ops.A, ops.B, b, mode="AB", K=K, rule="gcv")
+        rre = [np.linalg.norm(xk - x) / np.linalg.norm(x) for xk in p.xs]
+        assert int(np.argmin(rre)) + 1 < K
+        assert rre[-1] > 1.05 * min(rre)
+        total += 1
+        worse += np.linalg.norm(h.x - x) > rre[-1] * np.linalg.norm(x)
+    assert worse == 0
