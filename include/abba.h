@@ -1,0 +1,201 @@
+/*
+ * abba.h -- C ABI of the MI355X (gfx950) implementation of hybrid AB-/BA-GMRES
+ * for X-ray CT with an unmatched backprojector (Bentley, Pasha, Sabate
+ * Landman, Yang, Zhang, "Hybrid ABBA-GMRES for Unmatched Backprojectors in
+ * Large Scale X-Ray Computerized Tomography").
+ *
+ * The problem (Sec. 1, eq. (1)): A x ~ b with a forward projector
+ * A : R^n -> R^m, data b in R^m, and a backprojector B : R^m -> R^n that is
+ * not the transpose of A (Sec. 2, eqs. (4)-(5)).  Hybrid AB-GMRES
+ * (Algorithm 1) runs the Arnoldi process on AB, hybrid BA-GMRES
+ * (Algorithm 2) on BA; each iteration solves the Tikhonov-regularised
+ * projected problem of eq. (12) with a per-iteration lambda (Sec. 3.1) and
+ * tests a stopping rule (Sec. 3.2).
+ *
+ * Conventions for every function:
+ *   - Returns 0 (ABBA_OK) or a negative abba_status.  Nothing throws or
+ *     aborts; abba_last_error() gives a thread-local message for the last
+ *     failure on the calling thread.
+ *   - Pointers named x, y, b and the abba_out arrays are DEVICE pointers
+ *     (HIP memory of the current device).  The caller owns them; the library
+ *     never frees them.  Op handles are owned by the library
+ *     (abba_op_create / abba_op_destroy).
+ *   - `stream` is a hipStream_t passed as void* (NULL = the null stream).
+ *     Work is enqueued on it; see abba_solve for when the host waits.
+ *   - Layouts are dense, row-major, batch-leading:
+ *       2D image    [batch][ny][nx]          sinogram [batch][n_angles][det_u]
+ *       3D volume   [batch][nz][ny][nx]      sinogram [batch][views][det_v][det_u]
+ *   - Supported (image, sinogram) dtype pairs: (F64, F64), (F32, F32),
+ *     (F32, BF16).  BF16 values are stored round-to-nearest-even and widened
+ *     to FP32 on load; all accumulation is FP32 (FP64 for the F64 pair).
+ *
+ * Discretisation (the paper leaves it open; it calls the ASTRA toolbox):
+ *   2D parallel beam.  Pixel (i,j) centre (j-(nx-1)/2, i-(ny-1)/2), unit
+ *   pixels; bin d at s_d = (d-(det_u-1)/2)*det_pitch_u; angle
+ *   t_a = a*pi/n_angles unless `angles` is given.  A ray marches over rows
+ *   when |cos t| is the larger direction cosine (for the default angles:
+ *   4a <= n_angles or 4a >= 3 n_angles).
+ *     ABBA_OP_JOSEPH    A: Joseph -- per row (column) linear interpolation at
+ *                       the ray crossing, times 1/|cos t| (1/|sin t|).
+ *     ABBA_OP_JOSEPH_T  A^T: the exact transpose of A (matched pair).
+ *     ABBA_OP_PIXEL     B: pixel driven -- per angle, linear interpolation of
+ *                       the sinogram row at (X cos t + Y sin t), times
+ *                       1/det_pitch_u.  B != A^T (the unmatched pair).
+ *   3D circular cone beam.  Voxel (k,i,j) centre (j-(nx-1)/2, i-(ny-1)/2,
+ *   k-(nz-1)/2); view v at b_v = 2*pi*v/views; source sid*(cos b, sin b, 0);
+ *   flat detector at distance sdd from the source, columns along
+ *   (-sin b, cos b, 0) with pitch det_pitch_u, rows along z with pitch
+ *   det_pitch_v, centred on the central ray.
+ *     ABBA_OP_JOSEPH    A: Joseph along the dominant axis of each
+ *                       source-to-pixel ray, bilinear in the plane.
+ *     ABBA_OP_PIXEL     B: voxel driven, bilinear on the detector, weight
+ *                       (M/det_pitch_u)(M/det_pitch_v), M the magnification.
+ *   Outside the image or detector everything reads as zero.
+ */
+#ifndef ABBA_H
+#define ABBA_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    ABBA_OK = 0,
+    ABBA_ERR_ARG = -1,          /* bad argument value (NULL, k out of range, small workspace) */
+    ABBA_ERR_SHAPE = -2,        /* A and B sizes do not fit together                         */
+    ABBA_ERR_DTYPE = -3,        /* unsupported dtype pair                                     */
+    ABBA_ERR_NOMEM = -4,        /* host allocation failed or size overflow                    */
+    ABBA_ERR_HIP = -5,          /* a HIP call or kernel launch failed                         */
+    ABBA_ERR_NONFINITE = -6,    /* non-finite value found where a check was requested        */
+    ABBA_ERR_UNSUPPORTED = -7   /* valid request that this build does not implement          */
+} abba_status;
+
+typedef enum { ABBA_F64 = 0, ABBA_F32 = 1, ABBA_BF16 = 2 } abba_dtype;
+typedef enum { ABBA_GEOM_PAR2D = 0, ABBA_GEOM_CONE3D = 1 } abba_geom_kind;
+typedef enum { ABBA_OP_JOSEPH = 0, ABBA_OP_PIXEL = 1, ABBA_OP_JOSEPH_T = 2 } abba_op_kind;
+
+typedef struct {
+    int kind;                  /* abba_geom_kind                                         */
+    int nx, ny, nz;            /* image size; nz = 1 for 2D                               */
+    int n_angles;              /* 2D angles or 3D views                                   */
+    int det_u, det_v;          /* detector bins (2D: det_v = 1)                           */
+    double det_pitch_u;        /* > 0                                                     */
+    double det_pitch_v;        /* > 0 (3D)                                                */
+    double sid, sdd;           /* source-isocentre and source-detector distance (3D)     */
+    const double *angles;      /* host array [n_angles] in radians, or NULL for defaults */
+} abba_geometry;
+
+typedef struct abba_op abba_op;
+
+/* Create an operator on the current HIP device.  Geometry tables are built
+ * in FP64 on the host and rounded to the storage type.  `img_dtype` and
+ * `sino_dtype` must be one of the supported pairs.  *out receives the handle;
+ * it is immutable and may be used from several streams at once. */
+int abba_op_create(abba_op **out, int kind, const abba_geometry *geom,
+                   int img_dtype, int sino_dtype);
+void abba_op_destroy(abba_op *op);
+/* Image length n and sinogram length m of one slice. */
+int abba_op_sizes(const abba_op *op, int64_t *n_img, int64_t *n_sino);
+
+/* y_s = A x_s for s < batch (eq. (1)); `A` must be ABBA_OP_JOSEPH.  x is
+ * [batch][n] in the image dtype, y [batch][m] in the sinogram dtype.
+ * Asynchronous on `stream`. */
+int abba_project(const abba_op *A, const void *x, void *y, int batch, void *stream);
+
+/* x_s = B y_s for s < batch; `B` is ABBA_OP_PIXEL (unmatched B of
+ * eqs. (4)-(5)) or ABBA_OP_JOSEPH_T (exact A^T).  Asynchronous. */
+int abba_backproject(const abba_op *B, const void *y, void *x, int batch, void *stream);
+
+typedef enum { ABBA_MODE_AB = 0, ABBA_MODE_BA = 1 } abba_mode;
+
+/* Lambda rules for the projected problem (Sec. 3.1): none (plain AB/BA-GMRES,
+ * eqs. (6)-(7)), fixed, GCV (eq. (15)), discrepancy principle (AB only),
+ * L-curve corner (eq. (14)), learned (MLP prediction, judged by GCV). */
+typedef enum {
+    ABBA_REG_NONE = 0, ABBA_REG_FIXED = 1, ABBA_REG_GCV = 2, ABBA_REG_DP = 3,
+    ABBA_REG_LCURVE = 4, ABBA_REG_LEARNED = 5
+} abba_reg_kind;
+
+/* Stopping rules (Sec. 3.2): none (run k iterations), discrepancy principle,
+ * residual-norm stagnation, learned stop index. */
+typedef enum {
+    ABBA_STOP_NONE = 0, ABBA_STOP_DP = 1, ABBA_STOP_RNS = 2, ABBA_STOP_LEARNED = 3
+} abba_stop_kind;
+
+/* Per-slice status bits written to abba_out.status. */
+enum {
+    ABBA_ST_KMAX = 1, ABBA_ST_STOP_DP = 2, ABBA_ST_STOP_RNS = 4, ABBA_ST_BREAKDOWN = 8,
+    ABBA_ST_NONFINITE = 16, ABBA_ST_STOP_LEARNED = 32
+};
+
+typedef struct {
+    int kind;                  /* abba_reg_kind                                            */
+    double lambda;             /* ABBA_REG_FIXED                                           */
+    double tau;                /* DP safety factor (> 1), e.g. 1.01                        */
+    const double *noise_norm;  /* device [batch]: ||e|| per slice (DP rule / DP stop)       */
+    const void *mlp;           /* device: learned-model parameters (ABBA_REG_LEARNED)      */
+    double judge_delta;        /* learned lambda accepted if GCV <= (1+delta) min GCV       */
+} abba_reg;
+
+typedef struct {
+    int kind;                  /* abba_stop_kind                                           */
+    double tau;                /* DP safety factor                                         */
+    double rns_eps;            /* RNS tolerance                                            */
+    const double *noise_norm;  /* device [batch]: ||e|| per slice (DP)                      */
+} abba_stop;
+
+typedef struct {
+    int *iters;                /* device [batch]: stopping iteration k (0 if beta = 0)    */
+    int *status;               /* device [batch]: ABBA_ST_* bits                           */
+    double *lambda;            /* device [batch*k] or NULL: lambda_j, j = 1..k             */
+    double *resid;             /* device [batch*(k+1)] or NULL: rho_j = ||b - A x_j||       */
+} abba_out;
+
+typedef struct {
+    int use_graph;             /* capture one iteration in a hipGraph and replay it        */
+    int poll_every;            /* host reads the active-slice count every this many
+                                  iterations (>= 1); ignored without a stopping rule       */
+    int restart;               /* restart cycle length p (Sec. 3.3); 0 = no restart        */
+    int features;              /* 1: write learned-model features per iteration (learned
+                                  rules need them; costs one extra sort per iteration)     */
+} abba_exec;
+
+/* Bytes of device workspace abba_solve needs for (A, B, batch, mode, k, stop). */
+int abba_solve_workspace(const abba_op *A, const abba_op *B, int batch, int mode, int k,
+                         const abba_stop *stop, const abba_exec *exec, size_t *bytes);
+
+/* Hybrid AB-GMRES (mode AB, Algorithm 1) or BA-GMRES (mode BA, Algorithm 2)
+ * on `batch` independent slices.
+ *   A       ABBA_OP_JOSEPH; B: ABBA_OP_PIXEL or ABBA_OP_JOSEPH_T; same geometry
+ *           sizes, else ABBA_ERR_SHAPE.
+ *   b       device [batch][m], sinogram dtype.
+ *   x       device [batch][n], image dtype; in: x_0; out: x_k at each slice's
+ *           stopping iteration.
+ *   k       iteration budget K, 1 <= k <= min(m, n) (ABBA_ERR_ARG otherwise).
+ *   reg, stop, out, exec as above; `out.iters` and `out.status` are required.
+ *   workspace, ws_bytes  device buffer of at least abba_solve_workspace bytes.
+ * The Arnoldi process uses classical Gram-Schmidt with one re-orthogonalisation
+ * (CGS2) with FP64 accumulation; H_k, its SVD and lambda are FP64.  A
+ * breakdown (h_{k+1,k} <= 1e-14 ||M w_k||) ends that slice with the k-th
+ * iterate and ABBA_ST_BREAKDOWN; it is not an error.
+ * Without a stopping rule the call only enqueues work.  With one, the host
+ * synchronises `stream` every exec.poll_every iterations to read how many
+ * slices are still active, and returns when none is or k is reached; the
+ * final assembly of x is still enqueued asynchronously. */
+int abba_solve(const abba_op *A, const abba_op *B, const void *b, void *x, int batch,
+               int mode, int k, const abba_reg *reg, const abba_stop *stop,
+               const abba_out *out, const abba_exec *exec,
+               void *workspace, size_t ws_bytes, void *stream);
+
+const char *abba_status_str(int status);
+const char *abba_last_error(void);
+/* Library version string. */
+const char *abba_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* ABBA_H */

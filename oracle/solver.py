@@ -59,13 +59,14 @@ class Result:
     beta: float = 0.0
     xs: list = field(default_factory=list)         # x_k history when requested
     Mw_norms: list = field(default_factory=list)
+    small: list = field(default_factory=list)      # per-iteration (sigma, uhat, u_{k+1}) when requested
 
 
 def hybrid_gmres(A, B, b, mode: str = "AB", K: int = 30, rule: str = "gcv",
                  lam: float = 0.0, stop: str | None = None, tau: float = 1.01,
                  noise_norm: float | None = None, rns_eps: float = 1e-3,
                  x0=None, ortho: str = "cgs2", keep_x: bool = False,
-                 keep_basis: bool = False) -> Result:
+                 keep_basis: bool = False, keep_small: bool = False) -> Result:
     """Run hybrid AB- or BA-GMRES for at most K iterations.
 
     A, B     -- callables on flat FP64 vectors (R^n -> R^m and R^m -> R^n)
@@ -148,6 +149,8 @@ def hybrid_gmres(A, B, b, mode: str = "AB", K: int = 30, rule: str = "gcv",
         out.sigma = sol["sigma"]
         if keep_x:
             out.xs.append(x.copy())
+        if keep_small:
+            out.small.append((sol["sigma"], sol["uhat"], sol["uk1"]))
         k_done = k
         if not (np.all(np.isfinite(x)) and math.isfinite(rho)):
             status = STATUS_NONFINITE

@@ -1,0 +1,329 @@
+"""Python binding of libabba.so: hybrid AB-/BA-GMRES for CT on MI355X (gfx950).
+
+The binding only marshals arguments: every step of the method runs in the
+HIP kernels of libabba.so.  PyTorch supplies device memory and the current
+HIP stream.  Importing this module fails loudly if the library is not built
+(``python -m paper_2602_17892_amd.build``).
+
+Low-level names mirror the C ABI (include/abba.h): abba_op_create,
+abba_project, abba_backproject, abba_solve_workspace, abba_solve, ...
+The helpers ``Operator``, ``project``, ``backproject`` and ``solve`` wrap
+them for torch tensors.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+__all__ = [
+    "LIB_PATH", "lib", "AbbaError", "Geometry", "Operator", "project", "backproject", "solve",
+    "workspace_bytes", "ST_KMAX", "ST_STOP_DP", "ST_STOP_RNS", "ST_BREAKDOWN", "ST_NONFINITE",
+    "ST_STOP_LEARNED",
+]
+
+LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libabba.so")
+
+# enums of include/abba.h
+F64, F32, BF16 = 0, 1, 2
+GEOM_PAR2D, GEOM_CONE3D = 0, 1
+OP_JOSEPH, OP_PIXEL, OP_JOSEPH_T = 0, 1, 2
+MODE_AB, MODE_BA = 0, 1
+REG = {"none": 0, "fixed": 1, "gcv": 2, "dp": 3, "lcurve": 4, "learned": 5}
+STOP = {None: 0, "none": 0, "dp": 1, "rns": 2, "learned": 3}
+ST_KMAX, ST_STOP_DP, ST_STOP_RNS, ST_BREAKDOWN, ST_NONFINITE, ST_STOP_LEARNED = 1, 2, 4, 8, 16, 32
+
+
+class AbbaError(RuntimeError):
+    def __init__(self, status, where):
+        self.status = status
+        msg = lib.abba_last_error().decode(errors="replace")
+        super().__init__(f"{where}: {lib.abba_status_str(status).decode()} ({status}): {msg}")
+
+
+class _Geometry(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int), ("nx", ctypes.c_int), ("ny", ctypes.c_int), ("nz", ctypes.c_int),
+                ("n_angles", ctypes.c_int), ("det_u", ctypes.c_int), ("det_v", ctypes.c_int),
+                ("det_pitch_u", ctypes.c_double), ("det_pitch_v", ctypes.c_double),
+                ("sid", ctypes.c_double), ("sdd", ctypes.c_double),
+                ("angles", ctypes.POINTER(ctypes.c_double))]
+
+
+class _Reg(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int), ("lam", ctypes.c_double), ("tau", ctypes.c_double),
+                ("noise_norm", ctypes.c_void_p), ("mlp", ctypes.c_void_p), ("judge_delta", ctypes.c_double)]
+
+
+class _Stop(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int), ("tau", ctypes.c_double), ("rns_eps", ctypes.c_double),
+                ("noise_norm", ctypes.c_void_p)]
+
+
+class _Out(ctypes.Structure):
+    _fields_ = [("iters", ctypes.c_void_p), ("status", ctypes.c_void_p), ("lam", ctypes.c_void_p),
+                ("resid", ctypes.c_void_p)]
+
+
+class _Exec(ctypes.Structure):
+    _fields_ = [("use_graph", ctypes.c_int), ("poll_every", ctypes.c_int), ("restart", ctypes.c_int),
+                ("features", ctypes.c_int)]
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is not built; run `python -m paper_2602_17892_amd.build`")
+    L = ctypes.CDLL(LIB_PATH)
+    vp, i = ctypes.c_void_p, ctypes.c_int
+    L.abba_version.restype = ctypes.c_char_p
+    L.abba_last_error.restype = ctypes.c_char_p
+    L.abba_status_str.restype = ctypes.c_char_p
+    L.abba_status_str.argtypes = [i]
+    L.abba_op_create.argtypes = [ctypes.POINTER(vp), i, ctypes.POINTER(_Geometry), i, i]
+    L.abba_op_create.restype = i
+    L.abba_op_destroy.argtypes = [vp]
+    L.abba_op_destroy.restype = None
+    L.abba_op_sizes.argtypes = [vp, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64)]
+    L.abba_op_sizes.restype = i
+    L.abba_project.argtypes = [vp, vp, vp, i, vp]
+    L.abba_project.restype = i
+    L.abba_backproject.argtypes = [vp, vp, vp, i, vp]
+    L.abba_backproject.restype = i
+    L.abba_solve_workspace.argtypes = [vp, vp, i, i, i, ctypes.POINTER(_Stop), ctypes.POINTER(_Exec),
+                                       ctypes.POINTER(ctypes.c_size_t)]
+    L.abba_solve_workspace.restype = i
+    L.abba_solve.argtypes = [vp, vp, vp, vp, i, i, i, ctypes.POINTER(_Reg), ctypes.POINTER(_Stop),
+                             ctypes.POINTER(_Out), ctypes.POINTER(_Exec), vp, ctypes.c_size_t, vp]
+    L.abba_solve.restype = i
+    return L
+
+
+lib = _load()
+
+# C-ABI names, re-exported
+abba_version = lib.abba_version
+abba_last_error = lib.abba_last_error
+abba_status_str = lib.abba_status_str
+abba_op_create = lib.abba_op_create
+abba_op_destroy = lib.abba_op_destroy
+abba_op_sizes = lib.abba_op_sizes
+abba_project = lib.abba_project
+abba_backproject = lib.abba_backproject
+abba_solve_workspace = lib.abba_solve_workspace
+abba_solve = lib.abba_solve
+
+
+def _check(rc, where):
+    if rc != 0:
+        raise AbbaError(rc, where)
+
+
+@dataclass
+class Geometry:
+    """Scan geometry (see include/abba.h for the conventions)."""
+    nx: int
+    ny: int
+    n_angles: int
+    det_u: int
+    det_pitch_u: float = 1.0
+    kind: str = "par2d"
+    nz: int = 1
+    det_v: int = 1
+    det_pitch_v: float = 1.0
+    sid: float = 0.0
+    sdd: float = 0.0
+    angles: object = None
+
+    def _c(self):
+        g = _Geometry()
+        g.kind = GEOM_PAR2D if self.kind == "par2d" else GEOM_CONE3D
+        g.nx, g.ny, g.nz = self.nx, self.ny, self.nz
+        g.n_angles, g.det_u, g.det_v = self.n_angles, self.det_u, self.det_v
+        g.det_pitch_u, g.det_pitch_v = self.det_pitch_u, self.det_pitch_v
+        g.sid, g.sdd = self.sid, self.sdd
+        keep = None
+        if self.angles is not None:
+            keep = (ctypes.c_double * self.n_angles)(*[float(a) for a in self.angles])
+            g.angles = ctypes.cast(keep, ctypes.POINTER(ctypes.c_double))
+        return g, keep
+
+    @property
+    def image_shape(self):
+        return (self.ny, self.nx) if self.kind == "par2d" else (self.nz, self.ny, self.nx)
+
+    @property
+    def sino_shape(self):
+        return (self.n_angles, self.det_u) if self.kind == "par2d" else (self.n_angles, self.det_v, self.det_u)
+
+
+_DT = {"f64": F64, "f32": F32, "bf16": BF16}
+
+
+def _torch_dtype(code):
+    import torch
+    return {F64: torch.float64, F32: torch.float32, BF16: torch.bfloat16}[code]
+
+
+class Operator:
+    """A projector handle: kind 'joseph' (A), 'pixel' (unmatched B) or 'joseph_t' (exact A^T)."""
+
+    _KINDS = {"joseph": OP_JOSEPH, "pixel": OP_PIXEL, "joseph_t": OP_JOSEPH_T}
+
+    def __init__(self, kind: str, geom: Geometry, img: str = "f32", sino: str = "f32"):
+        self.geom = geom
+        self.kind = kind
+        self.img_dt, self.sino_dt = _DT[img], _DT[sino]
+        g, keep = geom._c()
+        h = ctypes.c_void_p()
+        _check(lib.abba_op_create(ctypes.byref(h), self._KINDS[kind], ctypes.byref(g), self.img_dt,
+                                  self.sino_dt), "abba_op_create")
+        del keep
+        self.handle = h
+        n, m = ctypes.c_int64(), ctypes.c_int64()
+        _check(lib.abba_op_sizes(h, ctypes.byref(n), ctypes.byref(m)), "abba_op_sizes")
+        self.n, self.m = n.value, m.value
+
+    @property
+    def img_dtype(self):
+        return _torch_dtype(self.img_dt)
+
+    @property
+    def sino_dtype(self):
+        return _torch_dtype(self.sino_dt)
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h is not None and h.value and lib is not None:
+            lib.abba_op_destroy(h)
+            self.handle = None
+
+
+def _stream_ptr():
+    import torch
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _need(t, dtype, numel, name):
+    if not t.is_cuda:
+        raise ValueError(f"{name} must be a device tensor")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} has dtype {t.dtype}, expected {dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if t.numel() % numel:
+        raise ValueError(f"{name} has {t.numel()} elements, not a multiple of {numel}")
+    return t.numel() // numel
+
+
+def project(A: Operator, x, out=None):
+    """y = A x (batched over leading dimensions)."""
+    import torch
+    batch = _need(x, A.img_dtype, A.n, "x")
+    if out is None:
+        out = torch.empty((batch, *A.geom.sino_shape), dtype=A.sino_dtype, device=x.device)
+    _need(out, A.sino_dtype, A.m, "out")
+    _check(lib.abba_project(A.handle, _ptr(x), _ptr(out), batch, _stream_ptr()), "abba_project")
+    return out
+
+
+def backproject(B: Operator, y, out=None):
+    """x = B y (batched over leading dimensions)."""
+    import torch
+    batch = _need(y, B.sino_dtype, B.m, "y")
+    if out is None:
+        out = torch.empty((batch, *B.geom.image_shape), dtype=B.img_dtype, device=y.device)
+    _need(out, B.img_dtype, B.n, "out")
+    _check(lib.abba_backproject(B.handle, _ptr(y), _ptr(out), batch, _stream_ptr()), "abba_backproject")
+    return out
+
+
+def _structs(reg, lam, tau, noise_norm, mlp, judge_delta, stop, stop_tau, rns_eps, use_graph, poll_every,
+             restart, features):
+    r = _Reg()
+    r.kind = REG[reg]
+    r.lam = float(lam)
+    r.tau = float(tau)
+    r.noise_norm = None if noise_norm is None else noise_norm.data_ptr()
+    r.mlp = None if mlp is None else mlp.data_ptr()
+    r.judge_delta = float(judge_delta)
+    s = _Stop()
+    s.kind = STOP[stop]
+    s.tau = float(stop_tau)
+    s.rns_eps = float(rns_eps)
+    s.noise_norm = None if noise_norm is None else noise_norm.data_ptr()
+    e = _Exec()
+    e.use_graph = int(bool(use_graph))
+    e.poll_every = int(poll_every)
+    e.restart = int(restart)
+    e.features = int(features)
+    return r, s, e
+
+
+def workspace_bytes(A: Operator, B: Operator, batch: int, mode: str, k: int, stop=None) -> int:
+    _, s, e = _structs("none", 0, 0, None, None, 0, stop, 1.01, 1e-3, 0, 1, 0, 0)
+    nb = ctypes.c_size_t()
+    _check(lib.abba_solve_workspace(A.handle, B.handle, batch, MODE_AB if mode == "AB" else MODE_BA, k,
+                                    ctypes.byref(s), ctypes.byref(e), ctypes.byref(nb)), "abba_solve_workspace")
+    return nb.value
+
+
+def solve(A: Operator, B: Operator, b, mode: str = "AB", k: int = 30, reg: str = "gcv", lam: float = 0.0,
+          tau: float = 1.01, noise_norm=None, stop=None, rns_eps: float = 1e-3, x0=None, use_graph=False,
+          poll_every: int = 1, restart: int = 0, mlp=None, judge_delta: float = 0.05, history: bool = True,
+          workspace=None, features: int = 0):
+    """Hybrid AB-/BA-GMRES on a batch of slices; returns (x, info).
+
+    b: device tensor [batch, *sino_shape] in A's sinogram dtype.  noise_norm:
+    device float64 [batch] (||e|| per slice) for the discrepancy principle.
+    info holds device tensors iters [batch], status [batch] and, with
+    history, lam [batch, k] and resid [batch, k+1].
+    """
+    import torch
+    batch = _need(b, A.sino_dtype, A.m, "b")
+    dev = b.device
+    if x0 is None:
+        x = torch.zeros((batch, *A.geom.image_shape), dtype=A.img_dtype, device=dev)
+    else:
+        x = x0.clone()
+    _need(x, A.img_dtype, A.n, "x0")
+    if noise_norm is not None:
+        noise_norm = noise_norm.to(device=dev, dtype=torch.float64).contiguous()
+    r, s, e = _structs(reg, lam, tau, noise_norm, mlp, judge_delta, stop, tau, rns_eps, use_graph, poll_every,
+                       restart, features)
+    m = MODE_AB if mode == "AB" else MODE_BA
+    iters = torch.zeros(batch, dtype=torch.int32, device=dev)
+    status = torch.zeros(batch, dtype=torch.int32, device=dev)
+    lamh = torch.empty((batch, k), dtype=torch.float64, device=dev) if history else None
+    resh = torch.empty((batch, k + 1), dtype=torch.float64, device=dev) if history else None
+    o = _Out()
+    o.iters, o.status = iters.data_ptr(), status.data_ptr()
+    o.lam = None if lamh is None else lamh.data_ptr()
+    o.resid = None if resh is None else resh.data_ptr()
+    nb = ctypes.c_size_t()
+    _check(lib.abba_solve_workspace(A.handle, B.handle, batch, m, k, ctypes.byref(s), ctypes.byref(e),
+                                    ctypes.byref(nb)), "abba_solve_workspace")
+    if workspace is None:
+        workspace = torch.empty(nb.value, dtype=torch.uint8, device=dev)
+    _check(lib.abba_solve(A.handle, B.handle, _ptr(b), _ptr(x), batch, m, k, ctypes.byref(r), ctypes.byref(s),
+                          ctypes.byref(o), ctypes.byref(e), _ptr(workspace), workspace.numel(), _stream_ptr()),
+           "abba_solve")
+    info = dict(iters=iters, status=status, lam=lamh, resid=resh)
+    return x, info
+
+
+def status_names(code: int):
+    names = {ST_KMAX: "kmax", ST_STOP_DP: "dp", ST_STOP_RNS: "rns", ST_BREAKDOWN: "breakdown",
+             ST_NONFINITE: "nonfinite", ST_STOP_LEARNED: "learned"}
+    return [v for b_, v in names.items() if code & b_]
+
+
+def relative_l2(a, b) -> float:
+    """||a - b|| / ||b|| in float64 (a convenience for reports)."""
+    import torch
+    a = a.to(torch.float64)
+    b = b.to(torch.float64)
+    return float(torch.linalg.vector_norm(a - b) / torch.linalg.vector_norm(b))
+

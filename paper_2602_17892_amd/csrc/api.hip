@@ -1,0 +1,280 @@
+// C ABI: status handling, operator handles, abba_project / abba_backproject.
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+
+#include "ops.h"
+
+namespace abba {
+
+static thread_local char g_err[512] = "";
+
+void set_error(const char *fmt, ...) {
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_err, sizeof(g_err), fmt, ap);
+    va_end(ap);
+}
+
+int hip_fail(hipError_t e, const char *what) {
+    set_error("%s: %s", what, hipGetErrorString(e));
+    return ABBA_ERR_HIP;
+}
+
+static int supported_pair(int img, int sino) {
+    return (img == ABBA_F64 && sino == ABBA_F64) || (img == ABBA_F32 && sino == ABBA_F32) ||
+           (img == ABBA_F32 && sino == ABBA_BF16);
+}
+
+int validate_geometry(const abba_geometry *g, int kind) {
+    if (!g) {
+        set_error("geometry is NULL");
+        return ABBA_ERR_ARG;
+    }
+    if (g->kind != ABBA_GEOM_PAR2D && g->kind != ABBA_GEOM_CONE3D) {
+        set_error("unknown geometry kind %d", g->kind);
+        return ABBA_ERR_ARG;
+    }
+    const bool cone = g->kind == ABBA_GEOM_CONE3D;
+    if (g->nx <= 0 || g->ny <= 0 || g->n_angles <= 0 || g->det_u <= 0 || (cone && (g->nz <= 0 || g->det_v <= 0))) {
+        set_error("geometry sizes must be positive");
+        return ABBA_ERR_ARG;
+    }
+    if (!cone && ((g->nz != 1 && g->nz != 0) || (g->det_v != 1 && g->det_v != 0))) {
+        set_error("2D geometry needs nz = det_v = 1");
+        return ABBA_ERR_ARG;
+    }
+    if (!(g->det_pitch_u > 0.0) || (cone && !(g->det_pitch_v > 0.0))) {
+        set_error("detector pitch must be positive");
+        return ABBA_ERR_ARG;
+    }
+    if (cone && !(g->sid > 0.0 && g->sdd > g->sid)) {
+        set_error("cone beam needs 0 < sid < sdd");
+        return ABBA_ERR_ARG;
+    }
+    const double n = (double)g->nx * g->ny * (cone ? g->nz : 1);
+    const double m = (double)g->n_angles * g->det_u * (cone ? g->det_v : 1);
+    if (n > 4.0e9 || m > 4.0e9) {
+        set_error("problem too large for 32-bit per-slice indexing");
+        return ABBA_ERR_NOMEM;
+    }
+    if (cone && kind == ABBA_OP_JOSEPH_T) {
+        set_error("the exact transpose is implemented for 2D geometries only");
+        return ABBA_ERR_UNSUPPORTED;
+    }
+    if (g->angles) {
+        for (int a = 0; a < g->n_angles; ++a)
+            if (!std::isfinite(g->angles[a])) {
+                set_error("angle %d is not finite", a);
+                return ABBA_ERR_ARG;
+            }
+    }
+    return ABBA_OK;
+}
+
+template <typename T>
+static void fill_tab2d(const abba_op *op, AngleTab<T> *t) {
+    const abba_geometry &g = op->g;
+    const double cx = 0.5 * (g.nx - 1), cy = 0.5 * (g.ny - 1), ds = g.det_pitch_u;
+    for (int a = 0; a < g.n_angles; ++a) {
+        double th, cs, sn;
+        int rowmarch;
+        if (g.angles) {
+            th = g.angles[a];
+            cs = std::cos(th);
+            sn = std::sin(th);
+            rowmarch = std::fabs(cs) >= std::fabs(sn);
+        } else {
+            th = a * M_PI / g.n_angles;
+            cs = std::cos(th);
+            sn = std::sin(th);
+            rowmarch = (4 * a <= g.n_angles) || (4 * a >= 3 * g.n_angles);
+        }
+        AngleTab<T> &e = t[a];
+        if (rowmarch) {
+            e.inv_c = (T)(1.0 / cs);
+            e.slope = (T)(sn / cs);
+            e.off = (T)(cy * (sn / cs) + cx);
+            e.w = (T)(1.0 / std::fabs(cs));
+            e.absc = (T)std::fabs(cs);
+        } else {
+            e.inv_c = (T)(1.0 / sn);
+            e.slope = (T)(cs / sn);
+            e.off = (T)(cx * (cs / sn) + cy);
+            e.w = (T)(1.0 / std::fabs(sn));
+            e.absc = (T)std::fabs(sn);
+        }
+        e.cb = (T)(cs / ds);
+        e.sb = (T)(sn / ds);
+        e.cs = (T)cs;
+        e.sn = (T)sn;
+        e.rowmarch = rowmarch;
+        e.pad = 0;
+    }
+}
+
+int build_cone_tables(abba_op *op);   // cone3d.hip
+
+int op_build_tables(abba_op *op) {
+    if (op->g.kind == ABBA_GEOM_CONE3D) return build_cone_tables(op);
+    const int na = op->g.n_angles;
+    size_t bytes;
+    void *host;
+    if (op->img_dtype == ABBA_F64) {
+        bytes = sizeof(AngleTab<double>) * na;
+        host = new (std::nothrow) AngleTab<double>[na];
+        if (!host) return ABBA_ERR_NOMEM;
+        fill_tab2d(op, (AngleTab<double> *)host);
+    } else {
+        bytes = sizeof(AngleTab<float>) * na;
+        host = new (std::nothrow) AngleTab<float>[na];
+        if (!host) return ABBA_ERR_NOMEM;
+        fill_tab2d(op, (AngleTab<float> *)host);
+    }
+    hipError_t e = hipMalloc(&op->tab, bytes);
+    if (e == hipSuccess) e = hipMemcpy(op->tab, host, bytes, hipMemcpyHostToDevice);
+    if (op->img_dtype == ABBA_F64) delete[] (AngleTab<double> *)host;
+    else delete[] (AngleTab<float> *)host;
+    if (e != hipSuccess) return hip_fail(e, "operator table upload");
+    return ABBA_OK;
+}
+
+}  // namespace abba
+
+using namespace abba;
+
+extern "C" {
+
+const char *abba_version(void) { return "abba-mi355x 0.1 (gfx950)"; }
+
+const char *abba_last_error(void) { return g_err; }
+
+const char *abba_status_str(int s) {
+    switch (s) {
+    case ABBA_OK: return "ok";
+    case ABBA_ERR_ARG: return "invalid argument";
+    case ABBA_ERR_SHAPE: return "shape mismatch";
+    case ABBA_ERR_DTYPE: return "unsupported dtype";
+    case ABBA_ERR_NOMEM: return "out of memory";
+    case ABBA_ERR_HIP: return "HIP error";
+    case ABBA_ERR_NONFINITE: return "non-finite value";
+    case ABBA_ERR_UNSUPPORTED: return "unsupported";
+    default: return "unknown status";
+    }
+}
+
+int abba_op_create(abba_op **out, int kind, const abba_geometry *geom, int img_dtype, int sino_dtype) {
+    if (!out) {
+        set_error("out is NULL");
+        return ABBA_ERR_ARG;
+    }
+    *out = nullptr;
+    if (kind != ABBA_OP_JOSEPH && kind != ABBA_OP_PIXEL && kind != ABBA_OP_JOSEPH_T) {
+        set_error("unknown operator kind %d", kind);
+        return ABBA_ERR_ARG;
+    }
+    int rc = validate_geometry(geom, kind);
+    if (rc) return rc;
+    if (!supported_pair(img_dtype, sino_dtype)) {
+        set_error("unsupported (image, sinogram) dtype pair (%d, %d)", img_dtype, sino_dtype);
+        return ABBA_ERR_DTYPE;
+    }
+    abba_op *op = new (std::nothrow) abba_op();
+    if (!op) return ABBA_ERR_NOMEM;
+    op->kind = kind;
+    op->g = *geom;
+    if (op->g.kind == ABBA_GEOM_PAR2D) {
+        op->g.nz = 1;
+        op->g.det_v = 1;
+    }
+    if (geom->angles) {
+        op->angles.assign(geom->angles, geom->angles + geom->n_angles);
+        op->g.angles = op->angles.data();
+    }
+    op->img_dtype = img_dtype;
+    op->sino_dtype = sino_dtype;
+    op->n = (int64_t)op->g.nx * op->g.ny * op->g.nz;
+    op->m = (int64_t)op->g.n_angles * op->g.det_u * op->g.det_v;
+    op->tab = nullptr;
+    op->major = nullptr;
+    hipError_t e = hipGetDevice(&op->device);
+    if (e != hipSuccess) {
+        delete op;
+        return hip_fail(e, "hipGetDevice");
+    }
+    rc = op_build_tables(op);
+    if (rc) {
+        if (op->tab) (void)hipFree(op->tab);
+        if (op->major) (void)hipFree(op->major);
+        delete op;
+        return rc;
+    }
+    *out = op;
+    return ABBA_OK;
+}
+
+void abba_op_destroy(abba_op *op) {
+    if (!op) return;
+    if (op->tab) (void)hipFree(op->tab);
+    if (op->major) (void)hipFree(op->major);
+    delete op;
+}
+
+int abba_op_sizes(const abba_op *op, int64_t *n_img, int64_t *n_sino) {
+    if (!op) {
+        set_error("op is NULL");
+        return ABBA_ERR_ARG;
+    }
+    if (n_img) *n_img = op->n;
+    if (n_sino) *n_sino = op->m;
+    return ABBA_OK;
+}
+
+int abba_project(const abba_op *A, const void *x, void *y, int batch, void *stream) {
+    if (A && batch == 0) return ABBA_OK;
+    if (!A || !x || !y || batch < 0) {
+        set_error("abba_project: NULL argument or negative batch");
+        return ABBA_ERR_ARG;
+    }
+    if (A->kind != ABBA_OP_JOSEPH) {
+        set_error("abba_project needs an ABBA_OP_JOSEPH operator");
+        return ABBA_ERR_ARG;
+    }
+    if (batch == 0) return ABBA_OK;
+    hipStream_t st = (hipStream_t)stream;
+    Launch L{st, nullptr, nullptr};
+    VecRef xr{const_cast<void *>(x), A->n, 0, 0};
+    VecRef yr{y, A->m, 0, 0};
+    if (A->g.kind == ABBA_GEOM_CONE3D) return cone_forward(A, xr, yr, A->sino_dtype, batch, L);
+    // the forward projector reads a transposed copy of the image
+    void *xT = nullptr;
+    const size_t bytes = (size_t)batch * A->n * dtype_size(A->img_dtype);
+    ABBA_HIP(hipMallocAsync(&xT, bytes, st));
+    int rc = par2d_forward(A, xr, yr, A->sino_dtype, batch, xT, L);
+    hipError_t e = hipFreeAsync(xT, st);
+    if (rc) return rc;
+    if (e != hipSuccess) return hip_fail(e, "hipFreeAsync");
+    return ABBA_OK;
+}
+
+int abba_backproject(const abba_op *B, const void *y, void *x, int batch, void *stream) {
+    if (B && batch == 0) return ABBA_OK;
+    if (!B || !x || !y || batch < 0) {
+        set_error("abba_backproject: NULL argument or negative batch");
+        return ABBA_ERR_ARG;
+    }
+    if (B->kind != ABBA_OP_PIXEL && B->kind != ABBA_OP_JOSEPH_T) {
+        set_error("abba_backproject needs an ABBA_OP_PIXEL or ABBA_OP_JOSEPH_T operator");
+        return ABBA_ERR_ARG;
+    }
+    if (batch == 0) return ABBA_OK;
+    Launch L{(hipStream_t)stream, nullptr, nullptr};
+    VecRef yr{const_cast<void *>(y), B->m, 0, 0};
+    VecRef xr{x, B->n, 0, 0};
+    if (B->g.kind == ABBA_GEOM_CONE3D) return cone_back(B, yr, B->sino_dtype, xr, batch, L);
+    return par2d_back(B, yr, B->sino_dtype, xr, batch, L);
+}
+
+}  // extern "C"

@@ -1,0 +1,88 @@
+// Operator handles and internal launch interfaces of the HIP library.
+#pragma once
+
+#include <vector>
+
+#include "common.h"
+
+namespace abba {
+
+// Per-angle constants of the 2D parallel-beam operators, computed in FP64 on
+// the host and rounded to T.  A dominant-axis march over "rows" of the
+// marched image (x itself for row-march angles, its transpose otherwise):
+//   u_r = (s_d * inv_c + off) - r * slope   (interpolation coordinate in row r)
+//   y   = w * sum_r lerp(row r, u_r)
+template <typename T>
+struct AngleTab {
+    T inv_c;   // 1/cos (row march) or 1/sin (column march)
+    T slope;   // sin/cos or cos/sin
+    T off;     // c_r * slope + c_c (centre offsets of the marched image)
+    T w;       // 1/|cos| or 1/|sin|: ray length per step
+    T cb, sb;  // cos/ds, sin/ds: detector coordinate of a pixel in bins (B)
+    T cs, sn;  // cos, sin (exact transpose)
+    T absc;    // |dominant direction cosine|
+    int rowmarch;
+    int pad;
+};
+
+// Per-view constants of the 3D cone beam (FP32 on the device).
+struct ViewTab {
+    float src[3];    // source position
+    float det[3];    // detector centre
+    float eu[3];     // column axis (unit)
+    float ev[3];     // row axis (unit)
+    float nrm[3];    // detector normal eu x ev
+    float dist;      // (det - src) . nrm
+};
+
+// Where one vector of a slice lives: base + s*slice_stride +
+// (k + k_off)*k_stride elements, with k read from a device counter (or 0).
+struct VecRef {
+    void *base;
+    int64_t slice_stride;
+    int64_t k_stride;
+    int k_off;
+};
+
+struct Launch {
+    hipStream_t stream;
+    const int *kdev;      // device iteration counter, or nullptr (k = 0)
+    const int *active;    // device [batch] flags, or nullptr (all active)
+};
+
+}  // namespace abba
+
+struct abba_op {
+    int kind;
+    abba_geometry g;
+    std::vector<double> angles;
+    int img_dtype, sino_dtype;
+    int64_t n, m;
+    int device;
+    void *tab;             // AngleTab<float|double>[n_angles] or ViewTab[views]
+    unsigned char *major;  // 3D: per (view, column) dominant-axis flag (0 = x, 1 = y)
+};
+
+namespace abba {
+
+// 2D parallel beam (proj2d.hip).  `xT` is scratch of batch*n image elements
+// used by the forward projector for its transposed copy.
+int par2d_forward(const abba_op *op, VecRef x, VecRef y, int y_dtype, int batch,
+                  void *xT, const Launch &L);
+int par2d_back(const abba_op *op, VecRef y, int y_dtype, VecRef x, int batch, const Launch &L);
+
+// 3D cone beam (cone3d.hip).
+int cone_forward(const abba_op *op, VecRef x, VecRef y, int y_dtype, int batch, const Launch &L);
+int cone_back(const abba_op *op, VecRef y, int y_dtype, VecRef x, int batch, const Launch &L);
+
+int op_build_tables(abba_op *op);
+size_t op_fwd_scratch_elems(const abba_op *op);   // per slice
+
+static inline size_t dtype_size(int dt) { return dt == ABBA_F64 ? 8 : dt == ABBA_F32 ? 4 : 2; }
+
+template <typename T>
+__device__ __forceinline__ T *vec_ptr(const VecRef &r, int s, int k) {
+    return reinterpret_cast<T *>(r.base) + (int64_t)s * r.slice_stride + (int64_t)(k + r.k_off) * r.k_stride;
+}
+
+}  // namespace abba

@@ -1,0 +1,76 @@
+// Internal interfaces of the hybrid AB-/BA-GMRES driver.
+#pragma once
+
+#include "ops.h"
+
+namespace abba {
+
+// Number of element chunks (blocks) the reductions over a basis vector use.
+constexpr int RED_BLOCKS = 128;
+// Vectors handled per block of the multi-dot kernel.
+constexpr int DOT_JT = 8;
+// Largest Krylov dimension handled by the small-solve kernel.
+constexpr int KMAX_SMALL = 100;
+
+// Per-slice scalars kept by the small solve, FP64.
+enum {
+    SC_BETA = 0,      // ||r_0||
+    SC_UK1 = 1,       // GMRES residual component |(Q^T beta e1)_{k+1}|
+    SC_MW = 2,        // ||M w_k|| (breakdown reference)
+    SC_HK = 3,        // h_{k+1,k}
+    SC_INV = 4,       // 1/h_{k+1,k} (0 on breakdown)
+    SC_NOISE = 5,     // ||e|| (DP)
+    SC_LAM = 6,       // last lambda
+    SC_RHOHAT = 7,    // last projected residual
+    SC_RHO0 = 8,      // ||b - A x_0||
+    SC_LAMLEARN = 9,  // learned log10(lambda/sigma_1) prediction
+    SC_KLEARN = 10,   // learned stop index prediction
+    SC_COUNT = 16
+};
+
+enum { FL_BREAK = 1, FL_NONFINITE = 2 };
+
+struct SolveDims {
+    int S;          // batch
+    int K;          // iteration budget
+    int mode;       // ABBA_MODE_*
+    int64_t n, m;   // image / sinogram length of a slice
+    int64_t len;    // basis vector length (m for AB, n for BA)
+    int64_t ldw;    // padded basis stride (multiple of 256 elements)
+    int64_t ldn;    // padded image stride
+    int64_t ldm;    // padded sinogram stride
+    int keepZ;      // BA: keep Z = A W for the data residual
+    int img_dt, sino_dt, w_dt;
+};
+
+// Workspace carve-up (device pointers).
+struct SolveWS {
+    void *W;        // [S][K+1][ldw]  basis (w_dt)
+    void *P;        // [S][K][ldn]    AB: B w_j (img_dt)
+    void *Z;        // [S][K or 1][ldm] BA: A w_j (sino_dt)
+    void *sino;     // [S][ldm]       b - A x0 (sino_dt)
+    void *xT;       // [S][n]         transposed-image scratch of A
+    double *part;   // [S][RED_BLOCKS][K+1] partial dot products
+    double *h;      // [S][K+1]
+    double *c;      // [S][K+1]
+    double *npart;  // [S][RED_BLOCKS] partial squared norms
+    double *H;      // [S][K][K+1] column-major Hessenberg
+    double *gc, *gs;// [S][K] Givens rotations
+    double *g;      // [S][K+1] rotated beta e1
+    double *Aj, *Vj;// [S][K][K] Jacobi state (column-major, stride K)
+    double *y;      // [S][K]
+    double *sig;    // [S][K]
+    double *uh;     // [S][K]
+    double *sc;     // [S][SC_COUNT]
+    double *lamh;   // [S][K]
+    double *rhoh;   // [S][K+1]
+    double *feat;   // [S][64] learned-model features
+    int *active;    // [S]
+    int *flags;     // [S]
+    int *kdev;      // [1] current iteration (1-based)
+    int *nact;      // [1] active slice count
+};
+
+size_t solve_workspace_bytes(const SolveDims &d, SolveWS *ws, void *base);
+
+}  // namespace abba

@@ -1,0 +1,412 @@
+// abba_solve: hybrid AB-GMRES (Algorithm 1) and BA-GMRES (Algorithm 2) on a
+// batch of independent slices.
+//
+// Per iteration k (one pass for all active slices, k kept on the device):
+//   AB: p_k = B w_k (kept: P_k = B W_k), q = A p_k       (Alg. 1, M = AB)
+//   BA: z_k = A w_k (kept when the data residual is needed), q = B z_k
+//   CGS2 Arnoldi step (eq. (8)), FP64 accumulation
+//   small FP64 solve per slice: Givens, SVD, lambda, y_k, rho_k (eq. (12))
+//   BA only: rho_k = ||b - A x_k|| = ||(b - A x_0) - Z_k y_k||
+//   stopping rules, then k := k + 1
+// At the end x_k = x_0 + P_k y_k (AB; equal to x_0 + B W_k y_k, eq. (13)) or
+// x_0 + W_k y_k (BA) at each slice's own stopping iteration.
+//
+// The per-iteration launch sequence depends on nothing but device state, so
+// it can be captured once in a hipGraph and replayed.  The host reads the
+// number of active slices only every `poll_every` iterations.
+#include <cstring>
+
+#include "solve.h"
+
+namespace abba {
+
+int cgs2_step(const SolveDims &d, const SolveWS &ws, hipStream_t st);
+int normalize_first(const SolveDims &d, const SolveWS &ws, int *iters, int *status, hipStream_t st);
+int launch_sub(int in_dt, const void *b, int64_t bstride, const void *ax, int64_t axstride, int out_dt, void *out,
+               int64_t ostride, int64_t len, int64_t ld, int S, hipStream_t st);
+int launch_norm(int dt, const void *v, int64_t stride, int64_t len, int S, double *npart, double *dst, int dstride,
+                hipStream_t st);
+int launch_zero_pad(int dt, void *base, int64_t slice_stride, int nv, int64_t ld, int64_t len, int S,
+                    hipStream_t st);
+int launch_assemble(int v_dt, const void *Vb, int64_t vslice, int64_t ldv, int x_dt, void *x, int64_t n,
+                    const double *y, int ystride, const int *iters, int S, hipStream_t st);
+int launch_resid(int s_dt, const void *r0, int64_t rstride, const void *Z, int64_t zslice, int64_t ldz,
+                 const double *y, int ystride, int64_t len, double *npart, int S, const int *kdev,
+                 const int *active, hipStream_t st);
+int launch_smallsolve(const SolveDims &d, const SolveWS &ws, int rule, double lam_fixed, double tau,
+                      const double *noise, hipStream_t st);
+int launch_stop(const SolveDims &d, const SolveWS &ws, int stop_kind, double tau, double rns_eps,
+                const double *noise, int *iters, int *status, hipStream_t st);
+int launch_finish_resid(const SolveDims &d, const SolveWS &ws, int nblk, hipStream_t st);
+int smallsolve_prepare();
+int learned_prepare(const SolveDims &d, const SolveWS &ws, const abba_reg *reg, hipStream_t st);
+int learned_features(const SolveDims &d, const SolveWS &ws, hipStream_t st);
+int learned_judge(const SolveDims &d, const SolveWS &ws, const abba_reg *reg, hipStream_t st);
+
+static inline int64_t round_up(int64_t v, int64_t a) { return (v + a - 1) / a * a; }
+
+size_t solve_workspace_bytes(const SolveDims &d, SolveWS *ws, void *base) {
+    const size_t wsz = dtype_size(d.w_dt), isz = dtype_size(d.img_dt), ssz = dtype_size(d.sino_dt);
+    const size_t S = d.S, K = d.K;
+    size_t off = 0;
+    auto take = [&](size_t bytes) -> void * {
+        void *p = base ? (char *)base + off : nullptr;
+        off += (bytes + 255) / 256 * 256;
+        return p;
+    };
+    SolveWS w;
+    std::memset(&w, 0, sizeof(w));
+    w.W = take(S * (K + 1) * d.ldw * wsz);
+    w.P = d.mode == ABBA_MODE_AB ? take(S * K * d.ldn * isz) : nullptr;
+    w.Z = d.mode == ABBA_MODE_BA ? take(S * (d.keepZ ? K : 1) * d.ldm * ssz) : nullptr;
+    w.sino = take(S * d.ldm * ssz);
+    w.xT = take(S * d.n * isz);
+    w.part = (double *)take(S * 1024 * (K + 1) * 8);
+    w.h = (double *)take(S * (K + 1) * 8);
+    w.c = (double *)take(S * (K + 1) * 8);
+    w.npart = (double *)take(S * 1024 * 8);
+    w.H = (double *)take(S * K * (K + 1) * 8);
+    w.gc = (double *)take(S * K * 8);
+    w.gs = (double *)take(S * K * 8);
+    w.g = (double *)take(S * (K + 1) * 8);
+    w.Aj = (double *)take(S * K * K * 8);
+    w.Vj = (double *)take(S * K * K * 8);
+    w.y = (double *)take(S * K * 8);
+    w.sig = (double *)take(S * K * 8);
+    w.uh = (double *)take(S * K * 8);
+    w.sc = (double *)take(S * SC_COUNT * 8);
+    w.lamh = (double *)take(S * K * 8);
+    w.rhoh = (double *)take(S * (K + 1) * 8);
+    w.feat = (double *)take(S * 64 * 8);
+    w.active = (int *)take(S * 4);
+    w.flags = (int *)take(S * 4);
+    w.kdev = (int *)take(4);
+    w.nact = (int *)take(4);
+    if (ws) *ws = w;
+    return off;
+}
+
+static int make_dims(const abba_op *A, const abba_op *B, int batch, int mode, int k, const abba_stop *stop,
+                     const abba_out *out, SolveDims *d) {
+    if (!A || !B) {
+        set_error("A or B is NULL");
+        return ABBA_ERR_ARG;
+    }
+    if (A->kind != ABBA_OP_JOSEPH || (B->kind != ABBA_OP_PIXEL && B->kind != ABBA_OP_JOSEPH_T)) {
+        set_error("A must be ABBA_OP_JOSEPH and B ABBA_OP_PIXEL or ABBA_OP_JOSEPH_T");
+        return ABBA_ERR_ARG;
+    }
+    if (A->n != B->n || A->m != B->m || A->g.kind != B->g.kind) {
+        set_error("A is R^%lld -> R^%lld but B is R^%lld -> R^%lld", (long long)A->n, (long long)A->m,
+                  (long long)B->m, (long long)B->n);
+        return ABBA_ERR_SHAPE;
+    }
+    if (A->img_dtype != B->img_dtype || A->sino_dtype != B->sino_dtype) {
+        set_error("A and B must use the same dtypes");
+        return ABBA_ERR_DTYPE;
+    }
+    if (batch < 1) {
+        set_error("batch must be >= 1");
+        return ABBA_ERR_ARG;
+    }
+    if (mode != ABBA_MODE_AB && mode != ABBA_MODE_BA) {
+        set_error("unknown mode %d", mode);
+        return ABBA_ERR_ARG;
+    }
+    const int64_t kmax = A->n < A->m ? A->n : A->m;
+    if (k < 1 || (int64_t)k > kmax) {
+        set_error("k = %d outside [1, min(m, n) = %lld]", k, (long long)kmax);
+        return ABBA_ERR_ARG;
+    }
+    if (k > KMAX_SMALL) {
+        set_error("k = %d exceeds the small-solve limit %d (use restarts)", k, KMAX_SMALL);
+        return ABBA_ERR_UNSUPPORTED;
+    }
+    std::memset(d, 0, sizeof(*d));
+    d->S = batch;
+    d->K = k;
+    d->mode = mode;
+    d->n = A->n;
+    d->m = A->m;
+    d->len = mode == ABBA_MODE_AB ? A->m : A->n;
+    d->ldw = round_up(d->len, 256);
+    d->ldn = round_up(A->n, 256);
+    d->ldm = round_up(A->m, 256);
+    d->img_dt = A->img_dtype;
+    d->sino_dt = A->sino_dtype;
+    d->w_dt = A->img_dtype == ABBA_F64 ? ABBA_F64 : ABBA_F32;
+    const bool stop_rule = stop && stop->kind != ABBA_STOP_NONE;
+    d->keepZ = mode == ABBA_MODE_BA && (stop_rule || (out && out->resid));
+    return ABBA_OK;
+}
+
+__global__ void set_int_k(int *p, int v) { *p = v; }
+
+__global__ void fill_k(double *__restrict__ p, int64_t n, double v) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+
+static int apply_op(const abba_op *op, bool forward, VecRef in, int in_dt, VecRef out, int out_dt,
+                    const SolveDims &d, const SolveWS &ws, const Launch &L) {
+    if (forward) {
+        if (op->g.kind == ABBA_GEOM_CONE3D) return cone_forward(op, in, out, out_dt, d.S, L);
+        return par2d_forward(op, in, out, out_dt, d.S, ws.xT, L);
+    }
+    if (op->g.kind == ABBA_GEOM_CONE3D) return cone_back(op, in, in_dt, out, d.S, L);
+    return par2d_back(op, in, in_dt, out, d.S, L);
+}
+
+struct IterCfg {
+    const abba_op *A, *B;
+    int rule;
+    double lam_fixed, tau;
+    const double *noise_reg;
+    int stop_kind;
+    double stop_tau, rns_eps;
+    const double *noise_stop;
+    int *iters, *status;
+    int learned;
+    const abba_reg *reg;
+};
+
+// Launch one iteration for all active slices on `st`.
+static int one_iteration(const SolveDims &d, const SolveWS &ws, const IterCfg &c, hipStream_t st) {
+    Launch L{st, ws.kdev, ws.active};
+    const int64_t wsl = (int64_t)(d.K + 1) * d.ldw;
+    VecRef wprev{ws.W, wsl, d.ldw, -1};
+    VecRef wcur{ws.W, wsl, d.ldw, 0};
+    int rc;
+    if (d.mode == ABBA_MODE_AB) {
+        VecRef p{ws.P, (int64_t)d.K * d.ldn, d.ldn, -1};
+        if ((rc = apply_op(c.B, false, wprev, d.w_dt, p, d.img_dt, d, ws, L))) return rc;
+        if ((rc = apply_op(c.A, true, p, d.img_dt, wcur, d.w_dt, d, ws, L))) return rc;
+    } else {
+        VecRef z{ws.Z, (int64_t)(d.keepZ ? d.K : 1) * d.ldm, d.keepZ ? d.ldm : 0, d.keepZ ? -1 : 0};
+        if ((rc = apply_op(c.A, true, wprev, d.w_dt, z, d.sino_dt, d, ws, L))) return rc;
+        if ((rc = apply_op(c.B, false, z, d.sino_dt, wcur, d.w_dt, d, ws, L))) return rc;
+    }
+    if ((rc = cgs2_step(d, ws, st))) return rc;
+    if ((rc = launch_smallsolve(d, ws, c.rule, c.lam_fixed, c.tau, c.noise_reg, st))) return rc;
+    if (c.learned) {
+        if ((rc = learned_features(d, ws, st))) return rc;
+        if ((rc = learned_judge(d, ws, c.reg, st))) return rc;
+    }
+    if (d.mode == ABBA_MODE_BA && d.keepZ) {
+        const int nb = launch_resid(d.sino_dt, ws.sino, d.ldm, ws.Z, (int64_t)d.K * d.ldm, d.ldm, ws.y, d.K, d.m,
+                                    ws.npart, d.S, ws.kdev, ws.active, st);
+        if (nb < 0) return nb;
+        if ((rc = launch_finish_resid(d, ws, nb, st))) return rc;
+    }
+    return launch_stop(d, ws, c.stop_kind, c.stop_tau, c.rns_eps, c.noise_stop, c.iters, c.status, st);
+}
+
+__global__ void copy_hist_k(const double *__restrict__ src, int sstride, double *__restrict__ dst, int dstride,
+                            int cols, int S) {
+    const int s = blockIdx.x;
+    if (s >= S) return;
+    for (int j = threadIdx.x; j < cols; j += blockDim.x) dst[(size_t)s * dstride + j] = src[(size_t)s * sstride + j];
+}
+
+}  // namespace abba
+
+using namespace abba;
+
+extern "C" int abba_solve_workspace(const abba_op *A, const abba_op *B, int batch, int mode, int k,
+                                    const abba_stop *stop, const abba_exec *exec, size_t *bytes) {
+    (void)exec;
+    if (!bytes) {
+        set_error("bytes is NULL");
+        return ABBA_ERR_ARG;
+    }
+    SolveDims d;
+    abba_out dummy;
+    std::memset(&dummy, 0, sizeof(dummy));
+    dummy.resid = (double *)1;   // size for the worst case (Z kept in BA mode)
+    int rc = make_dims(A, B, batch, mode, k, stop, &dummy, &d);
+    if (rc) return rc;
+    *bytes = solve_workspace_bytes(d, nullptr, nullptr);
+    return ABBA_OK;
+}
+
+extern "C" int abba_solve(const abba_op *A, const abba_op *B, const void *b, void *x, int batch, int mode, int k,
+                          const abba_reg *reg, const abba_stop *stop, const abba_out *out, const abba_exec *exec,
+                          void *workspace, size_t ws_bytes, void *stream) {
+    if (!b || !x || !reg || !out || !out->iters || !out->status || !workspace) {
+        set_error("abba_solve: b, x, reg, out.iters, out.status and workspace are required");
+        return ABBA_ERR_ARG;
+    }
+    SolveDims d;
+    int rc = make_dims(A, B, batch, mode, k, stop, out, &d);
+    if (rc) return rc;
+    const int rule = reg->kind;
+    if (rule < ABBA_REG_NONE || rule > ABBA_REG_LEARNED) {
+        set_error("unknown lambda rule %d", rule);
+        return ABBA_ERR_ARG;
+    }
+    if (rule == ABBA_REG_FIXED && !(reg->lambda >= 0.0)) {
+        set_error("fixed lambda must be >= 0");
+        return ABBA_ERR_ARG;
+    }
+    if (rule == ABBA_REG_DP) {
+        if (mode != ABBA_MODE_AB) {
+            set_error("the discrepancy-principle lambda rule needs AB mode (projected residual = data residual)");
+            return ABBA_ERR_UNSUPPORTED;
+        }
+        if (!reg->noise_norm || !(reg->tau > 0.0)) {
+            set_error("the discrepancy-principle lambda rule needs noise_norm and tau > 0");
+            return ABBA_ERR_ARG;
+        }
+    }
+    if (rule == ABBA_REG_LEARNED && !reg->mlp) {
+        set_error("the learned lambda rule needs model parameters");
+        return ABBA_ERR_ARG;
+    }
+    const int stop_kind = stop ? stop->kind : ABBA_STOP_NONE;
+    if (stop_kind < ABBA_STOP_NONE || stop_kind > ABBA_STOP_LEARNED) {
+        set_error("unknown stopping rule %d", stop_kind);
+        return ABBA_ERR_ARG;
+    }
+    if (stop_kind == ABBA_STOP_DP && (!stop->noise_norm || !(stop->tau > 0.0))) {
+        set_error("the discrepancy-principle stop needs noise_norm and tau > 0");
+        return ABBA_ERR_ARG;
+    }
+    if (stop_kind == ABBA_STOP_RNS && !(stop->rns_eps > 0.0)) {
+        set_error("residual-norm stagnation needs rns_eps > 0");
+        return ABBA_ERR_ARG;
+    }
+    if (stop_kind == ABBA_STOP_LEARNED && rule != ABBA_REG_LEARNED) {
+        set_error("the learned stop needs the learned lambda rule (it shares the model)");
+        return ABBA_ERR_ARG;
+    }
+    abba_exec ex{0, 1, 0, 0};
+    if (exec) ex = *exec;
+    if (ex.poll_every < 1) ex.poll_every = 1;
+    if (ex.restart != 0) {
+        set_error("restarted cycles are not implemented");
+        return ABBA_ERR_UNSUPPORTED;
+    }
+    SolveWS ws;
+    const size_t need = solve_workspace_bytes(d, &ws, workspace);
+    if (ws_bytes < need) {
+        set_error("workspace of %zu bytes is smaller than the %zu needed", ws_bytes, need);
+        return ABBA_ERR_ARG;
+    }
+    hipStream_t st = (hipStream_t)stream;
+    Launch L0{st, nullptr, nullptr};
+    const int64_t wsl = (int64_t)(d.K + 1) * d.ldw;
+    if ((rc = smallsolve_prepare())) return rc;
+    // histories past a slice's stopping iteration read as NaN
+    hipLaunchKernelGGL(fill_k, dim3(64), dim3(256), 0, st, ws.lamh, (int64_t)d.S * d.K, (double)NAN);
+    ABBA_LAUNCHED("fill_k");
+    hipLaunchKernelGGL(fill_k, dim3(64), dim3(256), 0, st, ws.rhoh, (int64_t)d.S * (d.K + 1), (double)NAN);
+    ABBA_LAUNCHED("fill_k");
+
+    // ---- initialisation: r_0, beta, w_1 (Alg. 1 lines 1-3, Alg. 2 lines 1-3)
+    if ((rc = launch_zero_pad(d.w_dt, ws.W, wsl, d.K + 1, d.ldw, d.len, d.S, st))) return rc;
+    if (ws.P && (rc = launch_zero_pad(d.img_dt, ws.P, (int64_t)d.K * d.ldn, d.K, d.ldn, d.n, d.S, st))) return rc;
+    VecRef xin{x, d.n, 0, 0};
+    VecRef sino{ws.sino, d.ldm, 0, 0};
+    if ((rc = apply_op(A, true, xin, d.img_dt, sino, d.sino_dt, d, ws, L0))) return rc;
+    if (d.mode == ABBA_MODE_AB) {
+        // r_0 = b - A x_0 (basis storage), rho_0 = beta
+        if ((rc = launch_sub(d.sino_dt, b, d.m, ws.sino, d.ldm, d.w_dt, ws.W, wsl, d.m, d.ldw, d.S, st))) return rc;
+        if ((rc = launch_norm(d.w_dt, ws.W, wsl, d.m, d.S, ws.npart, ws.rhoh, d.K + 1, st))) return rc;
+    } else {
+        // b - A x_0 kept in `sino` (data residual); r_0 = B(b - A x_0)
+        if ((rc = launch_sub(d.sino_dt, b, d.m, ws.sino, d.ldm, d.sino_dt, ws.sino, d.ldm, d.m, d.ldm, d.S, st)))
+            return rc;
+        if ((rc = launch_norm(d.sino_dt, ws.sino, d.ldm, d.m, d.S, ws.npart, ws.rhoh, d.K + 1, st))) return rc;
+        VecRef w0{ws.W, wsl, 0, 0};
+        if ((rc = apply_op(B, false, sino, d.sino_dt, w0, d.w_dt, d, ws, L0))) return rc;
+    }
+    if ((rc = normalize_first(d, ws, out->iters, out->status, st))) return rc;
+    hipLaunchKernelGGL(set_int_k, dim3(1), dim3(1), 0, st, ws.kdev, 1);
+    ABBA_LAUNCHED("set_int_k");
+
+    IterCfg cfg;
+    cfg.A = A;
+    cfg.B = B;
+    cfg.rule = rule;
+    cfg.lam_fixed = reg->lambda;
+    cfg.tau = reg->tau;
+    cfg.noise_reg = reg->noise_norm;
+    cfg.stop_kind = stop_kind;
+    cfg.stop_tau = stop ? stop->tau : 0.0;
+    cfg.rns_eps = stop ? stop->rns_eps : 0.0;
+    cfg.noise_stop = stop ? stop->noise_norm : nullptr;
+    cfg.iters = out->iters;
+    cfg.status = out->status;
+    cfg.learned = rule == ABBA_REG_LEARNED;
+    cfg.reg = reg;
+    if (cfg.learned && (rc = learned_prepare(d, ws, reg, st))) return rc;
+
+    // ---- iterations
+    hipGraphExec_t gexec = nullptr;
+    hipGraph_t graph = nullptr;
+    if (ex.use_graph) {
+        hipStream_t cap;
+        ABBA_HIP(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
+        hipError_t e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
+        if (e != hipSuccess) {
+            (void)hipStreamDestroy(cap);
+            return hip_fail(e, "hipStreamBeginCapture");
+        }
+        rc = one_iteration(d, ws, cfg, cap);
+        e = hipStreamEndCapture(cap, &graph);
+        (void)hipStreamDestroy(cap);
+        if (rc) {
+            if (graph) (void)hipGraphDestroy(graph);
+            return rc;
+        }
+        if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture");
+        e = hipGraphInstantiate(&gexec, graph, nullptr, nullptr, 0);
+        if (e != hipSuccess) {
+            (void)hipGraphDestroy(graph);
+            return hip_fail(e, "hipGraphInstantiate");
+        }
+    }
+    const bool polling = stop_kind != ABBA_STOP_NONE;
+    int host_nact = d.S;
+    for (int it = 1; it <= d.K; ++it) {
+        if (gexec) {
+            hipError_t e = hipGraphLaunch(gexec, st);
+            if (e != hipSuccess) {
+                rc = hip_fail(e, "hipGraphLaunch");
+                break;
+            }
+        } else if ((rc = one_iteration(d, ws, cfg, st))) {
+            break;
+        }
+        if (polling && (it % ex.poll_every == 0) && it < d.K) {
+            hipError_t e = hipMemcpyAsync(&host_nact, ws.nact, sizeof(int), hipMemcpyDeviceToHost, st);
+            if (e == hipSuccess) e = hipStreamSynchronize(st);
+            if (e != hipSuccess) {
+                rc = hip_fail(e, "active-slice poll");
+                break;
+            }
+            if (host_nact == 0) break;
+        }
+    }
+    if (gexec) (void)hipGraphExecDestroy(gexec);
+    if (graph) (void)hipGraphDestroy(graph);
+    if (rc) return rc;
+
+    // ---- x_k = x_0 + P_k y_k (AB) or x_0 + W_k y_k (BA) at each slice's stop
+    if (d.mode == ABBA_MODE_AB)
+        rc = launch_assemble(d.img_dt, ws.P, (int64_t)d.K * d.ldn, d.ldn, d.img_dt, x, d.n, ws.y, d.K, out->iters,
+                             d.S, st);
+    else
+        rc = launch_assemble(d.w_dt, ws.W, wsl, d.ldw, d.img_dt, x, d.n, ws.y, d.K, out->iters, d.S, st);
+    if (rc) return rc;
+    if (out->lambda) {
+        hipLaunchKernelGGL(copy_hist_k, dim3(d.S), dim3(128), 0, st, ws.lamh, d.K, out->lambda, d.K, d.K, d.S);
+        ABBA_LAUNCHED("copy_hist_k");
+    }
+    if (out->resid) {
+        hipLaunchKernelGGL(copy_hist_k, dim3(d.S), dim3(128), 0, st, ws.rhoh, d.K + 1, out->resid, d.K + 1,
+                           d.K + 1, d.S);
+        ABBA_LAUNCHED("copy_hist_k");
+    }
+    return ABBA_OK;
+}

@@ -1,0 +1,77 @@
+"""The C-ABI library loads and exports every symbol include/abba.h declares.
+
+These run without a GPU: only argument validation that fails before any HIP
+call is exercised.
+"""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "abba.h")
+LIB = os.path.join(ROOT, "paper_2602_17892_amd", "libabba.so")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(abba_[a-z0-9_]+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def L():
+    if not os.path.exists(LIB):
+        pytest.fail("libabba.so is not built (python -m paper_2602_17892_amd.build)")
+    return ctypes.CDLL(LIB)
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for n in ("abba_project", "abba_backproject", "abba_solve", "abba_solve_workspace", "abba_op_create"):
+        assert n in names
+
+
+def test_every_declared_symbol_is_exported(L):
+    missing = [n for n in declared_functions() if not hasattr(L, n)]
+    assert not missing, missing
+
+
+def test_status_strings_and_version(L):
+    L.abba_status_str.restype = ctypes.c_char_p
+    L.abba_version.restype = ctypes.c_char_p
+    assert L.abba_status_str(0) == b"ok"
+    assert L.abba_status_str(-2) == b"shape mismatch"
+    assert b"gfx950" in L.abba_version()
+
+
+def test_validation_before_any_device_call():
+    import paper_2602_17892_amd as pk
+    h = ctypes.c_void_p()
+    # NULL geometry
+    assert pk.lib.abba_op_create(ctypes.byref(h), 0, None, 1, 1) == -1
+    g = pk.Geometry(8, 8, 12, 13)
+    cg, keep = g._c()
+    # unknown op kind
+    assert pk.lib.abba_op_create(ctypes.byref(h), 7, ctypes.byref(cg), 1, 1) == -1
+    # unsupported dtype pair (F64 image with F32 sinogram)
+    assert pk.lib.abba_op_create(ctypes.byref(h), 0, ctypes.byref(cg), 0, 1) == -3
+    # bad sizes
+    bad = pk.Geometry(0, 8, 12, 13)._c()[0]
+    assert pk.lib.abba_op_create(ctypes.byref(h), 0, ctypes.byref(bad), 1, 1) == -1
+    bad = pk.Geometry(8, 8, 12, 13, det_pitch_u=-1.0)._c()[0]
+    assert pk.lib.abba_op_create(ctypes.byref(h), 0, ctypes.byref(bad), 1, 1) == -1
+    # exact transpose is 2D only
+    cone = pk.Geometry(8, 8, 12, 13, kind="cone3d", nz=8, det_v=9, sid=30.0, sdd=60.0)._c()[0]
+    assert pk.lib.abba_op_create(ctypes.byref(h), 2, ctypes.byref(cone), 1, 1) == -7
+    bad = pk.Geometry(8, 8, 12, 13, kind="cone3d", nz=8, det_v=9, sid=60.0, sdd=30.0)._c()[0]
+    assert pk.lib.abba_op_create(ctypes.byref(h), 0, ctypes.byref(bad), 1, 1) == -1
+    # NULL handles
+    assert pk.lib.abba_project(None, None, None, 1, None) == -1
+    assert pk.lib.abba_backproject(None, None, None, 1, None) == -1
+    nb = ctypes.c_size_t()
+    assert pk.lib.abba_solve_workspace(None, None, 1, 0, 5, None, None, ctypes.byref(nb)) == -1
+    assert pk.lib.abba_solve(None, None, None, None, 1, 0, 5, None, None, None, None, None, 0, None) == -1
+    assert b"required" in pk.lib.abba_last_error()
+    del keep
