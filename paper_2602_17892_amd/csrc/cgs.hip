@@ -77,21 +77,26 @@ __global__ __launch_bounds__(256) void dots_k(const TW *__restrict__ W, int64_t 
         const int jj = threadIdx.x;
         double t = 0.0;
         for (int w = 0; w < (int)(blockDim.x >> 6); ++w) t += red[jj][w];
-        part[((int64_t)s * nblk + blockIdx.x) * pstride + j0 + jj] = t;
+        part[((int64_t)s * pstride + j0 + jj) * nblk + blockIdx.x] = t;
     }
 }
 
-// out[s][j] = sum_blk part[s][blk][j] in block order, for j < k + extra.
+// out[s][j] = sum over blocks of part[s][j][blk]: one wave per vector j,
+// lanes stride over the (contiguous) block partials, then a fixed-order
+// butterfly, so the result does not depend on scheduling.
 __global__ __launch_bounds__(256) void reduce_k(const double *__restrict__ part, int nblk, int pstride,
                                                 double *__restrict__ out, int ostride, int extra, int kfixed,
                                                 const int *kdev, const int *active) {
     const int s = blockIdx.x;
     if (active && !active[s]) return;
     const int jcount = (kdev ? *kdev : kfixed) + extra;
-    for (int j = threadIdx.x; j < jcount; j += blockDim.x) {
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    for (int j = wid; j < jcount; j += nw) {
+        const double *p = part + ((int64_t)s * pstride + j) * nblk;
         double t = 0.0;
-        for (int b = 0; b < nblk; ++b) t += part[((int64_t)s * nblk + b) * pstride + j];
-        out[(int64_t)s * ostride + j] = t;
+        for (int b = lane; b < nblk; b += 64) t += p[b];
+        t = wave_sum(t);
+        if (lane == 0) out[(int64_t)s * ostride + j] = t;
     }
 }
 

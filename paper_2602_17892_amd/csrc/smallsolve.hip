@@ -197,8 +197,14 @@ __global__ __launch_bounds__(SS_THREADS) void smallsolve_k(SmallArgs a) {
     // ---- one-sided Jacobi on A (k x k), accumulating V
     const int grp = tid / SS_GROUP, gl = tid % SS_GROUP;
     const int n = k + (k & 1);           // even number of players (one dummy if k odd)
-    const double tol = 2.2e-16 * (double)k;
+    // A pair whose columns are off-orthogonal by delta perturbs the singular
+    // values only at O(delta^2) and the vectors at O(delta): 1e-12 is far
+    // below what any consumer of y needs, and well above the rounding noise
+    // of the computed inner products (which a k*eps threshold would chase).
+    const double tol = 1e-12;
+    int sweeps = 0;
     for (int sweep = 0; sweep < MAX_SWEEPS && k > 1; ++sweep) {
+        ++sweeps;
         if (tid == 0) s_rot = 0;
         __syncthreads();
         for (int rnd = 0; rnd < n - 1; ++rnd) {
@@ -417,6 +423,7 @@ __global__ __launch_bounds__(SS_THREADS) void smallsolve_k(SmallArgs a) {
             const double rho = sqrt(part + uk1 * uk1);
             Sc[SC_LAM] = lam;
             Sc[SC_RHOHAT] = rho;
+            Sc[SC_SWEEPS] = (double)sweeps;
             a.lamh[(size_t)s * K + j] = lam;
             if (a.ab_resid) a.rhoh[(size_t)s * (K + 1) + k] = rho;
             if (!isfinite(rho) || !isfinite(s1)) a.flags[s] |= FL_NONFINITE;

@@ -25,6 +25,7 @@ enum {
     SC_RHO0 = 8,      // ||b - A x_0||
     SC_LAMLEARN = 9,  // learned log10(lambda/sigma_1) prediction
     SC_KLEARN = 10,   // learned stop index prediction
+    SC_SWEEPS = 11,   // Jacobi sweeps of the last small solve (diagnostic)
     SC_COUNT = 16
 };
 
@@ -50,7 +51,7 @@ struct SolveWS {
     void *Z;        // [S][K or 1][ldm] BA: A w_j (sino_dt)
     void *sino;     // [S][ldm]       b - A x0 (sino_dt)
     void *xT;       // [S][n]         transposed-image scratch of A
-    double *part;   // [S][RED_BLOCKS][K+1] partial dot products
+    double *part;   // [S][K+1][nblk] partial dot products (vector-major)
     double *h;      // [S][K+1]
     double *c;      // [S][K+1]
     double *npart;  // [S][RED_BLOCKS] partial squared norms

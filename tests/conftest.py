@@ -18,3 +18,10 @@ def oracle_lib():
     import oracle
     oracle.build_oracle(force=False)
     return oracle.load_oracle()
+
+
+@pytest.fixture(autouse=True)
+def _announce(request):
+    # name the case before it runs, so a stall can be attributed
+    print(f"\n[start] {request.node.nodeid}", flush=True)
+    yield
