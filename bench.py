@@ -30,8 +30,18 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-# VALU issue rate: 256 CUs x 4 SIMD x 16 lanes x 2.4 GHz = 3.93e13 lane-ops/s
-VALU_LANE_OPS = 256 * 64 * 2.4e9
+# FP32 vector peak without packed FP32 math (the library is built with packed
+# FP32 instructions disabled): 256 CUs x 4 SIMD x 16 lanes x 2 flops (FMA)
+# x 2.4 GHz = 78.6 TFLOP/s.
+VALU_PEAK_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
+# Algorithmic flops per unit of work: Joseph forward, per ray-step (advance
+# the interpolation coordinate 1, fractional part 1, linear interpolation 3,
+# accumulate 1); pixel-driven backprojection, per pixel-angle pair (detector
+# coordinate 2, fractional part 1, linear interpolation 3, accumulate 1,
+# clamp 1).
+FLOPS_PER_RAY_STEP = 6
+FLOPS_PER_PIXEL_ANGLE = 8
+PROFILES = os.path.join(ROOT, "profiles")
 
 
 def parse():
@@ -47,6 +57,9 @@ def parse():
     p.add_argument("--poll", type=int, default=4)
     p.add_argument("--plain-slices", type=int, default=8)
     p.add_argument("--no-cpu-baseline", action="store_true")
+    p.add_argument("--roofline-reps", type=int, default=10)
+    p.add_argument("--projectors-only", action="store_true",
+                   help="only the projector launches (random images) and a copy of known size, for counter runs")
     p.add_argument("--quiet", action="store_true")
     return p.parse_args()
 
@@ -84,7 +97,7 @@ def make_inputs(args, pk, A, torch):
     return x, b, torch.tensor(en, dtype=torch.float64, device=dev), eta
 
 
-def time_apply(fn, torch, reps=5):
+def time_apply(fn, torch, reps=10):
     stream = torch.cuda.current_stream()
     fn()
     e0 = torch.cuda.Event(enable_timing=True)
@@ -95,6 +108,91 @@ def time_apply(fn, torch, reps=5):
     e1.record(stream)
     torch.cuda.synchronize()
     return e0.elapsed_time(e1) / 1e3 / reps
+
+
+def joseph_ray_steps(n, n_angles, n_det, ds=1.0):
+    """Ray-steps of one 2D Joseph forward projection: for every ray, the rows
+    (of the dominant axis) where at least one interpolation tap lies inside
+    the image, i.e. the interpolation coordinate is in (-1, n).  Equally
+    spaced angles on [0, pi), centred detector, square n x n image."""
+    import numpy as np
+    a = np.arange(n_angles)
+    th = a * math.pi / n_angles
+    rowmarch = (4 * a <= n_angles) | (4 * a >= 3 * n_angles)
+    cs, sn = np.cos(th), np.sin(th)
+    dom = np.where(rowmarch, cs, sn)
+    other = np.where(rowmarch, sn, cs)
+    c0 = 0.5 * (n - 1)
+    slope = other / dom
+    off = c0 * slope + c0
+    sd = (np.arange(n_det) - 0.5 * (n_det - 1)) * ds
+    u0 = sd[None, :] / dom[:, None] + off[:, None]
+    sl = np.broadcast_to(slope[:, None], u0.shape)
+    with np.errstate(divide="ignore", invalid="ignore"):
+        ra, rb = (u0 + 1) / sl, (u0 - n) / sl
+    lo, hi = np.minimum(ra, rb), np.maximum(ra, rb)
+    first = np.maximum(0, np.floor(lo) + 1)
+    last = np.minimum(n - 1, np.ceil(hi) - 1)
+    cnt = np.clip(last - first + 1, 0, None)
+    flat = sl == 0
+    cnt = np.where(flat, np.where((u0 > -1) & (u0 < n), n, 0), cnt)
+    return int(cnt.sum())
+
+
+def kernel_source_digest():
+    import hashlib
+    h = hashlib.sha256()
+    with open(os.path.join(ROOT, "paper_2602_17892_amd", "csrc", "proj2d.hip"), "rb") as f:
+        h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def recorded_traffic(kernel):
+    """HBM bytes per launch of `kernel` from the committed counter summary, or
+    None when there is none or the projector source changed since."""
+    path = os.path.join(PROFILES, f"{kernel}_traffic.md")
+    if not os.path.exists(path):
+        return None
+    vals = {}
+    with open(path) as f:
+        for line in f:
+            if line.startswith("- ") and " = " in line:
+                k, v = line[2:].split(" = ", 1)
+                vals[k.strip()] = v.strip().strip("`")
+    if vals.get("source_digest") != kernel_source_digest():
+        return None
+    try:
+        return float(vals["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def projectors_only(args):
+    """Projector launches at the benchmark's batch shape on seeded random
+    images, then device copies of a known size (the counter calibration)."""
+    import torch
+
+    import paper_2602_17892_amd as pk
+    torch.cuda.set_device(0)
+    S = args.slices
+    g = pk.Geometry(args.n, args.n, args.angles, args.det)
+    A = pk.Operator("joseph", g, "f32", "f32")
+    B = pk.Operator("pixel", g, "f32", "f32")
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(2)
+    x = torch.rand((S, args.n, args.n), generator=gen, device="cuda")
+    y = torch.empty((S, args.angles, args.det), device="cuda")
+    xo = torch.empty_like(x)
+    reps = 3
+    for _ in range(reps):
+        pk.project(A, x, out=y)
+    for _ in range(reps):
+        pk.backproject(B, y, out=xo)
+    for _ in range(reps):
+        xo.copy_(x)
+    torch.cuda.synchronize()
+    print(json.dumps({"projectors_only": True, "slices": S, "reps": reps,
+                      "copy_bytes_each_way": x.numel() * 4, "source_digest": kernel_source_digest()}), flush=True)
 
 
 def cpu_baseline(args, b_slice, en_slice, k_cap):
@@ -128,6 +226,9 @@ def main():
 
     import paper_2602_17892_amd as pk
     assert torch.cuda.is_available(), "bench.py needs a GPU"
+    if args.projectors_only:
+        projectors_only(args)
+        return
     torch.cuda.set_device(0)
     S, K = args.slices, args.kmax
     g = pk.Geometry(args.n, args.n, args.angles, args.det)
@@ -180,17 +281,30 @@ def main():
     # the batched run's work on the same subset: scale by the subset's share of iterations
     log(args, f"plain: {t_plain:.3f}s/slice on {P} slices, bitwise equal to batched: {same}")
 
-    # ---- projector throughput over the whole batch (one launch each)
+    # ---- projector launches over the whole batch, event-timed on the stream
+    # they run on (the same launch shape as inside the solve)
     xin = x_true.contiguous()
     yb = torch.empty_like(b)
     xo = torch.empty_like(xin)
-    t_A = time_apply(lambda: pk.project(A, xin, out=yb), torch)
-    t_B = time_apply(lambda: pk.backproject(B, b, out=xo), torch)
+    t_A = time_apply(lambda: pk.project(A, xin, out=yb), torch, args.roofline_reps)
+    t_B = time_apply(lambda: pk.backproject(B, b, out=xo), torch, args.roofline_reps)
     n, m = args.n * args.n, args.angles * args.det
     bytes_apply = S * (n + m) * 4
     gbs_A, gbs_B = bytes_apply / t_A / 1e9, bytes_apply / t_B / 1e9
     pairs = S * n * args.angles
-    log(args, f"A: {t_A * 1e3:.2f} ms ({gbs_A:.1f} GB/s); B: {t_B * 1e3:.2f} ms ({gbs_B:.1f} GB/s)")
+    steps = S * joseph_ray_steps(args.n, args.angles, args.det)
+    tf_A = steps * FLOPS_PER_RAY_STEP / t_A / 1e12
+    tf_B = pairs * FLOPS_PER_PIXEL_ANGLE / t_B / 1e12
+    log(args, f"A: {t_A * 1e3:.2f} ms ({gbs_A:.1f} GB/s, {tf_A:.2f} TFLOP/s); "
+              f"B: {t_B * 1e3:.2f} ms ({gbs_B:.1f} GB/s, {tf_B:.2f} TFLOP/s)")
+    if t_A >= t_B:
+        dom_name, dom_tf, dom_t = "joseph2d_fwd_k", tf_A, t_A
+    else:
+        dom_name, dom_tf, dom_t = "back2d_k", tf_B, t_B
+    roofline = {"bound": "alu", "achieved": round(dom_tf, 3), "peak": round(VALU_PEAK_TFLOPS, 1),
+                "unit": "TFLOP/s", "frac": round(dom_tf / VALU_PEAK_TFLOPS, 4),
+                "traffic": recorded_traffic(dom_name), "kernel": dom_name,
+                "ms_per_launch": round(dom_t * 1e3, 3)}
 
     value = S / t_batched
     out = {
@@ -217,7 +331,10 @@ def main():
         "projector": {"A_GBps": round(gbs_A, 2), "A_frac_hbm": round(gbs_A / HBM_PEAK_GBS, 5),
                       "B_GBps": round(gbs_B, 2), "B_frac_hbm": round(gbs_B / HBM_PEAK_GBS, 5),
                       "A_ms_batch": round(t_A * 1e3, 3), "B_ms_batch": round(t_B * 1e3, 3),
-                      "B_Gpairs_per_s": round(pairs / t_B / 1e9, 2)},
+                      "B_Gpairs_per_s": round(pairs / t_B / 1e9, 2),
+                      "A_TFLOPs": round(tf_A, 3), "B_TFLOPs": round(tf_B, 3), "A_ray_steps": steps,
+                      "B_pixel_angle_pairs": pairs},
+        "roofline": roofline,
     }
     if not args.no_cpu_baseline:
         s0 = int(np.argsort(iters)[len(iters) // 2])

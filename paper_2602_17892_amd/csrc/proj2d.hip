@@ -41,6 +41,16 @@ __global__ __launch_bounds__(256) void transpose_k(VecRef xr, T *__restrict__ xT
     }
 }
 
+// v if keep, else +0.0, by masking the bits: the loaded value is always
+// consumed, so the compiler cannot move the load under a branch.
+__device__ __forceinline__ float keep_if(float v, bool keep) {
+    return __uint_as_float(__float_as_uint(v) & (keep ? 0xffffffffu : 0u));
+}
+__device__ __forceinline__ double keep_if(double v, bool keep) {
+    const unsigned long long m = keep ? ~0ull : 0ull;
+    return __longlong_as_double((long long)((unsigned long long)__double_as_longlong(v) & m));
+}
+
 // ---------------------------------------------------------- Joseph A -------
 template <typename TI, typename TO>
 __global__ __launch_bounds__(256) void joseph2d_fwd_k(VecRef xr, const TI *__restrict__ xT, VecRef yr,
@@ -69,31 +79,64 @@ __global__ __launch_bounds__(256) void joseph2d_fwd_k(VecRef xr, const TI *__res
     }
     const T sd = ((T)d - cd) * ds;
     const T u0 = fma(sd, t.inv_c, t.off);
-    // rows whose crossing lies in (-1, C), widened by one row on each side
+    // Rows whose crossing lies in (-1, C), widened by one row on each side.
+    // Both ends are clamped to [-2, R+1] before the conversion to int: for a
+    // ray that misses the image at a near-zero slope (the column march at
+    // exactly 90 degrees has slope cos/sin ~ 6e-17) the quotients are ~1e17
+    // and would otherwise saturate the conversion.  So r0 is in [0, R], r1 in
+    // [-1, R-1] and the step count below cannot overflow.
     int r0 = 0, r1 = R - 1;
     if (t.slope != (T)0) {
         T ra = (u0 + (T)1) / t.slope, rb = (u0 - (T)C) / t.slope;
         T lo = fmin(ra, rb), hi = fmax(ra, rb);
-        lo = fmax(lo, (T)-2);
-        hi = fmin(hi, (T)(R + 1));
+        lo = fmin(fmax(lo, (T)-2), (T)(R + 1));
+        hi = fmin(fmax(hi, (T)-2), (T)(R + 1));
         r0 = max(0, (int)floor(lo) - 1);
         r1 = min(R - 1, (int)ceil(hi) + 1);
     } else if (!(u0 > (T)-1 && u0 < (T)C)) {
         r1 = -1;
     }
-    T acc = 0;
-    for (int r = r0; r <= r1; ++r) {
+    const int nsteps = r1 - r0 + 1;   // <= 0 when the ray misses the image
+    // Same clamped loads as one step at a time, four steps per pass: every
+    // load is issued before any is consumed, and a tap outside the row is
+    // zeroed by masking its bits (no branch, so no per-step memory wait).
+    T acc0 = 0, acc1 = 0;
+    int r = r0;
+    for (int i = 0; i + 4 <= nsteps; i += 4, r += 4) {
+        T v[8], f[4];
+        bool ok[8];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const T u = fma(-(T)(r + q), t.slope, u0);
+            const T jf = floor(u);
+            f[q] = u - jf;
+            const int j = (int)jf;
+            const TI *row = P + (int64_t)(r + q) * C;
+            const int ja = min(max(j, 0), C - 1), jb = min(max(j + 1, 0), C - 1);
+            v[2 * q] = (T)row[ja];
+            v[2 * q + 1] = (T)row[jb];
+            ok[2 * q] = j >= 0 && j < C;
+            ok[2 * q + 1] = j + 1 >= 0 && j + 1 < C;
+        }
+#pragma unroll
+        for (int e = 0; e < 8; ++e) v[e] = keep_if(v[e], ok[e]);
+        acc0 += fma(f[0], v[1] - v[0], v[0]);
+        acc1 += fma(f[1], v[3] - v[2], v[2]);
+        acc0 += fma(f[2], v[5] - v[4], v[4]);
+        acc1 += fma(f[3], v[7] - v[6], v[6]);
+    }
+    for (; r <= r1; ++r) {   // the last nsteps mod 4 rows
         const T u = fma(-(T)r, t.slope, u0);
         const T jf = floor(u);
         const T f = u - jf;
         const int j = (int)jf;
         const TI *row = P + (int64_t)r * C;
         const int ja = min(max(j, 0), C - 1), jb = min(max(j + 1, 0), C - 1);
-        T v0 = (T)row[ja], v1 = (T)row[jb];
-        v0 = (j >= 0 && j < C) ? v0 : (T)0;
-        v1 = (j + 1 >= 0 && j + 1 < C) ? v1 : (T)0;
-        acc += fma(f, v1 - v0, v0);
+        const T v0 = keep_if((T)row[ja], j >= 0 && j < C);
+        const T v1 = keep_if((T)row[jb], j + 1 >= 0 && j + 1 < C);
+        acc0 += fma(f, v1 - v0, v0);
     }
+    const T acc = acc0 + acc1;
     store_as<TO>(vec_ptr<TO>(yr, s, k), (int64_t)a * nd + d, acc * t.w);
 }
 
@@ -116,19 +159,45 @@ __global__ __launch_bounds__(256) void back2d_k(VecRef yr, VecRef xr,
     const TIN *y = vec_ptr<const TIN>(yr, s, k);
     T acc = 0;
     if (!EXACT_T) {
-        // B: linear interpolation of row a at t = (X cos + Y sin)/ds + cd
-        for (int a = 0; a < na; ++a) {
+        // B: linear interpolation of row a at t = (X cos + Y sin)/ds + cd,
+        // four angles per pass with masked (branch-free) taps
+        T a1 = 0, a2 = 0, a3 = 0;
+        int a = 0;
+        for (; a + 3 < na; a += 4) {
+            T v[8], f[4];
+            bool ok[8];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const T t = fma(X, tab[a + q].cb, fma(Y, tab[a + q].sb, cd));
+                const T df = floor(t);
+                f[q] = t - df;
+                const int d = (int)fmax(fmin(df, (T)nd), (T)-2);
+                const TIN *row = y + (int64_t)(a + q) * nd;
+                const int da = min(max(d, 0), nd - 1), db = min(max(d + 1, 0), nd - 1);
+                v[2 * q] = (T)load_as<TIN>(row, da);
+                v[2 * q + 1] = (T)load_as<TIN>(row, db);
+                ok[2 * q] = d >= 0 && d < nd;
+                ok[2 * q + 1] = d + 1 >= 0 && d + 1 < nd;
+            }
+#pragma unroll
+            for (int e = 0; e < 8; ++e) v[e] = keep_if(v[e], ok[e]);
+            acc += fma(f[0], v[1] - v[0], v[0]);
+            a1 += fma(f[1], v[3] - v[2], v[2]);
+            a2 += fma(f[2], v[5] - v[4], v[4]);
+            a3 += fma(f[3], v[7] - v[6], v[6]);
+        }
+        for (; a < na; ++a) {
             const T t = fma(X, tab[a].cb, fma(Y, tab[a].sb, cd));
             const T df = floor(t);
             const T f = t - df;
             const int d = (int)fmax(fmin(df, (T)nd), (T)-2);
             const TIN *row = y + (int64_t)a * nd;
             const int da = min(max(d, 0), nd - 1), db = min(max(d + 1, 0), nd - 1);
-            T v0 = (T)load_as<TIN>(row, da), v1 = (T)load_as<TIN>(row, db);
-            v0 = (d >= 0 && d < nd) ? v0 : (T)0;
-            v1 = (d + 1 >= 0 && d + 1 < nd) ? v1 : (T)0;
+            const T v0 = keep_if((T)load_as<TIN>(row, da), d >= 0 && d < nd);
+            const T v1 = keep_if((T)load_as<TIN>(row, db), d + 1 >= 0 && d + 1 < nd);
             acc += fma(f, v1 - v0, v0);
         }
+        acc = (acc + a1) + (a2 + a3);
         acc *= wb;
     } else {
         // A^T: gather the rays whose Joseph interpolation hat covers this
