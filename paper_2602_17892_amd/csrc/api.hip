@@ -204,6 +204,13 @@ int abba_op_create(abba_op **out, int kind, const abba_geometry *geom, int img_d
         delete op;
         return hip_fail(e, "hipGetDevice");
     }
+    // workgroups are dealt round-robin to the XCDs; the projectors renumber
+    // them so that each XCD (own L2) works on a contiguous range of slices
+    int nxcc = 1;
+    if (hipDeviceGetAttribute(&nxcc, hipDeviceAttributeNumberOfXccs, op->device) != hipSuccess || nxcc < 1)
+        nxcc = 1;
+    (void)hipGetLastError();
+    op->nxcc = nxcc;
     rc = op_build_tables(op);
     if (rc) {
         if (op->tab) (void)hipFree(op->tab);
@@ -248,12 +255,11 @@ int abba_project(const abba_op *A, const void *x, void *y, int batch, void *stre
     VecRef xr{const_cast<void *>(x), A->n, 0, 0};
     VecRef yr{y, A->m, 0, 0};
     if (A->g.kind == ABBA_GEOM_CONE3D) return cone_forward(A, xr, yr, A->sino_dtype, batch, L);
-    // the forward projector reads a transposed copy of the image
-    void *xT = nullptr;
-    const size_t bytes = (size_t)batch * A->n * dtype_size(A->img_dtype);
-    ABBA_HIP(hipMallocAsync(&xT, bytes, st));
-    int rc = par2d_forward(A, xr, yr, A->sino_dtype, batch, xT, L);
-    hipError_t e = hipFreeAsync(xT, st);
+    // the forward projector reads zero-padded copies of the image
+    void *scr = nullptr;
+    ABBA_HIP(hipMallocAsync(&scr, par2d_scratch_bytes(A, batch), st));
+    int rc = par2d_forward(A, xr, yr, A->sino_dtype, batch, scr, L);
+    hipError_t e = hipFreeAsync(scr, st);
     if (rc) return rc;
     if (e != hipSuccess) return hip_fail(e, "hipFreeAsync");
     return ABBA_OK;
@@ -270,11 +276,20 @@ int abba_backproject(const abba_op *B, const void *y, void *x, int batch, void *
         return ABBA_ERR_ARG;
     }
     if (batch == 0) return ABBA_OK;
-    Launch L{(hipStream_t)stream, nullptr, nullptr};
+    hipStream_t st = (hipStream_t)stream;
+    Launch L{st, nullptr, nullptr};
     VecRef yr{const_cast<void *>(y), B->m, 0, 0};
     VecRef xr{x, B->n, 0, 0};
     if (B->g.kind == ABBA_GEOM_CONE3D) return cone_back(B, yr, B->sino_dtype, xr, batch, L);
-    return par2d_back(B, yr, B->sino_dtype, xr, batch, L);
+    if (B->kind == ABBA_OP_JOSEPH_T) return par2d_back(B, yr, B->sino_dtype, xr, batch, nullptr, L);
+    // the pixel-driven backprojector reads a zero-padded copy of the sinogram
+    void *scr = nullptr;
+    ABBA_HIP(hipMallocAsync(&scr, par2d_scratch_bytes(B, batch), st));
+    int rc = par2d_back(B, yr, B->sino_dtype, xr, batch, scr, L);
+    hipError_t e = hipFreeAsync(scr, st);
+    if (rc) return rc;
+    if (e != hipSuccess) return hip_fail(e, "hipFreeAsync");
+    return ABBA_OK;
 }
 
 }  // extern "C"

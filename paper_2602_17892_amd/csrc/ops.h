@@ -59,24 +59,26 @@ struct abba_op {
     int img_dtype, sino_dtype;
     int64_t n, m;
     int device;
+    int nxcc;              // XCDs of the device (workgroups are dealt to them round-robin)
     void *tab;             // AngleTab<float|double>[n_angles] or ViewTab[views]
     unsigned char *major;  // 3D: per (view, column) dominant-axis flag (0 = x, 1 = y)
 };
 
 namespace abba {
 
-// 2D parallel beam (proj2d.hip).  `xT` is scratch of batch*n image elements
-// used by the forward projector for its transposed copy.
-int par2d_forward(const abba_op *op, VecRef x, VecRef y, int y_dtype, int batch,
-                  void *xT, const Launch &L);
-int par2d_back(const abba_op *op, VecRef y, int y_dtype, VecRef x, int batch, const Launch &L);
+// 2D parallel beam (proj2d.hip).  `scratch` holds the zero-padded copy of the
+// operator input: at least par2d_scratch_bytes(op, batch) bytes.  A and B of
+// one geometry may share it when they run in turn on one stream.
+int par2d_forward(const abba_op *op, VecRef x, VecRef y, int y_dtype, int batch, void *scratch,
+                  const Launch &L);
+int par2d_back(const abba_op *op, VecRef y, int y_dtype, VecRef x, int batch, void *scratch, const Launch &L);
+size_t par2d_scratch_bytes(const abba_op *op, int batch);
 
 // 3D cone beam (cone3d.hip).
 int cone_forward(const abba_op *op, VecRef x, VecRef y, int y_dtype, int batch, const Launch &L);
 int cone_back(const abba_op *op, VecRef y, int y_dtype, VecRef x, int batch, const Launch &L);
 
 int op_build_tables(abba_op *op);
-size_t op_fwd_scratch_elems(const abba_op *op);   // per slice
 
 static inline size_t dtype_size(int dt) { return dt == ABBA_F64 ? 8 : dt == ABBA_F32 ? 4 : 2; }
 

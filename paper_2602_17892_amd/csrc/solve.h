@@ -50,7 +50,7 @@ struct SolveWS {
     void *P;        // [S][K][ldn]    AB: B w_j (img_dt)
     void *Z;        // [S][K or 1][ldm] BA: A w_j (sino_dt)
     void *sino;     // [S][ldm]       b - A x0 (sino_dt)
-    void *xT;       // [S][n]         transposed-image scratch of A
+    void *scratch;  // zero-padded operator input (A and B take turns)
     double *part;   // [S][K+1][nblk] partial dot products (vector-major)
     double *h;      // [S][K+1]
     double *c;      // [S][K+1]
@@ -72,6 +72,6 @@ struct SolveWS {
     int *nact;      // [1] active slice count
 };
 
-size_t solve_workspace_bytes(const SolveDims &d, SolveWS *ws, void *base);
+size_t solve_workspace_bytes(const SolveDims &d, SolveWS *ws, void *base, size_t scratch_bytes);
 
 }  // namespace abba

@@ -45,7 +45,15 @@ int learned_judge(const SolveDims &d, const SolveWS &ws, const abba_reg *reg, hi
 
 static inline int64_t round_up(int64_t v, int64_t a) { return (v + a - 1) / a * a; }
 
-size_t solve_workspace_bytes(const SolveDims &d, SolveWS *ws, void *base) {
+// Scratch the operators of one solve need for `batch` slices.
+static size_t op_scratch_bytes(const abba_op *A, const abba_op *B, int batch) {
+    size_t b = 0;
+    if (A->g.kind != ABBA_GEOM_CONE3D) b = std::max(b, par2d_scratch_bytes(A, batch));
+    if (B->g.kind != ABBA_GEOM_CONE3D) b = std::max(b, par2d_scratch_bytes(B, batch));
+    return b;
+}
+
+size_t solve_workspace_bytes(const SolveDims &d, SolveWS *ws, void *base, size_t scratch_bytes) {
     const size_t wsz = dtype_size(d.w_dt), isz = dtype_size(d.img_dt), ssz = dtype_size(d.sino_dt);
     const size_t S = d.S, K = d.K;
     size_t off = 0;
@@ -60,7 +68,7 @@ size_t solve_workspace_bytes(const SolveDims &d, SolveWS *ws, void *base) {
     w.P = d.mode == ABBA_MODE_AB ? take(S * K * d.ldn * isz) : nullptr;
     w.Z = d.mode == ABBA_MODE_BA ? take(S * (d.keepZ ? K : 1) * d.ldm * ssz) : nullptr;
     w.sino = take(S * d.ldm * ssz);
-    w.xT = take(S * d.n * isz);
+    w.scratch = take(scratch_bytes);
     w.part = (double *)take(S * 1024 * (K + 1) * 8);
     w.h = (double *)take(S * (K + 1) * 8);
     w.c = (double *)take(S * (K + 1) * 8);
@@ -151,10 +159,10 @@ static int apply_op(const abba_op *op, bool forward, VecRef in, int in_dt, VecRe
                     const SolveDims &d, const SolveWS &ws, const Launch &L) {
     if (forward) {
         if (op->g.kind == ABBA_GEOM_CONE3D) return cone_forward(op, in, out, out_dt, d.S, L);
-        return par2d_forward(op, in, out, out_dt, d.S, ws.xT, L);
+        return par2d_forward(op, in, out, out_dt, d.S, ws.scratch, L);
     }
     if (op->g.kind == ABBA_GEOM_CONE3D) return cone_back(op, in, in_dt, out, d.S, L);
-    return par2d_back(op, in, in_dt, out, d.S, L);
+    return par2d_back(op, in, in_dt, out, d.S, ws.scratch, L);
 }
 
 struct IterCfg {
@@ -225,7 +233,7 @@ extern "C" int abba_solve_workspace(const abba_op *A, const abba_op *B, int batc
     dummy.resid = (double *)1;   // size for the worst case (Z kept in BA mode)
     int rc = make_dims(A, B, batch, mode, k, stop, &dummy, &d);
     if (rc) return rc;
-    *bytes = solve_workspace_bytes(d, nullptr, nullptr);
+    *bytes = solve_workspace_bytes(d, nullptr, nullptr, op_scratch_bytes(A, B, batch));
     return ABBA_OK;
 }
 
@@ -287,7 +295,7 @@ extern "C" int abba_solve(const abba_op *A, const abba_op *B, const void *b, voi
         return ABBA_ERR_UNSUPPORTED;
     }
     SolveWS ws;
-    const size_t need = solve_workspace_bytes(d, &ws, workspace);
+    const size_t need = solve_workspace_bytes(d, &ws, workspace, op_scratch_bytes(A, B, batch));
     if (ws_bytes < need) {
         set_error("workspace of %zu bytes is smaller than the %zu needed", ws_bytes, need);
         return ABBA_ERR_ARG;
