@@ -1,4 +1,5 @@
 // C ABI: status handling, operator handles, abba_project / abba_backproject.
+#include <algorithm>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -74,35 +75,35 @@ int validate_geometry(const abba_geometry *g, int kind) {
     return ABBA_OK;
 }
 
+// March direction of angle a: over rows when |cos| is the larger direction
+// cosine; for the default equispaced angles the integer rule 4a <= N or
+// 4a >= 3N (no floating-point tie at 45 degrees).
+static int rowmarch_of(const abba_geometry &g, int a) {
+    if (g.angles) return std::fabs(std::cos(g.angles[a])) >= std::fabs(std::sin(g.angles[a]));
+    return (4 * a <= g.n_angles) || (4 * a >= 3 * g.n_angles);
+}
+
 template <typename T>
 static void fill_tab2d(const abba_op *op, AngleTab<T> *t) {
     const abba_geometry &g = op->g;
     const double cx = 0.5 * (g.nx - 1), cy = 0.5 * (g.ny - 1), ds = g.det_pitch_u;
     for (int a = 0; a < g.n_angles; ++a) {
-        double th, cs, sn;
-        int rowmarch;
-        if (g.angles) {
-            th = g.angles[a];
-            cs = std::cos(th);
-            sn = std::sin(th);
-            rowmarch = std::fabs(cs) >= std::fabs(sn);
-        } else {
-            th = a * M_PI / g.n_angles;
-            cs = std::cos(th);
-            sn = std::sin(th);
-            rowmarch = (4 * a <= g.n_angles) || (4 * a >= 3 * g.n_angles);
-        }
+        const double th = g.angles ? g.angles[a] : a * M_PI / g.n_angles;
+        const double cs = std::cos(th), sn = std::sin(th);
+        const int rowmarch = rowmarch_of(g, a);
         AngleTab<T> &e = t[a];
         if (rowmarch) {
             e.inv_c = (T)(1.0 / cs);
             e.slope = (T)(sn / cs);
             e.off = (T)(cy * (sn / cs) + cx);
+            e.off2 = (T)(cy * (sn / cs) + cx + 2.0);
             e.w = (T)(1.0 / std::fabs(cs));
             e.absc = (T)std::fabs(cs);
         } else {
             e.inv_c = (T)(1.0 / sn);
             e.slope = (T)(cs / sn);
             e.off = (T)(cx * (cs / sn) + cy);
+            e.off2 = (T)(cx * (cs / sn) + cy + 2.0);
             e.w = (T)(1.0 / std::fabs(sn));
             e.absc = (T)std::fabs(sn);
         }
@@ -138,6 +139,24 @@ int op_build_tables(abba_op *op) {
     if (op->img_dtype == ABBA_F64) delete[] (AngleTab<double> *)host;
     else delete[] (AngleTab<float> *)host;
     if (e != hipSuccess) return hip_fail(e, "operator table upload");
+    // angle groups of one march direction for the LDS-band projector
+    std::vector<int> order, grp;
+    for (int pass = 1; pass >= 0; --pass) {
+        const int first = (int)order.size();
+        for (int a = 0; a < na; ++a)
+            if (rowmarch_of(op->g, a) == pass) order.push_back(a);
+        for (int i = first; i < (int)order.size(); i += JOSEPH_GA) {
+            grp.push_back(i);
+            grp.push_back(std::min(JOSEPH_GA, (int)order.size() - i));
+            grp.push_back(pass);
+            grp.push_back(0);
+        }
+    }
+    op->ngroups = (int)grp.size() / 4;
+    grp.insert(grp.end(), order.begin(), order.end());
+    e = hipMalloc(&op->agrp, grp.size() * sizeof(int));
+    if (e == hipSuccess) e = hipMemcpy(op->agrp, grp.data(), grp.size() * sizeof(int), hipMemcpyHostToDevice);
+    if (e != hipSuccess) return hip_fail(e, "angle group upload");
     return ABBA_OK;
 }
 
@@ -199,6 +218,8 @@ int abba_op_create(abba_op **out, int kind, const abba_geometry *geom, int img_d
     op->m = (int64_t)op->g.n_angles * op->g.det_u * op->g.det_v;
     op->tab = nullptr;
     op->major = nullptr;
+    op->agrp = nullptr;
+    op->ngroups = 0;
     hipError_t e = hipGetDevice(&op->device);
     if (e != hipSuccess) {
         delete op;
@@ -209,12 +230,17 @@ int abba_op_create(abba_op **out, int kind, const abba_geometry *geom, int img_d
     int nxcc = 1;
     if (hipDeviceGetAttribute(&nxcc, hipDeviceAttributeNumberOfXccs, op->device) != hipSuccess || nxcc < 1)
         nxcc = 1;
+    int ncu = 0;
+    if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, op->device) != hipSuccess || ncu < 1)
+        ncu = 1;
     (void)hipGetLastError();
     op->nxcc = nxcc;
+    op->ncu = ncu;
     rc = op_build_tables(op);
     if (rc) {
         if (op->tab) (void)hipFree(op->tab);
         if (op->major) (void)hipFree(op->major);
+        if (op->agrp) (void)hipFree(op->agrp);
         delete op;
         return rc;
     }
@@ -226,6 +252,7 @@ void abba_op_destroy(abba_op *op) {
     if (!op) return;
     if (op->tab) (void)hipFree(op->tab);
     if (op->major) (void)hipFree(op->major);
+    if (op->agrp) (void)hipFree(op->agrp);
     delete op;
 }
 

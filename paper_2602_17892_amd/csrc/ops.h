@@ -21,9 +21,14 @@ struct AngleTab {
     T cb, sb;  // cos/ds, sin/ds: detector coordinate of a pixel in bins (B)
     T cs, sn;  // cos, sin (exact transpose)
     T absc;    // |dominant direction cosine|
+    T off2;    // off + 2: u_r shifted into the coordinates of a row with two zeros in front
     int rowmarch;
     int pad;
 };
+
+// Angles per workgroup of the LDS-band Joseph projector; its angle groups
+// hold angles of one march direction only.
+constexpr int JOSEPH_GA = 4;
 
 // Per-view constants of the 3D cone beam (FP32 on the device).
 struct ViewTab {
@@ -60,7 +65,10 @@ struct abba_op {
     int64_t n, m;
     int device;
     int nxcc;              // XCDs of the device (workgroups are dealt to them round-robin)
+    int ncu;               // compute units of the device
     void *tab;             // AngleTab<float|double>[n_angles] or ViewTab[views]
+    int *agrp;             // 2D: [ngroups][4] {first, count, rowmarch, 0}, then the angle order [n_angles]
+    int ngroups;
     unsigned char *major;  // 3D: per (view, column) dominant-axis flag (0 = x, 1 = y)
 };
 

@@ -21,12 +21,18 @@
 // walks a contiguous range of slices (see xcd_remap).  Nothing uses atomics,
 // so results are deterministic.
 #include <algorithm>
+#include <cmath>
+#include <cstdlib>
+#include <cstring>
 
 #include "ops.h"
 
 namespace abba {
 
-constexpr int PAD = 2;   // zeros on each side of a padded row
+constexpr int PAD = 2;    // zeros on each side of a padded row
+constexpr int RPAD = 16;  // padded copies have a multiple of RPAD rows (extra rows are zero)
+
+__host__ __device__ constexpr int round_rows(int r) { return (r + RPAD - 1) / RPAD * RPAD; }
 
 // Largest number of workgroups per 1D launch (the grid's thread count stays
 // below 2^31); larger batches are split into several launches.
@@ -56,6 +62,14 @@ __device__ __forceinline__ const T *at_byte(const T *base, uint32_t off) {
 __device__ __forceinline__ float clampf(float x, float lo, float hi) { return __builtin_amdgcn_fmed3f(x, lo, hi); }
 __device__ __forceinline__ double clampf(double x, double lo, double hi) { return fmin(fmax(x, lo), hi); }
 
+// t - floor(t) in one instruction.
+template <typename T>
+__device__ __forceinline__ T fract_of(T t);
+template <>
+__device__ __forceinline__ float fract_of<float>(float t) { return __builtin_amdgcn_fractf(t); }
+template <>
+__device__ __forceinline__ double fract_of<double>(double t) { return __builtin_amdgcn_fract(t); }
+
 // ------------------------------------------------------ padded copies -----
 // Image -> xp [ny][nx + 4] (row-major) and xq [nx][ny + 4] (transposed), each
 // row with PAD zeros on both sides.  32 x 32 tiles through LDS.
@@ -67,8 +81,13 @@ __global__ __launch_bounds__(256) void pad_image_k(VecRef xr, T *__restrict__ xp
     const int k = kdev ? *kdev : 0;
     const T *x = vec_ptr<const T>(xr, s, k);
     const int lp = nx + 2 * PAD, lq = ny + 2 * PAD;
-    T *op = xp + (int64_t)s * ny * lp;
-    T *oq = xq + (int64_t)s * nx * lq;
+    T *op = xp + (int64_t)s * round_rows(ny) * lp;
+    T *oq = xq + (int64_t)s * round_rows(nx) * lq;
+    // the zero rows that round both copies up to a multiple of RPAD rows
+    if (blockIdx.x == 0 && blockIdx.y == 0) {
+        for (int e = threadIdx.x; e < (round_rows(ny) - ny) * lp; e += 256) op[(int64_t)ny * lp + e] = (T)0;
+        for (int e = threadIdx.x; e < (round_rows(nx) - nx) * lq; e += 256) oq[(int64_t)nx * lq + e] = (T)0;
+    }
     __shared__ T tile[32][33];
     const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;   // 32 x 8
     const int j0 = blockIdx.x * 32, i0 = blockIdx.y * 32;
@@ -100,25 +119,70 @@ __global__ __launch_bounds__(256) void pad_image_k(VecRef xr, T *__restrict__ xp
     }
 }
 
-// Sinogram -> yp [na][nd + 4] in the accumulation type T, PAD zeros on both
-// sides of every row.  One workgroup per (row, slice).
-template <typename TIN, typename T>
-__global__ __launch_bounds__(256) void pad_sino_k(VecRef yr, T *__restrict__ yp, int na, int nd, int s0,
-                                                  const int *kdev, const int *active) {
-    const int s = s0 + blockIdx.y;
-    if (active && !active[s]) return;
-    const int k = kdev ? *kdev : 0;
-    const int a = blockIdx.x;
-    const TIN *y = vec_ptr<const TIN>(yr, s, k) + (int64_t)a * nd;
-    const int ld = nd + 2 * PAD;
-    T *o = yp + ((int64_t)s * na + a) * ld;
-    for (int c = threadIdx.x; c < ld; c += 256) {
-        const int d = c - PAD;
-        o[c] = (d >= 0 && d < nd) ? (T)load_as<TIN>(y, d) : (T)0;
+// ---------------------------------------------------------- Joseph A -------
+// Ray (a, d) of a march direction with R rows of C pixels (padded rows of
+// L = C + 4 entries): u(r) = u0 - r*slope is the interpolation coordinate in
+// row r, shifted by the two leading pad zeros.  y = w * sum_r lerp(row r at
+// u(r)).  The rows are taken in bands of JH; a band contributes the sum over
+// its rows, accumulated at even and odd rows separately.  Both kernels below
+// compute exactly this with the same operations in the same order, so their
+// results are bitwise identical; they differ only in where the taps come
+// from (global memory or a band staged in LDS).
+template <typename T>
+struct JBand {
+    static constexpr int H = sizeof(T) == 8 ? 8 : 16;
+};
+static_assert(RPAD % 16 == 0 && RPAD % 8 == 0, "bands must tile the padded rows");
+
+// Rows whose crossing lies in (-1, C), widened by one row on each side.  Both
+// ends are clamped to [-2, R+1] before the conversion to int: for a ray that
+// misses the image at a near-zero slope (the column march at exactly 90
+// degrees has slope cos/sin ~ 6e-17) the quotients are ~1e17 and would
+// otherwise saturate the conversion.  r0 ends in [0, R], r1 in [-1, R-1].
+template <typename T>
+__device__ __forceinline__ void ray_rows(T uc, T slope, int R, int C, int &r0, int &r1) {
+    r0 = 0;
+    r1 = R - 1;
+    if (slope != (T)0) {
+        const T ra = (uc + (T)1) / slope, rb = (uc - (T)C) / slope;
+        const T lo = fmin(fmax(fmin(ra, rb), (T)-2), (T)(R + 1));
+        const T hi = fmin(fmax(fmax(ra, rb), (T)-2), (T)(R + 1));
+        r0 = max(0, (int)floor(lo) - 1);
+        r1 = min(R - 1, (int)ceil(hi) + 1);
+    } else if (!(uc > (T)-1 && uc < (T)C)) {
+        r1 = -1;
     }
 }
 
-// ---------------------------------------------------------- Joseph A -------
+// Union of the row ranges of the 64 rays of a wave (the same in all lanes).
+__device__ __forceinline__ void wave_union(int &r0, int &r1) {
+    for (int o = 32; o > 0; o >>= 1) {
+        r0 = min(r0, __shfl_xor(r0, o));
+        r1 = max(r1, __shfl_xor(r1, o));
+    }
+}
+
+// Contribution of the band whose first row is `rows` (stride L) for a ray
+// with coordinate ub = u(b0) in the band's first row.  Clamping to [0, C+2]
+// keeps the tap pair inside the padded row and reads zeros wherever a tap
+// is outside the image; after the clamp u >= 0, so (int) is floor.
+template <typename T, int H>
+__device__ __forceinline__ T band_sum(const T *rows, int L, T ub, T slope, int C) {
+    T a0 = 0, a1 = 0;
+#pragma unroll
+    for (int q = 0; q < H; ++q) {
+        const T u = fma(-(T)q, slope, ub);
+        const T f = fract_of(u);
+        const T *e = at_byte(rows + q * L, (uint32_t)(int)clampf(u, (T)0, (T)(C + 2)) * (uint32_t)sizeof(T));
+        const T v = fma(f, e[1] - e[0], e[0]);
+        if (q & 1) a1 += v;
+        else a0 += v;
+    }
+    return a0 + a1;
+}
+
+// Gather version: one thread per ray, a wave = 64 consecutive bins of one
+// angle, the wave walks the bands that meet the union of its rays' rows.
 template <typename TI, typename TO>
 __global__ __launch_bounds__(256) void joseph2d_fwd_k(const TI *__restrict__ xp, const TI *__restrict__ xq,
                                                       VecRef yr,
@@ -128,160 +192,248 @@ __global__ __launch_bounds__(256) void joseph2d_fwd_k(const TI *__restrict__ xp,
                                                       uint32_t nxcc, int s0, const int *kdev,
                                                       const int *active) {
     typedef typename acc_of<TI>::type T;
+    static_assert(sizeof(TI) == sizeof(T), "images are stored in the accumulation type");
+    constexpr int H = JBand<T>::H;
     // work order: (slice, angle, bin block), bin blocks fastest
     const uint32_t w = xcd_remap(blockIdx.x, gridDim.x, nxcc);
     const uint32_t wa = w / (uint32_t)nbx;
     const int a = (int)(wa % (uint32_t)na);
     const int s = s0 + (int)(wa / (uint32_t)na);
     if (active && !active[s]) return;
-    // lanes past the last bin (d >= nd) only take part in the wave's row
-    // range below; they store nothing
+    // lanes past the last bin only take part in the wave's row range
     const int d = (int)(w % (uint32_t)nbx) * 256 + threadIdx.x;
-    const bool live = d < nd;
     const int k = kdev ? *kdev : 0;
     const AngleTab<T> t = tab[a];
-    // march over the rows of the padded image (row march) or of its padded
-    // transpose (column march); R rows of C pixels, stride C + 4
-    const TI *P;
+    const T *P;
     int R, C;
     if (t.rowmarch) {
-        P = xp + (int64_t)s * ny * (nx + 2 * PAD);
+        P = (const T *)xp + (int64_t)s * round_rows(ny) * (nx + 2 * PAD);
         R = ny;
         C = nx;
     } else {
-        P = xq + (int64_t)s * nx * (ny + 2 * PAD);
+        P = (const T *)xq + (int64_t)s * round_rows(nx) * (ny + 2 * PAD);
         R = nx;
         C = ny;
     }
-    const uint32_t L = (uint32_t)(C + 2 * PAD);
+    const int L = C + 2 * PAD;
     const T sd = ((T)d - cd) * ds;
-    const T u0 = fma(sd, t.inv_c, t.off);
-    // Rows whose crossing lies in (-1, C), widened by one row on each side.
-    // Both ends are clamped to [-2, R+1] before the conversion to int: for a
-    // ray that misses the image at a near-zero slope (the column march at
-    // exactly 90 degrees has slope cos/sin ~ 6e-17) the quotients are ~1e17
-    // and would otherwise saturate the conversion.  So r0 is in [0, R], r1 in
-    // [-1, R-1] and the step count below cannot overflow.
-    int r0 = 0, r1 = R - 1;
-    if (t.slope != (T)0) {
-        T ra = (u0 + (T)1) / t.slope, rb = (u0 - (T)C) / t.slope;
-        T lo = fmin(ra, rb), hi = fmax(ra, rb);
-        lo = fmin(fmax(lo, (T)-2), (T)(R + 1));
-        hi = fmin(fmax(hi, (T)-2), (T)(R + 1));
-        r0 = max(0, (int)floor(lo) - 1);
-        r1 = min(R - 1, (int)ceil(hi) + 1);
-    } else if (!(u0 > (T)-1 && u0 < (T)C)) {
-        r1 = -1;
-    }
-    if (!live) {
+    const T u0 = fma(sd, t.inv_c, t.off2);
+    int r0, r1;
+    ray_rows(fma(sd, t.inv_c, t.off), t.slope, R, C, r0, r1);
+    if (d >= nd) {
         r0 = R;
         r1 = -1;
     }
-    // The whole wave steps through the union of its lanes' row ranges in
-    // lockstep, so that one load instruction reads one image row (a few
-    // cache lines) instead of a different row per lane.  In a row outside a
-    // lane's own range its taps fall into the zero pads and add exactly 0.
-    int rlo = r0, rhi = r1;
-    for (int o = 32; o > 0; o >>= 1) {
-        rlo = min(rlo, __shfl_xor(rlo, o));
-        rhi = max(rhi, __shfl_xor(rhi, o));
+    wave_union(r0, r1);
+    const int rlo = __builtin_amdgcn_readfirstlane(r0), rhi = __builtin_amdgcn_readfirstlane(r1);
+    T acc = 0;
+    for (int b0 = rlo / H * H; b0 <= rhi; b0 += H)
+        acc += band_sum<T, H>(P + (int64_t)b0 * L, L, fma(-(T)b0, t.slope, u0), t.slope, C);
+    if (d < nd) store_as<TO>(vec_ptr<TO>(yr, s, k), (int64_t)a * nd + d, acc * t.w);
+}
+
+// LDS version: a workgroup takes one slice, JOSEPH_GA angles of one march
+// direction and 768 bins (3 rays per thread and angle) and streams the padded
+// image through LDS band by band; each ray keeps its sum in a register.  A
+// wave skips a (ray slot, band) pair exactly when the gather version's wave
+// would not visit that band.
+constexpr int JB = 3;   // bins per thread and angle
+
+template <typename TI, typename TO>
+__global__ __launch_bounds__(256) void joseph2d_lds_k(const TI *__restrict__ xp, const TI *__restrict__ xq,
+                                                      VecRef yr,
+                                                      const AngleTab<typename acc_of<TI>::type> *__restrict__ tab,
+                                                      const int *__restrict__ agrp, int ngroups, int nbc, int nx,
+                                                      int ny, int nd, typename acc_of<TI>::type ds,
+                                                      typename acc_of<TI>::type cd, uint32_t nxcc, int s0,
+                                                      const int *kdev, const int *active) {
+    typedef typename acc_of<TI>::type T;
+    static_assert(sizeof(TI) == sizeof(T), "images are stored in the accumulation type");
+    constexpr int H = JBand<T>::H;
+    constexpr int GA = JOSEPH_GA;
+    extern __shared__ __align__(16) unsigned char smem[];
+    T *band = reinterpret_cast<T *>(smem);   // [H][L]
+    // work order: (slice, angle group, bin chunk of 768)
+    const uint32_t w = xcd_remap(blockIdx.x, gridDim.x, nxcc);
+    const int bc = (int)(w % (uint32_t)nbc);
+    const uint32_t w2 = w / (uint32_t)nbc;
+    const int gi = (int)(w2 % (uint32_t)ngroups);
+    const int s = s0 + (int)(w2 / (uint32_t)ngroups);
+    if (active && !active[s]) return;
+    const int k = kdev ? *kdev : 0;
+    const int g_first = agrp[4 * gi], g_count = agrp[4 * gi + 1], rowmarch = agrp[4 * gi + 2];
+    const int *order = agrp + 4 * ngroups;
+    const T *P;
+    int R, C;
+    if (rowmarch) {
+        P = (const T *)xp + (int64_t)s * round_rows(ny) * (nx + 2 * PAD);
+        R = ny;
+        C = nx;
+    } else {
+        P = (const T *)xq + (int64_t)s * round_rows(nx) * (ny + 2 * PAD);
+        R = nx;
+        C = ny;
     }
-    rlo = __builtin_amdgcn_readfirstlane(rlo);
-    rhi = __builtin_amdgcn_readfirstlane(rhi);
-    const int nsteps = rhi - rlo + 1;   // <= 0 when no ray of the wave meets the image
-    // Step in row r: u = u0 - r*slope, taps floor(u) and floor(u)+1, weight
-    // u - floor(u).  Clamping floor(u) to [-2, C] keeps the pair inside the
-    // padded row (columns jc+2, jc+3) and reads zeros wherever a tap is
-    // outside the image.  Four steps per pass, all loads issued first.
-    T acc0 = 0, acc1 = 0;
-    int r = rlo;
-    for (int i = 0; i + 4 <= nsteps; i += 4, r += 4) {
-        const TI *Pr = P + (int64_t)r * L;   // row r, the same for the whole wave
-        T v0[4], v1[4], f[4];
+    const int L = C + 2 * PAD;
+    T u0[GA][JB], acc[GA][JB], slope[GA];
+    uint32_t rng[GA][JB];   // wave union of rows: first | (last + 1) << 16
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            const T u = fma(-(T)(r + q), t.slope, u0);
-            const T jf = floor(u);
-            f[q] = u - jf;
-            const TI *p = at_byte(Pr + q * L, (uint32_t)((int)clampf(jf, (T)-2, (T)C) + PAD) * (uint32_t)sizeof(TI));
-            v0[q] = (T)p[0];
-            v1[q] = (T)p[1];
+    for (int ai = 0; ai < GA; ++ai) {
+        const int a = order[g_first + min(ai, g_count - 1)];
+        const AngleTab<T> t = tab[a];
+        slope[ai] = t.slope;
+#pragma unroll
+        for (int j = 0; j < JB; ++j) {
+            const int d = bc * (256 * JB) + j * 256 + (int)threadIdx.x;
+            const T sd = ((T)d - cd) * ds;
+            u0[ai][j] = fma(sd, t.inv_c, t.off2);
+            acc[ai][j] = 0;
+            int r0, r1;
+            ray_rows(fma(sd, t.inv_c, t.off), t.slope, R, C, r0, r1);
+            if (ai >= g_count || d >= nd) {
+                r0 = R;
+                r1 = -1;
+            }
+            wave_union(r0, r1);
+            rng[ai][j] = (uint32_t)r0 | ((uint32_t)(r1 + 1) << 16);
         }
-        acc0 += fma(f[0], v1[0] - v0[0], v0[0]);
-        acc1 += fma(f[1], v1[1] - v0[1], v0[1]);
-        acc0 += fma(f[2], v1[2] - v0[2], v0[2]);
-        acc1 += fma(f[3], v1[3] - v0[3], v0[3]);
     }
-    for (; r <= rhi; ++r) {   // the last nsteps mod 4 rows
-        const T u = fma(-(T)r, t.slope, u0);
-        const T jf = floor(u);
-        const T f = u - jf;
-        const TI *p = at_byte(P + (int64_t)r * L, (uint32_t)((int)clampf(jf, (T)-2, (T)C) + PAD) * (uint32_t)sizeof(TI));
-        const T a0 = (T)p[0];
-        const T a1 = (T)p[1];
-        acc0 += fma(f, a1 - a0, a0);
+    const int Rr = round_rows(R);
+    const bool vec4 = (L % 4) == 0;
+    for (int b0 = 0; b0 < Rr; b0 += H) {
+        __syncthreads();   // the previous band is no longer read
+        const T *src = P + (int64_t)b0 * L;
+        if (vec4 && sizeof(T) == 4) {
+            const float4 *s4 = reinterpret_cast<const float4 *>(src);
+            float4 *d4 = reinterpret_cast<float4 *>(band);
+            for (int c = threadIdx.x; c < H * L / 4; c += 256) d4[c] = s4[c];
+        } else {
+            for (int c = threadIdx.x; c < H * L; c += 256) band[c] = src[c];
+        }
+        __syncthreads();
+#pragma unroll
+        for (int ai = 0; ai < GA; ++ai) {
+#pragma unroll
+            for (int j = 0; j < JB; ++j) {
+                const int lo = (int)(rng[ai][j] & 0xffffu), hi1 = (int)(rng[ai][j] >> 16);
+                if (lo > b0 + H - 1 || hi1 <= b0) continue;   // the same in all lanes of the wave
+                acc[ai][j] += band_sum<T, H>(band, L, fma(-(T)b0, slope[ai], u0[ai][j]), slope[ai], C);
+            }
+        }
     }
-    if (!live) return;
-    const T acc = acc0 + acc1;
-    store_as<TO>(vec_ptr<TO>(yr, s, k), (int64_t)a * nd + d, acc * t.w);
+#pragma unroll
+    for (int ai = 0; ai < GA; ++ai) {
+        if (ai >= g_count) break;
+        const int a = order[g_first + ai];
+        const T wt = tab[a].w;
+        TO *yo = vec_ptr<TO>(yr, s, k) + (int64_t)a * nd;
+#pragma unroll
+        for (int j = 0; j < JB; ++j) {
+            const int d = bc * (256 * JB) + j * 256 + (int)threadIdx.x;
+            if (d < nd) store_as<TO>(yo, d, acc[ai][j] * wt);
+        }
+    }
 }
 
 // ------------------------------------------------------- pixel-driven B -----
-// x[i][j] = wb * sum_a lerp(row a of the sinogram at X cos + Y sin), read from
-// the padded sinogram yp (accumulation type T).
-template <typename TI>
-__global__ __launch_bounds__(256) void pixbp2d_k(const typename acc_of<TI>::type *__restrict__ yp, VecRef xr,
+// x[i][j] = wb * sum_a lerp(row a of the sinogram at t = X cos/ds + Y sin/ds + cd).
+// A workgroup owns a BT x BT pixel tile.  For a chunk of angles it stages in
+// LDS, per angle, the window of detector bins the tile projects onto, as
+// pairs (y[p], y[p+1] - y[p]) with zeros outside the detector; a pixel-angle
+// pair is then one LDS read, lerp = v + f*dv.  The window of angle a starts at
+// w0 = floor(t_min) - 1 (t_min over the tile's corners) and holds W entries,
+// W >= 31*(|cos| + |sin|)/ds + 5, so every tap of the tile lies inside it.
+constexpr int BT = 32;   // pixel tile edge
+
+template <typename TIN, typename TI>
+__global__ __launch_bounds__(256) void pixbp2d_k(VecRef yr, VecRef xr,
                                                  const AngleTab<typename acc_of<TI>::type> *__restrict__ tab,
                                                  int nx, int ny, int na, int nd, typename acc_of<TI>::type cd,
-                                                 typename acc_of<TI>::type wb, int ntx, int nty, uint32_t nxcc,
-                                                 int s0, const int *kdev, const int *active) {
+                                                 typename acc_of<TI>::type wb, int W, int G, int ntx, int nty,
+                                                 uint32_t nxcc, int s0, const int *kdev, const int *active) {
     typedef typename acc_of<TI>::type T;
-    // work order: (slice, tile row, tile column), 16 x 16 pixel tiles
+    extern __shared__ __align__(16) unsigned char smem[];
+    T *win = reinterpret_cast<T *>(smem);                           // [G][W][2]
+    int *wtab = reinterpret_cast<int *>(smem + (size_t)G * W * 2 * sizeof(T));   // [G]
+    // work order: (slice, tile row, tile column)
     const uint32_t w = xcd_remap(blockIdx.x, gridDim.x, nxcc);
     const uint32_t wt = w / (uint32_t)ntx;
     const int ty = (int)(wt % (uint32_t)nty);
+    const int tx = (int)(w % (uint32_t)ntx);
     const int s = s0 + (int)(wt / (uint32_t)nty);
     if (active && !active[s]) return;
     const int k = kdev ? *kdev : 0;
-    const int j = (int)(w % (uint32_t)ntx) * 16 + (threadIdx.x & 15);
-    const int i = ty * 16 + (threadIdx.x >> 4);
-    const T X = (T)j - (T)0.5 * (T)(nx - 1);
-    const T Y = (T)i - (T)0.5 * (T)(ny - 1);
-    const uint32_t ld = (uint32_t)(nd + 2 * PAD);
-    const T *Y0 = yp + (int64_t)s * na * ld;
-    // bin coordinate t = X cos/ds + Y sin/ds + cd, taps floor(t), floor(t)+1,
-    // clamped into the padded row as in A; four angles per pass
-    T acc0 = 0, acc1 = 0, acc2 = 0, acc3 = 0;
-    int a = 0;
-    for (; a + 4 <= na; a += 4) {
-        T v0[4], v1[4], f[4];
+    const TIN *y = vec_ptr<const TIN>(yr, s, k);
+    const T cx = (T)0.5 * (T)(nx - 1), cy = (T)0.5 * (T)(ny - 1);
+    // this thread: column j, rows i0 + 8m (m = 0..3)
+    const int j = tx * BT + (threadIdx.x & 31);
+    const int i0 = ty * BT + (threadIdx.x >> 5);
+    const T X = (T)j - cx;
+    T Ym[4];
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            const T tt = fma(X, tab[a + q].cb, fma(Y, tab[a + q].sb, cd));
-            const T df = floor(tt);
-            f[q] = tt - df;
-            const uint32_t e = (uint32_t)(a + q) * ld + (uint32_t)((int)clampf(df, (T)-2, (T)nd) + PAD);
-            const T *p = at_byte(Y0, e * (uint32_t)sizeof(T));
-            v0[q] = p[0];
-            v1[q] = p[1];
+    for (int m = 0; m < 4; ++m) Ym[m] = (T)(i0 + 8 * m) - cy;
+    // tile corners (the whole tile, also where it overhangs the image)
+    const T X0 = (T)(tx * BT) - cx, X1 = X0 + (T)(BT - 1);
+    const T Y0 = (T)(ty * BT) - cy, Y1 = Y0 + (T)(BT - 1);
+    T acc[4] = {0, 0, 0, 0};
+    for (int a0 = 0; a0 < na; a0 += G) {
+        const int g = min(G, na - a0);
+        __syncthreads();   // the previous chunk is no longer read
+        for (int al = threadIdx.x >> 6; al < g; al += 4) {
+            const int a = a0 + al;
+            const T cb = tab[a].cb, sb = tab[a].sb;
+            const T tmin = cd + fmin(X0 * cb, X1 * cb) + fmin(Y0 * sb, Y1 * sb);
+            const int w0 = (int)floor(tmin) - 1;
+            if ((threadIdx.x & 63) == 0) wtab[al] = w0;
+            const TIN *row = y + (int64_t)a * nd;
+            T *dst = win + (size_t)al * W * 2;
+            for (int c = threadIdx.x & 63; c < W; c += 64) {
+                const int p = w0 + c;
+                const T v = (p >= 0 && p < nd) ? (T)load_as<TIN>(row, p) : (T)0;
+                const T vn = (p + 1 >= 0 && p + 1 < nd) ? (T)load_as<TIN>(row, p + 1) : (T)0;
+                dst[2 * c] = v;
+                dst[2 * c + 1] = vn - v;
+            }
         }
-        acc0 += fma(f[0], v1[0] - v0[0], v0[0]);
-        acc1 += fma(f[1], v1[1] - v0[1], v0[1]);
-        acc2 += fma(f[2], v1[2] - v0[2], v0[2]);
-        acc3 += fma(f[3], v1[3] - v0[3], v0[3]);
+        __syncthreads();
+        for (int al = 0; al < g; ++al) {
+            const int a = a0 + al;
+            const T cb = tab[a].cb, sb = tab[a].sb;
+            // t relative to the window start: t - w0 = fma(Y, sb, X cb + cd - w0)
+            const T base = fma(X, cb, cd - (T)wtab[al]);
+            const T *wrow = win + (size_t)al * W * 2;
+#pragma unroll
+            for (int m = 0; m < 4; ++m) {
+                const T t = fma(Ym[m], sb, base);
+                const T f = fract_of(t);
+                // t >= 1 inside the window, so (int) is floor; the clamp only
+                // guards the LDS row
+                const int idx = (int)clampf(t, (T)0, (T)(W - 1));
+                const T v = wrow[2 * idx], dv = wrow[2 * idx + 1];
+                acc[m] += fma(f, dv, v);
+            }
+        }
     }
-    for (; a < na; ++a) {
-        const T tt = fma(X, tab[a].cb, fma(Y, tab[a].sb, cd));
-        const T df = floor(tt);
-        const T f = tt - df;
-        const uint32_t e = (uint32_t)a * ld + (uint32_t)((int)clampf(df, (T)-2, (T)nd) + PAD);
-        const T *p = at_byte(Y0, e * (uint32_t)sizeof(T));
-        const T a0 = p[0];
-        const T a1 = p[1];
-        acc0 += fma(f, a1 - a0, a0);
+    if (j < nx) {
+        TI *xo = vec_ptr<TI>(xr, s, k);
+#pragma unroll
+        for (int m = 0; m < 4; ++m) {
+            const int i = i0 + 8 * m;
+            if (i < ny) xo[(int64_t)i * nx + j] = (TI)(acc[m] * wb);
+        }
     }
-    const T acc = ((acc0 + acc1) + (acc2 + acc3)) * wb;
-    if (i < ny && j < nx) vec_ptr<TI>(xr, s, k)[(int64_t)i * nx + j] = (TI)acc;
+}
+
+// LDS window of the pixel-driven B: entries per angle and angles per chunk.
+static void pixbp_window(const abba_op *op, int *W, int *G) {
+    double m = 0;
+    for (int a = 0; a < op->g.n_angles; ++a) {
+        const double th = op->g.angles ? op->g.angles[a] : a * M_PI / op->g.n_angles;
+        m = std::max(m, std::fabs(std::cos(th)) + std::fabs(std::sin(th)));
+    }
+    *W = (int)std::ceil((BT - 1) * m / op->g.det_pitch_u) + 5;
+    const size_t per = (size_t)*W * 2 * (op->img_dtype == ABBA_F64 ? 8 : 4);
+    *G = (int)std::max<size_t>(1, std::min<size_t>(32, 32768 / per));
 }
 
 // ------------------------------------------------------------ exact A^T ----
@@ -329,18 +481,18 @@ __global__ __launch_bounds__(256) void josephT2d_k(VecRef yr, VecRef xr,
 static size_t acc_size(const abba_op *op) { return op->img_dtype == ABBA_F64 ? 8 : 4; }
 
 size_t par2d_scratch_bytes(const abba_op *op, int batch) {
-    const int64_t nx = op->g.nx, ny = op->g.ny, na = op->g.n_angles, nd = op->g.det_u;
-    const int64_t img = ny * (nx + 2 * PAD) + nx * (ny + 2 * PAD);
-    const int64_t sino = na * (nd + 2 * PAD);
-    return (size_t)batch * (size_t)std::max(img, sino) * acc_size(op);
+    if (op->kind != ABBA_OP_JOSEPH) return 0;   // only A reads a padded copy
+    const int64_t nx = op->g.nx, ny = op->g.ny;
+    return (size_t)batch * (size_t)(round_rows(ny) * (nx + 2 * PAD) + round_rows(nx) * (ny + 2 * PAD)) *
+           acc_size(op);
 }
 
 // A padded slice must be addressable with 32-bit byte offsets.
 static bool offsets_fit(const abba_op *op) {
-    const uint64_t nx = op->g.nx, ny = op->g.ny, na = op->g.n_angles, nd = op->g.det_u;
+    const uint64_t nx = op->g.nx, ny = op->g.ny;
     const uint64_t lim = 1ull << 31;
-    return ny * (nx + 2 * PAD) * acc_size(op) < lim && nx * (ny + 2 * PAD) * acc_size(op) < lim &&
-           na * (nd + 2 * PAD) * acc_size(op) < lim;
+    return (uint64_t)round_rows(ny) * (nx + 2 * PAD) * acc_size(op) < lim &&
+           (uint64_t)round_rows(nx) * (ny + 2 * PAD) * acc_size(op) < lim;
 }
 
 template <typename TI, typename TO>
@@ -348,12 +500,37 @@ static int fwd_launch(const abba_op *op, VecRef x, VecRef y, int batch, void *sc
     typedef typename acc_of<TI>::type T;
     const int nx = op->g.nx, ny = op->g.ny, na = op->g.n_angles, nd = op->g.det_u;
     TI *xp = (TI *)scratch;
-    TI *xq = xp + (int64_t)batch * ny * (nx + 2 * PAD);
+    TI *xq = xp + (int64_t)batch * round_rows(ny) * (nx + 2 * PAD);
     for (int s0 = 0; s0 < batch; s0 += MAX_GRID_YZ) {
         const int nb = std::min(MAX_GRID_YZ, batch - s0);
         dim3 tg((nx + 31) / 32, (ny + 31) / 32, nb);
         hipLaunchKernelGGL(pad_image_k<TI>, tg, dim3(256), 0, L.stream, x, xp, xq, nx, ny, s0, L.kdev, L.active);
         ABBA_LAUNCHED("pad_image_k");
+    }
+    // The LDS version needs a band of rows in 64 KB and enough workgroups to
+    // fill the device (it has ~90x fewer than the gather version); both give
+    // bitwise identical results.  ABBA_JOSEPH_PATH=gather|lds forces one.
+    constexpr int H = JBand<T>::H;
+    const int Lmax = std::max(nx, ny) + 2 * PAD;
+    const size_t band_bytes = (size_t)H * Lmax * sizeof(T);
+    const int nbc = (nd + 256 * JB - 1) / (256 * JB);
+    const uint64_t per = (uint64_t)op->ngroups * nbc;
+    const bool lds_ok = band_bytes <= 65536 && op->agrp && std::max(nx, ny) < 65535;
+    const char *force = std::getenv("ABBA_JOSEPH_PATH");
+    bool use_lds = lds_ok && per * (uint64_t)batch >= 8ull * (uint64_t)op->ncu;
+    if (force && std::strcmp(force, "gather") == 0) use_lds = false;
+    if (force && std::strcmp(force, "lds") == 0) use_lds = lds_ok;
+    if (use_lds) {
+        const int ch = (int)std::min<uint64_t>((uint64_t)batch, MAX_GROUPS / per);
+        for (int s0 = 0; s0 < batch; s0 += ch) {
+            const int nb = std::min(ch, batch - s0);
+            hipLaunchKernelGGL((joseph2d_lds_k<TI, TO>), dim3((uint32_t)(per * nb)), dim3(256), band_bytes,
+                               L.stream, (const TI *)xp, (const TI *)xq, y, (const AngleTab<T> *)op->tab,
+                               (const int *)op->agrp, op->ngroups, nbc, nx, ny, nd, (T)op->g.det_pitch_u,
+                               (T)(0.5 * (nd - 1)), (uint32_t)op->nxcc, s0, L.kdev, L.active);
+            ABBA_LAUNCHED("joseph2d_lds_k");
+        }
+        return ABBA_OK;
     }
     const int nbx = (nd + 255) / 256;
     const uint64_t per_slice = (uint64_t)nbx * na;
@@ -383,7 +560,7 @@ int par2d_forward(const abba_op *op, VecRef x, VecRef y, int y_dtype, int batch,
 }
 
 template <typename TIN, typename TI>
-static int back_launch(const abba_op *op, VecRef y, VecRef x, int batch, void *scratch, const Launch &L) {
+static int back_launch(const abba_op *op, VecRef y, VecRef x, int batch, const Launch &L) {
     typedef typename acc_of<TI>::type T;
     const int nx = op->g.nx, ny = op->g.ny, na = op->g.n_angles, nd = op->g.det_u;
     const double ds = op->g.det_pitch_u;
@@ -401,33 +578,33 @@ static int back_launch(const abba_op *op, VecRef y, VecRef x, int batch, void *s
         }
         return ABBA_OK;
     }
-    T *yp = (T *)scratch;
-    for (int s0 = 0; s0 < batch; s0 += MAX_GRID_YZ) {
-        const int nb = std::min(MAX_GRID_YZ, batch - s0);
-        hipLaunchKernelGGL((pad_sino_k<TIN, T>), dim3(na, nb), dim3(256), 0, L.stream, y, yp, na, nd, s0, L.kdev,
-                           L.active);
-        ABBA_LAUNCHED("pad_sino_k");
-    }
-    for (int s0 = 0; s0 < batch; s0 += chunk) {
-        const int nb = std::min(chunk, batch - s0);
-        hipLaunchKernelGGL((pixbp2d_k<TI>), dim3((uint32_t)(per_slice * nb)), dim3(256), 0, L.stream,
-                           (const T *)yp, x, (const AngleTab<T> *)op->tab, nx, ny, na, nd, (T)(0.5 * (nd - 1)),
-                           (T)(1.0 / ds), ntx, nty, (uint32_t)op->nxcc, s0, L.kdev, L.active);
+    int W, G;
+    pixbp_window(op, &W, &G);
+    const size_t shmem = (size_t)G * W * 2 * sizeof(T) + (size_t)G * sizeof(int);
+    if ((size_t)W * 2 * sizeof(T) > 32768) return ABBA_ERR_UNSUPPORTED;
+    const int btx = (nx + BT - 1) / BT, bty = (ny + BT - 1) / BT;
+    const uint64_t tiles = (uint64_t)btx * bty;
+    const int bchunk = (int)std::min<uint64_t>((uint64_t)batch, MAX_GROUPS / tiles);
+    for (int s0 = 0; s0 < batch; s0 += bchunk) {
+        const int nb = std::min(bchunk, batch - s0);
+        hipLaunchKernelGGL((pixbp2d_k<TIN, TI>), dim3((uint32_t)(tiles * nb)), dim3(256), shmem, L.stream, y, x,
+                           (const AngleTab<T> *)op->tab, nx, ny, na, nd, (T)(0.5 * (nd - 1)), (T)(1.0 / ds), W, G,
+                           btx, bty, (uint32_t)op->nxcc, s0, L.kdev, L.active);
         ABBA_LAUNCHED("pixbp2d_k");
     }
     return ABBA_OK;
 }
 
 int par2d_back(const abba_op *op, VecRef y, int y_dtype, VecRef x, int batch, void *scratch, const Launch &L) {
+    (void)scratch;
     if (batch <= 0) return ABBA_OK;
-    if (!offsets_fit(op) || (uint64_t)((op->g.nx + 15) / 16) * ((op->g.ny + 15) / 16) > MAX_GROUPS)
-        return ABBA_ERR_UNSUPPORTED;
+    if ((uint64_t)((op->g.nx + 15) / 16) * ((op->g.ny + 15) / 16) > MAX_GROUPS) return ABBA_ERR_UNSUPPORTED;
     if (op->img_dtype == ABBA_F64) {
         if (y_dtype != ABBA_F64) return ABBA_ERR_DTYPE;
-        return back_launch<double, double>(op, y, x, batch, scratch, L);
+        return back_launch<double, double>(op, y, x, batch, L);
     }
-    if (y_dtype == ABBA_F32) return back_launch<float, float>(op, y, x, batch, scratch, L);
-    if (y_dtype == ABBA_BF16) return back_launch<bf16, float>(op, y, x, batch, scratch, L);
+    if (y_dtype == ABBA_F32) return back_launch<float, float>(op, y, x, batch, L);
+    if (y_dtype == ABBA_BF16) return back_launch<bf16, float>(op, y, x, batch, L);
     return ABBA_ERR_DTYPE;
 }
 

@@ -137,6 +137,33 @@ def test_bf16_sinogram_storage(pk):
     assert e64 <= 2 ** -8 and e16 <= 2e-3 and eb <= 1e-5
 
 
+@pytest.mark.parametrize("shape", SHAPES + [(24, 24, 17, 35), (512, 512, 720, 725)])
+@pytest.mark.parametrize("dt", ["f64", "f32"])
+def test_joseph_gather_and_lds_paths_are_bitwise_equal(pk, shape, dt, monkeypatch):
+    """A has two kernels (per-ray gathers from global memory; bands of rows
+    staged in LDS, chosen for large batches).  They perform the same
+    operations in the same order, so their outputs must be identical bits;
+    the parity tests above cover the gather path against the oracle."""
+    if dt == "f64" and shape[0] == 512:
+        pytest.skip("FP64 at 512^2 adds nothing to the FP32 case")
+    nx, ny, na, nd = shape
+    angles = None
+    if shape == (24, 24, 17, 35):
+        angles = np.sort(np.random.default_rng(5).uniform(0, math.pi, 17)).tolist()
+    g = pk.Geometry(nx, ny, na, nd, angles=angles)
+    A = pk.Operator("joseph", g, dt, dt)
+    tdt = {"f64": torch.float64, "f32": torch.float32}[dt]
+    x = torch.as_tensor(np.random.default_rng(21).uniform(size=(3, ny, nx))).to(device="cuda", dtype=tdt)
+    monkeypatch.setenv("ABBA_JOSEPH_PATH", "gather")
+    yg = pk.project(A, x)
+    monkeypatch.setenv("ABBA_JOSEPH_PATH", "lds")
+    yl = pk.project(A, x)
+    torch.cuda.synchronize()
+    diff = (yg - yl).abs().max().item()
+    print(f"{shape} {dt}: max |gather - lds| = {diff:.3e}")
+    assert torch.equal(yg, yl)
+
+
 def test_adjoint_identity_gpu(pk):
     g = pk.Geometry(64, 64, 90, 91)
     A, At = pk.Operator("joseph", g), pk.Operator("joseph_t", g)
