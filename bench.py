@@ -297,10 +297,12 @@ def main():
     tf_B = pairs * FLOPS_PER_PIXEL_ANGLE / t_B / 1e12
     log(args, f"A: {t_A * 1e3:.2f} ms ({gbs_A:.1f} GB/s, {tf_A:.2f} TFLOP/s); "
               f"B: {t_B * 1e3:.2f} ms ({gbs_B:.1f} GB/s, {tf_B:.2f} TFLOP/s)")
+    # at this batch size A runs its LDS-band kernel (the gather kernel is
+    # used for batches too small to fill the device); B runs pixbp2d_k
     if t_A >= t_B:
-        dom_name, dom_tf, dom_t = "joseph2d_fwd_k", tf_A, t_A
+        dom_name, dom_tf, dom_t = "joseph2d_lds_k", tf_A, t_A
     else:
-        dom_name, dom_tf, dom_t = "back2d_k", tf_B, t_B
+        dom_name, dom_tf, dom_t = "pixbp2d_k", tf_B, t_B
     roofline = {"bound": "alu", "achieved": round(dom_tf, 3), "peak": round(VALU_PEAK_TFLOPS, 1),
                 "unit": "TFLOP/s", "frac": round(dom_tf / VALU_PEAK_TFLOPS, 4),
                 "traffic": recorded_traffic(dom_name), "kernel": dom_name,
