@@ -161,7 +161,18 @@ typedef struct {
     int restart;               /* restart cycle length p (Sec. 3.3); 0 = no restart        */
     int features;              /* 1: write learned-model features per iteration (learned
                                   rules need them; costs one extra sort per iteration)     */
+    int ortho;                 /* Gram-Schmidt schedule, ABBA_ORTHO_*                        */
 } abba_exec;
+
+/* Both schedules are CGS2 (classical Gram-Schmidt with one re-orthogonalisation,
+ * FP64 accumulation) and give the same iterates in exact arithmetic.
+ *   ABBA_ORTHO_DELAYED  the second pass of step k is done in the sweep of step
+ *                       k+1 (two sweeps over the basis per iteration instead of
+ *                       four; the projected problem of iteration k is completed
+ *                       after the operator has been applied to the next vector,
+ *                       so a slice stopping at iteration k applies M k+1 times).
+ *   ABBA_ORTHO_CGS2     both passes in step k (four sweeps per iteration). */
+enum { ABBA_ORTHO_DELAYED = 0, ABBA_ORTHO_CGS2 = 1 };
 
 /* Bytes of device workspace abba_solve needs for (A, B, batch, mode, k, stop). */
 int abba_solve_workspace(const abba_op *A, const abba_op *B, int batch, int mode, int k,
@@ -178,7 +189,8 @@ int abba_solve_workspace(const abba_op *A, const abba_op *B, int batch, int mode
  *   reg, stop, out, exec as above; `out.iters` and `out.status` are required.
  *   workspace, ws_bytes  device buffer of at least abba_solve_workspace bytes.
  * The Arnoldi process uses classical Gram-Schmidt with one re-orthogonalisation
- * (CGS2) with FP64 accumulation; H_k, its SVD and lambda are FP64.  A
+ * (CGS2, schedule exec.ortho) with FP64 accumulation; H_k, its SVD and lambda
+ * are FP64.  A
  * breakdown (h_{k+1,k} <= 1e-14 ||M w_k||) ends that slice with the k-th
  * iterate and ABBA_ST_BREAKDOWN; it is not an error.
  * Without a stopping rule the call only enqueues work.  With one, the host

@@ -12,8 +12,25 @@ B: R^m -> R^n and data b, the method runs the Arnoldi process on M = AB
 
 The paper's loop orthogonalises one basis vector at a time (modified
 Gram-Schmidt).  The GPU path uses classical Gram-Schmidt with one
-re-orthogonalisation pass (CGS2); in exact arithmetic both give the same
-W_{k+1} and H_k, so the oracle offers both ("mgs", "cgs2").
+re-orthogonalisation pass (CGS2), either as two passes per step or with the
+second pass delayed by one step ("dcgs2", below); in exact arithmetic all
+give the same W_{k+1} and H_k, so the oracle offers all three.
+
+Delayed CGS2 (dcgs2).  The operator is applied to the once-orthogonalised
+next vector v (the first pass of step k leaves v = M w_k - W_k h1), and the
+second pass of step k is carried out together with the first pass of step
+k+1: with z = M v, one sweep gives a = W_k^T v, gamma = v.v, b = W_k^T z and
+delta = v.z.  Then
+  * column k of H is completed: H[:k, k-1] += a, H[k, k-1] = alpha with
+    alpha^2 = gamma - |a|^2 (a is small), and w_{k+1} = (v - W_k a)/alpha;
+  * M w_{k+1} = (z - M W_k a)/alpha = (z - W_{k+1} t)/alpha with t = H_k a
+    (the Arnoldi relation M W_k = W_{k+1} H_k), so its first-pass
+    coefficients are h1 = W_{k+1}^T M w_{k+1}
+    = ([b ; (delta - a.b)/alpha] - t)/alpha, and the next once-orthogonalised
+    vector is z/alpha - W_{k+1} (t/alpha + h1).
+Each step reads the basis twice instead of four times; the projected problem
+of iteration k is known one operator application later, so a run that stops
+at iteration k has applied M k+1 times.
 
 Readings of points the paper leaves open:
   * x_0 = 0 unless given (u_0 = 0 in Algorithm 1).
@@ -105,15 +122,46 @@ def hybrid_gmres(A, B, b, mode: str = "AB", K: int = 30, rule: str = "gcv",
     status = STATUS_KMAX
     k_done = 0
     x = x0.copy()
-    for k in range(1, K + 1):
-        w = W[k - 1]
+
+    def apply_M(w):
         if mode == "AB":
-            q = np.asarray(A(np.asarray(B(w)).reshape(-1))).reshape(-1)
+            return np.asarray(A(np.asarray(B(w)).reshape(-1))).reshape(-1)
+        return np.asarray(B(np.asarray(A(w)).reshape(-1))).reshape(-1)
+
+    if ortho == "dcgs2":
+        # first pass of step 1: v = M w_1 - (w_1 . M w_1) w_1
+        z = apply_M(W[0])
+        H[0, 0] = float(np.dot(W[0], z))
+        v = z - H[0, 0] * W[0]
+    for k in range(1, K + 1):
+        if ortho == "dcgs2":
+            Wk = np.stack(W)                  # k x len
+            z = apply_M(v)
+            a, b_ = Wk @ v, Wk @ z
+            gamma, delta = float(np.dot(v, v)), float(np.dot(v, z))
+            H[:k, k - 1] += a
+            hk = math.sqrt(max(gamma - float(np.dot(a, a)), 0.0))
+            H[k, k - 1] = hk
+            mw = float(np.linalg.norm(H[:k + 1, k - 1]))   # ||M w_k|| by the Arnoldi relation
+            out.Mw_norms.append(mw)
+            broke = hk <= BREAKDOWN_TOL * mw
+            if broke:
+                H[k, k - 1] = 0.0
+            else:
+                W.append((v - Wk.T @ a) / hk)
+                if k < K:
+                    t = H[:k + 1, :k] @ a
+                    h1 = (np.append(b_, (delta - float(np.dot(a, b_))) / hk) - t) / hk
+                    H[:k + 1, k] = h1
+                    v = z / hk - np.stack(W).T @ (t / hk + h1)
         else:
-            q = np.asarray(B(np.asarray(A(w)).reshape(-1))).reshape(-1)
-        mw = float(np.linalg.norm(q))
-        out.Mw_norms.append(mw)
-        if ortho == "cgs2":
+            w = W[k - 1]
+            q = apply_M(w)
+            mw = float(np.linalg.norm(q))
+            out.Mw_norms.append(mw)
+        if ortho == "dcgs2":
+            pass
+        elif ortho == "cgs2":
             Wk = np.stack(W)                  # k x len
             h = Wk @ q
             q = q - Wk.T @ h
@@ -126,13 +174,14 @@ def hybrid_gmres(A, B, b, mode: str = "AB", K: int = 30, rule: str = "gcv",
                 q = q - H[i, k - 1] * W[i]
         else:
             raise ValueError(ortho)
-        hk = float(np.linalg.norm(q))
-        broke = hk <= BREAKDOWN_TOL * mw
-        if broke:
-            H[k, k - 1] = 0.0
-        else:
-            H[k, k - 1] = hk
-            W.append(q / hk)
+        if ortho != "dcgs2":
+            hk = float(np.linalg.norm(q))
+            broke = hk <= BREAKDOWN_TOL * mw
+            if broke:
+                H[k, k - 1] = 0.0
+            else:
+                H[k, k - 1] = hk
+                W.append(q / hk)
         Hk = H[:k + 1, :k]
         sol = ss.solve_projected(Hk, beta, rule, lam_fixed=lam, dp_target=target)
         y = sol["y"]

@@ -66,7 +66,7 @@ class _Out(ctypes.Structure):
 
 class _Exec(ctypes.Structure):
     _fields_ = [("use_graph", ctypes.c_int), ("poll_every", ctypes.c_int), ("restart", ctypes.c_int),
-                ("features", ctypes.c_int)]
+                ("features", ctypes.c_int), ("ortho", ctypes.c_int)]
 
 
 def _load():
@@ -240,8 +240,11 @@ def backproject(B: Operator, y, out=None):
     return out
 
 
+ORTHO = {"dcgs2": 0, "cgs2": 1}
+
+
 def _structs(reg, lam, tau, noise_norm, mlp, judge_delta, stop, stop_tau, rns_eps, use_graph, poll_every,
-             restart, features):
+             restart, features, ortho="dcgs2"):
     r = _Reg()
     r.kind = REG[reg]
     r.lam = float(lam)
@@ -259,6 +262,7 @@ def _structs(reg, lam, tau, noise_norm, mlp, judge_delta, stop, stop_tau, rns_ep
     e.poll_every = int(poll_every)
     e.restart = int(restart)
     e.features = int(features)
+    e.ortho = ORTHO[ortho]
     return r, s, e
 
 
@@ -273,8 +277,11 @@ def workspace_bytes(A: Operator, B: Operator, batch: int, mode: str, k: int, sto
 def solve(A: Operator, B: Operator, b, mode: str = "AB", k: int = 30, reg: str = "gcv", lam: float = 0.0,
           tau: float = 1.01, noise_norm=None, stop=None, rns_eps: float = 1e-3, x0=None, use_graph=False,
           poll_every: int = 1, restart: int = 0, mlp=None, judge_delta: float = 0.05, history: bool = True,
-          workspace=None, features: int = 0):
+          workspace=None, features: int = 0, ortho: str = "dcgs2"):
     """Hybrid AB-/BA-GMRES on a batch of slices; returns (x, info).
+
+    ortho: "dcgs2" (CGS2 with the second pass delayed to the next step's
+    sweep, the default) or "cgs2" (both passes in each step).
 
     b: device tensor [batch, *sino_shape] in A's sinogram dtype.  noise_norm:
     device float64 [batch] (||e|| per slice) for the discrepancy principle.
@@ -292,7 +299,7 @@ def solve(A: Operator, B: Operator, b, mode: str = "AB", k: int = 30, reg: str =
     if noise_norm is not None:
         noise_norm = noise_norm.to(device=dev, dtype=torch.float64).contiguous()
     r, s, e = _structs(reg, lam, tau, noise_norm, mlp, judge_delta, stop, tau, rns_eps, use_graph, poll_every,
-                       restart, features)
+                       restart, features, ortho)
     m = MODE_AB if mode == "AB" else MODE_BA
     iters = torch.zeros(batch, dtype=torch.int32, device=dev)
     status = torch.zeros(batch, dtype=torch.int32, device=dev)

@@ -322,6 +322,247 @@ __global__ __launch_bounds__(256) void resid_k(const TS *__restrict__ r0, int64_
     if (threadIdx.x == 0) npart[(int64_t)s * nblk + blockIdx.x] = t;
 }
 
+// ------------------------------------------------------- delayed CGS2 ---
+// Step k of CGS2 with the second pass delayed by one step (Arnoldi, eq. (8)).
+// On entry W_0..W_{k-1} are final, v = W_k is the once-orthogonalised next
+// vector and z = W_{k+1} = M v.  One sweep gives, for i <= k,
+//   a_i = W_i . v   (a_k = v.v)        b_i = W_i . z   (b_k = v.z)
+// part rows [0, K+2) hold the a partials, rows [K+2, 2K+4) the b partials.
+template <typename TW>
+__global__ __launch_bounds__(256) void ddots_k(const TW *__restrict__ W, int64_t slice_stride, int64_t ldw,
+                                               double *__restrict__ part, int nblk, int pstride, int boff,
+                                               const int *kdev, const int *active) {
+    typedef typename vec16<TW>::type V;
+    constexpr int N = vec16<TW>::N;
+    const int s = blockIdx.z;
+    if (active && !active[s]) return;
+    const int k = kdev ? *kdev : 0;
+    const int jcount = k + 1;
+    const int j0 = blockIdx.y * DOT_JT;
+    if (j0 >= jcount) return;
+    const int jn = min(DOT_JT, jcount - j0);
+    const TW *Ws = W + (int64_t)s * slice_stride;
+    const V *vp = reinterpret_cast<const V *>(Ws + (int64_t)k * ldw);
+    const V *zp = reinterpret_cast<const V *>(Ws + (int64_t)(k + 1) * ldw);
+    int64_t v0, v1;
+    chunk_of(ldw / N, nblk, blockIdx.x, v0, v1);
+    double acc[DOT_JT], bcc[DOT_JT];
+#pragma unroll
+    for (int jj = 0; jj < DOT_JT; ++jj) acc[jj] = bcc[jj] = 0.0;
+    for (int64_t e = v0 + threadIdx.x; e < v1; e += blockDim.x) {
+        double vv[N], zv[N];
+        unpack(vp[e], vv);
+        unpack(zp[e], zv);
+#pragma unroll
+        for (int jj = 0; jj < DOT_JT; ++jj) {
+            if (jj < jn) {
+                double wv[N];
+                unpack(reinterpret_cast<const V *>(Ws + (int64_t)(j0 + jj) * ldw)[e], wv);
+#pragma unroll
+                for (int q = 0; q < N; ++q) {
+                    acc[jj] = fma(wv[q], vv[q], acc[jj]);
+                    bcc[jj] = fma(wv[q], zv[q], bcc[jj]);
+                }
+            }
+        }
+    }
+    __shared__ double red[2][DOT_JT][4];
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+#pragma unroll
+    for (int jj = 0; jj < DOT_JT; ++jj) {
+        const double ta = wave_sum(acc[jj]);
+        const double tb = wave_sum(bcc[jj]);
+        if (lane == 0) {
+            red[0][jj][wid] = ta;
+            red[1][jj][wid] = tb;
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x < 2 * jn) {
+        const int which = threadIdx.x / jn, jj = threadIdx.x % jn;
+        double t = 0.0;
+        for (int w = 0; w < (int)(blockDim.x >> 6); ++w) t += red[which][jj][w];
+        part[((int64_t)s * pstride + which * boff + j0 + jj) * nblk + blockIdx.x] = t;
+    }
+}
+
+// Per slice, from a and b of step k (k on the device):
+//  * k >= 1: complete column k-1 of H: H[:k, k-1] += a[:k],
+//    h_{k+1,k} = alpha = sqrt(v.v - |a[:k]|^2), the breakdown test against
+//    ||M w_k|| = ||H[:, k-1]|| (the Arnoldi relation), 1/alpha in SC_INV;
+//    k = 0: nothing to complete, alpha = 1 (w_1 is final).
+//  * T[:, k] = (e_k - T[:, :k] a[:k]) / alpha: the final basis is
+//    W = V T with V the vectors as they were when M was applied to them.
+//  * the first pass of step k+1: with t = H[:k+1, :k] a[:k] and
+//    w_{k+1}.z = (b_k - a[:k].b[:k]) / alpha,
+//    h1 = ([b[:k] ; w_{k+1}.z] - t) / alpha   (column k of H, if k < K)
+//    gd = t / alpha + h1                      (coefficients of the update)
+__global__ __launch_bounds__(128) void dclose_k(const double *__restrict__ a, const double *__restrict__ bv,
+                                                int astride, double *__restrict__ H, double *__restrict__ T,
+                                                double *__restrict__ gd, int gstride, int K,
+                                                double *__restrict__ sc, int *__restrict__ flags, const int *kdev,
+                                                const int *active) {
+    const int s = blockIdx.x;
+    if (active && !active[s]) return;
+    const int k = *kdev;
+    const double *as = a + (int64_t)s * astride, *bs = bv + (int64_t)s * astride;
+    double *Hs = H + (int64_t)s * K * (K + 1);
+    double *Ts = T + (int64_t)s * K * K;
+    double *S = sc + (int64_t)s * SC_COUNT;
+    __shared__ double tt[KMAX_SMALL + 2];
+    __shared__ double sh[2];   // alpha (0 on breakdown), w_{k+1}.z
+    if (k >= 1) {
+        double *col = Hs + (int64_t)(k - 1) * (K + 1);
+        for (int i = threadIdx.x; i < k; i += blockDim.x) col[i] += as[i];
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            double a2 = 0.0, m2 = 0.0;
+            for (int i = 0; i < k; ++i) {
+                a2 = fma(as[i], as[i], a2);
+                m2 = fma(col[i], col[i], m2);
+            }
+            const double al2 = as[k] - a2;
+            const double alpha = al2 > 0.0 ? sqrt(al2) : (al2 == al2 ? 0.0 : al2);   // NaN stays NaN
+            const double mw = sqrt(fma(alpha, alpha, m2));
+            S[SC_MW] = mw;
+            int fl = 0;
+            if (!isfinite(alpha) || !isfinite(mw)) fl |= FL_NONFINITE;
+            if (!(alpha > 1e-14 * mw)) {
+                fl |= FL_BREAK;
+                col[k] = 0.0;
+                S[SC_HK] = 0.0;
+                S[SC_INV] = 0.0;
+                sh[0] = 0.0;
+            } else {
+                col[k] = alpha;
+                S[SC_HK] = alpha;
+                S[SC_INV] = 1.0 / alpha;
+                sh[0] = alpha;
+            }
+            flags[s] |= fl;
+        }
+        __syncthreads();
+    } else {
+        if (threadIdx.x == 0) {
+            S[SC_INV] = 1.0;
+            sh[0] = 1.0;
+        }
+        __syncthreads();
+    }
+    const double alpha = sh[0];
+    if (alpha == 0.0) return;   // breakdown: no next vector
+    if (k < K) {
+        for (int r = threadIdx.x; r <= k; r += blockDim.x) {
+            double v = r == k ? 1.0 : 0.0;
+            for (int i = r; i < k; ++i) v = fma(-as[i], Ts[(int64_t)i * K + r], v);
+            Ts[(int64_t)k * K + r] = v / alpha;
+        }
+    }
+    for (int r = threadIdx.x; r <= k; r += blockDim.x) {
+        double t = 0.0;
+        for (int l = r > 0 ? r - 1 : 0; l < k; ++l) t = fma(Hs[(int64_t)l * (K + 1) + r], as[l], t);
+        tt[r] = t;
+    }
+    if (threadIdx.x == 0) {
+        double ab = 0.0;
+        for (int i = 0; i < k; ++i) ab = fma(as[i], bs[i], ab);
+        sh[1] = (bs[k] - ab) / alpha;
+    }
+    __syncthreads();
+    for (int r = threadIdx.x; r <= k; r += blockDim.x) {
+        const double h1 = ((r < k ? bs[r] : sh[1]) - tt[r]) / alpha;
+        gd[(int64_t)s * gstride + r] = tt[r] / alpha + h1;
+        if (k < K) Hs[(int64_t)k * (K + 1) + r] = h1;
+    }
+}
+
+// The update sweep of step k (slices with 1/alpha = 0 are skipped):
+//   W_k     := (v - sum_{i<k} a_i W_i) / alpha                      (= w_{k+1})
+//   W_{k+1} := z / alpha - sum_{i<k} gd_i W_i - gd_k w_{k+1}        (next v)
+template <typename TW>
+__global__ __launch_bounds__(256) void dupdate_k(TW *__restrict__ W, int64_t slice_stride, int64_t ldw,
+                                                 const double *__restrict__ a, int astride,
+                                                 const double *__restrict__ gd, int gstride,
+                                                 const double *__restrict__ sc, int nblk, const int *kdev,
+                                                 const int *active) {
+    typedef typename vec16<TW>::type V;
+    constexpr int N = vec16<TW>::N;
+    const int s = blockIdx.z;
+    if (active && !active[s]) return;
+    const double inv = sc[(int64_t)s * SC_COUNT + SC_INV];
+    if (inv == 0.0) return;
+    const int k = kdev ? *kdev : 0;
+    TW *Ws = W + (int64_t)s * slice_stride;
+    V *vp = reinterpret_cast<V *>(Ws + (int64_t)k * ldw);
+    V *zp = reinterpret_cast<V *>(Ws + (int64_t)(k + 1) * ldw);
+    const double *as = a + (int64_t)s * astride, *gs = gd + (int64_t)s * gstride;
+    const double gk = gs[k];
+    int64_t v0, v1;
+    chunk_of(ldw / N, nblk, blockIdx.x, v0, v1);
+    for (int64_t e = v0 + threadIdx.x; e < v1; e += blockDim.x) {
+        double wv[N], zv[N];
+        unpack(vp[e], wv);
+        unpack(zp[e], zv);
+#pragma unroll
+        for (int q = 0; q < N; ++q) zv[q] *= inv;
+        int i = 0;
+        for (; i + 4 <= k; i += 4) {
+            double w0[N], w1[N], w2[N], w3[N];
+            unpack(reinterpret_cast<const V *>(Ws + (int64_t)(i + 0) * ldw)[e], w0);
+            unpack(reinterpret_cast<const V *>(Ws + (int64_t)(i + 1) * ldw)[e], w1);
+            unpack(reinterpret_cast<const V *>(Ws + (int64_t)(i + 2) * ldw)[e], w2);
+            unpack(reinterpret_cast<const V *>(Ws + (int64_t)(i + 3) * ldw)[e], w3);
+            const double a0 = as[i], a1 = as[i + 1], a2 = as[i + 2], a3 = as[i + 3];
+            const double g0 = gs[i], g1 = gs[i + 1], g2 = gs[i + 2], g3 = gs[i + 3];
+#pragma unroll
+            for (int q = 0; q < N; ++q) {
+                wv[q] = fma(-a0, w0[q], wv[q]);
+                zv[q] = fma(-g0, w0[q], zv[q]);
+                wv[q] = fma(-a1, w1[q], wv[q]);
+                zv[q] = fma(-g1, w1[q], zv[q]);
+                wv[q] = fma(-a2, w2[q], wv[q]);
+                zv[q] = fma(-g2, w2[q], zv[q]);
+                wv[q] = fma(-a3, w3[q], wv[q]);
+                zv[q] = fma(-g3, w3[q], zv[q]);
+            }
+        }
+        for (; i < k; ++i) {
+            double w0[N];
+            unpack(reinterpret_cast<const V *>(Ws + (int64_t)i * ldw)[e], w0);
+            const double a0 = as[i], g0 = gs[i];
+#pragma unroll
+            for (int q = 0; q < N; ++q) {
+                wv[q] = fma(-a0, w0[q], wv[q]);
+                zv[q] = fma(-g0, w0[q], zv[q]);
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < N; ++q) {
+            wv[q] *= inv;
+            zv[q] = fma(-gk, wv[q], zv[q]);
+        }
+        vp[e] = pack<TW>(wv);
+        zp[e] = pack<TW>(zv);
+    }
+}
+
+// y2[s][l] = sum_{l <= i < k} T[l][i] y[i]: the coefficients of x (or of the
+// data residual) in the vectors kept when M was applied to them.  k = iters
+// (final assembly) or the device counter.
+__global__ void ty_k(const double *__restrict__ T, const double *__restrict__ y, double *__restrict__ y2, int K,
+                     const int *__restrict__ iters, const int *kdev, const int *active) {
+    const int s = blockIdx.x;
+    if (active && !active[s]) return;
+    const int k = iters ? iters[s] : *kdev;
+    const double *Ts = T + (int64_t)s * K * K;
+    const double *ys = y + (int64_t)s * K;
+    for (int l = threadIdx.x; l < k; l += blockDim.x) {
+        double v = 0.0;
+        for (int i = l; i < k; ++i) v = fma(Ts[(int64_t)i * K + l], ys[i], v);
+        y2[(int64_t)s * K + l] = v;
+    }
+}
+
 // ------------------------------------------------------------ launchers ---
 static inline int nblk_for(int64_t nvec) {
     int64_t b = (nvec + 511) / 512;
@@ -336,7 +577,7 @@ template <typename TW>
 static int launch_dots(TW *W, const SolveDims &d, double *part, int nblk, int extra, int jtiles,
                        const int *kdev, const int *active, hipStream_t st) {
     dim3 grid(nblk, jtiles, d.S);
-    hipLaunchKernelGGL(dots_k<TW>, grid, dim3(256), 0, st, (const TW *)W, (int64_t)(d.K + 1) * d.ldw, d.ldw,
+    hipLaunchKernelGGL(dots_k<TW>, grid, dim3(256), 0, st, (const TW *)W, (int64_t)d.wslots * d.ldw, d.ldw,
                        part, nblk, d.K + 1, extra, kdev, active);
     ABBA_LAUNCHED("dots_k");
     return ABBA_OK;
@@ -347,10 +588,10 @@ static int launch_update(TW *W, const SolveDims &d, const double *coef, double *
                          const int *kdev, const int *active, hipStream_t st) {
     dim3 grid(nblk, 1, d.S);
     if (norm)
-        hipLaunchKernelGGL((update_k<TW, true>), grid, dim3(256), 0, st, W, (int64_t)(d.K + 1) * d.ldw, d.ldw,
+        hipLaunchKernelGGL((update_k<TW, true>), grid, dim3(256), 0, st, W, (int64_t)d.wslots * d.ldw, d.ldw,
                            coef, d.K + 1, npart, nblk, kdev, active);
     else
-        hipLaunchKernelGGL((update_k<TW, false>), grid, dim3(256), 0, st, W, (int64_t)(d.K + 1) * d.ldw, d.ldw,
+        hipLaunchKernelGGL((update_k<TW, false>), grid, dim3(256), 0, st, W, (int64_t)d.wslots * d.ldw, d.ldw,
                            coef, d.K + 1, npart, nblk, kdev, active);
     ABBA_LAUNCHED("update_k");
     return ABBA_OK;
@@ -379,9 +620,47 @@ static int cgs2_step_t(const SolveDims &d, const SolveWS &ws, hipStream_t st) {
                        d.K, ws.sc, ws.flags, ws.kdev, ws.active);
     ABBA_LAUNCHED("arnoldi_close_k");
     dim3 sg(std::min<int64_t>(1024, (d.ldw / vec16<TW>::N + 255) / 256), 1, d.S);
-    hipLaunchKernelGGL(scale_k<TW>, sg, dim3(256), 0, st, W, (int64_t)(d.K + 1) * d.ldw, d.ldw, ws.sc, 0,
+    hipLaunchKernelGGL(scale_k<TW>, sg, dim3(256), 0, st, W, (int64_t)d.wslots * d.ldw, d.ldw, ws.sc, 0,
                        ws.kdev, ws.active);
     ABBA_LAUNCHED("scale_k");
+    return ABBA_OK;
+}
+
+// One delayed-CGS2 step (both sweeps and the small per-slice algebra) on
+// the vectors W_k, W_{k+1} of every active slice; `kdev` = nullptr means k = 0.
+template <typename TW>
+static int dcgs2_step_t(const SolveDims &d, const SolveWS &ws, const int *kdev, hipStream_t st) {
+    TW *W = (TW *)ws.W;
+    const int nblk = cgs_nblk(d.ldw, d.w_dt);
+    const int jt = (d.K + 2 + DOT_JT - 1) / DOT_JT;
+    const int boff = d.K + 2, pstride = 2 * (d.K + 2);
+    const int64_t wsl = (int64_t)d.wslots * d.ldw;
+    hipLaunchKernelGGL(ddots_k<TW>, dim3(nblk, jt, d.S), dim3(256), 0, st, (const TW *)W, wsl, d.ldw, ws.part, nblk,
+                       pstride, boff, kdev, ws.active);
+    ABBA_LAUNCHED("ddots_k");
+    hipLaunchKernelGGL(reduce_k, dim3(d.S), dim3(256), 0, st, ws.part, nblk, pstride, ws.c, d.K + 2, 1, 0, kdev,
+                       ws.active);
+    ABBA_LAUNCHED("reduce_k");
+    hipLaunchKernelGGL(reduce_k, dim3(d.S), dim3(256), 0, st, ws.part + (size_t)boff * nblk, nblk, pstride, ws.h,
+                       d.K + 2, 1, 0, kdev, ws.active);
+    ABBA_LAUNCHED("reduce_k");
+    hipLaunchKernelGGL(dclose_k, dim3(d.S), dim3(128), 0, st, ws.c, ws.h, d.K + 2, ws.H, ws.T, ws.gd, d.K + 2, d.K,
+                       ws.sc, ws.flags, kdev ? kdev : ws.kdev, ws.active);
+    ABBA_LAUNCHED("dclose_k");
+    hipLaunchKernelGGL(dupdate_k<TW>, dim3(nblk, 1, d.S), dim3(256), 0, st, W, wsl, d.ldw, (const double *)ws.c,
+                       d.K + 2, (const double *)ws.gd, d.K + 2, (const double *)ws.sc, nblk, kdev, ws.active);
+    ABBA_LAUNCHED("dupdate_k");
+    return ABBA_OK;
+}
+
+int dcgs2_step(const SolveDims &d, const SolveWS &ws, const int *kdev, hipStream_t st) {
+    return d.w_dt == ABBA_F64 ? dcgs2_step_t<double>(d, ws, kdev, st) : dcgs2_step_t<float>(d, ws, kdev, st);
+}
+
+int launch_ty(const SolveDims &d, const SolveWS &ws, const int *iters, const int *kdev, const int *active,
+              hipStream_t st) {
+    hipLaunchKernelGGL(ty_k, dim3(d.S), dim3(128), 0, st, ws.T, ws.y, ws.y2, d.K, iters, kdev, active);
+    ABBA_LAUNCHED("ty_k");
     return ABBA_OK;
 }
 
@@ -430,7 +709,7 @@ static int normalize_first_t(const SolveDims &d, const SolveWS &ws, int *iters, 
                        ws.active, ws.flags, iters, status, d.S);
     ABBA_LAUNCHED("init_beta_k");
     dim3 sg(std::min<int64_t>(1024, (d.ldw / vec16<TW>::N + 255) / 256), 1, d.S);
-    hipLaunchKernelGGL(scale_k<TW>, sg, dim3(256), 0, st, W, (int64_t)(d.K + 1) * d.ldw, d.ldw, ws.sc, 0,
+    hipLaunchKernelGGL(scale_k<TW>, sg, dim3(256), 0, st, W, (int64_t)d.wslots * d.ldw, d.ldw, ws.sc, 0,
                        nullptr, ws.active);
     ABBA_LAUNCHED("scale_k");
     return ABBA_OK;

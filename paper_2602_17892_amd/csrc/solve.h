@@ -42,24 +42,30 @@ struct SolveDims {
     int64_t ldm;    // padded sinogram stride
     int keepZ;      // BA: keep Z = A W for the data residual
     int img_dt, sino_dt, w_dt;
+    int wslots;     // basis vectors per slice (K + 2: the delayed step also holds M v)
+    int pslots;     // kept operator outputs per slice (K + 1)
+    int ortho;      // ABBA_ORTHO_*
 };
 
 // Workspace carve-up (device pointers).
 struct SolveWS {
-    void *W;        // [S][K+1][ldw]  basis (w_dt)
-    void *P;        // [S][K][ldn]    AB: B w_j (img_dt)
-    void *Z;        // [S][K or 1][ldm] BA: A w_j (sino_dt)
+    void *W;        // [S][K+2][ldw]  basis (w_dt)
+    void *P;        // [S][K+1][ldn]  AB: B w_j (img_dt)
+    void *Z;        // [S][K+1 or 1][ldm] BA: A w_j (sino_dt)
     void *sino;     // [S][ldm]       b - A x0 (sino_dt)
     void *scratch;  // zero-padded operator input (A and B take turns)
-    double *part;   // [S][K+1][nblk] partial dot products (vector-major)
-    double *h;      // [S][K+1]
-    double *c;      // [S][K+1]
+    double *part;   // [S][2(K+2)][nblk] partial dot products (vector-major)
+    double *h;      // [S][K+2]
+    double *c;      // [S][K+2]
     double *npart;  // [S][RED_BLOCKS] partial squared norms
     double *H;      // [S][K][K+1] column-major Hessenberg
     double *gc, *gs;// [S][K] Givens rotations
     double *g;      // [S][K+1] rotated beta e1
     double *Aj, *Vj;// [S][K][K] Jacobi state (column-major, stride K)
     double *y;      // [S][K]
+    double *y2;     // [S][K]         delayed CGS2: T y
+    double *T;      // [S][K][K]      delayed CGS2: W = V T (column-major, upper triangular)
+    double *gd;     // [S][K+2]       delayed CGS2: update coefficients
     double *sig;    // [S][K]
     double *uh;     // [S][K]
     double *sc;     // [S][SC_COUNT]

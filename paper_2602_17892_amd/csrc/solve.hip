@@ -21,6 +21,9 @@
 namespace abba {
 
 int cgs2_step(const SolveDims &d, const SolveWS &ws, hipStream_t st);
+int dcgs2_step(const SolveDims &d, const SolveWS &ws, const int *kdev, hipStream_t st);
+int launch_ty(const SolveDims &d, const SolveWS &ws, const int *iters, const int *kdev, const int *active,
+              hipStream_t st);
 int normalize_first(const SolveDims &d, const SolveWS &ws, int *iters, int *status, hipStream_t st);
 int launch_sub(int in_dt, const void *b, int64_t bstride, const void *ax, int64_t axstride, int out_dt, void *out,
                int64_t ostride, int64_t len, int64_t ld, int S, hipStream_t st);
@@ -64,14 +67,14 @@ size_t solve_workspace_bytes(const SolveDims &d, SolveWS *ws, void *base, size_t
     };
     SolveWS w;
     std::memset(&w, 0, sizeof(w));
-    w.W = take(S * (K + 1) * d.ldw * wsz);
-    w.P = d.mode == ABBA_MODE_AB ? take(S * K * d.ldn * isz) : nullptr;
-    w.Z = d.mode == ABBA_MODE_BA ? take(S * (d.keepZ ? K : 1) * d.ldm * ssz) : nullptr;
+    w.W = take(S * d.wslots * d.ldw * wsz);
+    w.P = d.mode == ABBA_MODE_AB ? take(S * d.pslots * d.ldn * isz) : nullptr;
+    w.Z = d.mode == ABBA_MODE_BA ? take(S * (d.keepZ ? d.pslots : 1) * d.ldm * ssz) : nullptr;
     w.sino = take(S * d.ldm * ssz);
     w.scratch = take(scratch_bytes);
-    w.part = (double *)take(S * 1024 * (K + 1) * 8);
-    w.h = (double *)take(S * (K + 1) * 8);
-    w.c = (double *)take(S * (K + 1) * 8);
+    w.part = (double *)take(S * 1024 * 2 * (K + 2) * 8);
+    w.h = (double *)take(S * (K + 2) * 8);
+    w.c = (double *)take(S * (K + 2) * 8);
     w.npart = (double *)take(S * 1024 * 8);
     w.H = (double *)take(S * K * (K + 1) * 8);
     w.gc = (double *)take(S * K * 8);
@@ -80,6 +83,9 @@ size_t solve_workspace_bytes(const SolveDims &d, SolveWS *ws, void *base, size_t
     w.Aj = (double *)take(S * K * K * 8);
     w.Vj = (double *)take(S * K * K * 8);
     w.y = (double *)take(S * K * 8);
+    w.y2 = (double *)take(S * K * 8);
+    w.T = (double *)take(S * K * K * 8);
+    w.gd = (double *)take(S * (K + 2) * 8);
     w.sig = (double *)take(S * K * 8);
     w.uh = (double *)take(S * K * 8);
     w.sc = (double *)take(S * SC_COUNT * 8);
@@ -145,6 +151,9 @@ static int make_dims(const abba_op *A, const abba_op *B, int batch, int mode, in
     d->w_dt = A->img_dtype == ABBA_F64 ? ABBA_F64 : ABBA_F32;
     const bool stop_rule = stop && stop->kind != ABBA_STOP_NONE;
     d->keepZ = mode == ABBA_MODE_BA && (stop_rule || (out && out->resid));
+    d->wslots = k + 2;
+    d->pslots = k + 1;
+    d->ortho = ABBA_ORTHO_DELAYED;
     return ABBA_OK;
 }
 
@@ -178,30 +187,48 @@ struct IterCfg {
     const abba_reg *reg;
 };
 
+// The operator step of iteration k: q = M (input vector) into W, keeping
+// the intermediate (AB: B w in P, BA: A w in Z).  Two-pass CGS2 applies M to
+// the final w_k = W_{k-1} and writes W_k; the delayed schedule applies it to
+// the once-orthogonalised W_k and writes W_{k+1}.
+static int apply_M(const SolveDims &d, const SolveWS &ws, const IterCfg &c, const Launch &L) {
+    const bool delayed = d.ortho == ABBA_ORTHO_DELAYED;
+    const int in_off = delayed ? 0 : -1, out_off = delayed ? 1 : 0;
+    const int64_t wsl = (int64_t)d.wslots * d.ldw;
+    VecRef win{ws.W, wsl, d.ldw, in_off};
+    VecRef wout{ws.W, wsl, d.ldw, out_off};
+    int rc;
+    if (d.mode == ABBA_MODE_AB) {
+        VecRef p{ws.P, (int64_t)d.pslots * d.ldn, d.ldn, in_off};
+        if ((rc = apply_op(c.B, false, win, d.w_dt, p, d.img_dt, d, ws, L))) return rc;
+        return apply_op(c.A, true, p, d.img_dt, wout, d.w_dt, d, ws, L);
+    }
+    VecRef z{ws.Z, (int64_t)(d.keepZ ? d.pslots : 1) * d.ldm, d.keepZ ? d.ldm : 0, d.keepZ ? in_off : 0};
+    if ((rc = apply_op(c.A, true, win, d.w_dt, z, d.sino_dt, d, ws, L))) return rc;
+    return apply_op(c.B, false, z, d.sino_dt, wout, d.w_dt, d, ws, L);
+}
+
 // Launch one iteration for all active slices on `st`.
 static int one_iteration(const SolveDims &d, const SolveWS &ws, const IterCfg &c, hipStream_t st) {
     Launch L{st, ws.kdev, ws.active};
-    const int64_t wsl = (int64_t)(d.K + 1) * d.ldw;
-    VecRef wprev{ws.W, wsl, d.ldw, -1};
-    VecRef wcur{ws.W, wsl, d.ldw, 0};
+    const bool delayed = d.ortho == ABBA_ORTHO_DELAYED;
     int rc;
-    if (d.mode == ABBA_MODE_AB) {
-        VecRef p{ws.P, (int64_t)d.K * d.ldn, d.ldn, -1};
-        if ((rc = apply_op(c.B, false, wprev, d.w_dt, p, d.img_dt, d, ws, L))) return rc;
-        if ((rc = apply_op(c.A, true, p, d.img_dt, wcur, d.w_dt, d, ws, L))) return rc;
-    } else {
-        VecRef z{ws.Z, (int64_t)(d.keepZ ? d.K : 1) * d.ldm, d.keepZ ? d.ldm : 0, d.keepZ ? -1 : 0};
-        if ((rc = apply_op(c.A, true, wprev, d.w_dt, z, d.sino_dt, d, ws, L))) return rc;
-        if ((rc = apply_op(c.B, false, z, d.sino_dt, wcur, d.w_dt, d, ws, L))) return rc;
-    }
-    if ((rc = cgs2_step(d, ws, st))) return rc;
+    if ((rc = apply_M(d, ws, c, L))) return rc;
+    if ((rc = delayed ? dcgs2_step(d, ws, ws.kdev, st) : cgs2_step(d, ws, st))) return rc;
     if ((rc = launch_smallsolve(d, ws, c.rule, c.lam_fixed, c.tau, c.noise_reg, st))) return rc;
     if (c.learned) {
         if ((rc = learned_features(d, ws, st))) return rc;
         if ((rc = learned_judge(d, ws, c.reg, st))) return rc;
     }
     if (d.mode == ABBA_MODE_BA && d.keepZ) {
-        const int nb = launch_resid(d.sino_dt, ws.sino, d.ldm, ws.Z, (int64_t)d.K * d.ldm, d.ldm, ws.y, d.K, d.m,
+        // rho_k = ||(b - A x_0) - Z_k y_k||; with the delayed schedule Z holds
+        // A applied to the vectors before their second pass: Z_k y = Z' (T y)
+        const double *yk = ws.y;
+        if (delayed) {
+            if ((rc = launch_ty(d, ws, nullptr, ws.kdev, ws.active, st))) return rc;
+            yk = ws.y2;
+        }
+        const int nb = launch_resid(d.sino_dt, ws.sino, d.ldm, ws.Z, (int64_t)d.pslots * d.ldm, d.ldm, yk, d.K, d.m,
                                     ws.npart, d.S, ws.kdev, ws.active, st);
         if (nb < 0) return nb;
         if ((rc = launch_finish_resid(d, ws, nb, st))) return rc;
@@ -287,8 +314,13 @@ extern "C" int abba_solve(const abba_op *A, const abba_op *B, const void *b, voi
         set_error("the learned stop needs the learned lambda rule (it shares the model)");
         return ABBA_ERR_ARG;
     }
-    abba_exec ex{0, 1, 0, 0};
+    abba_exec ex{0, 1, 0, 0, ABBA_ORTHO_DELAYED};
     if (exec) ex = *exec;
+    if (ex.ortho != ABBA_ORTHO_DELAYED && ex.ortho != ABBA_ORTHO_CGS2) {
+        set_error("unknown Gram-Schmidt schedule %d", ex.ortho);
+        return ABBA_ERR_ARG;
+    }
+    d.ortho = ex.ortho;
     if (ex.poll_every < 1) ex.poll_every = 1;
     if (ex.restart != 0) {
         set_error("restarted cycles are not implemented");
@@ -302,7 +334,7 @@ extern "C" int abba_solve(const abba_op *A, const abba_op *B, const void *b, voi
     }
     hipStream_t st = (hipStream_t)stream;
     Launch L0{st, nullptr, nullptr};
-    const int64_t wsl = (int64_t)(d.K + 1) * d.ldw;
+    const int64_t wsl = (int64_t)d.wslots * d.ldw;
     if ((rc = smallsolve_prepare())) return rc;
     // histories past a slice's stopping iteration read as NaN
     hipLaunchKernelGGL(fill_k, dim3(64), dim3(256), 0, st, ws.lamh, (int64_t)d.S * d.K, (double)NAN);
@@ -311,8 +343,9 @@ extern "C" int abba_solve(const abba_op *A, const abba_op *B, const void *b, voi
     ABBA_LAUNCHED("fill_k");
 
     // ---- initialisation: r_0, beta, w_1 (Alg. 1 lines 1-3, Alg. 2 lines 1-3)
-    if ((rc = launch_zero_pad(d.w_dt, ws.W, wsl, d.K + 1, d.ldw, d.len, d.S, st))) return rc;
-    if (ws.P && (rc = launch_zero_pad(d.img_dt, ws.P, (int64_t)d.K * d.ldn, d.K, d.ldn, d.n, d.S, st))) return rc;
+    if ((rc = launch_zero_pad(d.w_dt, ws.W, wsl, d.wslots, d.ldw, d.len, d.S, st))) return rc;
+    if (ws.P && (rc = launch_zero_pad(d.img_dt, ws.P, (int64_t)d.pslots * d.ldn, d.pslots, d.ldn, d.n, d.S, st)))
+        return rc;
     VecRef xin{x, d.n, 0, 0};
     VecRef sino{ws.sino, d.ldm, 0, 0};
     if ((rc = apply_op(A, true, xin, d.img_dt, sino, d.sino_dt, d, ws, L0))) return rc;
@@ -329,8 +362,6 @@ extern "C" int abba_solve(const abba_op *A, const abba_op *B, const void *b, voi
         if ((rc = apply_op(B, false, sino, d.sino_dt, w0, d.w_dt, d, ws, L0))) return rc;
     }
     if ((rc = normalize_first(d, ws, out->iters, out->status, st))) return rc;
-    hipLaunchKernelGGL(set_int_k, dim3(1), dim3(1), 0, st, ws.kdev, 1);
-    ABBA_LAUNCHED("set_int_k");
 
     IterCfg cfg;
     cfg.A = A;
@@ -348,6 +379,17 @@ extern "C" int abba_solve(const abba_op *A, const abba_op *B, const void *b, voi
     cfg.learned = rule == ABBA_REG_LEARNED;
     cfg.reg = reg;
     if (cfg.learned && (rc = learned_prepare(d, ws, reg, st))) return rc;
+    if (d.ortho == ABBA_ORTHO_DELAYED) {
+        // step 0 of the delayed schedule: M w_1 and its first pass, giving
+        // the once-orthogonalised second vector (no projected problem yet)
+        hipLaunchKernelGGL(set_int_k, dim3(1), dim3(1), 0, st, ws.kdev, 0);
+        ABBA_LAUNCHED("set_int_k");
+        Launch L1{st, ws.kdev, ws.active};
+        if ((rc = apply_M(d, ws, cfg, L1))) return rc;
+        if ((rc = dcgs2_step(d, ws, ws.kdev, st))) return rc;
+    }
+    hipLaunchKernelGGL(set_int_k, dim3(1), dim3(1), 0, st, ws.kdev, 1);
+    ABBA_LAUNCHED("set_int_k");
 
     // ---- iterations
     hipGraphExec_t gexec = nullptr;
@@ -401,10 +443,17 @@ extern "C" int abba_solve(const abba_op *A, const abba_op *B, const void *b, voi
     if (rc) return rc;
 
     // ---- x_k = x_0 + P_k y_k (AB) or x_0 + W_k y_k (BA) at each slice's stop
-    if (d.mode == ABBA_MODE_AB)
-        rc = launch_assemble(d.img_dt, ws.P, (int64_t)d.K * d.ldn, d.ldn, d.img_dt, x, d.n, ws.y, d.K, out->iters,
-                             d.S, st);
-    else
+    if (d.mode == ABBA_MODE_AB) {
+        // delayed schedule: P holds B applied to the vectors before their
+        // second pass, B W_k y = P' (T y)
+        const double *yk = ws.y;
+        if (d.ortho == ABBA_ORTHO_DELAYED) {
+            if ((rc = launch_ty(d, ws, out->iters, nullptr, nullptr, st))) return rc;
+            yk = ws.y2;
+        }
+        rc = launch_assemble(d.img_dt, ws.P, (int64_t)d.pslots * d.ldn, d.ldn, d.img_dt, x, d.n, yk, d.K,
+                             out->iters, d.S, st);
+    } else
         rc = launch_assemble(d.w_dt, ws.W, wsl, d.ldw, d.img_dt, x, d.n, ws.y, d.K, out->iters, d.S, st);
     if (rc) return rc;
     if (out->lambda) {

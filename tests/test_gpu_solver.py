@@ -143,20 +143,22 @@ def fp32_gate(og, b, floor=1e-4, **kw):
 
 # ------------------------------------------------ 64^2 FP64 configuration ---
 
+@pytest.mark.parametrize("ortho", ["dcgs2", "cgs2"])
 @pytest.mark.parametrize("mode,rule", [("AB", "gcv"), ("BA", "gcv"), ("AB", "none"), ("BA", "none"),
                                        ("AB", "fixed"), ("BA", "fixed"), ("AB", "lcurve"), ("AB", "dp")])
-def test_solver_parity_c1_f64(pk, mode, rule):
-    # 64^2 FP64 image, 90 angles x 91 bins, 1% noise, 30 iterations
+def test_solver_parity_c1_f64(pk, mode, rule, ortho):
+    # 64^2 FP64 image, 90 angles x 91 bins, 1% noise, 30 iterations; both
+    # Gram-Schmidt schedules against the oracle's two-pass CGS2
     A, B, og, xt, bd, bu, ens = problem(pk, 64, 90, 91, 0.01, 0, 1, dt="f64")
     noise = torch.tensor(ens, device="cuda", dtype=torch.float64)
     K = 30 if rule != "none" else 12
-    x, info = pk.solve(A, B, bd, mode=mode, k=K, reg=rule, lam=15.0, noise_norm=noise)
+    x, info = pk.solve(A, B, bd, mode=mode, k=K, reg=rule, lam=15.0, noise_norm=noise, ortho=ortho)
     kw = dict(mode=mode, K=K, rule=rule, lam=15.0, noise_norm=float(ens[0]))
     o, gx, grho, glam, demu = derived_gates(og, bu[0], "f64", 1e-8, **kw)
     ex = rel(x.cpu().numpy(), o.x)
     er = rel(info["resid"][0].cpu().numpy(), o.rho)
     wl = lambda_gaps(rule, info["lam"][0].cpu().numpy(), o)
-    print(f"f64 {mode} {rule} K={K}: x {ex:.2e} (gate {gx:.1e}) rho {er:.2e} (gate {grho:.1e}) "
+    print(f"f64 {ortho} {mode} {rule} K={K}: x {ex:.2e} (gate {gx:.1e}) rho {er:.2e} (gate {grho:.1e}) "
           f"lambda-gap {wl:.1e} (gate {glam:.1e}) RRE {rel(x.cpu().numpy(), xt[0]):.4f}")
     assert int(info["iters"][0]) == o.iters
     assert ex <= gx and er <= grho and wl <= glam
@@ -187,20 +189,36 @@ def test_solver_parity_c1_f32(pk, mode, rule, K):
         assert ex <= 1e-4
 
 
+@pytest.mark.parametrize("ortho", ["dcgs2", "cgs2"])
 @pytest.mark.parametrize("mode,stop", [("AB", "dp"), ("BA", "dp"), ("AB", "rns"), ("BA", "rns")])
-def test_stopping_rules_parity(pk, mode, stop):
+def test_stopping_rules_parity(pk, mode, stop, ortho):
     A, B, og, xt, bd, bu, ens = problem(pk, 64, 90, 91, 0.02, 0, 4)
     noise = torch.tensor(ens, device="cuda", dtype=torch.float64)
-    x, info = pk.solve(A, B, bd, mode=mode, k=60, reg="gcv", noise_norm=noise, stop=stop, rns_eps=1e-2)
+    x, info = pk.solve(A, B, bd, mode=mode, k=60, reg="gcv", noise_norm=noise, stop=stop, rns_eps=1e-2,
+                       ortho=ortho)
     kw = dict(mode=mode, K=60, rule="gcv", stop=stop, noise_norm=float(ens[0]), rns_eps=1e-2)
     o = osv.hybrid_gmres(og.A, og.B, bu[0], **kw)
     gx, _, demu = fp32_gate(og, bu[0], **kw)
     it = int(info["iters"][0])
     st = int(info["status"][0])
     ex = rel(x.double().cpu().numpy(), o.x)
-    print(f"{mode} stop={stop}: iters gpu {it} oracle {o.iters}, status {st}/{o.status}, x {ex:.2e} (gate {gx:.1e})")
+    print(f"{ortho} {mode} stop={stop}: iters gpu {it} oracle {o.iters}, status {st}/{o.status}, x {ex:.2e} "
+          f"(gate {gx:.1e})")
     assert it == o.iters and st == o.status
     assert ex <= gx
+
+
+@pytest.mark.parametrize("mode", ["AB", "BA"])
+def test_delayed_and_two_pass_schedules_agree(pk, mode):
+    """The two Gram-Schmidt schedules are the same iteration: in FP64 they
+    agree to rounding while the Krylov process is well conditioned."""
+    A, B, og, xt, bd, bu, ens = problem(pk, 64, 90, 91, 0.01, 0, 2, dt="f64")
+    xd, idd = pk.solve(A, B, bd, mode=mode, k=12, reg="none", ortho="dcgs2")
+    xc, ic = pk.solve(A, B, bd, mode=mode, k=12, reg="none", ortho="cgs2")
+    e = rel(xd.cpu().numpy(), xc.cpu().numpy())
+    er = rel(idd["resid"].cpu().numpy(), ic["resid"].cpu().numpy())
+    print(f"{mode}: dcgs2 vs cgs2 x {e:.2e} rho {er:.2e}")
+    assert e < 1e-11 and er < 1e-11
 
 
 def test_batched_equals_per_slice_and_graph(pk):
