@@ -102,7 +102,11 @@ int abba_op_sizes(const abba_op *op, int64_t *n_img, int64_t *n_sino);
 
 /* y_s = A x_s for s < batch (eq. (1)); `A` must be ABBA_OP_JOSEPH.  x is
  * [batch][n] in the image dtype, y [batch][m] in the sinogram dtype.
- * Asynchronous on `stream`. */
+ * Asynchronous on `stream`; allocates its scratch (padded copies of x)
+ * stream-ordered.  Two kernels compute A with identical results: one per ray
+ * from global memory, and one that streams the image through LDS, used when
+ * the batch is large enough to fill the device; the environment variable
+ * ABBA_JOSEPH_PATH=gather|lds forces one of them. */
 int abba_project(const abba_op *A, const void *x, void *y, int batch, void *stream);
 
 /* x_s = B y_s for s < batch; `B` is ABBA_OP_PIXEL (unmatched B of
