@@ -121,6 +121,17 @@ class Cone3DOps:
                                  g.pu, g.pv, _p(self._src), _p(self._det), _p(self._eu), _p(self._ev))
         return y
 
+    def B_points(self, y, idx):
+        """(B y) at the flat voxel indices idx (the same sum as B)."""
+        g = self.g
+        y = np.ascontiguousarray(y, dtype=np.float64).reshape(g.m)
+        idx = np.ascontiguousarray(idx, dtype=np.int64)
+        out = np.zeros(idx.size)
+        self.lib.oracle_cone_bp_points(_p(y), idx.ctypes.data_as(ctypes.POINTER(ctypes.c_longlong)), _p(out),
+                                       idx.size, g.nx, g.ny, g.nz, g.n_views, g.nu, g.nv, g.pu, g.pv,
+                                       _p(self._src), _p(self._det), _p(self._eu), _p(self._ev))
+        return out
+
     def B(self, y):
         g = self.g
         y = np.ascontiguousarray(y, dtype=np.float64).reshape(g.m)

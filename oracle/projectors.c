@@ -267,43 +267,69 @@ void oracle_cone_fwd(const double *vol, double *sino, int nx, int ny, int nz,
     }
 }
 
+/* B at selected voxels only: out[t] = (B y)[k_t][i_t][j_t] for the flat voxel
+ * indices idx[t] = (k_t * ny + i_t) * nx + j_t, t < npts; the same sum as
+ * oracle_cone_bp (used to check large volumes on a sample). */
+static double cone_bp_voxel(const double *sino, int nx, int ny, int nz,
+                            int nviews, int nu, int nv, double pu, double pv,
+                            const double *src, const double *det,
+                            const double *eu, const double *ev, int k, int i, int j);
+
+void oracle_cone_bp_points(const double *sino, const long long *idx, double *out, int npts,
+                           int nx, int ny, int nz, int nviews, int nu, int nv, double pu, double pv,
+                           const double *src, const double *det, const double *eu, const double *ev)
+{
+    #pragma omp parallel for schedule(static)
+    for (int t = 0; t < npts; ++t) {
+        const long long f = idx[t];
+        const int j = (int)(f % nx), i = (int)((f / nx) % ny), k = (int)(f / ((long long)nx * ny));
+        out[t] = cone_bp_voxel(sino, nx, ny, nz, nviews, nu, nv, pu, pv, src, det, eu, ev, k, i, j);
+    }
+}
+
 void oracle_cone_bp(const double *sino, double *vol, int nx, int ny, int nz,
                     int nviews, int nu, int nv, double pu, double pv,
                     const double *src, const double *det,
                     const double *eu, const double *ev)
 {
-    const double cx = 0.5 * (nx - 1), cy = 0.5 * (ny - 1), cz = 0.5 * (nz - 1);
     #pragma omp parallel for schedule(static) collapse(2)
-    for (int k = 0; k < nz; ++k) {
-        for (int i = 0; i < ny; ++i) {
-            for (int j = 0; j < nx; ++j) {
-                const double X[3] = { j - cx, i - cy, k - cz };
-                double acc = 0.0;
-                for (int w = 0; w < nviews; ++w) {
-                    const double *S = src + 3 * w, *D = det + 3 * w;
-                    const double *U = eu + 3 * w, *V = ev + 3 * w;
-                    /* detector normal n = eu x ev; intersect S + t (X - S) with
-                     * the plane (P - D).n = 0 */
-                    const double n[3] = { U[1] * V[2] - U[2] * V[1],
-                                          U[2] * V[0] - U[0] * V[2],
-                                          U[0] * V[1] - U[1] * V[0] };
-                    const double r[3] = { X[0] - S[0], X[1] - S[1], X[2] - S[2] };
-                    const double num = (D[0] - S[0]) * n[0] + (D[1] - S[1]) * n[1] + (D[2] - S[2]) * n[2];
-                    const double den = r[0] * n[0] + r[1] * n[1] + r[2] * n[2];
-                    const double M = num / den;               /* magnification */
-                    double P[3];
-                    for (int t = 0; t < 3; ++t) P[t] = S[t] + M * r[t] - D[t];
-                    const double uu = (P[0] * U[0] + P[1] * U[1] + P[2] * U[2]) / pu + 0.5 * (nu - 1);
-                    const double vv = (P[0] * V[0] + P[1] * V[1] + P[2] * V[2]) / pv + 0.5 * (nv - 1);
-                    const double *view = sino + (size_t)w * nv * nu;
-                    double val;
+    for (int k = 0; k < nz; ++k)
+        for (int i = 0; i < ny; ++i)
+            for (int j = 0; j < nx; ++j)
+                vol[((size_t)k * ny + i) * nx + j] =
+                    cone_bp_voxel(sino, nx, ny, nz, nviews, nu, nv, pu, pv, src, det, eu, ev, k, i, j);
+}
+
+static double cone_bp_voxel(const double *sino, int nx, int ny, int nz,
+                            int nviews, int nu, int nv, double pu, double pv,
+                            const double *src, const double *det,
+                            const double *eu, const double *ev, int k, int i, int j)
+{
+    const double cx = 0.5 * (nx - 1), cy = 0.5 * (ny - 1), cz = 0.5 * (nz - 1);
+    const double X[3] = { j - cx, i - cy, k - cz };
+    double acc = 0.0;
+    for (int w = 0; w < nviews; ++w) {
+        const double *S = src + 3 * w, *D = det + 3 * w;
+        const double *U = eu + 3 * w, *V = ev + 3 * w;
+        /* detector normal n = eu x ev; intersect S + t (X - S) with
+         * the plane (P - D).n = 0 */
+        const double n[3] = { U[1] * V[2] - U[2] * V[1],
+                              U[2] * V[0] - U[0] * V[2],
+                              U[0] * V[1] - U[1] * V[0] };
+        const double r[3] = { X[0] - S[0], X[1] - S[1], X[2] - S[2] };
+        const double num = (D[0] - S[0]) * n[0] + (D[1] - S[1]) * n[1] + (D[2] - S[2]) * n[2];
+        const double den = r[0] * n[0] + r[1] * n[1] + r[2] * n[2];
+        const double M = num / den;               /* magnification */
+        double P[3];
+        for (int t = 0; t < 3; ++t) P[t] = S[t] + M * r[t] - D[t];
+        const double uu = (P[0] * U[0] + P[1] * U[1] + P[2] * U[2]) / pu + 0.5 * (nu - 1);
+        const double vv = (P[0] * V[0] + P[1] * V[1] + P[2] * V[2]) / pv + 0.5 * (nv - 1);
+        const double *view = sino + (size_t)w * nv * nu;
+        double val;
 #define F(p, q) (((p) >= 0 && (p) < nv && (q) >= 0 && (q) < nu) ? view[(size_t)(p) * nu + (q)] : 0.0)
-                    BILIN(F, vv, uu);
+        BILIN(F, vv, uu);
 #undef F
-                    acc += val * (M / pu) * (M / pv);
-                }
-                vol[((size_t)k * ny + i) * nx + j] = acc;
-            }
-        }
+        acc += val * (M / pu) * (M / pv);
     }
+    return acc;
 }

@@ -51,6 +51,10 @@ int validate_geometry(const abba_geometry *g, int kind) {
         set_error("detector pitch must be positive");
         return ABBA_ERR_ARG;
     }
+    if (cone && 2.0 * g->sid <= std::sqrt((double)g->nx * g->nx + (double)g->ny * g->ny + (double)g->nz * g->nz)) {
+        set_error("cone beam: the source (at distance sid from the centre) must lie outside the volume");
+        return ABBA_ERR_ARG;
+    }
     if (cone && !(g->sid > 0.0 && g->sdd > g->sid)) {
         set_error("cone beam needs 0 < sid < sdd");
         return ABBA_ERR_ARG;
@@ -220,6 +224,7 @@ int abba_op_create(abba_op **out, int kind, const abba_geometry *geom, int img_d
     op->major = nullptr;
     op->agrp = nullptr;
     op->ngroups = 0;
+    op->cone_axes = 0;
     hipError_t e = hipGetDevice(&op->device);
     if (e != hipSuccess) {
         delete op;
@@ -281,11 +286,12 @@ int abba_project(const abba_op *A, const void *x, void *y, int batch, void *stre
     Launch L{st, nullptr, nullptr};
     VecRef xr{const_cast<void *>(x), A->n, 0, 0};
     VecRef yr{y, A->m, 0, 0};
-    if (A->g.kind == ABBA_GEOM_CONE3D) return cone_forward(A, xr, yr, A->sino_dtype, batch, L);
+    const bool cone = A->g.kind == ABBA_GEOM_CONE3D;
     // the forward projector reads zero-padded copies of the image
     void *scr = nullptr;
-    ABBA_HIP(hipMallocAsync(&scr, par2d_scratch_bytes(A, batch), st));
-    int rc = par2d_forward(A, xr, yr, A->sino_dtype, batch, scr, L);
+    ABBA_HIP(hipMallocAsync(&scr, cone ? cone_scratch_bytes(A, batch) : par2d_scratch_bytes(A, batch), st));
+    int rc = cone ? cone_forward(A, xr, yr, A->sino_dtype, batch, scr, L)
+                  : par2d_forward(A, xr, yr, A->sino_dtype, batch, scr, L);
     hipError_t e = hipFreeAsync(scr, st);
     if (rc) return rc;
     if (e != hipSuccess) return hip_fail(e, "hipFreeAsync");
@@ -307,8 +313,17 @@ int abba_backproject(const abba_op *B, const void *y, void *x, int batch, void *
     Launch L{st, nullptr, nullptr};
     VecRef yr{const_cast<void *>(y), B->m, 0, 0};
     VecRef xr{x, B->n, 0, 0};
-    if (B->g.kind == ABBA_GEOM_CONE3D) return cone_back(B, yr, B->sino_dtype, xr, batch, L);
     if (B->kind == ABBA_OP_JOSEPH_T) return par2d_back(B, yr, B->sino_dtype, xr, batch, nullptr, L);
+    if (B->g.kind == ABBA_GEOM_CONE3D) {
+        // the voxel-driven backprojector reads a zero-padded copy of the views
+        void *scr = nullptr;
+        ABBA_HIP(hipMallocAsync(&scr, cone_scratch_bytes(B, batch), st));
+        int rc = cone_back(B, yr, B->sino_dtype, xr, batch, scr, L);
+        hipError_t e = hipFreeAsync(scr, st);
+        if (rc) return rc;
+        if (e != hipSuccess) return hip_fail(e, "hipFreeAsync");
+        return ABBA_OK;
+    }
     // the pixel-driven backprojector reads a zero-padded copy of the sinogram
     void *scr = nullptr;
     ABBA_HIP(hipMallocAsync(&scr, par2d_scratch_bytes(B, batch), st));

@@ -30,14 +30,18 @@ struct AngleTab {
 // hold angles of one march direction only.
 constexpr int JOSEPH_GA = 4;
 
-// Per-view constants of the 3D cone beam (FP32 on the device).
-struct ViewTab {
-    float src[3];    // source position
-    float det[3];    // detector centre
-    float eu[3];     // column axis (unit)
-    float ev[3];     // row axis (unit)
-    float nrm[3];    // detector normal eu x ev
-    float dist;      // (det - src) . nrm
+// Per-view constants of the 3D cone beam, FP64 (ray set-up is FP64; the
+// voxel-driven B rounds them to its accumulation type).
+struct ConeView {
+    double S[3];     // source position
+    double D[3];     // detector centre
+    double eu[3];    // column axis (unit)
+    double ev[3];    // row axis (unit)
+    double n[3];     // detector normal eu x ev
+    double dist;     // (D - S) . n: magnification numerator
+    double Sn;       // S . n
+    double Su, Sv;   // S . eu / pu, S . ev / pv
+    double cu, cv;   // (S - D) . eu / pu + (nu - 1)/2, the same for v
 };
 
 // Where one vector of a slice lives: base + s*slice_stride +
@@ -66,10 +70,11 @@ struct abba_op {
     int device;
     int nxcc;              // XCDs of the device (workgroups are dealt to them round-robin)
     int ncu;               // compute units of the device
-    void *tab;             // AngleTab<float|double>[n_angles] or ViewTab[views]
+    void *tab;             // AngleTab<float|double>[n_angles] or ConeView[views]
     int *agrp;             // 2D: [ngroups][4] {first, count, rowmarch, 0}, then the angle order [n_angles]
     int ngroups;
-    unsigned char *major;  // 3D: per (view, column) dominant-axis flag (0 = x, 1 = y)
+    unsigned char *major;  // unused
+    int cone_axes;         // 3D: bit a set if some ray has dominant axis a (0 x, 1 y, 2 z)
 };
 
 namespace abba {
@@ -83,8 +88,9 @@ int par2d_back(const abba_op *op, VecRef y, int y_dtype, VecRef x, int batch, vo
 size_t par2d_scratch_bytes(const abba_op *op, int batch);
 
 // 3D cone beam (cone3d.hip).
-int cone_forward(const abba_op *op, VecRef x, VecRef y, int y_dtype, int batch, const Launch &L);
-int cone_back(const abba_op *op, VecRef y, int y_dtype, VecRef x, int batch, const Launch &L);
+int cone_forward(const abba_op *op, VecRef x, VecRef y, int y_dtype, int batch, void *scratch, const Launch &L);
+int cone_back(const abba_op *op, VecRef y, int y_dtype, VecRef x, int batch, void *scratch, const Launch &L);
+size_t cone_scratch_bytes(const abba_op *op, int batch);
 
 int op_build_tables(abba_op *op);
 

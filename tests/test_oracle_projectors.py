@@ -282,3 +282,11 @@ def test_cone_backprojector_close_to_transpose_in_scale():
     lhs = float(ops.A(x).sum())
     rhs = float(x @ ops.B(np.ones(g.m)))
     assert abs(lhs - rhs) / abs(lhs) < 3e-2
+
+
+def test_cone_backprojector_at_points_equals_full():
+    g = Cone3D(12, 10, 8, 6, 16, 14, 1.3, 1.2, 30.0, 60.0)
+    o = Cone3DOps(g)
+    y = np.random.default_rng(1).standard_normal(g.m)
+    idx = np.array([0, 5, 77, 123, 500, g.n - 1])
+    assert np.array_equal(o.B_points(y, idx), o.B(y)[idx])
