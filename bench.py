@@ -41,6 +41,16 @@ VALU_PEAK_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
 # clamp 1).
 FLOPS_PER_RAY_STEP = 6
 FLOPS_PER_PIXEL_ANGLE = 8
+# 3D cone beam: Joseph per plane crossing (advance two coordinates 2,
+# fractional parts 2, bilinear interpolation 9, accumulate 1); voxel driven
+# per voxel-view pair (denominator 1, magnification 1, detector u and v 4,
+# fractional parts 2, bilinear interpolation 9, weight 2, accumulate 1).
+FLOPS_PER_CONE_STEP = 14
+FLOPS_PER_VOXEL_VIEW = 20
+# the 3D workload: 256^3 volume of random ellipsoids, 360 views on [0, 2 pi),
+# 384 x 384 detector at pitch 2.1, source-isocentre 500, source-detector 1000,
+# 1 % noise, BF16 sinogram, hybrid BA-GMRES with GCV for 50 iterations
+CONE = dict(n=256, views=360, nu=384, nv=384, pitch=2.1, sid=500.0, sdd=1000.0, eta=0.01, k=50)
 PROFILES = os.path.join(ROOT, "profiles")
 
 
@@ -60,6 +70,8 @@ def parse():
     p.add_argument("--roofline-reps", type=int, default=10)
     p.add_argument("--projectors-only", action="store_true",
                    help="only the projector launches (random images) and a copy of known size, for counter runs")
+    p.add_argument("--workload", choices=["slices", "cone"], default="slices",
+                   help="slices: the batched 2D workload (default); cone: the 3D cone-beam volume solve")
     p.add_argument("--quiet", action="store_true")
     return p.parse_args()
 
@@ -214,6 +226,159 @@ def cpu_baseline(args, b_slice, en_slice, k_cap):
     return t, o.iters, threads
 
 
+def cone_ray_steps(n, views, nu, nv, pitch, sid, sdd):
+    """Plane crossings of one cone-beam Joseph projection at which some
+    bilinear tap lies inside the n^3 volume: per ray, the planes of its
+    dominant axis whose two in-plane coordinates are both in (-1, n)."""
+    import numpy as np
+    c = 0.5 * (n - 1)
+    ou = (np.arange(nu) - 0.5 * (nu - 1)) * pitch
+    ov = (np.arange(nv) - 0.5 * (nv - 1)) * pitch
+    OU, OV = np.meshgrid(ou, ov)
+    total = 0
+    for v in range(views):
+        b = 2.0 * math.pi * v / views
+        S = np.array([sid * math.cos(b), sid * math.sin(b), 0.0])
+        D = -(sdd - sid) * np.array([math.cos(b), math.sin(b), 0.0])
+        eu = np.array([-math.sin(b), math.cos(b), 0.0])
+        d = [D[t] + OU * eu[t] + OV * (1.0 if t == 2 else 0.0) - S[t] for t in range(3)]
+        ad = np.stack([np.abs(x) for x in d])
+        major = np.where((ad[0] >= ad[1]) & (ad[0] >= ad[2]), 0, np.where(ad[1] >= ad[2], 1, 2))
+        for a in range(3):
+            sel = major == a
+            if not sel.any():
+                continue
+            da = d[a][sel]
+            t0 = (-c - S[a]) / da
+            dt = 1.0 / da
+            lo = np.zeros(da.shape)
+            hi = np.full(da.shape, n - 1.0)
+            for o in range(3):
+                if o == a:
+                    continue
+                p0 = S[o] + t0 * d[o][sel] + c
+                dp = dt * d[o][sel]
+                with np.errstate(divide="ignore", invalid="ignore"):
+                    ra, rb = (-1.0 - p0) / dp, (n - p0) / dp
+                flat = dp == 0
+                inside = (p0 > -1) & (p0 < n)
+                l = np.where(flat, np.where(inside, -np.inf, np.inf), np.minimum(ra, rb))
+                h = np.where(flat, np.where(inside, np.inf, -np.inf), np.maximum(ra, rb))
+                lo = np.maximum(lo, np.floor(l) + 1)
+                hi = np.minimum(hi, np.ceil(h) - 1)
+            total += int(np.clip(hi - lo + 1, 0, None).sum())
+    return total
+
+
+def cone_cpu_baseline(x_true, b, k):
+    """The FP64 oracle's projectors on a bounded sample of the 3D workload
+    (A on 4 of the views, B at 2,000 voxels), scaled to one BA solve of k
+    iterations: one B for r_0, then one A and one B per iteration."""
+    import numpy as np
+
+    import oracle
+    from oracle.geometry import Cone3D
+    from oracle.operators import Cone3DOps
+    oracle.build_oracle(force=False)
+    C = CONE
+    n = C["n"]
+    views = [0, 90, 180, 270]
+    beta = 2 * math.pi * np.array(views) / C["views"]
+    og_v = Cone3DOps(Cone3D(n, n, n, len(views), C["nu"], C["nv"], C["pitch"], C["pitch"], C["sid"], C["sdd"], beta))
+    og = Cone3DOps(Cone3D(n, n, n, C["views"], C["nu"], C["nv"], C["pitch"], C["pitch"], C["sid"], C["sdd"]))
+    idx = np.random.default_rng(0).choice(n ** 3, 2000, replace=False)
+    t0 = time.perf_counter()
+    og_v.A(x_true)
+    t_a = (time.perf_counter() - t0) * C["views"] / len(views)
+    t0 = time.perf_counter()
+    og.B_points(b, idx)
+    t_b = (time.perf_counter() - t0) * n ** 3 / len(idx)
+    t_solve = (k + 1) * t_b + k * t_a
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    return t_solve, t_a, t_b, threads
+
+
+def cone_workload(args):
+    import numpy as np
+    import torch
+
+    import paper_2602_17892_amd as pk
+    import synth
+    torch.cuda.set_device(0)
+    C = CONE
+    n, K = C["n"], C["k"]
+    g = pk.Geometry(n, n, C["views"], C["nu"], det_pitch_u=C["pitch"], kind="cone3d", nz=n, det_v=C["nv"],
+                    det_pitch_v=C["pitch"], sid=C["sid"], sdd=C["sdd"])
+    A = pk.Operator("joseph", g, "f32", "bf16")
+    B = pk.Operator("pixel", g, "f32", "bf16")
+    A32 = pk.Operator("joseph", g, "f32", "f32")
+    t0 = time.perf_counter()
+    vol, _ = synth.phantom3d(4, 0, n, device=torch.device("cuda"))
+    xt = vol.to(torch.float32).reshape(1, n, n, n).contiguous()
+    bt = pk.project(A32, xt).double()
+    gn = torch.as_tensor(synth.noise_direction(4, 0, bt.numel()), device="cuda").reshape(bt.shape)
+    b = (bt + C["eta"] * torch.linalg.vector_norm(bt) / torch.linalg.vector_norm(gn) * gn).to(torch.bfloat16)
+    del bt, gn
+    log(args, f"inputs: {n}^3 volume, {C['views']} views of {C['nv']}x{C['nu']} in {time.perf_counter() - t0:.1f}s")
+    ws = torch.empty(pk.workspace_bytes(A, B, 1, "BA", K, stop=None), dtype=torch.uint8, device="cuda")
+
+    def step():
+        return pk.solve(A, B, b, mode="BA", k=K, reg="gcv", workspace=ws, history=False)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        xk, info = step()
+    torch.cuda.synchronize()
+    t_solve = (time.perf_counter() - t0) / args.steps
+    rre = float(torch.linalg.vector_norm((xk - xt).double()) / torch.linalg.vector_norm(xt.double()))
+    log(args, f"BA K={K}: {t_solve:.3f}s/solve, RRE {rre:.4f}")
+    y = torch.empty_like(b)
+    xo = torch.empty_like(xt)
+    t_A = time_apply(lambda: pk.project(A, xt, out=y), torch, args.roofline_reps)
+    t_B = time_apply(lambda: pk.backproject(B, b, out=xo), torch, args.roofline_reps)
+    steps = cone_ray_steps(n, C["views"], C["nu"], C["nv"], C["pitch"], C["sid"], C["sdd"])
+    pairs = n ** 3 * C["views"]
+    tf_A = steps * FLOPS_PER_CONE_STEP / t_A / 1e12
+    tf_B = pairs * FLOPS_PER_VOXEL_VIEW / t_B / 1e12
+    bytes_apply = n ** 3 * 4 + C["views"] * C["nu"] * C["nv"] * 2
+    log(args, f"A: {t_A * 1e3:.2f} ms ({tf_A:.2f} TFLOP/s, {steps} plane crossings); "
+              f"B: {t_B * 1e3:.2f} ms ({tf_B:.2f} TFLOP/s)")
+    dom = ("cone_fwd_k", tf_A, t_A) if t_A >= t_B else ("cone_bp_k", tf_B, t_B)
+    out = {
+        "metric": "reconstructed volumes/sec (hybrid BA-GMRES, GCV lambda, 50 iterations, BF16 sinogram)",
+        "value": round(1.0 / t_solve, 4),
+        "unit": "volumes/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(t_solve * 1e3, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32 projectors+basis, bf16 sinogram storage, f64 reductions and small solves",
+        "data": "synthetic: seeded random-ellipsoid volume, b = A x + 1% relative Gaussian noise",
+        "config": {"workload": f"{n}^3 cone beam, {C['views']} views x {C['nv']}x{C['nu']} detector at pitch "
+                               f"{C['pitch']}, SID {C['sid']:g}, SDD {C['sdd']:g}, hybrid BA-GMRES GCV, k {K}"},
+        "rre": rre,
+        "projector": {"A_ms": round(t_A * 1e3, 3), "B_ms": round(t_B * 1e3, 3), "A_TFLOPs": round(tf_A, 3),
+                      "B_TFLOPs": round(tf_B, 3), "A_plane_crossings": steps, "B_voxel_view_pairs": pairs,
+                      "A_GBps": round(bytes_apply / t_A / 1e9, 2), "B_GBps": round(bytes_apply / t_B / 1e9, 2)},
+        "roofline": {"bound": "alu", "achieved": round(dom[1], 3), "peak": round(VALU_PEAK_TFLOPS, 1),
+                     "unit": "TFLOP/s", "frac": round(dom[1] / VALU_PEAK_TFLOPS, 4), "traffic": None,
+                     "kernel": dom[0], "ms_per_launch": round(dom[2] * 1e3, 3)},
+    }
+    if not args.no_cpu_baseline:
+        t_cpu, t_a, t_b, thr = cone_cpu_baseline(xt[0].double().cpu().numpy(), b[0].double().cpu().numpy(), K)
+        out["cpu_baseline"] = {"value": round(1.0 / t_cpu, 7), "unit": "volumes/s", "cores": thr, "kind": "oracle",
+                               "sample": f"FP64 oracle A on 4 of {C['views']} views ({t_a:.0f}s scaled to all) and B "
+                                         f"at 2000 voxels ({t_b:.0f}s scaled to all), times (k+1) B + k A; "
+                                         f"orthogonalisation not counted"}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -228,6 +393,9 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     if args.projectors_only:
         projectors_only(args)
+        return
+    if args.workload == "cone":
+        cone_workload(args)
         return
     torch.cuda.set_device(0)
     S, K = args.slices, args.kmax

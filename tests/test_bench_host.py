@@ -42,3 +42,27 @@ def test_recorded_traffic_ignores_stale_summaries(tmp_path, monkeypatch):
     f.write_text(f"- source_digest = `{bench.kernel_source_digest()}`\n- hbm_bytes_per_launch = 123.0\n")
     assert bench.recorded_traffic("k") == 123.0
     assert bench.recorded_traffic("absent") is None
+
+
+@pytest.mark.parametrize("n,views,nu,nv,pitch,sid,sdd", [(8, 6, 12, 10, 1.0, 30.0, 60.0),
+                                                         (10, 5, 14, 18, 1.5, 16.0, 26.0)])
+def test_cone_ray_steps_brute_force(n, views, nu, nv, pitch, sid, sdd):
+    # every ray, every plane of its dominant axis: count the planes where both
+    # in-plane coordinates of the crossing lie in (-1, n)
+    import math
+    c = 0.5 * (n - 1)
+    want = 0
+    for v in range(views):
+        b = 2 * math.pi * v / views
+        S = (sid * math.cos(b), sid * math.sin(b), 0.0)
+        for r in range(nv):
+            for col in range(nu):
+                ou, ov = (col - 0.5 * (nu - 1)) * pitch, (r - 0.5 * (nv - 1)) * pitch
+                P = (-(sdd - sid) * math.cos(b) - ou * math.sin(b), -(sdd - sid) * math.sin(b) + ou * math.cos(b), ov)
+                d = [P[t] - S[t] for t in range(3)]
+                a = max(range(3), key=lambda t: (abs(d[t]), -t))
+                for j in range(n):
+                    t = ((j - c) - S[a]) / d[a]
+                    crd = [S[o] + t * d[o] + c for o in range(3) if o != a]
+                    want += all(-1 < q < n for q in crd)
+    assert bench.cone_ray_steps(n, views, nu, nv, pitch, sid, sdd) == want

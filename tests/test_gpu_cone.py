@@ -157,3 +157,83 @@ def test_cone_c4_shape_sampled(pk):
     eb = rel(xbh[idx], og.B_points(yh, idx))
     print(f"C4 256^3 x 360 x 384^2: A (4 views) {ea:.2e}  B (2000 voxels) {eb:.2e}")
     assert ea <= 1e-5 and eb <= 1e-5
+
+
+def bf16_round(a):
+    """Round to the nearest BF16 (ties to even) through FP32, returned as FP64."""
+    u = np.ascontiguousarray(np.asarray(a, dtype=np.float32)).view(np.uint32).astype(np.uint64)
+    u = ((u + 0x7FFF + ((u >> 16) & 1)) & 0xFFFF0000).astype(np.uint32)
+    return u.view(np.float32).astype(np.float64)
+
+
+def test_bf16_round_helper():
+    # 1 + 2^-8 is a tie between 1 and 1 + 2^-7: to even (1); 1 + 3*2^-8 rounds up
+    v = bf16_round([1.0 + 2.0 ** -8, 1.0 + 3 * 2.0 ** -8, -2.5, 0.0])
+    assert list(v) == [1.0, 1.0 + 2.0 ** -6, -2.5, 0.0]
+
+
+def test_cone_bf16_solve_ba(pk):
+    # BA-GMRES with the sinogram stored in BF16: b and every A output in R^m
+    # are rounded on store.  The oracle runs the same iteration with its A
+    # output rounded the same way; the GPU's FP32 A lands on the other side of
+    # a BF16 rounding boundary for about 1e-7 / 2^-8 of the entries, each such
+    # flip moving one entry of M w by 2^-8 of itself: random relative
+    # perturbations of 1e-7 on the oracle's A move x_8 by about 1e-5, inside
+    # the 1e-4 gate on reconstructions.  Against the unrounded FP64 oracle the
+    # BF16 storage itself shows (about 3e-3 here), gated at 2^-7.
+    from oracle import solver as osv
+    shape = SHAPES[0]
+    A, B, og = make(pk, shape, "f32", "bf16")
+    nx, ny, nz, nvw, nu, nv = shape[:6]
+    r = np.random.default_rng(9)
+    x = np.zeros((nz, ny, nx))
+    x[3:11, 4:14, 5:15] = 1.0
+    x[6:9, 7:10, 8:12] = 0.5
+    bt = og.A(x)
+    b = bt + 0.01 * np.linalg.norm(bt) / math.sqrt(bt.size) * r.standard_normal(bt.size)
+    bd = dev(b.reshape(1, nvw, nv, nu), torch.bfloat16)
+    bu = bd.double().cpu().numpy().ravel()
+    K = 8
+    xg, info = pk.solve(A, B, bd, mode="BA", k=K, reg="gcv")
+    o16 = osv.hybrid_gmres(lambda v: bf16_round(og.A(v)), og.B, bu, mode="BA", K=K, rule="gcv")
+    o64 = osv.hybrid_gmres(og.A, og.B, bu, mode="BA", K=K, rule="gcv")
+    xh = xg.double().cpu().numpy()
+    e16, e64 = rel(xh, o16.x), rel(xh, o64.x)
+    print(f"cone BA K={K} BF16 sinogram: x vs oracle with BF16 stores {e16:.2e}, vs FP64 oracle {e64:.2e}")
+    assert int(info["iters"][0]) == K
+    assert e16 <= 1e-4 and e64 <= 2.0 ** -7
+
+
+def test_cone_c4_solve_ba_bf16(pk):
+    # The 256^3 configuration end to end: random-ellipsoid volume, 1 % noise,
+    # BF16 sinogram, hybrid BA-GMRES with GCV for 50 iterations.  At this size
+    # the checks are properties: the residual the solver reports from its
+    # stored Z agrees with an explicit ||b - A x_K|| up to the BF16 storage of
+    # Z (2^-8 of ||b||), the residual and the error fall from the first
+    # iteration to the last, and every value is finite.
+    import synth
+    nx, ny, nz, nvw, nu, nv, pu, pv, sid, sdd = C4
+    vol, _ = synth.phantom3d(4, 0, nx, device=torch.device("cuda"))
+    xt = vol.to(torch.float32).reshape(1, nz, ny, nx).contiguous()
+    A, B, _ = make(pk, C4, "f32", "bf16")
+    A32 = make(pk, C4, "f32", "f32")[0]
+    bt = pk.project(A32, xt).double()
+    g = torch.as_tensor(synth.noise_direction(4, 0, bt.numel()), device="cuda").reshape(bt.shape)
+    nbt = torch.linalg.vector_norm(bt)
+    b = (bt + 0.01 * nbt / torch.linalg.vector_norm(g) * g).to(torch.bfloat16)
+    K = 50
+    x1, _ = pk.solve(A, B, b, mode="BA", k=1, reg="gcv")
+    xk, info = pk.solve(A, B, b, mode="BA", k=K, reg="gcv")
+    torch.cuda.synchronize()
+    res = info["resid"][0].cpu().numpy()
+    assert int(info["iters"][0]) == K and np.isfinite(res).all()
+    assert bool(torch.isfinite(xk).all())
+    bd = b.double()
+    nb = float(torch.linalg.vector_norm(bd))
+    rho_exp = float(torch.linalg.vector_norm(bd - pk.project(A32, xk).double()))
+    rre1 = float(torch.linalg.vector_norm((x1 - xt).double()) / torch.linalg.vector_norm(xt.double()))
+    rrek = float(torch.linalg.vector_norm((xk - xt).double()) / torch.linalg.vector_norm(xt.double()))
+    print(f"C4 BA K={K} BF16: rho_K {res[K]:.6e} explicit {rho_exp:.6e} (||b|| {nb:.4e}), "
+          f"rho_1 {res[1]:.4e}; RRE x_1 {rre1:.4f} x_K {rrek:.4f}")
+    assert abs(res[K] - rho_exp) <= 2.0 ** -8 * nb
+    assert res[K] < res[1] and rrek < rre1
