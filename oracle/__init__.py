@@ -14,6 +14,7 @@ Modules
   smallsolve  -- Givens residual, SVD, GCV / DP / fixed / none lambda rules
                  and the regularised projected solve of eq. (12)
   solver      -- hybrid AB- and BA-GMRES (Algorithms 1 and 2)
-  mlp         -- FP64 reference of the learned lambda / stop-index network
+  learned     -- features, network, loss, Adam, labels and judge of the
+                 learned lambda / stop-index rule
 """
 from .build import build_oracle, load_oracle  # noqa: F401

@@ -50,6 +50,7 @@ from dataclasses import dataclass, field
 
 import numpy as np
 
+from . import learned as lrn
 from . import smallsolve as ss
 
 STATUS_KMAX = 1
@@ -83,12 +84,17 @@ def hybrid_gmres(A, B, b, mode: str = "AB", K: int = 30, rule: str = "gcv",
                  lam: float = 0.0, stop: str | None = None, tau: float = 1.01,
                  noise_norm: float | None = None, rns_eps: float = 1e-3,
                  x0=None, ortho: str = "cgs2", keep_x: bool = False,
-                 keep_basis: bool = False, keep_small: bool = False) -> Result:
+                 keep_basis: bool = False, keep_small: bool = False, mlp=None,
+                 judge_delta: float = 0.05) -> Result:
     """Run hybrid AB- or BA-GMRES for at most K iterations.
 
     A, B     -- callables on flat FP64 vectors (R^n -> R^m and R^m -> R^n)
-    rule     -- lambda rule: "none", "fixed" (uses lam), "gcv", "dp", "lcurve"
-    stop     -- None (run K iterations), "dp" or "rns"
+    rule     -- lambda rule: "none", "fixed" (uses lam), "gcv", "dp", "lcurve",
+                or "learned" (the network `mlp` proposes lambda, judged against
+                GCV with margin judge_delta; see oracle.learned)
+    stop     -- None (run K iterations), "dp", "rns" or "learned" (the
+                network's stop index, with the discrepancy principle first
+                when noise_norm is given)
     """
     b = np.asarray(b, dtype=np.float64).reshape(-1)
     if x0 is None:
@@ -113,6 +119,12 @@ def hybrid_gmres(A, B, b, mode: str = "AB", K: int = 30, rule: str = "gcv",
     if beta == 0.0:
         out.status = STATUS_BREAKDOWN
         return out
+    if rule == "learned" and mlp is None:
+        raise ValueError("the learned rule needs the network parameters")
+    if stop == "learned" and rule != "learned":
+        raise ValueError("the learned stop shares the learned rule's network")
+    gres = [beta]
+    k_hat = float(K)
     if (rule == "dp" or stop == "dp") and noise_norm is None:
         raise ValueError("the discrepancy principle needs ||e||")
     target = None if noise_norm is None else tau * noise_norm
@@ -183,7 +195,15 @@ def hybrid_gmres(A, B, b, mode: str = "AB", K: int = 30, rule: str = "gcv",
                 H[k, k - 1] = hk
                 W.append(q / hk)
         Hk = H[:k + 1, :k]
-        sol = ss.solve_projected(Hk, beta, rule, lam_fixed=lam, dp_target=target)
+        if rule == "learned":
+            base = ss.solve_projected(Hk, beta, "gcv")
+            gres.append(base["uk1"])
+            f = lrn.features(base["sigma"], gres)
+            lam_l, _, _, o1 = lrn.judge(mlp, f, base["sigma"], base["uhat"], base["uk1"], judge_delta)
+            k_hat = min(max(K * o1, 1.0), float(K))
+            sol = ss.solve_projected(Hk, beta, "fixed", lam_fixed=lam_l)
+        else:
+            sol = ss.solve_projected(Hk, beta, rule, lam_fixed=lam, dp_target=target)
         y = sol["y"]
         Wk = np.stack(W[:k])
         if mode == "AB":
@@ -207,11 +227,14 @@ def hybrid_gmres(A, B, b, mode: str = "AB", K: int = 30, rule: str = "gcv",
         if broke:
             status = STATUS_BREAKDOWN
             break
-        if stop == "dp" and rho <= target:
+        if (stop == "dp" or (stop == "learned" and target is not None)) and rho <= target:
             status = STATUS_STOP_DP
             break
         if stop == "rns" and abs(out.rho[-2] - rho) / out.rho[-2] < rns_eps:
             status = STATUS_STOP_RNS
+            break
+        if stop == "learned" and k >= k_hat:
+            status = STATUS_STOP_LEARNED
             break
     out.x = x
     out.iters = k_done
