@@ -156,6 +156,13 @@ typedef struct {
     int *status;               /* device [batch]: ABBA_ST_* bits                           */
     double *lambda;            /* device [batch*k] or NULL: lambda_j, j = 1..k             */
     double *resid;             /* device [batch*(k+1)] or NULL: rho_j = ||b - A x_j||       */
+    float *features;           /* device [batch][k][ABBA_MLP_FEATURES] (exec.features bit
+                                  ABBA_FEAT_OUT): the learned-rule features of iteration j
+                                  in row j-1; rows past a slice's stop are left as they are */
+    const void *x_true;        /* device [batch][n], image dtype (bit ABBA_FEAT_LABELS)    */
+    double *rre;               /* device [batch][k][ABBA_LABEL_GRID] (bit ABBA_FEAT_LABELS):
+                                  ||x_j(lam_g) - x_true|| / ||x_true|| for the grid
+                                  lam_g = sigma_1(H_j) 10^(-8 + 8 g / 63), AB mode only   */
 } abba_out;
 
 typedef struct {
@@ -163,10 +170,14 @@ typedef struct {
     int poll_every;            /* host reads the active-slice count every this many
                                   iterations (>= 1); ignored without a stopping rule       */
     int restart;               /* restart cycle length p (Sec. 3.3); 0 = no restart        */
-    int features;              /* 1: write learned-model features per iteration (learned
-                                  rules need them; costs one extra sort per iteration)     */
+    int features;              /* bits ABBA_FEAT_*: write the learned-rule features
+                                  (out.features) and/or training labels (out.rre)          */
     int ortho;                 /* Gram-Schmidt schedule, ABBA_ORTHO_*                        */
 } abba_exec;
+
+/* exec.features bits.  Labels need AB mode, out.x_true and out.rre; they add a
+ * [batch][k][k+1] FP64 Gram matrix to the workspace. */
+enum { ABBA_FEAT_OUT = 1, ABBA_FEAT_LABELS = 2 };
 
 /* Both schedules are CGS2 (classical Gram-Schmidt with one re-orthogonalisation,
  * FP64 accumulation) and give the same iterates in exact arithmetic.
@@ -205,6 +216,50 @@ int abba_solve(const abba_op *A, const abba_op *B, const void *b, void *x, int b
                int mode, int k, const abba_reg *reg, const abba_stop *stop,
                const abba_out *out, const abba_exec *exec,
                void *workspace, size_t ws_bytes, void *stream);
+
+/* ---- Learned lambda / stop index (an optional rule beside those of Sec. 3.1-3.2).
+ * Features (per slice and iteration k, from quantities the method produces
+ * regardless of lambda): the 32 largest singular values of H_k as
+ * log10(sigma_i/sigma_1), padded with -16, and the plain GMRES residuals
+ * (eq. (9)) of iterations k-31..k as log10(r_j/r_0), 0 before iteration 1;
+ * all scaled by 1/8.  Network: 64 -> 128 -> 128 -> 128 -> 2 with ReLU, FP32;
+ * parameters are one flat device array of ABBA_MLP_PARAMS floats:
+ * W1 [128][64], b1 [128], W2 [128][128], b2 [128], W3 [128][128], b3 [128],
+ * W4 [2][128], b4 [2].  Outputs: o0 = log10(lambda/sigma_1)/8, o1 = k_stop/K.
+ * In abba_solve with ABBA_REG_LEARNED the small solve first picks GCV's
+ * lambda (eq. (15)); the predicted lambda^ replaces it when
+ * GCV(lambda^) <= (1 + judge_delta) GCV(lambda_GCV).  ABBA_STOP_LEARNED stops
+ * at the first k >= K o1 (clamped to [1, K]), after the discrepancy principle
+ * when noise_norm is given.  All four calls are asynchronous on `stream`. */
+#define ABBA_MLP_FEATURES 64
+#define ABBA_MLP_PARAMS 41602
+#define ABBA_LABEL_GRID 64
+
+/* Y [n][2] = network(X [n][64]).  Bitwise the same as the inference inside
+ * abba_solve. */
+int abba_mlp_forward(const float *params, const float *X, int n, float *Y, void *stream);
+
+/* Mean squared error L = (1/n) sum_i |net(X[r_i]) - T[r_i]|^2 with r_i =
+ * idx[i] (device int32 [n], or NULL for r_i = i) and its gradient `grad`
+ * [ABBA_MLP_PARAMS] (device); `loss` is a device double or NULL.  X is
+ * [nrows][64], T [nrows][2]; rows r_i outside [0, nrows) count as absent.
+ * Allocates per-tile partial gradients stream-ordered; deterministic. */
+int abba_mlp_loss_grad(const float *params, const float *X, const float *T, int nrows, const int *idx, int n,
+                       float *grad, double *loss, void *stream);
+
+/* One Adam step (Kingma and Ba 2015, Algorithm 1, bias-corrected), step >= 1,
+ * on params with moment buffers m, v (device, ABBA_MLP_PARAMS each). */
+int abba_mlp_adam(float *params, const float *grad, float *m, float *v, int step, double lr, double beta1,
+                  double beta2, double eps, void *stream);
+
+/* Training targets from abba_solve's out.rre of `batch` runs of budget k:
+ * targets [batch][k][2] row j-1 = (log10(lambda*_j / sigma_1)/8, k* / k) with
+ * lambda*_j the grid minimiser of the RRE at iteration j (first index on
+ * ties) and k* the iteration of the smallest of those minima; rows past
+ * iters[s] (device, or NULL for k) are NaN.  k_star (device [batch]) may be
+ * NULL. */
+int abba_mlp_labels(const double *rre, int batch, int k, const int *iters, float *targets, int *k_star,
+                    void *stream);
 
 const char *abba_status_str(int status);
 const char *abba_last_error(void);

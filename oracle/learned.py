@@ -182,5 +182,5 @@ def judge(theta, f, sigma, uhat, uk1, delta):
     lam_gcv = ss.choose_gcv(sigma, uhat, uk1)
     lg = min(max(o0 / SCALE, LOG_LAM_MIN), LOG_LAM_MAX)
     lam_hat = s1 * 10.0 ** lg
-    ok = ss.gcv(lam_hat, sigma, uhat, uk1) <= (1.0 + delta) * ss.gcv(lam_gcv, sigma, uhat, uk1)
+    ok = s1 > 0.0 and ss.gcv(lam_hat, sigma, uhat, uk1) <= (1.0 + delta) * ss.gcv(lam_gcv, sigma, uhat, uk1)
     return (lam_hat if ok else lam_gcv), lam_hat, ok, o1

@@ -19,7 +19,7 @@ from dataclasses import dataclass
 __all__ = [
     "LIB_PATH", "lib", "AbbaError", "Geometry", "Operator", "project", "backproject", "solve",
     "workspace_bytes", "ST_KMAX", "ST_STOP_DP", "ST_STOP_RNS", "ST_BREAKDOWN", "ST_NONFINITE",
-    "ST_STOP_LEARNED",
+    "ST_STOP_LEARNED", "mlp_forward", "mlp_loss_grad", "mlp_adam", "mlp_labels", "MLP_PARAMS",
 ]
 
 LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libabba.so")
@@ -61,7 +61,8 @@ class _Stop(ctypes.Structure):
 
 class _Out(ctypes.Structure):
     _fields_ = [("iters", ctypes.c_void_p), ("status", ctypes.c_void_p), ("lam", ctypes.c_void_p),
-                ("resid", ctypes.c_void_p)]
+                ("resid", ctypes.c_void_p), ("features", ctypes.c_void_p), ("x_true", ctypes.c_void_p),
+                ("rre", ctypes.c_void_p)]
 
 
 class _Exec(ctypes.Structure):
@@ -94,6 +95,15 @@ def _load():
     L.abba_solve.argtypes = [vp, vp, vp, vp, i, i, i, ctypes.POINTER(_Reg), ctypes.POINTER(_Stop),
                              ctypes.POINTER(_Out), ctypes.POINTER(_Exec), vp, ctypes.c_size_t, vp]
     L.abba_solve.restype = i
+    L.abba_mlp_forward.argtypes = [vp, vp, i, vp, vp]
+    L.abba_mlp_forward.restype = i
+    L.abba_mlp_loss_grad.argtypes = [vp, vp, vp, i, vp, i, vp, vp, vp]
+    L.abba_mlp_loss_grad.restype = i
+    L.abba_mlp_adam.argtypes = [vp, vp, vp, vp, i, ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                                ctypes.c_double, vp]
+    L.abba_mlp_adam.restype = i
+    L.abba_mlp_labels.argtypes = [vp, i, i, vp, vp, vp, vp]
+    L.abba_mlp_labels.restype = i
     return L
 
 
@@ -110,6 +120,13 @@ abba_project = lib.abba_project
 abba_backproject = lib.abba_backproject
 abba_solve_workspace = lib.abba_solve_workspace
 abba_solve = lib.abba_solve
+abba_mlp_forward = lib.abba_mlp_forward
+abba_mlp_loss_grad = lib.abba_mlp_loss_grad
+abba_mlp_adam = lib.abba_mlp_adam
+abba_mlp_labels = lib.abba_mlp_labels
+
+MLP_FEATURES, MLP_PARAMS, LABEL_GRID = 64, 41602, 64
+FEAT_OUT, FEAT_LABELS = 1, 2
 
 
 def _check(rc, where):
@@ -266,8 +283,8 @@ def _structs(reg, lam, tau, noise_norm, mlp, judge_delta, stop, stop_tau, rns_ep
     return r, s, e
 
 
-def workspace_bytes(A: Operator, B: Operator, batch: int, mode: str, k: int, stop=None) -> int:
-    _, s, e = _structs("none", 0, 0, None, None, 0, stop, 1.01, 1e-3, 0, 1, 0, 0)
+def workspace_bytes(A: Operator, B: Operator, batch: int, mode: str, k: int, stop=None, labels=False) -> int:
+    _, s, e = _structs("none", 0, 0, None, None, 0, stop, 1.01, 1e-3, 0, 1, 0, FEAT_LABELS if labels else 0)
     nb = ctypes.c_size_t()
     _check(lib.abba_solve_workspace(A.handle, B.handle, batch, MODE_AB if mode == "AB" else MODE_BA, k,
                                     ctypes.byref(s), ctypes.byref(e), ctypes.byref(nb)), "abba_solve_workspace")
@@ -277,7 +294,7 @@ def workspace_bytes(A: Operator, B: Operator, batch: int, mode: str, k: int, sto
 def solve(A: Operator, B: Operator, b, mode: str = "AB", k: int = 30, reg: str = "gcv", lam: float = 0.0,
           tau: float = 1.01, noise_norm=None, stop=None, rns_eps: float = 1e-3, x0=None, use_graph=False,
           poll_every: int = 1, restart: int = 0, mlp=None, judge_delta: float = 0.05, history: bool = True,
-          workspace=None, features: int = 0, ortho: str = "dcgs2"):
+          workspace=None, features: bool = False, ortho: str = "dcgs2", x_true=None):
     """Hybrid AB-/BA-GMRES on a batch of slices; returns (x, info).
 
     ortho: "dcgs2" (CGS2 with the second pass delayed to the next step's
@@ -286,7 +303,10 @@ def solve(A: Operator, B: Operator, b, mode: str = "AB", k: int = 30, reg: str =
     b: device tensor [batch, *sino_shape] in A's sinogram dtype.  noise_norm:
     device float64 [batch] (||e|| per slice) for the discrepancy principle.
     info holds device tensors iters [batch], status [batch] and, with
-    history, lam [batch, k] and resid [batch, k+1].
+    history, lam [batch, k] and resid [batch, k+1].  features=True adds the
+    learned-rule features [batch, k, 64] (float32); x_true (device, image
+    dtype, AB mode) adds the RRE label grid rre [batch, k, 64].  mlp: device
+    float32 [MLP_PARAMS] for reg="learned".
     """
     import torch
     batch = _need(b, A.sino_dtype, A.m, "b")
@@ -298,8 +318,9 @@ def solve(A: Operator, B: Operator, b, mode: str = "AB", k: int = 30, reg: str =
     _need(x, A.img_dtype, A.n, "x0")
     if noise_norm is not None:
         noise_norm = noise_norm.to(device=dev, dtype=torch.float64).contiguous()
+    fbits = (FEAT_OUT if features else 0) | (FEAT_LABELS if x_true is not None else 0)
     r, s, e = _structs(reg, lam, tau, noise_norm, mlp, judge_delta, stop, tau, rns_eps, use_graph, poll_every,
-                       restart, features, ortho)
+                       restart, fbits, ortho)
     m = MODE_AB if mode == "AB" else MODE_BA
     iters = torch.zeros(batch, dtype=torch.int32, device=dev)
     status = torch.zeros(batch, dtype=torch.int32, device=dev)
@@ -309,6 +330,18 @@ def solve(A: Operator, B: Operator, b, mode: str = "AB", k: int = 30, reg: str =
     o.iters, o.status = iters.data_ptr(), status.data_ptr()
     o.lam = None if lamh is None else lamh.data_ptr()
     o.resid = None if resh is None else resh.data_ptr()
+    feats = torch.zeros((batch, k, MLP_FEATURES), dtype=torch.float32, device=dev) if features else None
+    o.features = None if feats is None else feats.data_ptr()
+    rre = None
+    if x_true is not None:
+        _need(x_true, A.img_dtype, A.n, "x_true")
+        if x_true.numel() != batch * A.n:
+            raise ValueError("x_true must hold one image per slice")
+        rre = torch.full((batch, k, LABEL_GRID), float("nan"), dtype=torch.float64, device=dev)
+        o.x_true = x_true.data_ptr()
+        o.rre = rre.data_ptr()
+    if mlp is not None:
+        _need(mlp, torch.float32, MLP_PARAMS, "mlp")
     nb = ctypes.c_size_t()
     _check(lib.abba_solve_workspace(A.handle, B.handle, batch, m, k, ctypes.byref(s), ctypes.byref(e),
                                     ctypes.byref(nb)), "abba_solve_workspace")
@@ -317,8 +350,85 @@ def solve(A: Operator, B: Operator, b, mode: str = "AB", k: int = 30, reg: str =
     _check(lib.abba_solve(A.handle, B.handle, _ptr(b), _ptr(x), batch, m, k, ctypes.byref(r), ctypes.byref(s),
                           ctypes.byref(o), ctypes.byref(e), _ptr(workspace), workspace.numel(), _stream_ptr()),
            "abba_solve")
-    info = dict(iters=iters, status=status, lam=lamh, resid=resh)
+    info = dict(iters=iters, status=status, lam=lamh, resid=resh, features=feats, rre=rre)
     return x, info
+
+
+def mlp_forward(params, X):
+    """Y [n, 2] = network(X [n, 64]) (float32 device tensors)."""
+    import torch
+    n = _need(X, torch.float32, MLP_FEATURES, "X")
+    _need(params, torch.float32, MLP_PARAMS, "params")
+    Y = torch.empty((n, 2), dtype=torch.float32, device=X.device)
+    _check(lib.abba_mlp_forward(_ptr(params), _ptr(X), n, _ptr(Y), _stream_ptr()), "abba_mlp_forward")
+    return Y
+
+
+def mlp_loss_grad(params, X, T, idx=None, grad=None, loss=None):
+    """(loss, grad) of the mean squared error over rows idx of (X, T) (all rows if None)."""
+    import torch
+    nrows = _need(X, torch.float32, MLP_FEATURES, "X")
+    if _need(T, torch.float32, 2, "T") != nrows:
+        raise ValueError("X and T need the same number of rows")
+    _need(params, torch.float32, MLP_PARAMS, "params")
+    n = nrows
+    if idx is not None:
+        n = _need(idx, torch.int32, 1, "idx")
+    grad = torch.empty(MLP_PARAMS, dtype=torch.float32, device=X.device) if grad is None else grad
+    loss = torch.empty(1, dtype=torch.float64, device=X.device) if loss is None else loss
+    _check(lib.abba_mlp_loss_grad(_ptr(params), _ptr(X), _ptr(T), nrows, None if idx is None else _ptr(idx), n,
+                                  _ptr(grad), _ptr(loss), _stream_ptr()), "abba_mlp_loss_grad")
+    return loss, grad
+
+
+def mlp_adam(params, grad, m, v, step, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8):
+    """One Adam step in place on params (m, v: moment buffers)."""
+    _check(lib.abba_mlp_adam(_ptr(params), _ptr(grad), _ptr(m), _ptr(v), int(step), float(lr), float(beta1),
+                             float(beta2), float(eps), _stream_ptr()), "abba_mlp_adam")
+
+
+def mlp_labels(rre, iters=None):
+    """Training targets [batch, k, 2] and k* [batch] from solve(..., x_true=...)'s rre."""
+    import torch
+    batch, k = rre.shape[0], rre.shape[1]
+    _need(rre, torch.float64, k * LABEL_GRID, "rre")
+    tgt = torch.empty((batch, k, 2), dtype=torch.float32, device=rre.device)
+    ks = torch.empty(batch, dtype=torch.int32, device=rre.device)
+    if iters is not None:
+        _need(iters, torch.int32, batch, "iters")
+    _check(lib.abba_mlp_labels(_ptr(rre), batch, k, None if iters is None else _ptr(iters), _ptr(tgt), _ptr(ks),
+                               _stream_ptr()), "abba_mlp_labels")
+    return tgt, ks
+
+
+def mlp_train(params, X, T, epochs, batch=4096, lr=1e-3, seed=0, log=None):
+    """Adam on the mean squared error over minibatches of (X, T), in place on
+    params; the sample order of each epoch is a seeded permutation drawn on
+    the host.  Returns the mean loss of each epoch."""
+    import numpy as np
+    import torch
+    nrows = _need(X, torch.float32, MLP_FEATURES, "X")
+    m = torch.zeros(MLP_PARAMS, dtype=torch.float32, device=X.device)
+    v = torch.zeros_like(m)
+    grad = torch.empty_like(m)
+    loss = torch.empty(1, dtype=torch.float64, device=X.device)
+    rng = np.random.default_rng(seed)
+    step, hist = 0, []
+    for ep in range(epochs):
+        perm = torch.as_tensor(rng.permutation(nrows).astype(np.int32), device=X.device)
+        tot = torch.zeros(1, dtype=torch.float64, device=X.device)
+        nb = 0
+        for i0 in range(0, nrows, batch):
+            idx = perm[i0:i0 + batch]
+            mlp_loss_grad(params, X, T, idx=idx, grad=grad, loss=loss)
+            step += 1
+            mlp_adam(params, grad, m, v, step, lr)
+            tot += loss
+            nb += 1
+        hist.append(float(tot) / nb)
+        if log:
+            log(f"epoch {ep}: loss {hist[-1]:.5f}")
+    return hist
 
 
 def status_names(code: int):

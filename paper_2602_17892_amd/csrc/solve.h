@@ -45,6 +45,8 @@ struct SolveDims {
     int wslots;     // basis vectors per slice (K + 2: the delayed step also holds M v)
     int pslots;     // kept operator outputs per slice (K + 1)
     int ortho;      // ABBA_ORTHO_*
+    int feat_out;   // write the learned-rule features to out.features
+    int labels;     // write RRE label grids to out.rre (AB mode)
 };
 
 // Workspace carve-up (device pointers).
@@ -71,7 +73,11 @@ struct SolveWS {
     double *sc;     // [S][SC_COUNT]
     double *lamh;   // [S][K]
     double *rhoh;   // [S][K+1]
-    double *feat;   // [S][64] learned-model features
+    float *feat;    // [S][64] learned-rule features of the current iteration
+    float *pred;    // [S][2]  network outputs
+    double *gres;   // [S][K+1] plain GMRES residual history (r_0 = beta)
+    double *gram;   // [S][K][K+1] labels: Gram matrix of P' and P'^T (x_true - x_0)
+    double *enorm;  // [S][2]  labels: ||x_true - x_0||^2, ||x_true||^2
     int *active;    // [S]
     int *flags;     // [S]
     int *kdev;      // [1] current iteration (1-based)

@@ -43,9 +43,9 @@ int launch_stop(const SolveDims &d, const SolveWS &ws, int stop_kind, double tau
                 const double *noise, int *iters, int *status, hipStream_t st);
 int launch_finish_resid(const SolveDims &d, const SolveWS &ws, int nblk, hipStream_t st);
 int smallsolve_prepare();
-int learned_prepare(const SolveDims &d, const SolveWS &ws, const abba_reg *reg, hipStream_t st);
-int learned_features(const SolveDims &d, const SolveWS &ws, hipStream_t st);
-int learned_judge(const SolveDims &d, const SolveWS &ws, const abba_reg *reg, hipStream_t st);
+int learned_prepare(const SolveDims &d, const SolveWS &ws, const void *x0, const abba_out *out, hipStream_t st);
+int learned_step(const SolveDims &d, const SolveWS &ws, const abba_reg *reg, int learned, const void *x0,
+                 const abba_out *out, hipStream_t st);
 
 static inline int64_t round_up(int64_t v, int64_t a) { return (v + a - 1) / a * a; }
 
@@ -92,7 +92,11 @@ size_t solve_workspace_bytes(const SolveDims &d, SolveWS *ws, void *base, size_t
     w.sc = (double *)take(S * SC_COUNT * 8);
     w.lamh = (double *)take(S * K * 8);
     w.rhoh = (double *)take(S * (K + 1) * 8);
-    w.feat = (double *)take(S * 64 * 8);
+    w.feat = (float *)take(S * 64 * 4);
+    w.pred = (float *)take(S * 2 * 4);
+    w.gres = (double *)take(S * (K + 1) * 8);
+    w.gram = d.labels ? (double *)take(S * K * (K + 1) * 8) : nullptr;
+    w.enorm = d.labels ? (double *)take(S * 2 * 8) : nullptr;
     w.active = (int *)take(S * 4);
     w.flags = (int *)take(S * 4);
     w.kdev = (int *)take(4);
@@ -186,6 +190,8 @@ struct IterCfg {
     int *iters, *status;
     int learned;
     const abba_reg *reg;
+    const abba_out *out;
+    const void *x0;
 };
 
 // The operator step of iteration k: q = M (input vector) into W, keeping
@@ -217,9 +223,8 @@ static int one_iteration(const SolveDims &d, const SolveWS &ws, const IterCfg &c
     if ((rc = apply_M(d, ws, c, L))) return rc;
     if ((rc = delayed ? dcgs2_step(d, ws, ws.kdev, st) : cgs2_step(d, ws, st))) return rc;
     if ((rc = launch_smallsolve(d, ws, c.rule, c.lam_fixed, c.tau, c.noise_reg, st))) return rc;
-    if (c.learned) {
-        if ((rc = learned_features(d, ws, st))) return rc;
-        if ((rc = learned_judge(d, ws, c.reg, st))) return rc;
+    if (c.learned || d.feat_out || d.labels) {
+        if ((rc = learned_step(d, ws, c.reg, c.learned, c.x0, c.out, st))) return rc;
     }
     if (d.mode == ABBA_MODE_BA && d.keepZ) {
         // rho_k = ||(b - A x_0) - Z_k y_k||; with the delayed schedule Z holds
@@ -250,7 +255,6 @@ using namespace abba;
 
 extern "C" int abba_solve_workspace(const abba_op *A, const abba_op *B, int batch, int mode, int k,
                                     const abba_stop *stop, const abba_exec *exec, size_t *bytes) {
-    (void)exec;
     if (!bytes) {
         set_error("bytes is NULL");
         return ABBA_ERR_ARG;
@@ -261,6 +265,7 @@ extern "C" int abba_solve_workspace(const abba_op *A, const abba_op *B, int batc
     dummy.resid = (double *)1;   // size for the worst case (Z kept in BA mode)
     int rc = make_dims(A, B, batch, mode, k, stop, &dummy, &d);
     if (rc) return rc;
+    d.labels = exec && (exec->features & ABBA_FEAT_LABELS) && mode == ABBA_MODE_AB;
     *bytes = solve_workspace_bytes(d, nullptr, nullptr, op_scratch_bytes(A, B, batch));
     return ABBA_OK;
 }
@@ -327,6 +332,26 @@ extern "C" int abba_solve(const abba_op *A, const abba_op *B, const void *b, voi
         set_error("restarted cycles are not implemented");
         return ABBA_ERR_UNSUPPORTED;
     }
+    if (ex.features & ~(ABBA_FEAT_OUT | ABBA_FEAT_LABELS)) {
+        set_error("unknown feature bits %d", ex.features);
+        return ABBA_ERR_ARG;
+    }
+    d.feat_out = (ex.features & ABBA_FEAT_OUT) != 0;
+    d.labels = (ex.features & ABBA_FEAT_LABELS) != 0;
+    if (d.feat_out && !out->features) {
+        set_error("exec.features asks for features but out.features is NULL");
+        return ABBA_ERR_ARG;
+    }
+    if (d.labels) {
+        if (mode != ABBA_MODE_AB) {
+            set_error("RRE labels are formed in AB mode only");
+            return ABBA_ERR_UNSUPPORTED;
+        }
+        if (!out->x_true || !out->rre) {
+            set_error("RRE labels need out.x_true and out.rre");
+            return ABBA_ERR_ARG;
+        }
+    }
     SolveWS ws;
     const size_t need = solve_workspace_bytes(d, &ws, workspace, op_scratch_bytes(A, B, batch));
     if (ws_bytes < need) {
@@ -379,7 +404,9 @@ extern "C" int abba_solve(const abba_op *A, const abba_op *B, const void *b, voi
     cfg.status = out->status;
     cfg.learned = rule == ABBA_REG_LEARNED;
     cfg.reg = reg;
-    if (cfg.learned && (rc = learned_prepare(d, ws, reg, st))) return rc;
+    cfg.out = out;
+    cfg.x0 = x;
+    if ((cfg.learned || d.feat_out || d.labels) && (rc = learned_prepare(d, ws, x, out, st))) return rc;
     if (d.ortho == ABBA_ORTHO_DELAYED) {
         // step 0 of the delayed schedule: M w_1 and its first pass, giving
         // the once-orthogonalised second vector (no projected problem yet)

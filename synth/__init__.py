@@ -217,3 +217,21 @@ def default_ndet(n: int) -> int:
     """Detector bins covering the image diagonal: D = ceil(N*sqrt(2)) (odd-rounded)."""
     d = int(math.ceil(n * math.sqrt(2.0)))
     return d
+
+
+# --------------------------------------------------------------------------
+# Initial weights of the learned-rule network (64 -> 128 -> 128 -> 128 -> 2)
+# --------------------------------------------------------------------------
+
+MLP_LAYERS = [(128, 64), (128, 128), (128, 128), (2, 128)]
+
+
+def mlp_init(seed: int) -> np.ndarray:
+    """Flat float32 parameters [W1, b1, W2, b2, W3, b3, W4, b4]: He-normal
+    weights (standard deviation sqrt(2 / fan_in)), zero biases."""
+    r = np.random.default_rng([7, int(seed)])
+    parts = []
+    for o, i in MLP_LAYERS:
+        parts.append(r.standard_normal(o * i) * math.sqrt(2.0 / i))
+        parts.append(np.zeros(o))
+    return np.concatenate(parts).astype(np.float32)

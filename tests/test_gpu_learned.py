@@ -1,0 +1,227 @@
+"""GPU parity of the learned lambda / stop-index rule against the FP64 oracle
+(oracle.learned): network forward, loss gradient, Adam, the features and RRE
+label grids written by the solver, the judged solve, and a small end-to-end
+training run.  Gates: 1e-5 relative for FP32 network outputs, 1e-4 for FP32
+gradients, 1e-6 absolute for features, 1e-9 relative for FP64 label grids.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import learned as L
+from oracle import solver as osv
+from oracle.geometry import Par2D
+from oracle.operators import Par2DOps
+
+pytestmark = [pytest.mark.gpu, pytest.mark.usefixtures("oracle_lib")]
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def pk():
+    import paper_2602_17892_amd as pk
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    return pk
+
+
+def rel(a, b):
+    a = np.asarray(a, dtype=np.float64).ravel()
+    b = np.asarray(b, dtype=np.float64).ravel()
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+def cuda(a, dtype=torch.float32):
+    return torch.as_tensor(np.ascontiguousarray(a)).to(device="cuda", dtype=dtype)
+
+
+def test_mlp_forward(pk):
+    theta = synth.mlp_init(1)
+    X = np.random.default_rng(2).uniform(-2, 0.5, (300, 64)).astype(np.float32)   # 5 tiles, ragged
+    Y = pk.mlp_forward(cuda(theta), cuda(X)).double().cpu().numpy()
+    Yo, _ = L.forward(theta.astype(np.float64), X.astype(np.float64))
+    e = rel(Y, Yo)
+    print(f"mlp forward: {e:.2e}")
+    assert e <= 1e-5
+    assert pk.mlp_forward(cuda(theta), cuda(X[:0].reshape(0, 64))).shape == (0, 2)
+
+
+def test_mlp_loss_grad(pk):
+    theta = synth.mlp_init(3)
+    r = np.random.default_rng(4)
+    X = r.uniform(-2, 0.5, (300, 64)).astype(np.float32)
+    T = r.uniform(-1, 1, (300, 2)).astype(np.float32)
+    idx = r.permutation(300)[:150].astype(np.int32)
+    t, Xd, Td, idd = cuda(theta), cuda(X), cuda(T), cuda(idx, torch.int32)
+    loss, grad = pk.mlp_loss_grad(t, Xd, Td, idx=idd)
+    lo, go = L.loss_grad(theta.astype(np.float64), X[idx].astype(np.float64), T[idx].astype(np.float64))
+    el, eg = abs(float(loss) - lo) / lo, rel(grad.cpu().numpy(), go)
+    # per layer as well: every block of the flat gradient
+    off, worst = 0, 0.0
+    for o, i in L.LAYERS:
+        for sz in (o * i, o):
+            worst = max(worst, rel(grad.cpu().numpy()[off:off + sz], go[off:off + sz]))
+            off += sz
+    print(f"mlp loss {el:.2e}, grad {eg:.2e} (worst block {worst:.2e})")
+    assert el <= 1e-5 and eg <= 1e-4 and worst <= 1e-4
+    # deterministic: the same call again gives the same bits
+    loss2, grad2 = pk.mlp_loss_grad(t, Xd, Td, idx=idd)
+    assert torch.equal(grad, grad2) and torch.equal(loss, loss2)
+    # all rows (no index), one tile exactly
+    loss3, grad3 = pk.mlp_loss_grad(t, Xd[:64].contiguous(), Td[:64].contiguous())
+    lo3, go3 = L.loss_grad(theta.astype(np.float64), X[:64].astype(np.float64), T[:64].astype(np.float64))
+    assert abs(float(loss3) - lo3) / lo3 <= 1e-5 and rel(grad3.cpu().numpy(), go3) <= 1e-4
+
+
+def test_mlp_adam(pk):
+    r = np.random.default_rng(5)
+    theta = synth.mlp_init(6)
+    th = cuda(theta)
+    m = torch.zeros_like(th)
+    v = torch.zeros_like(th)
+    to, mo, vo = theta.astype(np.float64), np.zeros(theta.size), np.zeros(theta.size)
+    for step in range(1, 4):
+        g = r.standard_normal(theta.size).astype(np.float32) * 0.1
+        pk.mlp_adam(th, cuda(g), m, v, step, lr=1e-2)
+        to, mo, vo = L.adam(to, g.astype(np.float64), mo, vo, step, 1e-2)
+    d = th.double().cpu().numpy() - theta
+    e = rel(d, to - theta)
+    print(f"adam: update {e:.2e}")
+    assert e <= 1e-5
+
+
+def problem(n=32, na=45, nd=47, idx=3, eta=0.01):
+    og = Par2DOps(Par2D(n, n, na, nd))
+    x, _ = synth.phantom2d(0, idx, n)
+    bt = og.A(x).ravel()
+    b, en = synth.add_relative_noise(bt, synth.noise_direction(0, idx, bt.size), eta)
+    return og, x, b, en
+
+
+def ops(pk, dt, n=32, na=45, nd=47):
+    g = pk.Geometry(n, n, na, nd)
+    return pk.Operator("joseph", g, dt, dt), pk.Operator("pixel", g, dt, dt)
+
+
+@pytest.mark.parametrize("dt", ["f64", "f32"])
+def test_solver_features(pk, dt):
+    og, x, b, _ = problem()
+    A, B = ops(pk, dt)
+    tdt = torch.float64 if dt == "f64" else torch.float32
+    bd = cuda(b.reshape(1, 45, 47), tdt)
+    K = 12
+    _, info = pk.solve(A, B, bd, mode="AB", k=K, reg="gcv", features=True)
+    F = info["features"][0].cpu().numpy()
+    o = osv.hybrid_gmres(og.A, og.B, bd.double().cpu().numpy().ravel(), mode="AB", K=K, rule="gcv",
+                         keep_small=True)
+    gres = [o.beta]
+    worst = 0.0
+    for k, (sig, _, uk1) in enumerate(o.small, start=1):
+        gres.append(uk1)
+        f = L.features(sig, gres)
+        worst = max(worst, float(np.max(np.abs(F[k - 1] - f))))
+    print(f"features {dt}: max abs {worst:.2e}")
+    assert worst <= 1e-6
+
+
+@pytest.mark.parametrize("ortho", ["dcgs2", "cgs2"])
+def test_solver_label_grid(pk, ortho):
+    og, x, b, _ = problem(idx=4)
+    A, B = ops(pk, "f64")
+    K = 8
+    _, info = pk.solve(A, B, cuda(b.reshape(1, 45, 47), torch.float64), mode="AB", k=K, reg="gcv",
+                       x_true=cuda(x.reshape(1, 32, 32), torch.float64), ortho=ortho)
+    R = info["rre"][0].cpu().numpy()
+    o = osv.hybrid_gmres(og.A, og.B, b, mode="AB", K=K, rule="gcv", keep_basis=True)
+    Ro = L.rre_grid(og.B, o.H, o.beta, o.W, np.zeros(x.size), x.ravel())
+    e = float(np.max(np.abs(R - Ro) / Ro))
+    print(f"label grid ({ortho}): max rel {e:.2e}")
+    assert e <= 1e-9
+    tg, ks = pk.mlp_labels(info["rre"], info["iters"])
+    To, kso = L.labels(Ro, K)
+    assert int(ks[0]) == kso
+    assert np.allclose(tg[0].cpu().numpy(), To, rtol=0, atol=1e-7)
+
+
+@pytest.mark.parametrize("mode", ["AB", "BA"])
+def test_learned_solve(pk, mode):
+    og, x, b, en = problem(idx=5)
+    A, B = ops(pk, "f64")
+    theta = synth.mlp_init(8)
+    (W1, b1), _, _, (W4, b4) = L.unpack(theta)
+    W4 *= 0.02
+    W4[1, :] = 0.0
+    b4[:] = [-0.3, 0.55]          # stop at k = ceil(0.55 K) = 6 for K = 10
+    K = 10
+    bd = cuda(b.reshape(1, 45, 47), torch.float64)
+    xg, info = pk.solve(A, B, bd, mode=mode, k=K, reg="learned", stop="learned", mlp=cuda(theta),
+                        judge_delta=0.05)
+    o = osv.hybrid_gmres(og.A, og.B, b, mode=mode, K=K, rule="learned", stop="learned", mlp=theta.astype(np.float64),
+                         judge_delta=0.05)
+    lam_g = info["lam"][0].cpu().numpy()[:o.iters]
+    acc = [abs(lg / lo - 1) < 1e-3 for lg, lo in zip(lam_g, o.lam)]
+    ex = rel(xg.cpu().numpy(), o.x)
+    print(f"learned {mode}: iters {int(info['iters'][0])} / oracle {o.iters}, x {ex:.2e}, "
+          f"lam rel max {max(abs(lg / lo - 1) for lg, lo in zip(lam_g, o.lam)):.2e}")
+    assert int(info["iters"][0]) == o.iters == 6
+    assert int(info["status"][0]) & pk.ST_STOP_LEARNED
+    assert all(acc) and ex <= 1e-5
+
+
+def test_learned_training_end_to_end(pk):
+    # training data from the method itself: 48 runs at 32^2 with labels from
+    # the true images, then Adam on the network; evaluation on 8 fresh slices
+    n, na, nd, K = 32, 45, 47, 20
+    A, B = ops(pk, "f32")
+    S = 48
+    xs, bs, ens = [], [], []
+    for s in range(S):
+        og_x, _ = synth.phantom2d(5, s, n)
+        xs.append(og_x)
+    xt = cuda(np.stack(xs))
+    bt = pk.project(A, xt).double()
+    eta = np.array([synth.noise_level(5, s, 1e-3, 5e-2) for s in range(S)])
+    for s in range(S):
+        g = cuda(synth.noise_direction(5, s, na * nd).reshape(na, nd), torch.float64)
+        nb = torch.linalg.vector_norm(bt[s])
+        bs.append(bt[s] + eta[s] * nb / torch.linalg.vector_norm(g) * g)
+        ens.append(float(eta[s] * nb))
+    b = torch.stack(bs).to(torch.float32).contiguous()
+    _, info = pk.solve(A, B, b, mode="AB", k=K, reg="gcv", features=True, x_true=xt)
+    tg, ks = pk.mlp_labels(info["rre"], info["iters"])
+    X = info["features"].reshape(-1, 64).contiguous()
+    T = tg.reshape(-1, 2).contiguous()
+    ok = torch.isfinite(T).all(dim=1)
+    X, T = X[ok].contiguous(), T[ok].contiguous()
+    theta = cuda(synth.mlp_init(9))
+    l0, _ = pk.mlp_loss_grad(theta, X, T)
+    hist = pk.mlp_train(theta, X, T, epochs=60, batch=256, lr=2e-3, seed=1)
+    l1, _ = pk.mlp_loss_grad(theta, X, T)
+    print(f"training: {X.shape[0]} samples, loss {float(l0):.4f} -> {float(l1):.4f}; k* mean "
+          f"{ks.float().mean():.1f}")
+    assert float(l1) < 0.25 * float(l0) and hist[-1] < hist[0]
+    # the trained rule against GCV + DP on fresh slices
+    E = 8
+    xe = cuda(np.stack([synth.phantom2d(6, s, n)[0] for s in range(E)]))
+    be = pk.project(A, xe).double()
+    ene = []
+    rows = []
+    for s in range(E):
+        g = cuda(synth.noise_direction(6, s, na * nd).reshape(na, nd), torch.float64)
+        nb = torch.linalg.vector_norm(be[s])
+        rows.append(be[s] + 0.01 * nb / torch.linalg.vector_norm(g) * g)
+        ene.append(float(0.01 * nb))
+    be = torch.stack(rows).to(torch.float32).contiguous()
+    en = torch.tensor(ene, dtype=torch.float64, device="cuda")
+    xg, ig = pk.solve(A, B, be, mode="AB", k=K, reg="gcv", stop="dp", noise_norm=en)
+    xl, il = pk.solve(A, B, be, mode="AB", k=K, reg="learned", stop="learned", noise_norm=en, mlp=theta)
+
+    def rre(xr):
+        return (torch.linalg.vector_norm((xr - xe).reshape(E, -1).double(), dim=1)
+                / torch.linalg.vector_norm(xe.reshape(E, -1).double(), dim=1)).cpu().numpy()
+    rg, rl = rre(xg), rre(xl)
+    print(f"GCV+DP: iters {ig['iters'].float().mean():.1f}, median RRE {np.median(rg):.4f}; "
+          f"learned: iters {il['iters'].float().mean():.1f}, median RRE {np.median(rl):.4f}")
+    assert np.all(np.isfinite(rl)) and int(il["iters"].min()) >= 1
