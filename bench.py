@@ -70,8 +70,13 @@ def parse():
     p.add_argument("--roofline-reps", type=int, default=10)
     p.add_argument("--projectors-only", action="store_true",
                    help="only the projector launches (random images) and a copy of known size, for counter runs")
-    p.add_argument("--workload", choices=["slices", "cone"], default="slices",
-                   help="slices: the batched 2D workload (default); cone: the 3D cone-beam volume solve")
+    p.add_argument("--workload", choices=["slices", "cone", "learned"], default="slices",
+                   help="slices: the batched 2D workload (default); cone: the 3D cone-beam volume solve; "
+                        "learned: train the lambda/stop network on method-generated runs, then compare it "
+                        "with GCV + DP")
+    p.add_argument("--train-runs", type=int, default=4096)
+    p.add_argument("--eval-slices", type=int, default=1024)
+    p.add_argument("--epochs", type=int, default=20)
     p.add_argument("--quiet", action="store_true")
     return p.parse_args()
 
@@ -81,25 +86,25 @@ def log(args, *a):
         print(*a, file=sys.stderr, flush=True)
 
 
-def make_inputs(args, pk, A, torch):
-    """Seeded phantoms (synthetic, on the GPU), b = A x + e with ||e|| = eta ||A x||."""
+def synth_batch(pk, A, torch, cfg_id, first, count, n, lo, hi):
+    """Seeded phantoms (synthetic, on the GPU) idx = first..first+count-1,
+    b = A x + e with ||e|| = eta ||A x||, eta log-uniform in [lo, hi]."""
     import numpy as np
 
     import synth
-    S, n = args.slices, args.n
     dev = torch.device("cuda")
-    x = torch.empty((S, n, n), dtype=torch.float32, device=dev)
-    eta = np.empty(S)
-    for s in range(S):
-        img, _ = synth.phantom2d(2, s, n, device=dev)
+    x = torch.empty((count, n, n), dtype=torch.float32, device=dev)
+    eta = np.empty(count)
+    for s in range(count):
+        img, _ = synth.phantom2d(cfg_id, first + s, n, device=dev)
         x[s] = img.to(torch.float32)
-        eta[s] = synth.noise_level(2, s, 1e-3, 5e-2)
+        eta[s] = synth.noise_level(cfg_id, first + s, lo, hi)
     bt = pk.project(A, x)
     b = torch.empty_like(bt)
-    en = np.empty(S)
+    en = np.empty(count)
     m = bt[0].numel()
-    for s in range(S):
-        g = torch.as_tensor(synth.noise_direction(2, s, m), device=dev, dtype=torch.float64)
+    for s in range(count):
+        g = torch.as_tensor(synth.noise_direction(cfg_id, first + s, m), device=dev, dtype=torch.float64)
         btd = bt[s].double().reshape(-1)
         nb = float(torch.linalg.vector_norm(btd))
         e = (eta[s] * nb / float(torch.linalg.vector_norm(g))) * g
@@ -107,6 +112,10 @@ def make_inputs(args, pk, A, torch):
         en[s] = eta[s] * nb
     torch.cuda.synchronize()
     return x, b, torch.tensor(en, dtype=torch.float64, device=dev), eta
+
+
+def make_inputs(args, pk, A, torch):
+    return synth_batch(pk, A, torch, 2, 0, args.slices, args.n, 1e-3, 5e-2)
 
 
 def time_apply(fn, torch, reps=10):
@@ -379,6 +388,111 @@ def cone_workload(args):
     print(json.dumps(out), flush=True)
 
 
+def learned_workload(args):
+    """Training: runs of hybrid AB-GMRES (K = 100, GCV) on 256^2 random-ellipse
+    slices, 360 angles x 363 bins, noise log-uniform in [0.1%, 5%], with the
+    features and the RRE label grids of every iteration; Adam on the network.
+    Evaluation: fresh 512^2 slices, 720 x 725, same noise range; GCV + DP
+    against the learned lambda and stop (with DP first), batches of 256."""
+    import numpy as np
+    import torch
+
+    import paper_2602_17892_amd as pk
+    import synth
+    torch.cuda.set_device(0)
+    K, SB = args.kmax, 256
+    gt = pk.Geometry(256, 256, 360, 363)
+    At, Bt = pk.Operator("joseph", gt, "f32", "f32"), pk.Operator("pixel", gt, "f32", "f32")
+    ws = torch.empty(pk.workspace_bytes(At, Bt, SB, "AB", K, labels=True), dtype=torch.uint8, device="cuda")
+    Xs, Ts, kst = [], [], []
+    t0 = time.perf_counter()
+    for first in range(0, args.train_runs, SB):
+        cnt = min(SB, args.train_runs - first)
+        x, b, _, _ = synth_batch(pk, At, torch, 5, first, cnt, 256, 1e-3, 5e-2)
+        _, info = pk.solve(At, Bt, b, mode="AB", k=K, reg="gcv", features=True, x_true=x, workspace=ws,
+                           history=False)
+        tg, ks = pk.mlp_labels(info["rre"], info["iters"])
+        ok = torch.isfinite(tg.reshape(-1, 2)).all(dim=1)
+        Xs.append(info["features"].reshape(-1, 64)[ok])
+        Ts.append(tg.reshape(-1, 2)[ok])
+        kst.append(ks)
+        del x, b, info
+    torch.cuda.synchronize()
+    t_gen = time.perf_counter() - t0
+    del ws
+    X = torch.cat(Xs).contiguous()
+    T = torch.cat(Ts).contiguous()
+    kst = torch.cat(kst).cpu().numpy()
+    log(args, f"training data: {args.train_runs} runs -> {X.shape[0]} samples in {t_gen:.1f}s, "
+              f"k* mean {kst.mean():.1f} [{kst.min()}, {kst.max()}]")
+    theta = torch.as_tensor(synth.mlp_init(0), device="cuda")
+    l0, _ = pk.mlp_loss_grad(theta, X, T)
+    t0 = time.perf_counter()
+    hist = pk.mlp_train(theta, X, T, epochs=args.epochs, batch=4096, lr=1e-3, seed=0,
+                        log=(lambda m: log(args, m)) if not args.quiet else None)
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    log(args, f"training: loss {float(l0):.4f} -> {hist[-1]:.4f} in {t_train:.1f}s")
+
+    ge = pk.Geometry(512, 512, 720, 725)
+    A, B = pk.Operator("joseph", ge, "f32", "f32"), pk.Operator("pixel", ge, "f32", "f32")
+    ws = torch.empty(pk.workspace_bytes(A, B, SB, "AB", K, stop="dp"), dtype=torch.uint8, device="cuda")
+    res = {"gcv": dict(t=0.0, iters=[], rre=[]), "learned": dict(t=0.0, iters=[], rre=[])}
+    for first in range(0, args.eval_slices, SB):
+        cnt = min(SB, args.eval_slices - first)
+        x, b, en, _ = synth_batch(pk, A, torch, 6, first, cnt, 512, 1e-3, 5e-2)
+        for name in ("gcv", "learned"):
+            kw = dict(reg="gcv", stop="dp") if name == "gcv" else dict(reg="learned", stop="learned", mlp=theta,
+                                                                      judge_delta=0.05)
+            pk.solve(A, B, b[:1].contiguous(), mode="AB", k=2, noise_norm=en[:1], history=False, **kw)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            xr, info = pk.solve(A, B, b, mode="AB", k=K, tau=1.01, noise_norm=en, use_graph=True,
+                                poll_every=args.poll, workspace=ws, history=False, **kw)
+            torch.cuda.synchronize()
+            res[name]["t"] += time.perf_counter() - t0
+            res[name]["iters"].append(info["iters"].cpu().numpy())
+            res[name]["rre"].append((torch.linalg.vector_norm((xr - x).reshape(cnt, -1).double(), dim=1)
+                                     / torch.linalg.vector_norm(x.reshape(cnt, -1).double(), dim=1)).cpu().numpy())
+        del x, b, en
+    for r in res.values():
+        r["iters"] = np.concatenate(r["iters"])
+        r["rre"] = np.concatenate(r["rre"])
+    E = args.eval_slices
+    ratio = res["learned"]["rre"] / res["gcv"]["rre"]
+    for name, r in res.items():
+        log(args, f"{name}: {E / r['t']:.2f} slices/s, iters mean {r['iters'].mean():.1f}, "
+                  f"median RRE {np.median(r['rre']):.4f}")
+    log(args, f"learned RRE <= 1.02 x GCV+DP RRE on {np.mean(ratio <= 1.02) * 100:.1f}% of slices")
+    out = {
+        "metric": "reconstructed slices/sec with the learned lambda and stop index vs GCV + DP",
+        "value": round(E / res["learned"]["t"], 3),
+        "unit": "slices/s",
+        "n_gpus": 1,
+        "steps": 1,
+        "warmup": 0,
+        "ms_per_step": round(res["learned"]["t"] * 1e3, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32 projectors+basis+network, f64 reductions and small solves",
+        "data": "synthetic: seeded random-ellipse phantoms; training labels from the true images",
+        "config": {"workload": f"train on {args.train_runs} runs at 256^2 (360 x 363, K {K}), evaluate on "
+                               f"{E} slices at 512^2 (720 x 725), eta log-uniform [0.1%,5%]"},
+        "gcv_dp": {"slices_per_s": round(E / res["gcv"]["t"], 3), "iters_mean": float(res["gcv"]["iters"].mean()),
+                   "rre_median": float(np.median(res["gcv"]["rre"]))},
+        "learned": {"slices_per_s": round(E / res["learned"]["t"], 3),
+                    "iters_mean": float(res["learned"]["iters"].mean()),
+                    "rre_median": float(np.median(res["learned"]["rre"])),
+                    "frac_rre_within_2pct_of_gcv": float(np.mean(ratio <= 1.02)),
+                    "rre_ratio_median": float(np.median(ratio))},
+        "training": {"runs": args.train_runs, "samples": int(X.shape[0]), "epochs": args.epochs,
+                     "loss_start": float(l0), "loss_end": hist[-1], "data_s": round(t_gen, 2),
+                     "train_s": round(t_train, 2), "k_star_mean": float(kst.mean())},
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -396,6 +510,9 @@ def main():
         return
     if args.workload == "cone":
         cone_workload(args)
+        return
+    if args.workload == "learned":
+        learned_workload(args)
         return
     torch.cuda.set_device(0)
     S, K = args.slices, args.kmax

@@ -48,11 +48,29 @@ def test_mlp_forward(pk):
     assert pk.mlp_forward(cuda(theta), cuda(X[:0].reshape(0, 64))).shape == (0, 2)
 
 
+def relu_margins(theta, X):
+    """Per sample: the smallest |pre-activation| of the hidden layers relative
+    to that layer's RMS, in FP64.  A ReLU whose input is within FP32 rounding
+    of zero may take the other branch on the GPU, which changes the gradient
+    by a whole term; such samples are left out of the gradient comparisons
+    (the decision itself has no preferred precision)."""
+    a = np.asarray(X, np.float64)
+    out = []
+    for W, b in L.unpack(np.asarray(theta, np.float64))[:3]:
+        z = a @ W.T + b
+        out.append(np.min(np.abs(z) / np.sqrt(np.mean(z * z)), axis=1))
+        a = np.maximum(z, 0.0)
+    return np.min(np.stack(out), axis=0)
+
+
 def test_mlp_loss_grad(pk):
     theta = synth.mlp_init(3)
     r = np.random.default_rng(4)
-    X = r.uniform(-2, 0.5, (300, 64)).astype(np.float32)
-    T = r.uniform(-1, 1, (300, 2)).astype(np.float32)
+    X = r.uniform(-2, 0.5, (400, 64)).astype(np.float32)
+    T = r.uniform(-1, 1, (400, 2)).astype(np.float32)
+    safe = np.flatnonzero(relu_margins(theta, X) >= 1e-4)
+    X, T = X[safe[:300]], T[safe[:300]]
+    assert X.shape[0] == 300
     idx = r.permutation(300)[:150].astype(np.int32)
     t, Xd, Td, idd = cuda(theta), cuda(X), cuda(T), cuda(idx, torch.int32)
     loss, grad = pk.mlp_loss_grad(t, Xd, Td, idx=idd)
@@ -114,16 +132,32 @@ def test_solver_features(pk, dt):
     K = 12
     _, info = pk.solve(A, B, bd, mode="AB", k=K, reg="gcv", features=True)
     F = info["features"][0].cpu().numpy()
-    o = osv.hybrid_gmres(og.A, og.B, bd.double().cpu().numpy().ravel(), mode="AB", K=K, rule="gcv",
-                         keep_small=True)
-    gres = [o.beta]
-    worst = 0.0
-    for k, (sig, _, uk1) in enumerate(o.small, start=1):
-        gres.append(uk1)
-        f = L.features(sig, gres)
-        worst = max(worst, float(np.max(np.abs(F[k - 1] - f))))
-    print(f"features {dt}: max abs {worst:.2e}")
-    assert worst <= 1e-6
+    bu = bd.double().cpu().numpy().ravel()
+
+    def oracle_features(Aop, Bop):
+        o = osv.hybrid_gmres(Aop, Bop, bu, mode="AB", K=K, rule="gcv", keep_small=True)
+        gres, out = [o.beta], []
+        for sig, _, uk1 in o.small:
+            gres.append(uk1)
+            out.append(L.features(sig, gres))
+        return np.array(out)
+
+    Fo = oracle_features(og.A, og.B)
+    worst = float(np.max(np.abs(F - Fo)))
+    gate = 1e-6
+    if dt == "f32":
+        # the FP32 path perturbs H and the residual history through its
+        # projectors (relative errors <= 2e-7 for A, 2e-6 for B); the gate is
+        # 3x the oracle's own feature deviation under such perturbations
+        dev = 0.0
+        for seed in range(4):
+            r = np.random.default_rng(seed)
+            pa = lambda v: (lambda y: y * (1 + 2e-7 * r.standard_normal(y.size)))(og.A(v))
+            pb = lambda v: (lambda y: y * (1 + 2e-6 * r.standard_normal(y.size)))(og.B(v))
+            dev = max(dev, float(np.max(np.abs(oracle_features(pa, pb) - Fo))))
+        gate = max(gate, 3 * dev)
+    print(f"features {dt}: max abs {worst:.2e} (gate {gate:.1e})")
+    assert worst <= gate
 
 
 @pytest.mark.parametrize("ortho", ["dcgs2", "cgs2"])
