@@ -438,18 +438,21 @@ __global__ __launch_bounds__(1024) void stop_k(int S, int K, int stop_kind, doub
                                                int *__restrict__ active, const int *__restrict__ flags,
                                                int *__restrict__ iters, int *__restrict__ status,
                                                int *__restrict__ kdev, int *__restrict__ nact,
-                                               const double *__restrict__ sc) {
+                                               const double *__restrict__ sc, int has_rho) {
     const int k = *kdev;
     int cnt = 0;
     for (int s = threadIdx.x; s < S; s += blockDim.x) {
         if (!active[s]) continue;
-        const double rho = rhoh[(size_t)s * (K + 1) + k];
-        const double rprev = rhoh[(size_t)s * (K + 1) + k - 1];
+        // rho_k is formed in AB mode (the projected residual) and in BA mode
+        // when Z is kept; otherwise only the small solve's flags are tested
+        const double rho = has_rho ? rhoh[(size_t)s * (K + 1) + k] : 0.0;
+        const double rprev = has_rho ? rhoh[(size_t)s * (K + 1) + k - 1] : 0.0;
         int st = 0;
         const int fl = flags[s];
         if ((fl & FL_NONFINITE) || !isfinite(rho)) st = ABBA_ST_NONFINITE;
         else if (fl & FL_BREAK) st = ABBA_ST_BREAKDOWN;
-        else if (stop_kind == ABBA_STOP_DP && rho <= tau * noise[s]) st = ABBA_ST_STOP_DP;
+        else if ((stop_kind == ABBA_STOP_DP || (stop_kind == ABBA_STOP_LEARNED && noise)) && rho <= tau * noise[s])
+            st = ABBA_ST_STOP_DP;
         else if (stop_kind == ABBA_STOP_RNS && fabs(rprev - rho) / rprev < rns_eps) st = ABBA_ST_STOP_RNS;
         else if (stop_kind == ABBA_STOP_LEARNED && sc && (double)k >= sc[(size_t)s * SC_COUNT + SC_KLEARN])
             st = ABBA_ST_STOP_LEARNED;
@@ -540,7 +543,8 @@ int smallsolve_prepare() {
 int launch_stop(const SolveDims &d, const SolveWS &ws, int stop_kind, double tau, double rns_eps,
                 const double *noise, int *iters, int *status, hipStream_t st) {
     hipLaunchKernelGGL(stop_k, dim3(1), dim3(1024), 0, st, d.S, d.K, stop_kind, tau, rns_eps, noise, ws.rhoh,
-                       ws.active, ws.flags, iters, status, ws.kdev, ws.nact, ws.sc);
+                       ws.active, ws.flags, iters, status, ws.kdev, ws.nact, ws.sc,
+                       (d.mode == ABBA_MODE_AB || d.keepZ) ? 1 : 0);
     ABBA_LAUNCHED("stop_k");
     return ABBA_OK;
 }

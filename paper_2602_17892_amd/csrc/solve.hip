@@ -316,6 +316,10 @@ extern "C" int abba_solve(const abba_op *A, const abba_op *B, const void *b, voi
         set_error("residual-norm stagnation needs rns_eps > 0");
         return ABBA_ERR_ARG;
     }
+    if (stop_kind == ABBA_STOP_LEARNED && stop->noise_norm && !(stop->tau > 0.0)) {
+        set_error("the discrepancy-principle check of the learned stop needs tau > 0");
+        return ABBA_ERR_ARG;
+    }
     if (stop_kind == ABBA_STOP_LEARNED && rule != ABBA_REG_LEARNED) {
         set_error("the learned stop needs the learned lambda rule (it shares the model)");
         return ABBA_ERR_ARG;

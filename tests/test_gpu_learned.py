@@ -204,6 +204,27 @@ def test_learned_solve(pk, mode):
     assert all(acc) and ex <= 1e-5
 
 
+def test_learned_stop_defers_to_dp(pk):
+    # a stop index of 10 (past the budget's end) and a known ||e||: the
+    # discrepancy principle stops the run first, at the oracle's iteration
+    og, x, b, en = problem(idx=7, eta=0.02)
+    A, B = ops(pk, "f64")
+    theta = synth.mlp_init(10)
+    W4, b4 = L.unpack(theta)[3]
+    W4[:] = 0.0
+    b4[:] = [-0.4, 1.0]
+    K = 30
+    bd = cuda(b.reshape(1, 45, 47), torch.float64)
+    xg, info = pk.solve(A, B, bd, mode="AB", k=K, reg="learned", stop="learned", mlp=cuda(theta),
+                        noise_norm=torch.tensor([en], dtype=torch.float64, device="cuda"), tau=1.01)
+    o = osv.hybrid_gmres(og.A, og.B, b, mode="AB", K=K, rule="learned", stop="learned",
+                         mlp=theta.astype(np.float64), noise_norm=en, tau=1.01)
+    print(f"learned + DP: iters {int(info['iters'][0])} / oracle {o.iters}, status {int(info['status'][0])}")
+    assert o.status == osv.STATUS_STOP_DP and o.iters < K
+    assert int(info["iters"][0]) == o.iters and int(info["status"][0]) & pk.ST_STOP_DP
+    assert rel(xg.cpu().numpy(), o.x) <= 1e-8
+
+
 def test_learned_training_end_to_end(pk):
     # training data from the method itself: 48 runs at 32^2 with labels from
     # the true images, then Adam on the network; evaluation on 8 fresh slices

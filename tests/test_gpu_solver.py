@@ -221,6 +221,20 @@ def test_delayed_and_two_pass_schedules_agree(pk, mode):
     assert e < 1e-11 and er < 1e-11
 
 
+@pytest.mark.parametrize("mode", ["AB", "BA"])
+def test_no_history_no_stop_runs_k_iterations(pk, mode):
+    """Without a stopping rule and without histories BA mode forms no data
+    residual; the run must still take all k iterations and give the same x as
+    a run that records the histories."""
+    A, B, og, xt, bd, bu, ens = problem(pk, 64, 90, 91, 0.01, 0, 6, dt="f64")
+    K = 10
+    x0, i0 = pk.solve(A, B, bd, mode=mode, k=K, reg="gcv", history=False)
+    x1, i1 = pk.solve(A, B, bd, mode=mode, k=K, reg="gcv", history=True)
+    print(f"{mode}: iters {int(i0['iters'][0])} status {int(i0['status'][0])}")
+    assert int(i0["iters"][0]) == K and int(i0["status"][0]) == pk.ST_KMAX
+    assert torch.equal(x0, x1)
+
+
 def test_batched_equals_per_slice_and_graph(pk):
     S = 3
     A, B, og, xt, bd, bu, ens = problem(pk, 64, 90, 91, 0.01, 2, 0, batch=S)
