@@ -137,15 +137,13 @@ def test_bf16_sinogram_storage(pk):
     assert e64 <= 2 ** -8 and e16 <= 2e-3 and eb <= 1e-5
 
 
-@pytest.mark.parametrize("shape", SHAPES + [(24, 24, 17, 35), (512, 512, 720, 725)])
-@pytest.mark.parametrize("dt", ["f64", "f32"])
+@pytest.mark.parametrize("shape,dt", [(s, d) for d in ("f64", "f32") for s in SHAPES + [(24, 24, 17, 35)]]
+                         + [((512, 512, 720, 725), "f32")])
 def test_joseph_gather_and_lds_paths_are_bitwise_equal(pk, shape, dt, monkeypatch):
     """A has two kernels (per-ray gathers from global memory; bands of rows
     staged in LDS, chosen for large batches).  They perform the same
     operations in the same order, so their outputs must be identical bits;
     the parity tests above cover the gather path against the oracle."""
-    if dt == "f64" and shape[0] == 512:
-        pytest.skip("FP64 at 512^2 adds nothing to the FP32 case")
     nx, ny, na, nd = shape
     angles = None
     if shape == (24, 24, 17, 35):
