@@ -199,6 +199,8 @@ def projectors_only(args):
     g = pk.Geometry(args.n, args.n, args.angles, args.det)
     A = pk.Operator("joseph", g, "f32", "f32")
     B = pk.Operator("pixel", g, "f32", "f32")
+    pk.autotune(A, S)
+    pk.autotune(B, S)
     gen = torch.Generator(device="cuda")
     gen.manual_seed(2)
     x = torch.rand((S, args.n, args.n), generator=gen, device="cuda")
@@ -523,6 +525,12 @@ def main():
     x_true, b, en, eta = make_inputs(args, pk, A, torch)
     log(args, f"inputs: {S} slices of {args.n}^2, {args.angles}x{args.det} in {time.perf_counter() - t0:.1f}s")
 
+    # launch choices of the projectors for this batch size and for single
+    # slices (the plain path), timed before anything is measured
+    t0 = time.perf_counter()
+    tune = {"A": pk.autotune(A, S), "B": pk.autotune(B, S), "A_plain": pk.autotune(A, 1), "B_plain": pk.autotune(B, 1)}
+    log(args, f"autotune ({time.perf_counter() - t0:.1f}s): " + "; ".join(
+        f"{k} {v['ms']:.3f} ms (built-in {v['default_ms']:.3f})" for k, v in tune.items()))
     ws_bytes = pk.workspace_bytes(A, B, S, "AB", K, stop="dp")
     ws = torch.empty(ws_bytes, dtype=torch.uint8, device="cuda")
     log(args, f"workspace {ws_bytes / 2**30:.1f} GiB")
@@ -582,10 +590,11 @@ def main():
     tf_B = pairs * FLOPS_PER_PIXEL_ANGLE / t_B / 1e12
     log(args, f"A: {t_A * 1e3:.2f} ms ({gbs_A:.1f} GB/s, {tf_A:.2f} TFLOP/s); "
               f"B: {t_B * 1e3:.2f} ms ({gbs_B:.1f} GB/s, {tf_B:.2f} TFLOP/s)")
-    # at this batch size A runs its LDS-band kernel (the gather kernel is
-    # used for batches too small to fill the device); B runs pixbp2d_k
+    # A runs the kernel its tuning chose (the built-in rule takes the LDS-band
+    # kernel at this batch size); B runs pixbp2d_k
+    a_name = "joseph2d_fwd_k" if tune["A"]["a_path"] == 0 else "joseph2d_lds_k"
     if t_A >= t_B:
-        dom_name, dom_tf, dom_t = "joseph2d_lds_k", tf_A, t_A
+        dom_name, dom_tf, dom_t = a_name, tf_A, t_A
     else:
         dom_name, dom_tf, dom_t = "pixbp2d_k", tf_B, t_B
     roofline = {"bound": "alu", "achieved": round(dom_tf, 3), "peak": round(VALU_PEAK_TFLOPS, 1),
@@ -622,6 +631,8 @@ def main():
                       "A_TFLOPs": round(tf_A, 3), "B_TFLOPs": round(tf_B, 3), "A_ray_steps": steps,
                       "B_pixel_angle_pairs": pairs},
         "roofline": roofline,
+        "autotune": {k: {"choice": {c: v[c] for c in ("a_path", "a_jb", "b_g", "czt")}, "ms": round(v["ms"], 3),
+                         "builtin_ms": round(v["default_ms"], 3)} for k, v in tune.items()},
     }
     if not args.no_cpu_baseline:
         s0 = int(np.argsort(iters)[len(iters) // 2])

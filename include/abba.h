@@ -113,6 +113,34 @@ int abba_project(const abba_op *A, const void *x, void *y, int batch, void *stre
  * eqs. (4)-(5)) or ABBA_OP_JOSEPH_T (exact A^T).  Asynchronous. */
 int abba_backproject(const abba_op *B, const void *y, void *x, int batch, void *stream);
 
+/* ---- Launch tuning (tile shapes and kernel choices of the projectors).
+ * Every choice computes the same result bits: it changes how work is split
+ * over workgroups, never the order of any sum. */
+typedef struct {
+    int a_path;        /* 2D A: 0 per-ray gather kernel, 1 LDS-band kernel, -1 built-in rule */
+    int a_jb;          /* 2D A, LDS kernel: bins per thread and angle, 2..4 (0: 3)           */
+    int b_g;           /* 2D B: angles per LDS chunk (0: built-in, at most 64 KB of LDS)      */
+    int czt;           /* 3D B: voxels per thread along z, 2, 4 or 8 (0: 4)                   */
+    double ms;         /* abba_autotune: mean time of one apply with the chosen launch       */
+    double default_ms; /* abba_autotune: the same with the built-in rules                    */
+    int candidates;    /* abba_autotune: launch choices timed besides the built-in rules     */
+} abba_tune;
+
+/* Times the launch choices of `op` for `batch` slices (reps applies each,
+ * after one warm-up; reps < 1 means 3) on a fixed input pattern in buffers
+ * it allocates and frees, with HIP events on `stream`, and keeps the fastest
+ * (the built-in rules included) in the operator for that batch size; later
+ * calls with that batch size, abba_solve included, use it.  `best` (host) may
+ * be NULL.  Synchronises `stream`.  An operator keeps 8 batch sizes (the
+ * oldest is dropped); changing them while the operator runs is a race. */
+int abba_autotune(abba_op *op, int batch, int reps, void *stream, abba_tune *best);
+
+/* Sets the launch choices of `op` for `batch` (t NULL: forget them). */
+int abba_op_set_tuning(abba_op *op, int batch, const abba_tune *t);
+
+/* 1 and *t filled if `op` has launch choices for `batch`, 0 if not. */
+int abba_op_get_tuning(const abba_op *op, int batch, abba_tune *t);
+
 typedef enum { ABBA_MODE_AB = 0, ABBA_MODE_BA = 1 } abba_mode;
 
 /* Lambda rules for the projected problem (Sec. 3.1): none (plain AB/BA-GMRES,

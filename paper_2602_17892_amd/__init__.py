@@ -19,7 +19,7 @@ from dataclasses import dataclass
 __all__ = [
     "LIB_PATH", "lib", "AbbaError", "Geometry", "Operator", "project", "backproject", "solve",
     "workspace_bytes", "ST_KMAX", "ST_STOP_DP", "ST_STOP_RNS", "ST_BREAKDOWN", "ST_NONFINITE",
-    "ST_STOP_LEARNED", "mlp_forward", "mlp_loss_grad", "mlp_adam", "mlp_labels", "MLP_PARAMS",
+    "ST_STOP_LEARNED", "autotune", "set_tuning", "get_tuning", "mlp_forward", "mlp_loss_grad", "mlp_adam", "mlp_labels", "MLP_PARAMS",
 ]
 
 LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libabba.so")
@@ -65,6 +65,11 @@ class _Out(ctypes.Structure):
                 ("rre", ctypes.c_void_p)]
 
 
+class _Tune(ctypes.Structure):
+    _fields_ = [("a_path", ctypes.c_int), ("a_jb", ctypes.c_int), ("b_g", ctypes.c_int), ("czt", ctypes.c_int),
+                ("ms", ctypes.c_double), ("default_ms", ctypes.c_double), ("candidates", ctypes.c_int)]
+
+
 class _Exec(ctypes.Structure):
     _fields_ = [("use_graph", ctypes.c_int), ("poll_every", ctypes.c_int), ("restart", ctypes.c_int),
                 ("features", ctypes.c_int), ("ortho", ctypes.c_int)]
@@ -95,6 +100,12 @@ def _load():
     L.abba_solve.argtypes = [vp, vp, vp, vp, i, i, i, ctypes.POINTER(_Reg), ctypes.POINTER(_Stop),
                              ctypes.POINTER(_Out), ctypes.POINTER(_Exec), vp, ctypes.c_size_t, vp]
     L.abba_solve.restype = i
+    L.abba_autotune.argtypes = [vp, i, i, vp, ctypes.POINTER(_Tune)]
+    L.abba_autotune.restype = i
+    L.abba_op_set_tuning.argtypes = [vp, i, ctypes.POINTER(_Tune)]
+    L.abba_op_set_tuning.restype = i
+    L.abba_op_get_tuning.argtypes = [vp, i, ctypes.POINTER(_Tune)]
+    L.abba_op_get_tuning.restype = i
     L.abba_mlp_forward.argtypes = [vp, vp, i, vp, vp]
     L.abba_mlp_forward.restype = i
     L.abba_mlp_loss_grad.argtypes = [vp, vp, vp, i, vp, i, vp, vp, vp]
@@ -120,6 +131,9 @@ abba_project = lib.abba_project
 abba_backproject = lib.abba_backproject
 abba_solve_workspace = lib.abba_solve_workspace
 abba_solve = lib.abba_solve
+abba_autotune = lib.abba_autotune
+abba_op_set_tuning = lib.abba_op_set_tuning
+abba_op_get_tuning = lib.abba_op_get_tuning
 abba_mlp_forward = lib.abba_mlp_forward
 abba_mlp_loss_grad = lib.abba_mlp_loss_grad
 abba_mlp_adam = lib.abba_mlp_adam
@@ -255,6 +269,37 @@ def backproject(B: Operator, y, out=None):
     _need(out, B.img_dtype, B.n, "out")
     _check(lib.abba_backproject(B.handle, _ptr(y), _ptr(out), batch, _stream_ptr()), "abba_backproject")
     return out
+
+
+def _tune_dict(t):
+    return dict(a_path=t.a_path, a_jb=t.a_jb, b_g=t.b_g, czt=t.czt)
+
+
+def autotune(op: Operator, batch: int, reps: int = 3):
+    """Time the launch choices of `op` at `batch` and keep the fastest for that
+    batch size (abba_autotune).  Returns the choice with its time and the
+    built-in rules' time in ms."""
+    t = _Tune()
+    _check(lib.abba_autotune(op.handle, int(batch), int(reps), _stream_ptr(), ctypes.byref(t)), "abba_autotune")
+    return dict(_tune_dict(t), ms=t.ms, default_ms=t.default_ms, candidates=t.candidates)
+
+
+def set_tuning(op: Operator, batch: int, a_path=-1, a_jb=0, b_g=0, czt=0, clear=False):
+    """Fix the launch choices of `op` for `batch` (clear=True forgets them)."""
+    if clear:
+        _check(lib.abba_op_set_tuning(op.handle, int(batch), None), "abba_op_set_tuning")
+        return
+    t = _Tune(a_path, a_jb, b_g, czt, 0.0, 0.0, 0)
+    _check(lib.abba_op_set_tuning(op.handle, int(batch), ctypes.byref(t)), "abba_op_set_tuning")
+
+
+def get_tuning(op: Operator, batch: int):
+    """The launch choices `op` keeps for `batch`, or None."""
+    t = _Tune()
+    r = lib.abba_op_get_tuning(op.handle, int(batch), ctypes.byref(t))
+    if r < 0:
+        _check(r, "abba_op_get_tuning")
+    return _tune_dict(t) if r == 1 else None
 
 
 ORTHO = {"dcgs2": 0, "cgs2": 1}

@@ -334,4 +334,138 @@ int abba_backproject(const abba_op *B, const void *y, void *x, int batch, void *
     return ABBA_OK;
 }
 
+// ------------------------------------------------------------ tuning ------
+static void to_c(const TuneEntry &t, abba_tune *o) {
+    o->a_path = t.a_path;
+    o->a_jb = t.a_jb;
+    o->b_g = t.b_g;
+    o->czt = t.czt;
+}
+
+static void store_tuning(abba_op *op, const TuneEntry &e) {
+    for (int i = 0; i < op->ntune; ++i)
+        if (op->tune[i].batch == e.batch) {
+            op->tune[i] = e;
+            return;
+        }
+    if (op->ntune == MAX_TUNE) {   // forget the oldest entry
+        for (int i = 1; i < MAX_TUNE; ++i) op->tune[i - 1] = op->tune[i];
+        --op->ntune;
+    }
+    op->tune[op->ntune++] = e;
+}
+
+int abba_op_set_tuning(abba_op *op, int batch, const abba_tune *t) {
+    if (!op || batch < 1) {
+        set_error("abba_op_set_tuning: NULL operator or batch < 1");
+        return ABBA_ERR_ARG;
+    }
+    if (!t) {
+        for (int i = 0; i < op->ntune; ++i)
+            if (op->tune[i].batch == batch) {
+                for (int j = i + 1; j < op->ntune; ++j) op->tune[j - 1] = op->tune[j];
+                --op->ntune;
+                break;
+            }
+        return ABBA_OK;
+    }
+    store_tuning(op, TuneEntry{batch, t->a_path, t->a_jb, t->b_g, t->czt});
+    return ABBA_OK;
+}
+
+int abba_op_get_tuning(const abba_op *op, int batch, abba_tune *t) {
+    if (!op || !t) {
+        set_error("abba_op_get_tuning: NULL argument");
+        return ABBA_ERR_ARG;
+    }
+    for (int i = 0; i < op->ntune; ++i)
+        if (op->tune[i].batch == batch) {
+            to_c(op->tune[i], t);
+            return 1;
+        }
+    return 0;
+}
+
+__global__ void tune_fill_k(float *p, int64_t n, int dt) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const float v = (float)((i * 2654435761ull) % 1000ull) * 1e-3f;   // a fixed pattern in [0, 1)
+        if (dt == ABBA_F64) reinterpret_cast<double *>(p)[i] = v;
+        else if (dt == ABBA_F32) p[i] = v;
+        else reinterpret_cast<uint16_t *>(p)[i] = (uint16_t)(__float_as_uint(v) >> 16);
+    }
+}
+
+int abba_autotune(abba_op *op, int batch, int reps, void *stream, abba_tune *best) {
+    if (!op || batch < 1) {
+        set_error("abba_autotune: NULL operator or batch < 1");
+        return ABBA_ERR_ARG;
+    }
+    if (reps < 1) reps = 3;
+    const bool fwd = op->kind == ABBA_OP_JOSEPH;
+    const int in_dt = fwd ? op->img_dtype : op->sino_dtype, out_dt = fwd ? op->sino_dtype : op->img_dtype;
+    const int64_t in_len = (int64_t)batch * (fwd ? op->n : op->m), out_len = (int64_t)batch * (fwd ? op->m : op->n);
+    TuneEntry cand[16];
+    const int nc = op->g.kind == ABBA_GEOM_CONE3D ? cone_tune_candidates(op, cand, 16)
+                                                  : par2d_tune_candidates(op, cand, 16);
+    hipStream_t st = (hipStream_t)stream;
+    void *in = nullptr, *out = nullptr;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    int rc = ABBA_OK;
+    double best_ms = 1e300, def_ms = 0.0;
+    TuneEntry win{batch, -1, 0, 0, 0};
+    auto run = [&]() {
+        return fwd ? abba_project(op, in, out, batch, stream) : abba_backproject(op, in, out, batch, stream);
+    };
+    auto timed = [&](const TuneEntry &t, double *ms) -> int {
+        op->trial = t;
+        op->trial_on = 1;
+        int r = run();   // warm-up (first launches of a kernel variant load its code)
+        if (!r && hipEventRecord(e0, st) != hipSuccess) r = hip_fail(hipGetLastError(), "hipEventRecord");
+        for (int i = 0; i < reps && !r; ++i) r = run();
+        if (!r && hipEventRecord(e1, st) != hipSuccess) r = hip_fail(hipGetLastError(), "hipEventRecord");
+        if (!r && hipEventSynchronize(e1) != hipSuccess) r = hip_fail(hipGetLastError(), "hipEventSynchronize");
+        float f = 0.f;
+        if (!r && hipEventElapsedTime(&f, e0, e1) != hipSuccess) r = hip_fail(hipGetLastError(), "hipEventElapsedTime");
+        op->trial_on = 0;
+        *ms = (double)f / reps;
+        return r;
+    };
+    hipError_t e = hipMalloc(&in, (size_t)in_len * dtype_size(in_dt));
+    if (e == hipSuccess) e = hipMalloc(&out, (size_t)out_len * dtype_size(out_dt));
+    if (e == hipSuccess) e = hipEventCreate(&e0);
+    if (e == hipSuccess) e = hipEventCreate(&e1);
+    if (e != hipSuccess) rc = hip_fail(e, "abba_autotune set-up");
+    if (!rc) {
+        hipLaunchKernelGGL(tune_fill_k, dim3(1024), dim3(256), 0, st, (float *)in, in_len, in_dt);
+        e = hipGetLastError();
+        if (e != hipSuccess) rc = hip_fail(e, "tune_fill_k");
+    }
+    if (!rc) rc = timed(TuneEntry{batch, -1, 0, 0, 0}, &def_ms);
+    if (!rc) best_ms = def_ms;
+    for (int i = 0; i < nc && !rc; ++i) {
+        TuneEntry t = cand[i];
+        t.batch = batch;
+        double ms = 0.0;
+        rc = timed(t, &ms);
+        if (!rc && ms < best_ms) {
+            best_ms = ms;
+            win = t;
+        }
+    }
+    op->trial_on = 0;
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    if (in) (void)hipFree(in);
+    if (out) (void)hipFree(out);
+    if (rc) return rc;
+    store_tuning(op, win);
+    if (best) {
+        to_c(win, best);
+        best->ms = best_ms;
+        best->default_ms = def_ms;
+        best->candidates = nc;
+    }
+    return ABBA_OK;
+}
+
 }  // extern "C"

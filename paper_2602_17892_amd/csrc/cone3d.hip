@@ -338,11 +338,11 @@ __global__ __launch_bounds__(256) void cone_fwd_k(const TI *__restrict__ vx, con
     store_as<TO>(vec_ptr<TO>(yr, s, k), ((int64_t)vw * nv + r) * nu + c, (acc0 + acc1) * wgt);
 }
 
-// B: one thread per 4 voxels along z (a 16 x 16 (y, x) tile per workgroup);
-// loop over the views.
-constexpr int CZT = 4;
+// B: one thread per CZT voxels along z (a 16 x 16 (y, x) tile per workgroup;
+// CZT is a launch choice that leaves every sum unchanged); loop over the views.
+constexpr int CZT_DEFAULT = 4;
 
-template <typename TI>
+template <typename TI, int CZT>
 __global__ __launch_bounds__(256) void cone_bp_k(const typename acc_of<TI>::type *__restrict__ yp, int64_t ss,
                                                  VecRef xr, const ConeB<typename acc_of<TI>::type> *__restrict__ vb,
                                                  int nx, int ny, int nz, int nviews, int nu, int nv,
@@ -451,6 +451,29 @@ int cone_forward(const abba_op *op, VecRef x, VecRef y, int y_dtype, int batch, 
     return ABBA_ERR_DTYPE;
 }
 
+template <typename TI, int CZT>
+static int cone_bp_launch(const abba_op *op, const typename acc_of<TI>::type *yp, VecRef x, int batch,
+                          const Launch &L) {
+    typedef typename acc_of<TI>::type T;
+    const abba_geometry &g = op->g;
+    const ConeCopies cc = cone_copies(op);
+    const int ntx = (g.nx + 15) / 16, nty = (g.ny + 15) / 16, ntz = (g.nz + CZT - 1) / CZT;
+    const uint64_t per = (uint64_t)ntx * nty * ntz;
+    if (per > CMAX_GROUPS) return ABBA_ERR_UNSUPPORTED;
+    const int ch = (int)std::min<uint64_t>((uint64_t)batch, CMAX_GROUPS / per);
+    const size_t bytes_d = sizeof(ConeView) * g.n_angles;
+    const ConeB<T> *vb = reinterpret_cast<const ConeB<T> *>((const unsigned char *)op->tab + bytes_d);
+    for (int s0 = 0; s0 < batch; s0 += ch) {
+        const int nb = std::min(ch, batch - s0);
+        hipLaunchKernelGGL((cone_bp_k<TI, CZT>), dim3((uint32_t)(per * nb)), dim3(256), 0, L.stream, yp,
+                           (int64_t)cc.sino, x, vb, g.nx, g.ny, g.nz, g.n_angles, g.det_u, g.det_v,
+                           (T)(1.0 / (g.det_pitch_u * g.det_pitch_v)), ntx, nty, ntz, (uint32_t)op->nxcc, s0, L.kdev,
+                           L.active);
+        ABBA_LAUNCHED("cone_bp_k");
+    }
+    return ABBA_OK;
+}
+
 template <typename TIN, typename TI>
 static int cone_bp_t(const abba_op *op, VecRef y, VecRef x, int batch, void *scratch, const Launch &L) {
     typedef typename acc_of<TI>::type T;
@@ -465,21 +488,20 @@ static int cone_bp_t(const abba_op *op, VecRef y, VecRef x, int batch, void *scr
                            g.n_angles, g.det_u, g.det_v, s0, (int64_t)cc.sino, L.kdev, L.active);
         ABBA_LAUNCHED("cone_pad_sino_k");
     }
-    const int ntx = (g.nx + 15) / 16, nty = (g.ny + 15) / 16, ntz = (g.nz + CZT - 1) / CZT;
-    const uint64_t per = (uint64_t)ntx * nty * ntz;
-    if (per > CMAX_GROUPS) return ABBA_ERR_UNSUPPORTED;
-    const int ch = (int)std::min<uint64_t>((uint64_t)batch, CMAX_GROUPS / per);
-    const size_t bytes_d = sizeof(ConeView) * g.n_angles;
-    const ConeB<T> *vb = reinterpret_cast<const ConeB<T> *>((const unsigned char *)op->tab + bytes_d);
-    for (int s0 = 0; s0 < batch; s0 += ch) {
-        const int nb = std::min(ch, batch - s0);
-        hipLaunchKernelGGL((cone_bp_k<TI>), dim3((uint32_t)(per * nb)), dim3(256), 0, L.stream, (const T *)yp,
-                           (int64_t)cc.sino, x, vb, g.nx, g.ny, g.nz, g.n_angles, g.det_u, g.det_v,
-                           (T)(1.0 / (g.det_pitch_u * g.det_pitch_v)), ntx, nty, ntz, (uint32_t)op->nxcc, s0, L.kdev,
-                           L.active);
-        ABBA_LAUNCHED("cone_bp_k");
-    }
-    return ABBA_OK;
+    int czt = CZT_DEFAULT;
+    if (const TuneEntry *t = tune_for(op, batch))
+        if (t->czt == 2 || t->czt == 4 || t->czt == 8) czt = t->czt;
+    if (czt == 2) return cone_bp_launch<TI, 2>(op, yp, x, batch, L);
+    if (czt == 8) return cone_bp_launch<TI, 8>(op, yp, x, batch, L);
+    return cone_bp_launch<TI, 4>(op, yp, x, batch, L);
+}
+
+int cone_tune_candidates(const abba_op *op, TuneEntry *out, int cap) {
+    int n = 0;
+    if (op->kind == ABBA_OP_PIXEL)
+        for (int c : {2, 4, 8})
+            if (n < cap) out[n++] = TuneEntry{0, 0, 0, 0, c};
+    return n;
 }
 
 int cone_back(const abba_op *op, VecRef y, int y_dtype, VecRef x, int batch, void *scratch, const Launch &L) {

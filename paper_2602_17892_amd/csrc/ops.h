@@ -53,6 +53,18 @@ struct VecRef {
     int k_off;
 };
 
+// Launch choices of one operator at one batch size (from abba_autotune or
+// abba_op_set_tuning).  Every choice computes the same result bits; -1 or 0
+// leaves a choice to the built-in rule.
+struct TuneEntry {
+    int batch;
+    int a_path;   // 2D A: 0 gather kernel, 1 LDS-band kernel
+    int a_jb;     // 2D A, LDS kernel: bins per thread and angle (2, 3 or 4)
+    int b_g;      // 2D B: angles per LDS chunk
+    int czt;      // 3D B: voxels per thread along z (2, 4 or 8)
+};
+constexpr int MAX_TUNE = 8;
+
 struct Launch {
     hipStream_t stream;
     const int *kdev;      // device iteration counter, or nullptr (k = 0)
@@ -75,6 +87,10 @@ struct abba_op {
     int ngroups;
     unsigned char *major;  // unused
     int cone_axes;         // 3D: bit a set if some ray has dominant axis a (0 x, 1 y, 2 z)
+    abba::TuneEntry tune[abba::MAX_TUNE];   // per batch size (not thread-safe to change
+    int ntune;                              // while the operator is in use)
+    abba::TuneEntry trial;                  // abba_autotune's candidate under test
+    int trial_on;
 };
 
 namespace abba {
@@ -93,6 +109,19 @@ int cone_back(const abba_op *op, VecRef y, int y_dtype, VecRef x, int batch, voi
 size_t cone_scratch_bytes(const abba_op *op, int batch);
 
 int op_build_tables(abba_op *op);
+
+// Launch choices abba_autotune times (each computes the same result bits).
+int par2d_tune_candidates(const abba_op *op, TuneEntry *out, int cap);
+int cone_tune_candidates(const abba_op *op, TuneEntry *out, int cap);
+
+// The launch choices for `batch`: the candidate under test, else the stored
+// entry for that batch size, else nullptr (built-in rules).
+static inline const TuneEntry *tune_for(const abba_op *op, int batch) {
+    if (op->trial_on) return &op->trial;
+    for (int i = 0; i < op->ntune; ++i)
+        if (op->tune[i].batch == batch) return &op->tune[i];
+    return nullptr;
+}
 
 static inline size_t dtype_size(int dt) { return dt == ABBA_F64 ? 8 : dt == ABBA_F32 ? 4 : 2; }
 

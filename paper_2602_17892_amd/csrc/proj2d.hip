@@ -233,13 +233,13 @@ __global__ __launch_bounds__(256) void joseph2d_fwd_k(const TI *__restrict__ xp,
 }
 
 // LDS version: a workgroup takes one slice, JOSEPH_GA angles of one march
-// direction and 768 bins (3 rays per thread and angle) and streams the padded
-// image through LDS band by band; each ray keeps its sum in a register.  A
-// wave skips a (ray slot, band) pair exactly when the gather version's wave
-// would not visit that band.
-constexpr int JB = 3;   // bins per thread and angle
+// direction and 256*JB bins (JB rays per thread and angle, a launch choice)
+// and streams the padded image through LDS band by band; each ray keeps its
+// sum in a register.  A wave skips a (ray slot, band) pair exactly when the
+// gather version's wave would not visit that band.
+constexpr int JB_DEFAULT = 3;
 
-template <typename TI, typename TO>
+template <typename TI, typename TO, int JB>
 __global__ __launch_bounds__(256) void joseph2d_lds_k(const TI *__restrict__ xp, const TI *__restrict__ xq,
                                                       VecRef yr,
                                                       const AngleTab<typename acc_of<TI>::type> *__restrict__ tab,
@@ -253,7 +253,7 @@ __global__ __launch_bounds__(256) void joseph2d_lds_k(const TI *__restrict__ xp,
     constexpr int GA = JOSEPH_GA;
     extern __shared__ __align__(16) unsigned char smem[];
     T *band = reinterpret_cast<T *>(smem);   // [H][L]
-    // work order: (slice, angle group, bin chunk of 768)
+    // work order: (slice, angle group, bin chunk of 256*JB)
     const uint32_t w = xcd_remap(blockIdx.x, gridDim.x, nxcc);
     const int bc = (int)(w % (uint32_t)nbc);
     const uint32_t w2 = w / (uint32_t)nbc;
@@ -436,6 +436,13 @@ static void pixbp_window(const abba_op *op, int *W, int *G) {
     *G = (int)std::max<size_t>(1, std::min<size_t>(32, 32768 / per));
 }
 
+// Most angles per chunk whose windows fit in 64 KB of LDS.
+static int pixbp_max_g(const abba_op *op, int W) {
+    const size_t per = (size_t)W * 2 * (op->img_dtype == ABBA_F64 ? 8 : 4) + sizeof(int);
+    return (int)std::max<size_t>(1, 65536 / per);
+}
+
+
 // ------------------------------------------------------------ exact A^T ----
 // Gather of the rays whose Joseph interpolation hat covers the pixel: weight
 // hat((s_d - p)/c)/|c|, p = X cos + Y sin, c the dominant direction cosine.
@@ -495,6 +502,36 @@ static bool offsets_fit(const abba_op *op) {
            (uint64_t)round_rows(nx) * (ny + 2 * PAD) * acc_size(op) < lim;
 }
 
+template <typename T>
+static bool lds_fits(const abba_op *op) {
+    const size_t band_bytes = (size_t)JBand<T>::H * (std::max(op->g.nx, op->g.ny) + 2 * PAD) * sizeof(T);
+    return band_bytes <= 65536 && op->agrp && std::max(op->g.nx, op->g.ny) < 65535;
+}
+
+// Workgroups of one slice in the LDS version.
+static uint64_t lds_groups(const abba_op *op, int jb) {
+    return (uint64_t)op->ngroups * ((op->g.det_u + 256 * jb - 1) / (256 * jb));
+}
+
+template <typename TI, typename TO, int JB>
+static int lds_launch(const abba_op *op, const TI *xp, const TI *xq, VecRef y, int batch, const Launch &L) {
+    typedef typename acc_of<TI>::type T;
+    const int nx = op->g.nx, ny = op->g.ny, nd = op->g.det_u;
+    const size_t band_bytes = (size_t)JBand<T>::H * (std::max(nx, ny) + 2 * PAD) * sizeof(T);
+    const int nbc = (nd + 256 * JB - 1) / (256 * JB);
+    const uint64_t per = lds_groups(op, JB);
+    const int ch = (int)std::min<uint64_t>((uint64_t)batch, MAX_GROUPS / per);
+    for (int s0 = 0; s0 < batch; s0 += ch) {
+        const int nb = std::min(ch, batch - s0);
+        hipLaunchKernelGGL((joseph2d_lds_k<TI, TO, JB>), dim3((uint32_t)(per * nb)), dim3(256), band_bytes,
+                           L.stream, xp, xq, y, (const AngleTab<T> *)op->tab, (const int *)op->agrp, op->ngroups,
+                           nbc, nx, ny, nd, (T)op->g.det_pitch_u, (T)(0.5 * (nd - 1)), (uint32_t)op->nxcc, s0,
+                           L.kdev, L.active);
+        ABBA_LAUNCHED("joseph2d_lds_k");
+    }
+    return ABBA_OK;
+}
+
 template <typename TI, typename TO>
 static int fwd_launch(const abba_op *op, VecRef x, VecRef y, int batch, void *scratch, const Launch &L) {
     typedef typename acc_of<TI>::type T;
@@ -509,28 +546,23 @@ static int fwd_launch(const abba_op *op, VecRef x, VecRef y, int batch, void *sc
     }
     // The LDS version needs a band of rows in 64 KB and enough workgroups to
     // fill the device (it has ~90x fewer than the gather version); both give
-    // bitwise identical results.  ABBA_JOSEPH_PATH=gather|lds forces one.
-    constexpr int H = JBand<T>::H;
-    const int Lmax = std::max(nx, ny) + 2 * PAD;
-    const size_t band_bytes = (size_t)H * Lmax * sizeof(T);
-    const int nbc = (nd + 256 * JB - 1) / (256 * JB);
-    const uint64_t per = (uint64_t)op->ngroups * nbc;
-    const bool lds_ok = band_bytes <= 65536 && op->agrp && std::max(nx, ny) < 65535;
+    // bitwise identical results, as do its bin-chunk widths.  A tuning entry
+    // for this batch size overrides the rule; ABBA_JOSEPH_PATH=gather|lds
+    // overrides both.
+    const bool lds_ok = lds_fits<T>(op);
+    int jb = JB_DEFAULT;
+    bool use_lds = lds_ok && lds_groups(op, jb) * (uint64_t)batch >= 8ull * (uint64_t)op->ncu;
+    if (const TuneEntry *t = tune_for(op, batch)) {
+        if (t->a_path == 0 || t->a_path == 1) use_lds = t->a_path == 1 && lds_ok;
+        if (t->a_jb >= 2 && t->a_jb <= 4) jb = t->a_jb;
+    }
     const char *force = std::getenv("ABBA_JOSEPH_PATH");
-    bool use_lds = lds_ok && per * (uint64_t)batch >= 8ull * (uint64_t)op->ncu;
     if (force && std::strcmp(force, "gather") == 0) use_lds = false;
     if (force && std::strcmp(force, "lds") == 0) use_lds = lds_ok;
     if (use_lds) {
-        const int ch = (int)std::min<uint64_t>((uint64_t)batch, MAX_GROUPS / per);
-        for (int s0 = 0; s0 < batch; s0 += ch) {
-            const int nb = std::min(ch, batch - s0);
-            hipLaunchKernelGGL((joseph2d_lds_k<TI, TO>), dim3((uint32_t)(per * nb)), dim3(256), band_bytes,
-                               L.stream, (const TI *)xp, (const TI *)xq, y, (const AngleTab<T> *)op->tab,
-                               (const int *)op->agrp, op->ngroups, nbc, nx, ny, nd, (T)op->g.det_pitch_u,
-                               (T)(0.5 * (nd - 1)), (uint32_t)op->nxcc, s0, L.kdev, L.active);
-            ABBA_LAUNCHED("joseph2d_lds_k");
-        }
-        return ABBA_OK;
+        if (jb == 2) return lds_launch<TI, TO, 2>(op, xp, xq, y, batch, L);
+        if (jb == 4) return lds_launch<TI, TO, 4>(op, xp, xq, y, batch, L);
+        return lds_launch<TI, TO, 3>(op, xp, xq, y, batch, L);
     }
     const int nbx = (nd + 255) / 256;
     const uint64_t per_slice = (uint64_t)nbx * na;
@@ -580,6 +612,8 @@ static int back_launch(const abba_op *op, VecRef y, VecRef x, int batch, const L
     }
     int W, G;
     pixbp_window(op, &W, &G);
+    if (const TuneEntry *t = tune_for(op, batch))
+        if (t->b_g > 0) G = std::min(t->b_g, pixbp_max_g(op, W));
     const size_t shmem = (size_t)G * W * 2 * sizeof(T) + (size_t)G * sizeof(int);
     if ((size_t)W * 2 * sizeof(T) > 32768) return ABBA_ERR_UNSUPPORTED;
     const int btx = (nx + BT - 1) / BT, bty = (ny + BT - 1) / BT;
@@ -606,6 +640,27 @@ int par2d_back(const abba_op *op, VecRef y, int y_dtype, VecRef x, int batch, vo
     if (y_dtype == ABBA_F32) return back_launch<float, float>(op, y, x, batch, L);
     if (y_dtype == ABBA_BF16) return back_launch<bf16, float>(op, y, x, batch, L);
     return ABBA_ERR_DTYPE;
+}
+
+// Launch choices abba_autotune times for this operator (all give the same bits).
+int par2d_tune_candidates(const abba_op *op, TuneEntry *out, int cap) {
+    int n = 0;
+    auto add = [&](TuneEntry e) {
+        if (n < cap) out[n++] = e;
+    };
+    if (op->kind == ABBA_OP_JOSEPH) {
+        add(TuneEntry{0, 0, 0, 0, 0});
+        const bool fits = op->img_dtype == ABBA_F64 ? lds_fits<double>(op) : lds_fits<float>(op);
+        if (fits)
+            for (int jb = 2; jb <= 4; ++jb) add(TuneEntry{0, 1, jb, 0, 0});
+    } else if (op->kind == ABBA_OP_PIXEL) {
+        int W, G;
+        pixbp_window(op, &W, &G);
+        const int gmax = pixbp_max_g(op, W);
+        for (int g : {8, 16, 32, 64, 128})
+            if (g <= gmax) add(TuneEntry{0, 0, 0, g, 0});
+    }
+    return n;
 }
 
 }  // namespace abba

@@ -1,0 +1,92 @@
+"""Launch tuning: every launch choice of a projector computes the same bits
+(it changes how work is split over workgroups, never the order of a sum), and
+abba_autotune keeps one of them for the batch size it timed."""
+import numpy as np
+import pytest
+
+import synth
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def pk():
+    import paper_2602_17892_amd as pk
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    return pk
+
+
+def ops2d(pk, shape, dt="f32"):
+    nx, ny, na, nd = shape
+    g = pk.Geometry(nx, ny, na, nd)
+    return pk.Operator("joseph", g, dt, dt), pk.Operator("pixel", g, dt, dt)
+
+
+def images(S, ny, nx, seed, dtype=torch.float32):
+    r = np.random.default_rng(seed)
+    return torch.as_tensor(r.uniform(size=(S, ny, nx))).to(device="cuda", dtype=dtype)
+
+
+@pytest.mark.parametrize("shape", [(100, 90, 73, 131), (64, 64, 90, 91), (256, 256, 180, 363)])
+@pytest.mark.parametrize("dt", ["f32", "f64"])
+def test_2d_launch_choices_bitwise_equal(pk, shape, dt):
+    nx, ny, na, nd = shape
+    A, B = ops2d(pk, shape, dt)
+    S = 3
+    tdt = torch.float64 if dt == "f64" else torch.float32
+    x = images(S, ny, nx, 1, tdt)
+    y = images(S, na, nd, 2, tdt)
+    ya0, xb0 = pk.project(A, x), pk.backproject(B, y)
+    for path, jb in [(0, 0), (1, 2), (1, 3), (1, 4)]:
+        pk.set_tuning(A, S, a_path=path, a_jb=jb)
+        assert pk.get_tuning(A, S) == dict(a_path=path, a_jb=jb, b_g=0, czt=0)
+        assert torch.equal(pk.project(A, x), ya0), (path, jb)
+    for g in (1, 8, 16, 64, 128):
+        pk.set_tuning(B, S, b_g=g)
+        assert torch.equal(pk.backproject(B, y), xb0), g
+    pk.set_tuning(A, S, clear=True)
+    pk.set_tuning(B, S, clear=True)
+    assert pk.get_tuning(A, S) is None and pk.get_tuning(B, S) is None
+
+
+def test_cone_launch_choices_bitwise_equal(pk):
+    nx, ny, nz, nvw, nu, nv = 20, 18, 13, 16, 28, 24
+    g = pk.Geometry(nx, ny, nvw, nu, det_pitch_u=1.3, kind="cone3d", nz=nz, det_v=nv, det_pitch_v=1.2,
+                    sid=40.0, sdd=80.0)
+    B = pk.Operator("pixel", g, "f32", "f32")
+    y = images(2, nvw * nv, nu, 3).reshape(2, nvw, nv, nu).contiguous()
+    x0 = pk.backproject(B, y)
+    for c in (2, 4, 8):
+        pk.set_tuning(B, 2, czt=c)
+        assert torch.equal(pk.backproject(B, y), x0), c
+
+
+def test_autotune_keeps_a_choice(pk):
+    A, B = ops2d(pk, (128, 128, 180, 183))
+    S = 16
+    x = images(S, 128, 128, 4)
+    ya0 = pk.project(A, x)
+    ta = pk.autotune(A, S, reps=2)
+    tb = pk.autotune(B, S, reps=2)
+    print(f"A: {ta}\nB: {tb}")
+    assert ta["candidates"] == 4 and tb["candidates"] >= 3
+    assert ta["ms"] <= ta["default_ms"] and tb["ms"] <= tb["default_ms"]
+    assert pk.get_tuning(A, S) == {k: ta[k] for k in ("a_path", "a_jb", "b_g", "czt")}
+    assert torch.equal(pk.project(A, x), ya0)
+    # the solver uses the stored choice and returns the same bits
+    og_b = pk.project(A, x).contiguous()
+    x1, _ = pk.solve(A, B, og_b, mode="AB", k=4, reg="gcv")
+    pk.set_tuning(A, S, clear=True)
+    pk.set_tuning(B, S, clear=True)
+    x2, _ = pk.solve(A, B, og_b, mode="AB", k=4, reg="gcv")
+    assert torch.equal(x1, x2)
+
+
+def test_tuning_argument_errors(pk):
+    A, _ = ops2d(pk, (16, 16, 20, 23))
+    with pytest.raises(pk.AbbaError):
+        pk.set_tuning(A, 0, a_path=1)
+    with pytest.raises(pk.AbbaError):
+        pk.autotune(A, 0)
