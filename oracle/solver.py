@@ -243,3 +243,36 @@ def hybrid_gmres(A, B, b, mode: str = "AB", K: int = 30, rule: str = "gcv",
     if keep_basis:
         out.W = np.stack(W)
     return out
+
+
+def hybrid_gmres_restarted(A, B, b, p: int, mode: str = "AB", K: int = 30, rule: str = "gcv",
+                           lam: float = 0.0, stop: str | None = None, tau: float = 1.01,
+                           noise_norm: float | None = None, rns_eps: float = 1e-3, x0=None,
+                           ortho: str = "cgs2") -> Result:
+    """Restarted hybrid AB-/BA-GMRES (Sec. 3.3): cycles of at most p iterations,
+    each started from the final iterate of the previous cycle, K iterations
+    in all.  lambda and the stopping rule act on every iteration of every
+    cycle; a cycle ended by a stopping rule, a breakdown or non-finite data
+    ends the run.  Histories are concatenated: lam_k for k = 1..iters and
+    rho_k for k = 0..iters, rho_0 of each cycle being the last rho of the
+    previous one (the same data residual)."""
+    if p < 1:
+        raise ValueError("the cycle length p must be >= 1")
+    b = np.asarray(b, dtype=np.float64).reshape(-1)
+    x = None if x0 is None else np.asarray(x0, dtype=np.float64).reshape(-1)
+    lam_h, rho_h, done, status = [], None, 0, STATUS_KMAX
+    out = None
+    while done < K:
+        pc = min(p, K - done)
+        out = hybrid_gmres(A, B, b, mode=mode, K=pc, rule=rule, lam=lam, stop=stop, tau=tau,
+                           noise_norm=noise_norm, rns_eps=rns_eps, x0=x, ortho=ortho)
+        if rho_h is None:
+            rho_h = [out.rho[0]]
+        rho_h += out.rho[1:]
+        lam_h += out.lam
+        x = out.x
+        done += out.iters
+        if out.status != STATUS_KMAX:
+            status = out.status
+            break
+    return Result(x=x, iters=done, status=status, lam=lam_h, rho=rho_h, beta=out.beta)

@@ -322,3 +322,67 @@ def test_semi_convergence_and_hybrid_stabilisation():
         total += 1
         worse += np.linalg.norm(h.x - x) > rre[-1] * np.linalg.norm(x)
     assert worse == 0
+
+
+def test_restart_longer_than_budget_is_the_plain_run(oracle_lib):
+    og, b = _restart_problem()
+    o = sv.hybrid_gmres(og.A, og.B, b, mode="AB", K=8, rule="gcv")
+    r = sv.hybrid_gmres_restarted(og.A, og.B, b, p=8, mode="AB", K=8, rule="gcv")
+    assert np.array_equal(o.x, r.x) and o.lam == r.lam and o.rho == r.rho
+
+
+def test_restart_every_iteration_is_minimal_residual_descent(oracle_lib):
+    # p = 1 without regularisation: each cycle is one GMRES step from x, i.e.
+    # x <- x + a B r with r = b - A x and a = <r, A B r> / |A B r|^2
+    # (AB mode); in BA mode x <- x + a s with s = B r and a = <s, B A s>/|B A s|^2
+    og, b = _restart_problem()
+    for mode in ("AB", "BA"):
+        x = np.zeros(_restart_problem.x.size)
+        for _ in range(5):
+            r = b - og.A(x)
+            if mode == "AB":
+                d = og.B(r)
+                q = og.A(d)
+                a = np.dot(r, q) / np.dot(q, q)
+            else:
+                d = og.B(r)
+                q = og.B(og.A(d))
+                a = np.dot(d, q) / np.dot(q, q)
+            x = x + a * d
+        o = sv.hybrid_gmres_restarted(og.A, og.B, b, p=1, mode=mode, K=5, rule="none")
+        assert o.iters == 5 and o.status == sv.STATUS_KMAX
+        assert np.linalg.norm(o.x - x) <= 1e-12 * np.linalg.norm(x)
+
+
+def test_restart_histories_join_at_cycle_boundaries(oracle_lib):
+    og, b = _restart_problem()
+    o = sv.hybrid_gmres_restarted(og.A, og.B, b, p=3, mode="BA", K=8, rule="gcv")
+    assert o.iters == 8 and len(o.lam) == 8 and len(o.rho) == 9
+    # rho_k is the data residual of x_k in every cycle, so the first rho of a
+    # cycle repeats the last of the previous one: check the last against A x
+    assert abs(o.rho[-1] - np.linalg.norm(b - og.A(o.x))) <= 1e-12 * o.rho[-1]
+    # the composition of two runs: 3 iterations, then 3 + 2 from that iterate
+    c1 = sv.hybrid_gmres(og.A, og.B, b, mode="BA", K=3, rule="gcv")
+    c2 = sv.hybrid_gmres(og.A, og.B, b, mode="BA", K=3, rule="gcv", x0=c1.x)
+    c3 = sv.hybrid_gmres(og.A, og.B, b, mode="BA", K=2, rule="gcv", x0=c2.x)
+    assert np.array_equal(c3.x, o.x)
+
+
+def test_restart_stops_by_dp_inside_a_cycle(oracle_lib):
+    og, b = _restart_problem(eta=0.05)
+    en = 0.05 * np.linalg.norm(og.A(_restart_problem.x))
+    o = sv.hybrid_gmres_restarted(og.A, og.B, b, p=6, mode="AB", K=40, rule="gcv", stop="dp", noise_norm=en)
+    assert o.status == sv.STATUS_STOP_DP and 6 < o.iters < 12
+    assert o.rho[-1] <= 1.01 * en and all(r > 1.01 * en for r in o.rho[:-1])
+
+
+def _restart_problem(eta=0.01):
+    from oracle.geometry import Par2D
+    from oracle.operators import Par2DOps
+    import synth
+    og = Par2DOps(Par2D(24, 24, 30, 35))
+    x, _ = synth.phantom2d(0, 11, 24)
+    _restart_problem.x = x.ravel()
+    bt = og.A(x).ravel()
+    b, _ = synth.add_relative_noise(bt, synth.noise_direction(0, 11, bt.size), eta)
+    return og, b
