@@ -197,7 +197,9 @@ typedef struct {
     int use_graph;             /* capture one iteration in a hipGraph and replay it        */
     int poll_every;            /* host reads the active-slice count every this many
                                   iterations (>= 1); ignored without a stopping rule       */
-    int restart;               /* restart cycle length p (Sec. 3.3); 0 = no restart        */
+    int restart;               /* restart cycle length p (Sec. 3.3); 0 = no restart: with
+                                  0 < p < k the run is cycles of at most p iterations, each
+                                  started from the previous cycle's iterate, k in all      */
     int features;              /* bits ABBA_FEAT_*: write the learned-rule features
                                   (out.features) and/or training labels (out.rre)          */
     int ortho;                 /* Gram-Schmidt schedule, ABBA_ORTHO_*                        */
@@ -229,6 +231,13 @@ int abba_solve_workspace(const abba_op *A, const abba_op *B, int batch, int mode
  *   x       device [batch][n], image dtype; in: x_0; out: x_k at each slice's
  *           stopping iteration.
  *   k       iteration budget K, 1 <= k <= min(m, n) (ABBA_ERR_ARG otherwise).
+ *           With exec.restart = p, 0 < p < k (Sec. 3.3): the basis holds one
+ *           cycle of p vectors (the workspace is sized for p), k is the total
+ *           over all cycles and may exceed 100; iters, status and the
+ *           histories count iterations over the whole run.  A stopping rule,
+ *           a breakdown or non-finite data end a slice's run inside any
+ *           cycle; the learned rule, features and labels need unrestarted
+ *           runs (ABBA_ERR_UNSUPPORTED).
  *   reg, stop, out, exec as above; `out.iters` and `out.status` are required.
  *   workspace, ws_bytes  device buffer of at least abba_solve_workspace bytes.
  * The Arnoldi process uses classical Gram-Schmidt with one re-orthogonalisation

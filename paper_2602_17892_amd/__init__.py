@@ -328,8 +328,9 @@ def _structs(reg, lam, tau, noise_norm, mlp, judge_delta, stop, stop_tau, rns_ep
     return r, s, e
 
 
-def workspace_bytes(A: Operator, B: Operator, batch: int, mode: str, k: int, stop=None, labels=False) -> int:
-    _, s, e = _structs("none", 0, 0, None, None, 0, stop, 1.01, 1e-3, 0, 1, 0, FEAT_LABELS if labels else 0)
+def workspace_bytes(A: Operator, B: Operator, batch: int, mode: str, k: int, stop=None, labels=False,
+                    restart: int = 0) -> int:
+    _, s, e = _structs("none", 0, 0, None, None, 0, stop, 1.01, 1e-3, 0, 1, restart, FEAT_LABELS if labels else 0)
     nb = ctypes.c_size_t()
     _check(lib.abba_solve_workspace(A.handle, B.handle, batch, MODE_AB if mode == "AB" else MODE_BA, k,
                                     ctypes.byref(s), ctypes.byref(e), ctypes.byref(nb)), "abba_solve_workspace")

@@ -671,9 +671,17 @@ int cgs2_step(const SolveDims &d, const SolveWS &ws, hipStream_t st) {
 // beta = ||W_0||, W_0 /= beta (k fixed at 0); sets sc[SC_BETA] via init_beta_k.
 __global__ void init_beta_k(const double *__restrict__ h, int hstride, double *__restrict__ sc, double *__restrict__ g,
                             int K, int *__restrict__ active, int *__restrict__ flags, int *__restrict__ iters,
-                            int *__restrict__ status, int S) {
+                            int *__restrict__ status, const int *__restrict__ alive, int S) {
     const int s = blockIdx.x * blockDim.x + threadIdx.x;
     if (s >= S) return;
+    if (alive && !alive[s]) {   // a slice that finished in an earlier restart cycle
+        sc[(int64_t)s * SC_COUNT + SC_INV] = 0.0;
+        flags[s] = 0;
+        iters[s] = 0;
+        status[s] = 0;
+        active[s] = 0;
+        return;
+    }
     const double b2 = h[(int64_t)s * hstride];
     const double beta = sqrt(b2);   // NaN stays NaN (no fmax: it would drop it)
     double *Sc = sc + (int64_t)s * SC_COUNT;
@@ -697,7 +705,8 @@ __global__ void init_beta_k(const double *__restrict__ h, int hstride, double *_
 }
 
 template <typename TW>
-static int normalize_first_t(const SolveDims &d, const SolveWS &ws, int *iters, int *status, hipStream_t st) {
+static int normalize_first_t(const SolveDims &d, const SolveWS &ws, int *iters, int *status, const int *alive,
+                             hipStream_t st) {
     TW *W = (TW *)ws.W;
     const int nblk = cgs_nblk(d.ldw, d.w_dt);
     int rc;
@@ -706,7 +715,7 @@ static int normalize_first_t(const SolveDims &d, const SolveWS &ws, int *iters, 
                        nullptr, nullptr);
     ABBA_LAUNCHED("reduce_k");
     hipLaunchKernelGGL(init_beta_k, dim3((d.S + 63) / 64), dim3(64), 0, st, ws.h, d.K + 1, ws.sc, ws.g, d.K,
-                       ws.active, ws.flags, iters, status, d.S);
+                       ws.active, ws.flags, iters, status, alive, d.S);
     ABBA_LAUNCHED("init_beta_k");
     dim3 sg(std::min<int64_t>(1024, (d.ldw / vec16<TW>::N + 255) / 256), 1, d.S);
     hipLaunchKernelGGL(scale_k<TW>, sg, dim3(256), 0, st, W, (int64_t)d.wslots * d.ldw, d.ldw, ws.sc, 0,
@@ -715,9 +724,10 @@ static int normalize_first_t(const SolveDims &d, const SolveWS &ws, int *iters, 
     return ABBA_OK;
 }
 
-int normalize_first(const SolveDims &d, const SolveWS &ws, int *iters, int *status, hipStream_t st) {
-    return d.w_dt == ABBA_F64 ? normalize_first_t<double>(d, ws, iters, status, st)
-                              : normalize_first_t<float>(d, ws, iters, status, st);
+int normalize_first(const SolveDims &d, const SolveWS &ws, int *iters, int *status, const int *alive,
+                    hipStream_t st) {
+    return d.w_dt == ABBA_F64 ? normalize_first_t<double>(d, ws, iters, status, alive, st)
+                              : normalize_first_t<float>(d, ws, iters, status, alive, st);
 }
 
 // out = b - ax (first `len` entries, padding zeroed); dtypes by tag.

@@ -78,6 +78,9 @@ struct SolveWS {
     double *gres;   // [S][K+1] plain GMRES residual history (r_0 = beta)
     double *gram;   // [S][K][K+1] labels: Gram matrix of P' and P'^T (x_true - x_0)
     double *enorm;  // [S][2]  labels: ||x_true - x_0||^2, ||x_true||^2
+    int *citers;    // [S] restarted runs: iterations of the current cycle
+    int *cstatus;   // [S] restarted runs: status of the current cycle
+    int *alive;     // [S] restarted runs: the slice takes part in the next cycle
     int *active;    // [S]
     int *flags;     // [S]
     int *kdev;      // [1] current iteration (1-based)

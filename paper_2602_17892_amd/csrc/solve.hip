@@ -25,7 +25,8 @@ int cgs2_step(const SolveDims &d, const SolveWS &ws, hipStream_t st);
 int dcgs2_step(const SolveDims &d, const SolveWS &ws, const int *kdev, hipStream_t st);
 int launch_ty(const SolveDims &d, const SolveWS &ws, const int *iters, const int *kdev, const int *active,
               hipStream_t st);
-int normalize_first(const SolveDims &d, const SolveWS &ws, int *iters, int *status, hipStream_t st);
+int normalize_first(const SolveDims &d, const SolveWS &ws, int *iters, int *status, const int *alive,
+                    hipStream_t st);
 int launch_sub(int in_dt, const void *b, int64_t bstride, const void *ax, int64_t axstride, int out_dt, void *out,
                int64_t ostride, int64_t len, int64_t ld, int S, hipStream_t st);
 int launch_norm(int dt, const void *v, int64_t stride, int64_t len, int S, double *npart, double *dst, int dstride,
@@ -97,6 +98,9 @@ size_t solve_workspace_bytes(const SolveDims &d, SolveWS *ws, void *base, size_t
     w.gres = (double *)take(S * (K + 1) * 8);
     w.gram = d.labels ? (double *)take(S * K * (K + 1) * 8) : nullptr;
     w.enorm = d.labels ? (double *)take(S * 2 * 8) : nullptr;
+    w.citers = (int *)take(S * 4);
+    w.cstatus = (int *)take(S * 4);
+    w.alive = (int *)take(S * 4);
     w.active = (int *)take(S * 4);
     w.flags = (int *)take(S * 4);
     w.kdev = (int *)take(4);
@@ -242,11 +246,165 @@ static int one_iteration(const SolveDims &d, const SolveWS &ws, const IterCfg &c
     return launch_stop(d, ws, c.stop_kind, c.stop_tau, c.rns_eps, c.noise_stop, c.iters, c.status, st);
 }
 
+__global__ void cycle_begin_k(int *__restrict__ alive, int *__restrict__ iters, int *__restrict__ status, int S) {
+    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= S) return;
+    alive[s] = 1;
+    iters[s] = 0;
+    status[s] = 0;
+}
+
+// End of a restart cycle that started `done` iterations in (one block):
+// every slice that took part adds its cycle's iteration count and histories
+// to the run's; it goes on to the next cycle if no rule ended the cycle and
+// iterations are left, else its status becomes final.  *nalive receives the
+// number of slices that go on.
+__global__ __launch_bounds__(1024) void cycle_end_k(int *__restrict__ alive, const int *__restrict__ citers,
+                                                    const int *__restrict__ cstatus, const double *__restrict__ lamh,
+                                                    const double *__restrict__ rhoh, int K, int *__restrict__ iters,
+                                                    int *__restrict__ status, double *__restrict__ out_lam,
+                                                    double *__restrict__ out_rho, int ktot, int done,
+                                                    int *__restrict__ nalive, int S) {
+    int cnt = 0;
+    for (int s = threadIdx.x; s < S; s += blockDim.x) {
+        if (!alive[s]) continue;
+        const int kc = citers[s], st = cstatus[s];
+        if (out_lam)
+            for (int j = 0; j < kc; ++j) out_lam[(int64_t)s * ktot + done + j] = lamh[(int64_t)s * K + j];
+        if (out_rho) {
+            if (done == 0) out_rho[(int64_t)s * (ktot + 1)] = rhoh[(int64_t)s * (K + 1)];
+            for (int j = 1; j <= kc; ++j)
+                out_rho[(int64_t)s * (ktot + 1) + done + j] = rhoh[(int64_t)s * (K + 1) + j];
+        }
+        iters[s] = done + kc;
+        if ((st == 0 || st == ABBA_ST_KMAX) && kc > 0 && done + kc < ktot) {
+            ++cnt;
+        } else {
+            status[s] = st ? st : ABBA_ST_KMAX;
+            alive[s] = 0;
+        }
+    }
+    __shared__ int red[16];
+    int v = cnt;
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int t = 0;
+        for (int w = 0; w < (int)(blockDim.x >> 6); ++w) t += red[w];
+        *nalive = t;
+    }
+}
+
 __global__ void copy_hist_k(const double *__restrict__ src, int sstride, double *__restrict__ dst, int dstride,
                             int cols, int S) {
     const int s = blockIdx.x;
     if (s >= S) return;
     for (int j = threadIdx.x; j < cols; j += blockDim.x) dst[(size_t)s * dstride + j] = src[(size_t)s * sstride + j];
+}
+
+// One cycle of the method for every slice with alive[s] (all if alive is
+// NULL): r_0, beta, w_1 from the current x, then up to kcap iterations, each
+// ending in the stopping rules; cfg.iters / cfg.status receive the iteration
+// count and status of the cycle.
+static int run_cycle(const SolveDims &d, const SolveWS &ws, const IterCfg &cfg, const void *b, void *x,
+                     const int *alive, int kcap, const abba_exec &ex, hipGraphExec_t *gexec, hipGraph_t *graph,
+                     hipStream_t st) {
+    Launch L0{st, nullptr, nullptr};
+    const int64_t wsl = (int64_t)d.wslots * d.ldw;
+    int rc;
+    // histories past a slice's stopping iteration read as NaN
+    hipLaunchKernelGGL(fill_k, dim3(64), dim3(256), 0, st, ws.lamh, (int64_t)d.S * d.K, (double)NAN);
+    ABBA_LAUNCHED("fill_k");
+    hipLaunchKernelGGL(fill_k, dim3(64), dim3(256), 0, st, ws.rhoh, (int64_t)d.S * (d.K + 1), (double)NAN);
+    ABBA_LAUNCHED("fill_k");
+
+    // ---- initialisation: r_0, beta, w_1 (Alg. 1 lines 1-3, Alg. 2 lines 1-3)
+    if ((rc = launch_zero_pad(d.w_dt, ws.W, wsl, d.wslots, d.ldw, d.len, d.S, st))) return rc;
+    if (ws.P && (rc = launch_zero_pad(d.img_dt, ws.P, (int64_t)d.pslots * d.ldn, d.pslots, d.ldn, d.n, d.S, st)))
+        return rc;
+    VecRef xin{x, d.n, 0, 0};
+    VecRef sino{ws.sino, d.ldm, 0, 0};
+    if ((rc = apply_op(cfg.A, true, xin, d.img_dt, sino, d.sino_dt, d, ws, L0))) return rc;
+    if (d.mode == ABBA_MODE_AB) {
+        // r_0 = b - A x_0 (basis storage), rho_0 = beta
+        if ((rc = launch_sub(d.sino_dt, b, d.m, ws.sino, d.ldm, d.w_dt, ws.W, wsl, d.m, d.ldw, d.S, st))) return rc;
+        if ((rc = launch_norm(d.w_dt, ws.W, wsl, d.m, d.S, ws.npart, ws.rhoh, d.K + 1, st))) return rc;
+    } else {
+        // b - A x_0 kept in `sino` (data residual); r_0 = B(b - A x_0)
+        if ((rc = launch_sub(d.sino_dt, b, d.m, ws.sino, d.ldm, d.sino_dt, ws.sino, d.ldm, d.m, d.ldm, d.S, st)))
+            return rc;
+        if ((rc = launch_norm(d.sino_dt, ws.sino, d.ldm, d.m, d.S, ws.npart, ws.rhoh, d.K + 1, st))) return rc;
+        VecRef w0{ws.W, wsl, 0, 0};
+        if ((rc = apply_op(cfg.B, false, sino, d.sino_dt, w0, d.w_dt, d, ws, L0))) return rc;
+    }
+    if ((rc = normalize_first(d, ws, cfg.iters, cfg.status, alive, st))) return rc;
+    if ((cfg.learned || d.feat_out || d.labels) && (rc = learned_prepare(d, ws, x, cfg.out, st))) return rc;
+    if (d.ortho == ABBA_ORTHO_DELAYED) {
+        // step 0 of the delayed schedule: M w_1 and its first pass, giving
+        // the once-orthogonalised second vector (no projected problem yet)
+        hipLaunchKernelGGL(set_int_k, dim3(1), dim3(1), 0, st, ws.kdev, 0);
+        ABBA_LAUNCHED("set_int_k");
+        Launch L1{st, ws.kdev, ws.active};
+        if ((rc = apply_M(d, ws, cfg, L1))) return rc;
+        if ((rc = dcgs2_step(d, ws, ws.kdev, st))) return rc;
+    }
+    hipLaunchKernelGGL(set_int_k, dim3(1), dim3(1), 0, st, ws.kdev, 1);
+    ABBA_LAUNCHED("set_int_k");
+
+    // ---- iterations
+    if (ex.use_graph && !*gexec) {
+        hipStream_t cap;
+        ABBA_HIP(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
+        hipError_t e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
+        if (e != hipSuccess) {
+            (void)hipStreamDestroy(cap);
+            return hip_fail(e, "hipStreamBeginCapture");
+        }
+        rc = one_iteration(d, ws, cfg, cap);
+        e = hipStreamEndCapture(cap, graph);
+        (void)hipStreamDestroy(cap);
+        if (rc) return rc;
+        if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture");
+        e = hipGraphInstantiate(gexec, *graph, nullptr, nullptr, 0);
+        if (e != hipSuccess) return hip_fail(e, "hipGraphInstantiate");
+    }
+    const bool polling = cfg.stop_kind != ABBA_STOP_NONE;
+    int host_nact = d.S;
+    for (int it = 1; it <= kcap; ++it) {
+        if (*gexec) {
+            hipError_t e = hipGraphLaunch(*gexec, st);
+            if (e != hipSuccess) return hip_fail(e, "hipGraphLaunch");
+        } else if ((rc = one_iteration(d, ws, cfg, st))) {
+            return rc;
+        }
+        if (polling && (it % ex.poll_every == 0) && it < kcap) {
+            hipError_t e = hipMemcpyAsync(&host_nact, ws.nact, sizeof(int), hipMemcpyDeviceToHost, st);
+            if (e == hipSuccess) e = hipStreamSynchronize(st);
+            if (e != hipSuccess) return hip_fail(e, "active-slice poll");
+            if (host_nact == 0) break;
+        }
+    }
+    return ABBA_OK;
+}
+
+// x += P_k y_k (AB) or W_k y_k (BA) with each slice's own k = iters[s].
+static int assemble_cycle(const SolveDims &d, const SolveWS &ws, void *x, const int *iters, hipStream_t st) {
+    int rc;
+    if (d.mode == ABBA_MODE_AB) {
+        // delayed schedule: P holds B applied to the vectors before their
+        // second pass, B W_k y = P' (T y)
+        const double *yk = ws.y;
+        if (d.ortho == ABBA_ORTHO_DELAYED) {
+            if ((rc = launch_ty(d, ws, iters, nullptr, nullptr, st))) return rc;
+            yk = ws.y2;
+        }
+        return launch_assemble(d.img_dt, ws.P, (int64_t)d.pslots * d.ldn, d.ldn, d.img_dt, x, d.n, yk, d.K, iters,
+                               d.S, st);
+    }
+    return launch_assemble(d.w_dt, ws.W, (int64_t)d.wslots * d.ldw, d.ldw, d.img_dt, x, d.n, ws.y, d.K, iters,
+                           d.S, st);
 }
 
 }  // namespace abba
@@ -263,7 +421,8 @@ extern "C" int abba_solve_workspace(const abba_op *A, const abba_op *B, int batc
     abba_out dummy;
     std::memset(&dummy, 0, sizeof(dummy));
     dummy.resid = (double *)1;   // size for the worst case (Z kept in BA mode)
-    int rc = make_dims(A, B, batch, mode, k, stop, &dummy, &d);
+    const int kc = exec && exec->restart > 0 && exec->restart < k ? exec->restart : k;
+    int rc = make_dims(A, B, batch, mode, kc, stop, &dummy, &d);
     if (rc) return rc;
     d.labels = exec && (exec->features & ABBA_FEAT_LABELS) && mode == ABBA_MODE_AB;
     *bytes = solve_workspace_bytes(d, nullptr, nullptr, op_scratch_bytes(A, B, batch));
@@ -277,8 +436,21 @@ extern "C" int abba_solve(const abba_op *A, const abba_op *B, const void *b, voi
         set_error("abba_solve: b, x, reg, out.iters, out.status and workspace are required");
         return ABBA_ERR_ARG;
     }
+    abba_exec ex{0, 1, 0, 0, ABBA_ORTHO_DELAYED};
+    if (exec) ex = *exec;
+    if (ex.restart < 0) {
+        set_error("restart cycle length must be >= 0");
+        return ABBA_ERR_ARG;
+    }
+    if (k < 1) {
+        set_error("k = %d must be >= 1", k);
+        return ABBA_ERR_ARG;
+    }
+    // restarted runs keep a basis of one cycle (Sec. 3.3); k is then the total
+    const bool restarting = ex.restart > 0 && ex.restart < k;
+    const int kc = restarting ? ex.restart : k;
     SolveDims d;
-    int rc = make_dims(A, B, batch, mode, k, stop, out, &d);
+    int rc = make_dims(A, B, batch, mode, kc, stop, out, &d);
     if (rc) return rc;
     const int rule = reg->kind;
     if (rule < ABBA_REG_NONE || rule > ABBA_REG_LEARNED) {
@@ -324,16 +496,14 @@ extern "C" int abba_solve(const abba_op *A, const abba_op *B, const void *b, voi
         set_error("the learned stop needs the learned lambda rule (it shares the model)");
         return ABBA_ERR_ARG;
     }
-    abba_exec ex{0, 1, 0, 0, ABBA_ORTHO_DELAYED};
-    if (exec) ex = *exec;
     if (ex.ortho != ABBA_ORTHO_DELAYED && ex.ortho != ABBA_ORTHO_CGS2) {
         set_error("unknown Gram-Schmidt schedule %d", ex.ortho);
         return ABBA_ERR_ARG;
     }
     d.ortho = ex.ortho;
     if (ex.poll_every < 1) ex.poll_every = 1;
-    if (ex.restart != 0) {
-        set_error("restarted cycles are not implemented");
+    if (restarting && (rule == ABBA_REG_LEARNED || ex.features)) {
+        set_error("the learned rule, features and labels are defined for unrestarted runs");
         return ABBA_ERR_UNSUPPORTED;
     }
     if (ex.features & ~(ABBA_FEAT_OUT | ABBA_FEAT_LABELS)) {
@@ -363,35 +533,7 @@ extern "C" int abba_solve(const abba_op *A, const abba_op *B, const void *b, voi
         return ABBA_ERR_ARG;
     }
     hipStream_t st = (hipStream_t)stream;
-    Launch L0{st, nullptr, nullptr};
-    const int64_t wsl = (int64_t)d.wslots * d.ldw;
     if ((rc = smallsolve_prepare())) return rc;
-    // histories past a slice's stopping iteration read as NaN
-    hipLaunchKernelGGL(fill_k, dim3(64), dim3(256), 0, st, ws.lamh, (int64_t)d.S * d.K, (double)NAN);
-    ABBA_LAUNCHED("fill_k");
-    hipLaunchKernelGGL(fill_k, dim3(64), dim3(256), 0, st, ws.rhoh, (int64_t)d.S * (d.K + 1), (double)NAN);
-    ABBA_LAUNCHED("fill_k");
-
-    // ---- initialisation: r_0, beta, w_1 (Alg. 1 lines 1-3, Alg. 2 lines 1-3)
-    if ((rc = launch_zero_pad(d.w_dt, ws.W, wsl, d.wslots, d.ldw, d.len, d.S, st))) return rc;
-    if (ws.P && (rc = launch_zero_pad(d.img_dt, ws.P, (int64_t)d.pslots * d.ldn, d.pslots, d.ldn, d.n, d.S, st)))
-        return rc;
-    VecRef xin{x, d.n, 0, 0};
-    VecRef sino{ws.sino, d.ldm, 0, 0};
-    if ((rc = apply_op(A, true, xin, d.img_dt, sino, d.sino_dt, d, ws, L0))) return rc;
-    if (d.mode == ABBA_MODE_AB) {
-        // r_0 = b - A x_0 (basis storage), rho_0 = beta
-        if ((rc = launch_sub(d.sino_dt, b, d.m, ws.sino, d.ldm, d.w_dt, ws.W, wsl, d.m, d.ldw, d.S, st))) return rc;
-        if ((rc = launch_norm(d.w_dt, ws.W, wsl, d.m, d.S, ws.npart, ws.rhoh, d.K + 1, st))) return rc;
-    } else {
-        // b - A x_0 kept in `sino` (data residual); r_0 = B(b - A x_0)
-        if ((rc = launch_sub(d.sino_dt, b, d.m, ws.sino, d.ldm, d.sino_dt, ws.sino, d.ldm, d.m, d.ldm, d.S, st)))
-            return rc;
-        if ((rc = launch_norm(d.sino_dt, ws.sino, d.ldm, d.m, d.S, ws.npart, ws.rhoh, d.K + 1, st))) return rc;
-        VecRef w0{ws.W, wsl, 0, 0};
-        if ((rc = apply_op(B, false, sino, d.sino_dt, w0, d.w_dt, d, ws, L0))) return rc;
-    }
-    if ((rc = normalize_first(d, ws, out->iters, out->status, st))) return rc;
 
     IterCfg cfg;
     cfg.A = A;
@@ -404,98 +546,69 @@ extern "C" int abba_solve(const abba_op *A, const abba_op *B, const void *b, voi
     cfg.stop_tau = stop ? stop->tau : 0.0;
     cfg.rns_eps = stop ? stop->rns_eps : 0.0;
     cfg.noise_stop = stop ? stop->noise_norm : nullptr;
-    cfg.iters = out->iters;
-    cfg.status = out->status;
+    // a restarted run counts iterations and status per cycle, then merges them
+    cfg.iters = restarting ? ws.citers : out->iters;
+    cfg.status = restarting ? ws.cstatus : out->status;
     cfg.learned = rule == ABBA_REG_LEARNED;
     cfg.reg = reg;
     cfg.out = out;
     cfg.x0 = x;
-    if ((cfg.learned || d.feat_out || d.labels) && (rc = learned_prepare(d, ws, x, out, st))) return rc;
-    if (d.ortho == ABBA_ORTHO_DELAYED) {
-        // step 0 of the delayed schedule: M w_1 and its first pass, giving
-        // the once-orthogonalised second vector (no projected problem yet)
-        hipLaunchKernelGGL(set_int_k, dim3(1), dim3(1), 0, st, ws.kdev, 0);
-        ABBA_LAUNCHED("set_int_k");
-        Launch L1{st, ws.kdev, ws.active};
-        if ((rc = apply_M(d, ws, cfg, L1))) return rc;
-        if ((rc = dcgs2_step(d, ws, ws.kdev, st))) return rc;
-    }
-    hipLaunchKernelGGL(set_int_k, dim3(1), dim3(1), 0, st, ws.kdev, 1);
-    ABBA_LAUNCHED("set_int_k");
-
-    // ---- iterations
     hipGraphExec_t gexec = nullptr;
     hipGraph_t graph = nullptr;
-    if (ex.use_graph) {
-        hipStream_t cap;
-        ABBA_HIP(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
-        hipError_t e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
-        if (e != hipSuccess) {
-            (void)hipStreamDestroy(cap);
-            return hip_fail(e, "hipStreamBeginCapture");
-        }
-        rc = one_iteration(d, ws, cfg, cap);
-        e = hipStreamEndCapture(cap, &graph);
-        (void)hipStreamDestroy(cap);
-        if (rc) {
-            if (graph) (void)hipGraphDestroy(graph);
-            return rc;
-        }
-        if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture");
-        e = hipGraphInstantiate(&gexec, graph, nullptr, nullptr, 0);
-        if (e != hipSuccess) {
-            (void)hipGraphDestroy(graph);
-            return hip_fail(e, "hipGraphInstantiate");
-        }
-    }
-    const bool polling = stop_kind != ABBA_STOP_NONE;
-    int host_nact = d.S;
-    for (int it = 1; it <= d.K; ++it) {
-        if (gexec) {
-            hipError_t e = hipGraphLaunch(gexec, st);
-            if (e != hipSuccess) {
-                rc = hip_fail(e, "hipGraphLaunch");
-                break;
-            }
-        } else if ((rc = one_iteration(d, ws, cfg, st))) {
-            break;
-        }
-        if (polling && (it % ex.poll_every == 0) && it < d.K) {
-            hipError_t e = hipMemcpyAsync(&host_nact, ws.nact, sizeof(int), hipMemcpyDeviceToHost, st);
-            if (e == hipSuccess) e = hipStreamSynchronize(st);
-            if (e != hipSuccess) {
-                rc = hip_fail(e, "active-slice poll");
-                break;
-            }
-            if (host_nact == 0) break;
-        }
-    }
-    if (gexec) (void)hipGraphExecDestroy(gexec);
-    if (graph) (void)hipGraphDestroy(graph);
-    if (rc) return rc;
+    auto cleanup = [&]() {
+        if (gexec) (void)hipGraphExecDestroy(gexec);
+        if (graph) (void)hipGraphDestroy(graph);
+    };
 
-    // ---- x_k = x_0 + P_k y_k (AB) or x_0 + W_k y_k (BA) at each slice's stop
-    if (d.mode == ABBA_MODE_AB) {
-        // delayed schedule: P holds B applied to the vectors before their
-        // second pass, B W_k y = P' (T y)
-        const double *yk = ws.y;
-        if (d.ortho == ABBA_ORTHO_DELAYED) {
-            if ((rc = launch_ty(d, ws, out->iters, nullptr, nullptr, st))) return rc;
-            yk = ws.y2;
+    if (!restarting) {
+        rc = run_cycle(d, ws, cfg, b, x, nullptr, d.K, ex, &gexec, &graph, st);
+        if (!rc) rc = assemble_cycle(d, ws, x, out->iters, st);
+        cleanup();
+        if (rc) return rc;
+        if (out->lambda) {
+            hipLaunchKernelGGL(copy_hist_k, dim3(d.S), dim3(128), 0, st, ws.lamh, d.K, out->lambda, d.K, d.K, d.S);
+            ABBA_LAUNCHED("copy_hist_k");
         }
-        rc = launch_assemble(d.img_dt, ws.P, (int64_t)d.pslots * d.ldn, d.ldn, d.img_dt, x, d.n, yk, d.K,
-                             out->iters, d.S, st);
-    } else
-        rc = launch_assemble(d.w_dt, ws.W, wsl, d.ldw, d.img_dt, x, d.n, ws.y, d.K, out->iters, d.S, st);
-    if (rc) return rc;
+        if (out->resid) {
+            hipLaunchKernelGGL(copy_hist_k, dim3(d.S), dim3(128), 0, st, ws.rhoh, d.K + 1, out->resid, d.K + 1,
+                               d.K + 1, d.S);
+            ABBA_LAUNCHED("copy_hist_k");
+        }
+        return ABBA_OK;
+    }
+
+    // ---- restarted cycles (Sec. 3.3): x_0 <- the last cycle's iterate
     if (out->lambda) {
-        hipLaunchKernelGGL(copy_hist_k, dim3(d.S), dim3(128), 0, st, ws.lamh, d.K, out->lambda, d.K, d.K, d.S);
-        ABBA_LAUNCHED("copy_hist_k");
+        hipLaunchKernelGGL(fill_k, dim3(64), dim3(256), 0, st, out->lambda, (int64_t)d.S * k, (double)NAN);
+        ABBA_LAUNCHED("fill_k");
     }
     if (out->resid) {
-        hipLaunchKernelGGL(copy_hist_k, dim3(d.S), dim3(128), 0, st, ws.rhoh, d.K + 1, out->resid, d.K + 1,
-                           d.K + 1, d.S);
-        ABBA_LAUNCHED("copy_hist_k");
+        hipLaunchKernelGGL(fill_k, dim3(64), dim3(256), 0, st, out->resid, (int64_t)d.S * (k + 1), (double)NAN);
+        ABBA_LAUNCHED("fill_k");
     }
-    return ABBA_OK;
+    hipLaunchKernelGGL(cycle_begin_k, dim3((d.S + 255) / 256), dim3(256), 0, st, ws.alive, out->iters, out->status,
+                       d.S);
+    ABBA_LAUNCHED("cycle_begin_k");
+    for (int done = 0; done < k && !rc;) {
+        const int pc = std::min(d.K, k - done);
+        rc = run_cycle(d, ws, cfg, b, x, ws.alive, pc, ex, &gexec, &graph, st);
+        if (!rc) rc = assemble_cycle(d, ws, x, ws.citers, st);
+        if (rc) break;
+        hipLaunchKernelGGL(cycle_end_k, dim3(1), dim3(1024), 0, st, ws.alive, ws.citers, ws.cstatus, ws.lamh,
+                           ws.rhoh, d.K, out->iters, out->status, out->lambda, out->resid, k, done, ws.nact, d.S);
+        ABBA_LAUNCHED("cycle_end_k");
+        done += pc;
+        if (done < k) {
+            int alive = 0;
+            hipError_t e = hipMemcpyAsync(&alive, ws.nact, sizeof(int), hipMemcpyDeviceToHost, st);
+            if (e == hipSuccess) e = hipStreamSynchronize(st);
+            if (e != hipSuccess) {
+                rc = hip_fail(e, "alive-slice poll");
+                break;
+            }
+            if (alive == 0) break;
+        }
+    }
+    cleanup();
+    return rc;
 }

@@ -327,3 +327,67 @@ def test_c2_full_run_properties(pk):
         assert np.all(np.isfinite(lam)) and np.all(lam > 0)
         assert np.all(np.isfinite(rho)) and rho[-1] < rho[0]
         assert int(info["iters"][0]) == 100 and rre < 0.2
+
+
+@pytest.mark.parametrize("mode", ["AB", "BA"])
+@pytest.mark.parametrize("ortho", ["dcgs2", "cgs2"])
+def test_restarted_parity(pk, mode, ortho):
+    """Restarted cycles (Sec. 3.3) against the oracle: x, iteration count,
+    lambda and rho histories over the whole run; the basis holds one cycle."""
+    A, B, og, xt, bd, bu, ens = problem(pk, 64, 90, 91, 0.01, 0, 12, dt="f64")
+    K, p = 11, 4
+    x, info = pk.solve(A, B, bd, mode=mode, k=K, reg="gcv", restart=p, ortho=ortho)
+    o = osv.hybrid_gmres_restarted(og.A, og.B, bu[0], p=p, mode=mode, K=K, rule="gcv")
+    ex = rel(x.cpu().numpy(), o.x)
+    er = rel(info["resid"][0].cpu().numpy(), o.rho)
+    lam = info["lam"][0].cpu().numpy()
+    el = float(np.max(np.abs(lam / np.array(o.lam) - 1)))
+    print(f"restart {mode} {ortho} p={p}: x {ex:.2e} rho {er:.2e} lam {el:.2e}")
+    assert int(info["iters"][0]) == K and int(info["status"][0]) == pk.ST_KMAX
+    assert ex <= 1e-8 and er <= 1e-8 and el <= 1e-6
+    assert pk.workspace_bytes(A, B, 1, mode, K, restart=p) < pk.workspace_bytes(A, B, 1, mode, K)
+
+
+def test_restarted_dp_stop_and_batch(pk):
+    """Three slices with different noise levels stop by the discrepancy
+    principle in different cycles; each equals its own run and the oracle."""
+    A, B, og, xt, bd, bu, ens = problem(pk, 64, 90, 91, 0.05, 0, 13, dt="f64", batch=3)
+    # DP thresholds tau ||e|| of 1.16, 1.171 and 1.23 ||e||: the oracle's
+    # restarted GCV runs first meet them at k = 7, 13 and 5 (cycles 2, 3, 1)
+    scale = np.array([1.16, 1.171, 1.23]) / 1.01
+    noise = torch.tensor(ens * scale, device="cuda", dtype=torch.float64)
+    K, p = 40, 6
+    x, info = pk.solve(A, B, bd, mode="AB", k=K, reg="gcv", restart=p, stop="dp", noise_norm=noise)
+    iters = info["iters"].cpu().numpy()
+    for s in range(3):
+        o = osv.hybrid_gmres_restarted(og.A, og.B, bu[s], p=p, mode="AB", K=K, rule="gcv", stop="dp",
+                                       noise_norm=float(ens[s] * scale[s]))
+        ex = rel(x[s].cpu().numpy(), o.x)
+        print(f"slice {s}: iters {iters[s]} / oracle {o.iters}, status {int(info['status'][s])}, x {ex:.2e}")
+        assert iters[s] == o.iters and int(info["status"][s]) == o.status and ex <= 1e-8
+        x1, i1 = pk.solve(A, B, bd[s:s + 1].contiguous(), mode="AB", k=K, reg="gcv", restart=p, stop="dp",
+                          noise_norm=noise[s:s + 1])
+        assert torch.equal(x1[0], x[s]) and int(i1["iters"][0]) == iters[s]
+    assert iters.tolist() == [7, 13, 5]
+
+
+def test_restarted_budget_beyond_one_basis(pk):
+    """k = 150 total iterations in cycles of 25 (one basis never exceeds 25
+    vectors), FP32 against the oracle with the FP32 gate."""
+    A, B, og, xt, bd, bu, ens = problem(pk, 32, 45, 47, 0.02, 0, 14, dt="f32")
+    x, info = pk.solve(A, B, bd, mode="BA", k=150, reg="gcv", restart=25)
+    o = osv.hybrid_gmres_restarted(og.A, og.B, bu[0], p=25, mode="BA", K=150, rule="gcv")
+    ex = rel(x.cpu().numpy(), o.x)
+    print(f"restart k=150 p=25 BA f32: x {ex:.2e}, iters {int(info['iters'][0])}")
+    assert int(info["iters"][0]) == 150 and ex <= 1e-4
+
+
+def test_restart_argument_errors(pk):
+    A, B, og, xt, bd, bu, ens = problem(pk, 16, 20, 23, 0.01, 0, 1)
+    th = torch.zeros(pk.MLP_PARAMS, device="cuda")
+    with pytest.raises(pk.AbbaError):
+        pk.solve(A, B, bd, k=10, restart=-1)
+    with pytest.raises(pk.AbbaError):
+        pk.solve(A, B, bd, k=10, restart=3, reg="learned", mlp=th)
+    with pytest.raises(pk.AbbaError):
+        pk.solve(A, B, bd, k=10, restart=3, features=True)
