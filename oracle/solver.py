@@ -59,6 +59,9 @@ STATUS_STOP_RNS = 4
 STATUS_BREAKDOWN = 8
 STATUS_NONFINITE = 16
 STATUS_STOP_LEARNED = 32
+STATUS_STOP_NCP = 64
+
+NCP_KS = 1.36      # 5 % Kolmogorov-Smirnov band: +-1.36 / sqrt(q)
 
 BREAKDOWN_TOL = 1e-14
 
@@ -78,6 +81,31 @@ class Result:
     xs: list = field(default_factory=list)         # x_k history when requested
     Mw_norms: list = field(default_factory=list)
     small: list = field(default_factory=list)      # per-iteration (sigma, uhat, u_{k+1}) when requested
+    ncp: list = field(default_factory=list)        # NCP distance of r_k, k = 1..iters (stop "ncp")
+
+
+def ncp_distance(r, det: int) -> float:
+    """Distance of the residual's normalised cumulative periodogram (NCP) from
+    that of white noise (Sec. 3.2; Hansen 2010).  r is read as rows of `det`
+    detector bins (a sinogram); each row's periodogram |DFT|^2 at frequencies
+    1..q = det // 2 (the mean excluded) is summed over the rows, the NCP is
+    c_f = sum_{j<=f} P_j / sum_{j<=q} P_j, and the distance is
+    max_f |c_f - f/q| (0 when the spectrum is empty)."""
+    R = np.asarray(r, dtype=np.float64).reshape(-1, det)
+    q = det // 2
+    P = (np.abs(np.fft.fft(R, axis=1)) ** 2)[:, 1:q + 1].sum(axis=0)
+    tot = float(P.sum())
+    if q < 1 or tot == 0.0:
+        return 0.0
+    c = np.cumsum(P) / tot
+    return float(np.max(np.abs(c - np.arange(1, q + 1) / q)))
+
+
+def ncp_white(r, det: int) -> bool:
+    """The NCP stopping test: the residual passes as white noise when its NCP
+    stays within the 5 % Kolmogorov-Smirnov band around the straight line."""
+    q = det // 2
+    return q >= 1 and ncp_distance(r, det) <= NCP_KS / math.sqrt(q)
 
 
 def hybrid_gmres(A, B, b, mode: str = "AB", K: int = 30, rule: str = "gcv",
@@ -85,16 +113,17 @@ def hybrid_gmres(A, B, b, mode: str = "AB", K: int = 30, rule: str = "gcv",
                  noise_norm: float | None = None, rns_eps: float = 1e-3,
                  x0=None, ortho: str = "cgs2", keep_x: bool = False,
                  keep_basis: bool = False, keep_small: bool = False, mlp=None,
-                 judge_delta: float = 0.05) -> Result:
+                 judge_delta: float = 0.05, det: int | None = None) -> Result:
     """Run hybrid AB- or BA-GMRES for at most K iterations.
 
     A, B     -- callables on flat FP64 vectors (R^n -> R^m and R^m -> R^n)
     rule     -- lambda rule: "none", "fixed" (uses lam), "gcv", "dp", "lcurve",
                 or "learned" (the network `mlp` proposes lambda, judged against
                 GCV with margin judge_delta; see oracle.learned)
-    stop     -- None (run K iterations), "dp", "rns" or "learned" (the
-                network's stop index, with the discrepancy principle first
-                when noise_norm is given)
+    stop     -- None (run K iterations), "dp", "rns", "ncp" (the residual,
+                read as rows of `det` bins, passes the NCP white-noise test)
+                or "learned" (the network's stop index, with the discrepancy
+                principle first when noise_norm is given)
     """
     b = np.asarray(b, dtype=np.float64).reshape(-1)
     if x0 is None:
@@ -121,6 +150,8 @@ def hybrid_gmres(A, B, b, mode: str = "AB", K: int = 30, rule: str = "gcv",
         return out
     if rule == "learned" and mlp is None:
         raise ValueError("the learned rule needs the network parameters")
+    if stop == "ncp" and not det:
+        raise ValueError("the NCP test needs the detector row length det")
     if stop == "learned" and rule != "learned":
         raise ValueError("the learned stop shares the learned rule's network")
     gres = [beta]
@@ -233,6 +264,11 @@ def hybrid_gmres(A, B, b, mode: str = "AB", K: int = 30, rule: str = "gcv",
         if stop == "rns" and abs(out.rho[-2] - rho) / out.rho[-2] < rns_eps:
             status = STATUS_STOP_RNS
             break
+        if stop == "ncp":
+            out.ncp.append(ncp_distance(rk, det))
+            if ncp_white(rk, det):
+                status = STATUS_STOP_NCP
+                break
         if stop == "learned" and k >= k_hat:
             status = STATUS_STOP_LEARNED
             break
@@ -248,7 +284,7 @@ def hybrid_gmres(A, B, b, mode: str = "AB", K: int = 30, rule: str = "gcv",
 def hybrid_gmres_restarted(A, B, b, p: int, mode: str = "AB", K: int = 30, rule: str = "gcv",
                            lam: float = 0.0, stop: str | None = None, tau: float = 1.01,
                            noise_norm: float | None = None, rns_eps: float = 1e-3, x0=None,
-                           ortho: str = "cgs2") -> Result:
+                           ortho: str = "cgs2", det: int | None = None) -> Result:
     """Restarted hybrid AB-/BA-GMRES (Sec. 3.3): cycles of at most p iterations,
     each started from the final iterate of the previous cycle, K iterations
     in all.  lambda and the stopping rule act on every iteration of every
@@ -265,7 +301,7 @@ def hybrid_gmres_restarted(A, B, b, p: int, mode: str = "AB", K: int = 30, rule:
     while done < K:
         pc = min(p, K - done)
         out = hybrid_gmres(A, B, b, mode=mode, K=pc, rule=rule, lam=lam, stop=stop, tau=tau,
-                           noise_norm=noise_norm, rns_eps=rns_eps, x0=x, ortho=ortho)
+                           noise_norm=noise_norm, rns_eps=rns_eps, x0=x, ortho=ortho, det=det)
         if rho_h is None:
             rho_h = [out.rho[0]]
         rho_h += out.rho[1:]

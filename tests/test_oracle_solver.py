@@ -386,3 +386,57 @@ def _restart_problem(eta=0.01):
     bt = og.A(x).ravel()
     b, _ = synth.add_relative_noise(bt, synth.noise_direction(0, 11, bt.size), eta)
     return og, b
+
+
+def test_ncp_of_a_sinusoid_is_a_step():
+    # one frequency f0 in every row: the NCP is 0 below f0 and 1 from f0 on,
+    # so the distance is max((f0 - 1)/q, 1 - f0/q)
+    D, rows = 40, 3
+    q = D // 2
+    for f0 in (1, 5, 13, 20):
+        d = np.arange(D)
+        r = np.stack([np.cos(2 * np.pi * f0 * d / D + 0.3 * a) for a in range(rows)]).ravel()
+        want = max((f0 - 1) / q, 1 - f0 / q)
+        assert abs(sv.ncp_distance(r, D) - want) <= 1e-12
+
+
+def test_ncp_against_a_brute_force_dft():
+    rng = np.random.default_rng(3)
+    D, rows = 17, 4
+    r = rng.standard_normal(rows * D) + np.linspace(0, 3, rows * D)
+    R = r.reshape(rows, D)
+    q = D // 2
+    P = np.zeros(q)
+    for f in range(1, q + 1):
+        for a in range(rows):
+            re = sum(R[a, j] * math.cos(2 * math.pi * f * j / D) for j in range(D))
+            im = sum(R[a, j] * math.sin(2 * math.pi * f * j / D) for j in range(D))
+            P[f - 1] += re * re + im * im
+    c = np.cumsum(P) / P.sum()
+    want = max(abs(c[f - 1] - f / q) for f in range(1, q + 1))
+    assert abs(sv.ncp_distance(r, D) - want) <= 1e-12
+
+
+def test_ncp_white_noise_passes_and_smooth_signal_fails():
+    rng = np.random.default_rng(4)
+    D, rows = 91, 90
+    assert sv.ncp_white(rng.standard_normal(rows * D), D)
+    d = np.arange(D)
+    smooth = np.tile(np.exp(-((d - 45) / 12.0) ** 2), rows) + 0.01 * rng.standard_normal(rows * D)
+    assert not sv.ncp_white(smooth, D)
+    assert sv.ncp_distance(np.zeros(rows * D), D) == 0.0
+
+
+def test_ncp_stop_fires_once_the_residual_is_white(oracle_lib):
+    og = Par2DOps(Par2D(32, 32, 45, 47))
+    x, _ = synth.phantom2d(0, 15, 32)
+    bt = og.A(x).ravel()
+    b, en = synth.add_relative_noise(bt, synth.noise_direction(0, 15, bt.size), 0.02)
+    o = sv.hybrid_gmres(og.A, og.B, b, mode="AB", K=40, rule="gcv", stop="ncp", det=47)
+    assert o.status == sv.STATUS_STOP_NCP and 1 < o.iters < 40
+    thr = sv.NCP_KS / math.sqrt(47 // 2)
+    assert o.ncp[-1] <= thr and all(v > thr for v in o.ncp[:-1])
+    # as the paper reports for its test problem, NCP stops before the
+    # discrepancy principle does
+    od = sv.hybrid_gmres(og.A, og.B, b, mode="AB", K=40, rule="gcv", stop="dp", noise_norm=en)
+    assert od.status == sv.STATUS_STOP_DP and o.iters < od.iters
