@@ -152,15 +152,20 @@ typedef enum {
 } abba_reg_kind;
 
 /* Stopping rules (Sec. 3.2): none (run k iterations), discrepancy principle,
- * residual-norm stagnation, learned stop index. */
+ * residual-norm stagnation, learned stop index, normalised cumulative
+ * periodogram.  NCP reads the data residual b - A x_k as rows of det_u
+ * detector bins; each row's periodogram |DFT|^2 at frequencies 1..q,
+ * q = det_u / 2, is summed over the rows; the run stops at the first k whose
+ * NCP c_f = sum_{j<=f} P_j / sum_j P_j stays within the 5 % Kolmogorov-Smirnov
+ * band of white noise: max_f |c_f - f/q| <= 1.36 / sqrt(q). */
 typedef enum {
-    ABBA_STOP_NONE = 0, ABBA_STOP_DP = 1, ABBA_STOP_RNS = 2, ABBA_STOP_LEARNED = 3
+    ABBA_STOP_NONE = 0, ABBA_STOP_DP = 1, ABBA_STOP_RNS = 2, ABBA_STOP_LEARNED = 3, ABBA_STOP_NCP = 4
 } abba_stop_kind;
 
 /* Per-slice status bits written to abba_out.status. */
 enum {
     ABBA_ST_KMAX = 1, ABBA_ST_STOP_DP = 2, ABBA_ST_STOP_RNS = 4, ABBA_ST_BREAKDOWN = 8,
-    ABBA_ST_NONFINITE = 16, ABBA_ST_STOP_LEARNED = 32
+    ABBA_ST_NONFINITE = 16, ABBA_ST_STOP_LEARNED = 32, ABBA_ST_STOP_NCP = 64
 };
 
 typedef struct {
@@ -188,6 +193,8 @@ typedef struct {
                                   ABBA_FEAT_OUT): the learned-rule features of iteration j
                                   in row j-1; rows past a slice's stop are left as they are */
     const void *x_true;        /* device [batch][n], image dtype (bit ABBA_FEAT_LABELS)    */
+    double *ncp;               /* device [batch*k] or NULL (ABBA_STOP_NCP): the NCP distance
+                                  max_f |c_f - f/q| of r_j, j = 1..k                        */
     double *rre;               /* device [batch][k][ABBA_LABEL_GRID] (bit ABBA_FEAT_LABELS):
                                   ||x_j(lam_g) - x_true|| / ||x_true|| for the grid
                                   lam_g = sigma_1(H_j) 10^(-8 + 8 g / 63), AB mode only   */

@@ -19,7 +19,7 @@ from dataclasses import dataclass
 __all__ = [
     "LIB_PATH", "lib", "AbbaError", "Geometry", "Operator", "project", "backproject", "solve",
     "workspace_bytes", "ST_KMAX", "ST_STOP_DP", "ST_STOP_RNS", "ST_BREAKDOWN", "ST_NONFINITE",
-    "ST_STOP_LEARNED", "autotune", "set_tuning", "get_tuning", "mlp_forward", "mlp_loss_grad", "mlp_adam", "mlp_labels", "MLP_PARAMS",
+    "ST_STOP_LEARNED", "ST_STOP_NCP", "autotune", "set_tuning", "get_tuning", "mlp_forward", "mlp_loss_grad", "mlp_adam", "mlp_labels", "MLP_PARAMS",
 ]
 
 LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libabba.so")
@@ -30,8 +30,9 @@ GEOM_PAR2D, GEOM_CONE3D = 0, 1
 OP_JOSEPH, OP_PIXEL, OP_JOSEPH_T = 0, 1, 2
 MODE_AB, MODE_BA = 0, 1
 REG = {"none": 0, "fixed": 1, "gcv": 2, "dp": 3, "lcurve": 4, "learned": 5}
-STOP = {None: 0, "none": 0, "dp": 1, "rns": 2, "learned": 3}
+STOP = {None: 0, "none": 0, "dp": 1, "rns": 2, "learned": 3, "ncp": 4}
 ST_KMAX, ST_STOP_DP, ST_STOP_RNS, ST_BREAKDOWN, ST_NONFINITE, ST_STOP_LEARNED = 1, 2, 4, 8, 16, 32
+ST_STOP_NCP = 64
 
 
 class AbbaError(RuntimeError):
@@ -62,7 +63,7 @@ class _Stop(ctypes.Structure):
 class _Out(ctypes.Structure):
     _fields_ = [("iters", ctypes.c_void_p), ("status", ctypes.c_void_p), ("lam", ctypes.c_void_p),
                 ("resid", ctypes.c_void_p), ("features", ctypes.c_void_p), ("x_true", ctypes.c_void_p),
-                ("rre", ctypes.c_void_p)]
+                ("ncp", ctypes.c_void_p), ("rre", ctypes.c_void_p)]
 
 
 class _Tune(ctypes.Structure):
@@ -376,6 +377,8 @@ def solve(A: Operator, B: Operator, b, mode: str = "AB", k: int = 30, reg: str =
     o.iters, o.status = iters.data_ptr(), status.data_ptr()
     o.lam = None if lamh is None else lamh.data_ptr()
     o.resid = None if resh is None else resh.data_ptr()
+    ncph = torch.empty((batch, k), dtype=torch.float64, device=dev) if (history and stop == "ncp") else None
+    o.ncp = None if ncph is None else ncph.data_ptr()
     feats = torch.zeros((batch, k, MLP_FEATURES), dtype=torch.float32, device=dev) if features else None
     o.features = None if feats is None else feats.data_ptr()
     rre = None
@@ -396,7 +399,7 @@ def solve(A: Operator, B: Operator, b, mode: str = "AB", k: int = 30, reg: str =
     _check(lib.abba_solve(A.handle, B.handle, _ptr(b), _ptr(x), batch, m, k, ctypes.byref(r), ctypes.byref(s),
                           ctypes.byref(o), ctypes.byref(e), _ptr(workspace), workspace.numel(), _stream_ptr()),
            "abba_solve")
-    info = dict(iters=iters, status=status, lam=lamh, resid=resh, features=feats, rre=rre)
+    info = dict(iters=iters, status=status, lam=lamh, resid=resh, features=feats, rre=rre, ncp=ncph)
     return x, info
 
 
@@ -479,7 +482,7 @@ def mlp_train(params, X, T, epochs, batch=4096, lr=1e-3, seed=0, log=None):
 
 def status_names(code: int):
     names = {ST_KMAX: "kmax", ST_STOP_DP: "dp", ST_STOP_RNS: "rns", ST_BREAKDOWN: "breakdown",
-             ST_NONFINITE: "nonfinite", ST_STOP_LEARNED: "learned"}
+             ST_NONFINITE: "nonfinite", ST_STOP_LEARNED: "learned", ST_STOP_NCP: "ncp"}
     return [v for b_, v in names.items() if code & b_]
 
 

@@ -438,7 +438,8 @@ __global__ __launch_bounds__(1024) void stop_k(int S, int K, int stop_kind, doub
                                                int *__restrict__ active, const int *__restrict__ flags,
                                                int *__restrict__ iters, int *__restrict__ status,
                                                int *__restrict__ kdev, int *__restrict__ nact,
-                                               const double *__restrict__ sc, int has_rho) {
+                                               const double *__restrict__ sc, int has_rho,
+                                               const double *__restrict__ ncpd, double ncp_thr) {
     const int k = *kdev;
     int cnt = 0;
     for (int s = threadIdx.x; s < S; s += blockDim.x) {
@@ -456,6 +457,8 @@ __global__ __launch_bounds__(1024) void stop_k(int S, int K, int stop_kind, doub
         else if (stop_kind == ABBA_STOP_RNS && fabs(rprev - rho) / rprev < rns_eps) st = ABBA_ST_STOP_RNS;
         else if (stop_kind == ABBA_STOP_LEARNED && sc && (double)k >= sc[(size_t)s * SC_COUNT + SC_KLEARN])
             st = ABBA_ST_STOP_LEARNED;
+        else if (stop_kind == ABBA_STOP_NCP && ncpd && ncpd[s] <= ncp_thr)
+            st = ABBA_ST_STOP_NCP;
         else if (k >= K) st = ABBA_ST_KMAX;
         iters[s] = k;
         if (st) {
@@ -544,7 +547,8 @@ int launch_stop(const SolveDims &d, const SolveWS &ws, int stop_kind, double tau
                 const double *noise, int *iters, int *status, hipStream_t st) {
     hipLaunchKernelGGL(stop_k, dim3(1), dim3(1024), 0, st, d.S, d.K, stop_kind, tau, rns_eps, noise, ws.rhoh,
                        ws.active, ws.flags, iters, status, ws.kdev, ws.nact, ws.sc,
-                       (d.mode == ABBA_MODE_AB || d.keepZ) ? 1 : 0);
+                       (d.mode == ABBA_MODE_AB || d.keepZ) ? 1 : 0, d.ncp ? ws.ncpd : nullptr,
+                       d.ncp ? 1.36 / sqrt((double)(d.det / 2)) : 0.0);
     ABBA_LAUNCHED("stop_k");
     return ABBA_OK;
 }

@@ -11,6 +11,11 @@ constexpr int RED_BLOCKS = 128;
 constexpr int DOT_JT = 8;
 // Largest Krylov dimension handled by the small-solve kernel.
 constexpr int KMAX_SMALL = 100;
+// NCP stopping rule: detector rows per workgroup of the periodogram kernel,
+// and the longest detector row it handles (q = det / 2 <= 1024).
+constexpr int NCP_RC = 16;
+constexpr int NCP_MAX_DET = 2049;
+int ncp_row_chunks(int rows);
 
 // Per-slice scalars kept by the small solve, FP64.
 enum {
@@ -47,6 +52,9 @@ struct SolveDims {
     int ortho;      // ABBA_ORTHO_*
     int feat_out;   // write the learned-rule features to out.features
     int labels;     // write RRE label grids to out.rre (AB mode)
+    int ncp;        // the NCP stopping rule: residual vectors and periodograms
+    int det;        // NCP: bins per detector row
+    int nrch;       // NCP: row chunks per slice of the periodogram kernel
 };
 
 // Workspace carve-up (device pointers).
@@ -78,6 +86,11 @@ struct SolveWS {
     double *gres;   // [S][K+1] plain GMRES residual history (r_0 = beta)
     double *gram;   // [S][K][K+1] labels: Gram matrix of P' and P'^T (x_true - x_0)
     double *enorm;  // [S][2]  labels: ||x_true - x_0||^2, ||x_true||^2
+    void *rvec;     // [S][ldm]  NCP: the data residual r_k (accumulation type)
+    double *tcoef;  // [S][K+1]  NCP: coefficients of r_k in the kept vectors
+    float *spec;    // [S][nrch][q] NCP: periodogram partial sums
+    double *ncpd;   // [S]       NCP: distance of the current iteration
+    double *ncph;   // [S][K]    NCP: distance history of the cycle
     int *citers;    // [S] restarted runs: iterations of the current cycle
     int *cstatus;   // [S] restarted runs: status of the current cycle
     int *alive;     // [S] restarted runs: the slice takes part in the next cycle

@@ -45,6 +45,7 @@ int launch_stop(const SolveDims &d, const SolveWS &ws, int stop_kind, double tau
 int launch_finish_resid(const SolveDims &d, const SolveWS &ws, int nblk, hipStream_t st);
 int smallsolve_prepare();
 int learned_prepare(const SolveDims &d, const SolveWS &ws, const void *x0, const abba_out *out, hipStream_t st);
+int launch_ncp(const SolveDims &d, const SolveWS &ws, const double *coef_ba, hipStream_t st);
 int learned_step(const SolveDims &d, const SolveWS &ws, const abba_reg *reg, int learned, const void *x0,
                  const abba_out *out, hipStream_t st);
 
@@ -98,6 +99,13 @@ size_t solve_workspace_bytes(const SolveDims &d, SolveWS *ws, void *base, size_t
     w.gres = (double *)take(S * (K + 1) * 8);
     w.gram = d.labels ? (double *)take(S * K * (K + 1) * 8) : nullptr;
     w.enorm = d.labels ? (double *)take(S * 2 * 8) : nullptr;
+    if (d.ncp) {
+        w.rvec = take(S * d.ldm * (d.w_dt == ABBA_F64 ? 8 : 4));
+        w.tcoef = (double *)take(S * (K + 1) * 8);
+        w.spec = (float *)take(S * d.nrch * (d.det / 2) * 4);
+        w.ncpd = (double *)take(S * 8);
+        w.ncph = (double *)take(S * K * 8);
+    }
     w.citers = (int *)take(S * 4);
     w.cstatus = (int *)take(S * 4);
     w.alive = (int *)take(S * 4);
@@ -163,6 +171,16 @@ static int make_dims(const abba_op *A, const abba_op *B, int batch, int mode, in
     d->wslots = k + 2;
     d->pslots = k + 1;
     d->ortho = ABBA_ORTHO_DELAYED;
+    if (stop && stop->kind == ABBA_STOP_NCP) {
+        const int det = A->g.det_u;
+        if (det < 2 || det > NCP_MAX_DET || A->m % det) {
+            set_error("the NCP rule reads rows of 2..%d detector bins (det_u = %d)", NCP_MAX_DET, det);
+            return ABBA_ERR_UNSUPPORTED;
+        }
+        d->ncp = 1;
+        d->det = det;
+        d->nrch = ncp_row_chunks((int)(A->m / det));
+    }
     return ABBA_OK;
 }
 
@@ -230,10 +248,10 @@ static int one_iteration(const SolveDims &d, const SolveWS &ws, const IterCfg &c
     if (c.learned || d.feat_out || d.labels) {
         if ((rc = learned_step(d, ws, c.reg, c.learned, c.x0, c.out, st))) return rc;
     }
+    const double *yk = ws.y;
     if (d.mode == ABBA_MODE_BA && d.keepZ) {
         // rho_k = ||(b - A x_0) - Z_k y_k||; with the delayed schedule Z holds
         // A applied to the vectors before their second pass: Z_k y = Z' (T y)
-        const double *yk = ws.y;
         if (delayed) {
             if ((rc = launch_ty(d, ws, nullptr, ws.kdev, ws.active, st))) return rc;
             yk = ws.y2;
@@ -243,6 +261,7 @@ static int one_iteration(const SolveDims &d, const SolveWS &ws, const IterCfg &c
         if (nb < 0) return nb;
         if ((rc = launch_finish_resid(d, ws, nb, st))) return rc;
     }
+    if (d.ncp && (rc = launch_ncp(d, ws, yk, st))) return rc;
     return launch_stop(d, ws, c.stop_kind, c.stop_tau, c.rns_eps, c.noise_stop, c.iters, c.status, st);
 }
 
@@ -261,9 +280,10 @@ __global__ void cycle_begin_k(int *__restrict__ alive, int *__restrict__ iters, 
 // number of slices that go on.
 __global__ __launch_bounds__(1024) void cycle_end_k(int *__restrict__ alive, const int *__restrict__ citers,
                                                     const int *__restrict__ cstatus, const double *__restrict__ lamh,
-                                                    const double *__restrict__ rhoh, int K, int *__restrict__ iters,
-                                                    int *__restrict__ status, double *__restrict__ out_lam,
-                                                    double *__restrict__ out_rho, int ktot, int done,
+                                                    const double *__restrict__ rhoh, const double *__restrict__ ncph,
+                                                    int K, int *__restrict__ iters, int *__restrict__ status,
+                                                    double *__restrict__ out_lam, double *__restrict__ out_rho,
+                                                    double *__restrict__ out_ncp, int ktot, int done,
                                                     int *__restrict__ nalive, int S) {
     int cnt = 0;
     for (int s = threadIdx.x; s < S; s += blockDim.x) {
@@ -271,6 +291,8 @@ __global__ __launch_bounds__(1024) void cycle_end_k(int *__restrict__ alive, con
         const int kc = citers[s], st = cstatus[s];
         if (out_lam)
             for (int j = 0; j < kc; ++j) out_lam[(int64_t)s * ktot + done + j] = lamh[(int64_t)s * K + j];
+        if (out_ncp && ncph)
+            for (int j = 0; j < kc; ++j) out_ncp[(int64_t)s * ktot + done + j] = ncph[(int64_t)s * K + j];
         if (out_rho) {
             if (done == 0) out_rho[(int64_t)s * (ktot + 1)] = rhoh[(int64_t)s * (K + 1)];
             for (int j = 1; j <= kc; ++j)
@@ -319,6 +341,10 @@ static int run_cycle(const SolveDims &d, const SolveWS &ws, const IterCfg &cfg, 
     ABBA_LAUNCHED("fill_k");
     hipLaunchKernelGGL(fill_k, dim3(64), dim3(256), 0, st, ws.rhoh, (int64_t)d.S * (d.K + 1), (double)NAN);
     ABBA_LAUNCHED("fill_k");
+    if (d.ncp) {
+        hipLaunchKernelGGL(fill_k, dim3(64), dim3(256), 0, st, ws.ncph, (int64_t)d.S * d.K, (double)NAN);
+        ABBA_LAUNCHED("fill_k");
+    }
 
     // ---- initialisation: r_0, beta, w_1 (Alg. 1 lines 1-3, Alg. 2 lines 1-3)
     if ((rc = launch_zero_pad(d.w_dt, ws.W, wsl, d.wslots, d.ldw, d.len, d.S, st))) return rc;
@@ -476,7 +502,7 @@ extern "C" int abba_solve(const abba_op *A, const abba_op *B, const void *b, voi
         return ABBA_ERR_ARG;
     }
     const int stop_kind = stop ? stop->kind : ABBA_STOP_NONE;
-    if (stop_kind < ABBA_STOP_NONE || stop_kind > ABBA_STOP_LEARNED) {
+    if (stop_kind < ABBA_STOP_NONE || stop_kind > ABBA_STOP_NCP) {
         set_error("unknown stopping rule %d", stop_kind);
         return ABBA_ERR_ARG;
     }
@@ -574,6 +600,10 @@ extern "C" int abba_solve(const abba_op *A, const abba_op *B, const void *b, voi
                                d.K + 1, d.S);
             ABBA_LAUNCHED("copy_hist_k");
         }
+        if (out->ncp && d.ncp) {
+            hipLaunchKernelGGL(copy_hist_k, dim3(d.S), dim3(128), 0, st, ws.ncph, d.K, out->ncp, d.K, d.K, d.S);
+            ABBA_LAUNCHED("copy_hist_k");
+        }
         return ABBA_OK;
     }
 
@@ -586,6 +616,10 @@ extern "C" int abba_solve(const abba_op *A, const abba_op *B, const void *b, voi
         hipLaunchKernelGGL(fill_k, dim3(64), dim3(256), 0, st, out->resid, (int64_t)d.S * (k + 1), (double)NAN);
         ABBA_LAUNCHED("fill_k");
     }
+    if (out->ncp && d.ncp) {
+        hipLaunchKernelGGL(fill_k, dim3(64), dim3(256), 0, st, out->ncp, (int64_t)d.S * k, (double)NAN);
+        ABBA_LAUNCHED("fill_k");
+    }
     hipLaunchKernelGGL(cycle_begin_k, dim3((d.S + 255) / 256), dim3(256), 0, st, ws.alive, out->iters, out->status,
                        d.S);
     ABBA_LAUNCHED("cycle_begin_k");
@@ -595,7 +629,8 @@ extern "C" int abba_solve(const abba_op *A, const abba_op *B, const void *b, voi
         if (!rc) rc = assemble_cycle(d, ws, x, ws.citers, st);
         if (rc) break;
         hipLaunchKernelGGL(cycle_end_k, dim3(1), dim3(1024), 0, st, ws.alive, ws.citers, ws.cstatus, ws.lamh,
-                           ws.rhoh, d.K, out->iters, out->status, out->lambda, out->resid, k, done, ws.nact, d.S);
+                           ws.rhoh, d.ncp ? ws.ncph : nullptr, d.K, out->iters, out->status, out->lambda, out->resid,
+                           d.ncp ? out->ncp : nullptr, k, done, ws.nact, d.S);
         ABBA_LAUNCHED("cycle_end_k");
         done += pc;
         if (done < k) {

@@ -391,3 +391,41 @@ def test_restart_argument_errors(pk):
         pk.solve(A, B, bd, k=10, restart=3, reg="learned", mlp=th)
     with pytest.raises(pk.AbbaError):
         pk.solve(A, B, bd, k=10, restart=3, features=True)
+
+
+@pytest.mark.parametrize("mode", ["AB", "BA"])
+def test_ncp_stop_parity(pk, mode):
+    """NCP stopping (Sec. 3.2): the distance history of the residual's
+    cumulative periodogram from white noise, the stop iteration and x against
+    the oracle (FP64 path; periodograms are summed in FP32 on the GPU, so the
+    distance is compared to 1e-6)."""
+    A, B, og, xt, bd, bu, ens = problem(pk, 32, 45, 47, 0.02, 0, 15, dt="f64")
+    K = 40
+    x, info = pk.solve(A, B, bd, mode=mode, k=K, reg="gcv", stop="ncp")
+    o = osv.hybrid_gmres(og.A, og.B, bu[0], mode=mode, K=K, rule="gcv", stop="ncp", det=47)
+    it = int(info["iters"][0])
+    d = info["ncp"][0].cpu().numpy()[:it]
+    ed = float(np.max(np.abs(d - np.array(o.ncp))))
+    ex = rel(x.cpu().numpy(), o.x)
+    thr = osv.NCP_KS / np.sqrt(47 // 2)
+    print(f"NCP {mode}: iters {it} / oracle {o.iters}, distance max diff {ed:.2e}, x {ex:.2e}; "
+          f"distances {np.round(d, 4).tolist()} (band {thr:.4f})")
+    assert o.status == osv.STATUS_STOP_NCP and int(info["status"][0]) == pk.ST_STOP_NCP
+    assert it == o.iters and ed <= 1e-6 and ex <= 1e-8
+
+
+def test_ncp_stop_batch_f32(pk):
+    """FP32 path, three slices: each stops where its own per-slice run stops,
+    with distances within the FP32 gate of the oracle's."""
+    A, B, og, xt, bd, bu, ens = problem(pk, 32, 45, 47, 0.02, 0, 16, dt="f32", batch=3)
+    K = 40
+    x, info = pk.solve(A, B, bd, mode="AB", k=K, reg="gcv", stop="ncp", use_graph=True, poll_every=3)
+    for s in range(3):
+        o = osv.hybrid_gmres(og.A, og.B, bu[s], mode="AB", K=K, rule="gcv", stop="ncp", det=47)
+        it = int(info["iters"][s])
+        d = info["ncp"][s].cpu().numpy()[:min(it, o.iters)]
+        ed = float(np.max(np.abs(d - np.array(o.ncp)[:d.size])))
+        print(f"slice {s}: iters {it} / oracle {o.iters}, distance max diff {ed:.2e}")
+        assert ed <= 1e-4 and abs(it - o.iters) <= 1
+        x1, i1 = pk.solve(A, B, bd[s:s + 1].contiguous(), mode="AB", k=K, reg="gcv", stop="ncp")
+        assert torch.equal(x1[0], x[s]) and int(i1["iters"][0]) == it
