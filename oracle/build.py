@@ -40,8 +40,11 @@ def load_oracle():
     lib.oracle_cone_bp.argtypes = [dp, dp, i, i, i, i, i, i, d, d, dp, dp, dp, dp]
     lib.oracle_cone_bp_points.argtypes = [dp, ctypes.POINTER(ctypes.c_longlong), dp, i, i, i, i, i, i, i, d, d,
                                           dp, dp, dp, dp]
+    lib.oracle_fan_fwd.argtypes = [dp, dp, i, i, i, i, d, dp, dp, dp]
+    lib.oracle_fan_bp.argtypes = [dp, dp, i, i, i, i, d, dp, dp, dp]
     for f in (lib.oracle_joseph2d, lib.oracle_joseph2d_t, lib.oracle_pixbp2d,
-              lib.oracle_cone_fwd, lib.oracle_cone_bp, lib.oracle_cone_bp_points):
+              lib.oracle_cone_fwd, lib.oracle_cone_bp, lib.oracle_cone_bp_points,
+              lib.oracle_fan_fwd, lib.oracle_fan_bp):
         f.restype = None
     _lib = lib
     return lib

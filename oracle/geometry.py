@@ -10,6 +10,10 @@ floating point; for user angles by |cos t| >= |sin t| in FP64.
 source S = sid*(cos b, sin b, 0); flat detector centred at
 D = -(sdd - sid)*(cos b, sin b, 0) with column axis eu = (-sin b, cos b, 0)
 and row axis ev = (0, 0, 1).
+
+2D fan beam, flat detector: the image plane of the cone geometry -- view v
+at beta_v = 2*pi*v/n_views (unless given), source sid*(cos b, sin b),
+detector centre -(sdd - sid)*(cos b, sin b), column axis (-sin b, cos b).
 """
 from __future__ import annotations
 
@@ -92,3 +96,36 @@ class Cone3D:
     @property
     def m(self) -> int:
         return self.n_views * self.nu * self.nv
+
+
+@dataclass
+class FanFlat2D:
+    nx: int
+    ny: int
+    n_views: int
+    nu: int
+    pu: float
+    sid: float
+    sdd: float
+    angles: np.ndarray | None = None
+    src: np.ndarray = field(init=False)
+    det: np.ndarray = field(init=False)
+    eu: np.ndarray = field(init=False)
+
+    def __post_init__(self):
+        if self.angles is None:
+            beta = 2.0 * math.pi * np.arange(self.n_views) / self.n_views
+        else:
+            beta = np.asarray(self.angles, dtype=np.float64)
+        c, s = np.cos(beta), np.sin(beta)
+        self.src = np.stack([self.sid * c, self.sid * s], axis=1)
+        self.det = np.stack([-(self.sdd - self.sid) * c, -(self.sdd - self.sid) * s], axis=1)
+        self.eu = np.stack([-s, c], axis=1)
+
+    @property
+    def n(self) -> int:
+        return self.nx * self.ny
+
+    @property
+    def m(self) -> int:
+        return self.n_views * self.nu

@@ -139,3 +139,39 @@ class Cone3DOps:
         self.lib.oracle_cone_bp(_p(y), _p(x), g.nx, g.ny, g.nz, g.n_views, g.nu, g.nv,
                                 g.pu, g.pv, _p(self._src), _p(self._det), _p(self._eu), _p(self._ev))
         return x
+
+
+class FanFlat2DOps:
+    """A (Joseph) and B (pixel driven, weight M / pu) of the 2D fan beam with a
+    flat detector, over the plain-C definitions in projectors.c."""
+
+    def __init__(self, geom):
+        self.g = geom
+        self.lib = load_oracle()
+        self._src = np.ascontiguousarray(geom.src)
+        self._det = np.ascontiguousarray(geom.det)
+        self._eu = np.ascontiguousarray(geom.eu)
+
+    @property
+    def n(self):
+        return self.g.n
+
+    @property
+    def m(self):
+        return self.g.m
+
+    def A(self, x):
+        g = self.g
+        x = np.ascontiguousarray(x, dtype=np.float64).reshape(g.n)
+        y = np.zeros(g.m)
+        self.lib.oracle_fan_fwd(_p(x), _p(y), g.nx, g.ny, g.n_views, g.nu, g.pu, _p(self._src), _p(self._det),
+                                _p(self._eu))
+        return y
+
+    def B(self, y):
+        g = self.g
+        y = np.ascontiguousarray(y, dtype=np.float64).reshape(g.m)
+        x = np.zeros(g.n)
+        self.lib.oracle_fan_bp(_p(y), _p(x), g.nx, g.ny, g.n_views, g.nu, g.pu, _p(self._src), _p(self._det),
+                               _p(self._eu))
+        return x

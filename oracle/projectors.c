@@ -333,3 +333,85 @@ static double cone_bp_voxel(const double *sino, int nx, int ny, int nz,
     }
     return acc;
 }
+
+/* ------------------------------------------------------------------------
+ * 2D fan beam with a flat detector (the geometry of the paper's third test
+ * problem).  View w: source S_w, detector centre D_w, column axis U_w (unit),
+ * all in the image plane; bin c at D + (c - (nu-1)/2) pu U.
+ *
+ * A: for the line S->P, march over the columns (|dx| >= |dy|) or rows of the
+ *    image and interpolate linearly along the other axis at the crossing,
+ *    zero outside, weighted by |P - S| / |(P - S)_major| (the step length).
+ * B: pixel driven.  Project the pixel centre X from S onto the detector line:
+ *    M = (D - S).n / (X - S).n with n = the unit normal of the detector
+ *    (pointing from the detector to the source), u = (S + M (X - S) - D).U / pu
+ *    + (nu-1)/2; interpolate the view linearly at u (zero outside) and weight
+ *    by M / pu.
+ * ---------------------------------------------------------------------- */
+static double fan_ray(const double *img, int nx, int ny, const double S[2], const double P[2])
+{
+    const double cx = 0.5 * (nx - 1), cy = 0.5 * (ny - 1);
+    const double d[2] = { P[0] - S[0], P[1] - S[1] };
+    const double len = sqrt(d[0] * d[0] + d[1] * d[1]);
+    double acc = 0.0;
+    if (fabs(d[0]) >= fabs(d[1])) {
+        for (int j = 0; j < nx; ++j) {
+            const double t = ((j - cx) - S[0]) / d[0];
+            const double yy = S[1] + t * d[1] + cy;
+            const double i0 = floor(yy), f = yy - i0;
+            acc += (1.0 - f) * pix2(img, nx, ny, (int)i0, j) + f * pix2(img, nx, ny, (int)i0 + 1, j);
+        }
+        return acc * len / fabs(d[0]);
+    }
+    for (int i = 0; i < ny; ++i) {
+        const double t = ((i - cy) - S[1]) / d[1];
+        const double xx = S[0] + t * d[0] + cx;
+        const double j0 = floor(xx), f = xx - j0;
+        acc += (1.0 - f) * pix2(img, nx, ny, i, (int)j0) + f * pix2(img, nx, ny, i, (int)j0 + 1);
+    }
+    return acc * len / fabs(d[1]);
+}
+
+void oracle_fan_fwd(const double *img, double *sino, int nx, int ny, int nviews, int nu, double pu,
+                    const double *src, const double *det, const double *eu)
+{
+    #pragma omp parallel for schedule(static) collapse(2)
+    for (int w = 0; w < nviews; ++w) {
+        for (int c = 0; c < nu; ++c) {
+            const double *S = src + 2 * w, *D = det + 2 * w, *U = eu + 2 * w;
+            const double ou = (c - 0.5 * (nu - 1)) * pu;
+            const double P[2] = { D[0] + ou * U[0], D[1] + ou * U[1] };
+            sino[(size_t)w * nu + c] = fan_ray(img, nx, ny, S, P);
+        }
+    }
+}
+
+void oracle_fan_bp(const double *sino, double *img, int nx, int ny, int nviews, int nu, double pu,
+                   const double *src, const double *det, const double *eu)
+{
+    const double cx = 0.5 * (nx - 1), cy = 0.5 * (ny - 1);
+    #pragma omp parallel for schedule(static) collapse(2)
+    for (int i = 0; i < ny; ++i) {
+        for (int j = 0; j < nx; ++j) {
+            const double X[2] = { j - cx, i - cy };
+            double acc = 0.0;
+            for (int w = 0; w < nviews; ++w) {
+                const double *S = src + 2 * w, *D = det + 2 * w, *U = eu + 2 * w;
+                /* unit normal of the detector line, towards the source */
+                const double n[2] = { U[1], -U[0] };
+                const double num = (D[0] - S[0]) * n[0] + (D[1] - S[1]) * n[1];
+                const double den = (X[0] - S[0]) * n[0] + (X[1] - S[1]) * n[1];
+                const double M = num / den;
+                const double P[2] = { S[0] + M * (X[0] - S[0]) - D[0], S[1] + M * (X[1] - S[1]) - D[1] };
+                const double u = (P[0] * U[0] + P[1] * U[1]) / pu + 0.5 * (nu - 1);
+                const double u0 = floor(u), f = u - u0;
+                const int c = (int)u0;
+                const double *row = sino + (size_t)w * nu;
+                const double a = (c >= 0 && c < nu) ? row[c] : 0.0;
+                const double b = (c + 1 >= 0 && c + 1 < nu) ? row[c + 1] : 0.0;
+                acc += ((1.0 - f) * a + f * b) * (M / pu);
+            }
+            img[(size_t)i * nx + j] = acc;
+        }
+    }
+}

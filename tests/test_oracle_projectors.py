@@ -290,3 +290,54 @@ def test_cone_backprojector_at_points_equals_full():
     y = np.random.default_rng(1).standard_normal(g.m)
     idx = np.array([0, 5, 77, 123, 500, g.n - 1])
     assert np.array_equal(o.B_points(y, idx), o.B(y)[idx])
+
+
+def test_fan_flat_approaches_parallel_beam(oracle_lib):
+    # a distant source with magnification 2 and detector pitch 2: fan view
+    # beta sees (to O(radius / sid)) the parallel projection at
+    # theta = beta + pi/2 with unit bins, for both A and B
+    from oracle.geometry import FanFlat2D, Par2D
+    from oracle.operators import FanFlat2DOps, Par2DOps
+    n, nd = 24, 37
+    beta = np.array([0.0, 0.3, 1.1, 2.0, 3.9, 5.5])
+    fan = FanFlat2DOps(FanFlat2D(n, n, beta.size, nd, 2.0, 1e7, 2e7, beta))
+    par = Par2DOps(Par2D(n, n, beta.size, nd, 1.0, beta + np.pi / 2))
+    r = np.random.default_rng(2)
+    x = r.uniform(size=n * n)
+    y = r.standard_normal(beta.size * nd)
+    ea = np.linalg.norm(fan.A(x) - par.A(x)) / np.linalg.norm(par.A(x))
+    eb = np.linalg.norm(fan.B(y) - par.B(y)) / np.linalg.norm(par.B(y))
+    assert ea < 1e-5 and eb < 1e-5
+
+
+def test_fan_flat_disk_chords(oracle_lib):
+    # A of a uniform disk against the chord lengths of the fan rays (the
+    # pixelisation error of the disk boundary shrinks at first order)
+    from oracle.geometry import FanFlat2D
+    from oracle.operators import FanFlat2DOps
+    errs = []
+    for n in (32, 64, 128):
+        R = 0.3 * n
+        c = np.arange(n) - 0.5 * (n - 1)
+        X, Y = np.meshgrid(c, c)
+        sub = 8
+        o = (np.arange(sub) + 0.5) / sub - 0.5
+        img = np.zeros((n, n))
+        for ox in o:
+            for oy in o:
+                img += ((X + ox) ** 2 + (Y + oy) ** 2 <= R * R)
+        img /= sub * sub
+        nu, pu, sid, sdd = int(2 * n), 1.0, 2.0 * n, 4.0 * n
+        g = FanFlat2D(n, n, 12, nu, pu, sid, sdd)
+        y = FanFlat2DOps(g).A(img).reshape(12, nu)
+        want = np.zeros_like(y)
+        for w in range(12):
+            S, D, U = g.src[w], g.det[w], g.eu[w]
+            for cc in range(nu):
+                P = D + (cc - 0.5 * (nu - 1)) * pu * U
+                d = (P - S) / np.linalg.norm(P - S)
+                # distance of the line from the centre, chord 2 sqrt(R^2 - h^2)
+                h = abs(S[0] * d[1] - S[1] * d[0])
+                want[w, cc] = 2 * np.sqrt(max(R * R - h * h, 0.0))
+        errs.append(np.abs(y - want).max() / (2 * R))
+    assert errs[0] > errs[1] > errs[2] and errs[2] < 0.03
