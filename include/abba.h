@@ -50,6 +50,14 @@
  *                       source-to-pixel ray, bilinear in the plane.
  *     ABBA_OP_PIXEL     B: voxel driven, bilinear on the detector, weight
  *                       (M/det_pitch_u)(M/det_pitch_v), M the magnification.
+ *   2D fan beam, flat detector (the image plane of the cone geometry: nz and
+ *   det_v are 1).  View v at b_v = 2*pi*v/views; source sid*(cos b, sin b);
+ *   detector at distance sdd from the source, bins along (-sin b, cos b) with
+ *   pitch det_pitch_u, centred on the central ray.
+ *     ABBA_OP_JOSEPH    A: Joseph along the dominant axis of each
+ *                       source-to-bin ray, linear interpolation, step weight.
+ *     ABBA_OP_PIXEL     B: pixel driven, linear on the detector, weight
+ *                       M/det_pitch_u.
  *   Outside the image or detector everything reads as zero.
  */
 #ifndef ABBA_H
@@ -74,7 +82,7 @@ typedef enum {
 } abba_status;
 
 typedef enum { ABBA_F64 = 0, ABBA_F32 = 1, ABBA_BF16 = 2 } abba_dtype;
-typedef enum { ABBA_GEOM_PAR2D = 0, ABBA_GEOM_CONE3D = 1 } abba_geom_kind;
+typedef enum { ABBA_GEOM_PAR2D = 0, ABBA_GEOM_CONE3D = 1, ABBA_GEOM_FAN2D = 2 } abba_geom_kind;
 typedef enum { ABBA_OP_JOSEPH = 0, ABBA_OP_PIXEL = 1, ABBA_OP_JOSEPH_T = 2 } abba_op_kind;
 
 typedef struct {

@@ -26,7 +26,7 @@ LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libabba.so"
 
 # enums of include/abba.h
 F64, F32, BF16 = 0, 1, 2
-GEOM_PAR2D, GEOM_CONE3D = 0, 1
+GEOM_PAR2D, GEOM_CONE3D, GEOM_FAN2D = 0, 1, 2
 OP_JOSEPH, OP_PIXEL, OP_JOSEPH_T = 0, 1, 2
 MODE_AB, MODE_BA = 0, 1
 REG = {"none": 0, "fixed": 1, "gcv": 2, "dp": 3, "lcurve": 4, "learned": 5}
@@ -167,7 +167,7 @@ class Geometry:
 
     def _c(self):
         g = _Geometry()
-        g.kind = GEOM_PAR2D if self.kind == "par2d" else GEOM_CONE3D
+        g.kind = {"par2d": GEOM_PAR2D, "cone3d": GEOM_CONE3D, "fan2d": GEOM_FAN2D}[self.kind]
         g.nx, g.ny, g.nz = self.nx, self.ny, self.nz
         g.n_angles, g.det_u, g.det_v = self.n_angles, self.det_u, self.det_v
         g.det_pitch_u, g.det_pitch_v = self.det_pitch_u, self.det_pitch_v
@@ -180,11 +180,11 @@ class Geometry:
 
     @property
     def image_shape(self):
-        return (self.ny, self.nx) if self.kind == "par2d" else (self.nz, self.ny, self.nx)
+        return (self.nz, self.ny, self.nx) if self.kind == "cone3d" else (self.ny, self.nx)
 
     @property
     def sino_shape(self):
-        return (self.n_angles, self.det_u) if self.kind == "par2d" else (self.n_angles, self.det_v, self.det_u)
+        return (self.n_angles, self.det_v, self.det_u) if self.kind == "cone3d" else (self.n_angles, self.det_u)
 
 
 _DT = {"f64": F64, "f32": F32, "bf16": BF16}

@@ -34,10 +34,11 @@ int validate_geometry(const abba_geometry *g, int kind) {
         set_error("geometry is NULL");
         return ABBA_ERR_ARG;
     }
-    if (g->kind != ABBA_GEOM_PAR2D && g->kind != ABBA_GEOM_CONE3D) {
+    if (g->kind != ABBA_GEOM_PAR2D && g->kind != ABBA_GEOM_CONE3D && g->kind != ABBA_GEOM_FAN2D) {
         set_error("unknown geometry kind %d", g->kind);
         return ABBA_ERR_ARG;
     }
+    const bool fan = g->kind == ABBA_GEOM_FAN2D;
     const bool cone = g->kind == ABBA_GEOM_CONE3D;
     if (g->nx <= 0 || g->ny <= 0 || g->n_angles <= 0 || g->det_u <= 0 || (cone && (g->nz <= 0 || g->det_v <= 0))) {
         set_error("geometry sizes must be positive");
@@ -46,6 +47,18 @@ int validate_geometry(const abba_geometry *g, int kind) {
     if (!cone && ((g->nz != 1 && g->nz != 0) || (g->det_v != 1 && g->det_v != 0))) {
         set_error("2D geometry needs nz = det_v = 1");
         return ABBA_ERR_ARG;
+    }
+    if (fan && 2.0 * g->sid <= std::sqrt((double)g->nx * g->nx + (double)g->ny * g->ny)) {
+        set_error("fan beam: the source (at distance sid from the centre) must lie outside the image");
+        return ABBA_ERR_ARG;
+    }
+    if (fan && !(g->sid > 0.0 && g->sdd > g->sid)) {
+        set_error("fan beam needs 0 < sid < sdd");
+        return ABBA_ERR_ARG;
+    }
+    if (fan && kind == ABBA_OP_JOSEPH_T) {
+        set_error("the exact transpose is implemented for parallel beams only");
+        return ABBA_ERR_UNSUPPORTED;
     }
     if (!(g->det_pitch_u > 0.0) || (cone && !(g->det_pitch_v > 0.0))) {
         set_error("detector pitch must be positive");
@@ -123,7 +136,7 @@ static void fill_tab2d(const abba_op *op, AngleTab<T> *t) {
 int build_cone_tables(abba_op *op);   // cone3d.hip
 
 int op_build_tables(abba_op *op) {
-    if (op->g.kind == ABBA_GEOM_CONE3D) return build_cone_tables(op);
+    if (cone_path(op)) return build_cone_tables(op);
     const int na = op->g.n_angles;
     size_t bytes;
     void *host;
@@ -208,10 +221,11 @@ int abba_op_create(abba_op **out, int kind, const abba_geometry *geom, int img_d
     if (!op) return ABBA_ERR_NOMEM;
     op->kind = kind;
     op->g = *geom;
-    if (op->g.kind == ABBA_GEOM_PAR2D) {
+    if (op->g.kind != ABBA_GEOM_CONE3D) {
         op->g.nz = 1;
         op->g.det_v = 1;
     }
+    if (op->g.kind == ABBA_GEOM_FAN2D) op->g.det_pitch_v = 1.0;
     if (geom->angles) {
         op->angles.assign(geom->angles, geom->angles + geom->n_angles);
         op->g.angles = op->angles.data();
@@ -286,7 +300,7 @@ int abba_project(const abba_op *A, const void *x, void *y, int batch, void *stre
     Launch L{st, nullptr, nullptr};
     VecRef xr{const_cast<void *>(x), A->n, 0, 0};
     VecRef yr{y, A->m, 0, 0};
-    const bool cone = A->g.kind == ABBA_GEOM_CONE3D;
+    const bool cone = cone_path(A);
     // the forward projector reads zero-padded copies of the image
     void *scr = nullptr;
     ABBA_HIP(hipMallocAsync(&scr, cone ? cone_scratch_bytes(A, batch) : par2d_scratch_bytes(A, batch), st));
@@ -314,7 +328,7 @@ int abba_backproject(const abba_op *B, const void *y, void *x, int batch, void *
     VecRef yr{const_cast<void *>(y), B->m, 0, 0};
     VecRef xr{x, B->n, 0, 0};
     if (B->kind == ABBA_OP_JOSEPH_T) return par2d_back(B, yr, B->sino_dtype, xr, batch, nullptr, L);
-    if (B->g.kind == ABBA_GEOM_CONE3D) {
+    if (cone_path(B)) {
         // the voxel-driven backprojector reads a zero-padded copy of the views
         void *scr = nullptr;
         ABBA_HIP(hipMallocAsync(&scr, cone_scratch_bytes(B, batch), st));
@@ -405,7 +419,7 @@ int abba_autotune(abba_op *op, int batch, int reps, void *stream, abba_tune *bes
     const int in_dt = fwd ? op->img_dtype : op->sino_dtype, out_dt = fwd ? op->sino_dtype : op->img_dtype;
     const int64_t in_len = (int64_t)batch * (fwd ? op->n : op->m), out_len = (int64_t)batch * (fwd ? op->m : op->n);
     TuneEntry cand[16];
-    const int nc = op->g.kind == ABBA_GEOM_CONE3D ? cone_tune_candidates(op, cand, 16)
+    const int nc = cone_path(op) ? cone_tune_candidates(op, cand, 16)
                                                   : par2d_tune_candidates(op, cand, 16);
     hipStream_t st = (hipStream_t)stream;
     void *in = nullptr, *out = nullptr;

@@ -12,6 +12,11 @@
 //    plane (magnification M = (D - S).n / (X - S).n), the view is
 //    interpolated bilinearly there and weighted by (M/pu)(M/pv).
 //
+// The 2D fan beam with a flat detector runs the same kernels as the z = 0
+// plane of this geometry (nz = nv = 1, pv = 1): the plane coordinate of every
+// tap is exactly 0, so the bilinear interpolation is the linear one, and B
+// takes the weight M/pu (one transverse dimension).
+//
 // Both read zero-padded copies of their input (two zeros on each side of the
 // two interpolated axes), so a clamped position reads its taps without masks:
 // for A one copy per dominant axis that occurs, permuted so that every plane
@@ -346,8 +351,9 @@ template <typename TI, int CZT>
 __global__ __launch_bounds__(256) void cone_bp_k(const typename acc_of<TI>::type *__restrict__ yp, int64_t ss,
                                                  VecRef xr, const ConeB<typename acc_of<TI>::type> *__restrict__ vb,
                                                  int nx, int ny, int nz, int nviews, int nu, int nv,
-                                                 typename acc_of<TI>::type ipp, int ntx, int nty, int ntz,
-                                                 uint32_t nxcc, int s0, const int *kdev, const int *active) {
+                                                 typename acc_of<TI>::type ipp, int mpow, int ntx, int nty,
+                                                 int ntz, uint32_t nxcc, int s0, const int *kdev,
+                                                 const int *active) {
     typedef typename acc_of<TI>::type T;
     const uint32_t w = cremap(blockIdx.x, gridDim.x, nxcc);
     const int txi = (int)(w % (uint32_t)ntx);
@@ -386,7 +392,8 @@ __global__ __launch_bounds__(256) void cone_bp_k(const typename acc_of<TI>::type
             const T *e = view + (int64_t)iv * Lu + iu;
             const T a00 = e[0], a01 = e[1], a10 = e[Lu], a11 = e[Lu + 1];
             const T lo = fma(fu, a01 - a00, a00), hi = fma(fu, a11 - a10, a10);
-            acc[m] = fma(M * M * ipp, fma(fv, hi - lo, lo), acc[m]);
+            const T wgt = mpow == 2 ? M * M * ipp : M * ipp;
+            acc[m] = fma(wgt, fma(fv, hi - lo, lo), acc[m]);
         }
     }
     if (i < ny && j < nx) {
@@ -467,8 +474,8 @@ static int cone_bp_launch(const abba_op *op, const typename acc_of<TI>::type *yp
         const int nb = std::min(ch, batch - s0);
         hipLaunchKernelGGL((cone_bp_k<TI, CZT>), dim3((uint32_t)(per * nb)), dim3(256), 0, L.stream, yp,
                            (int64_t)cc.sino, x, vb, g.nx, g.ny, g.nz, g.n_angles, g.det_u, g.det_v,
-                           (T)(1.0 / (g.det_pitch_u * g.det_pitch_v)), ntx, nty, ntz, (uint32_t)op->nxcc, s0, L.kdev,
-                           L.active);
+                           (T)(1.0 / (g.det_pitch_u * g.det_pitch_v)), g.kind == ABBA_GEOM_FAN2D ? 1 : 2, ntx, nty,
+                           ntz, (uint32_t)op->nxcc, s0, L.kdev, L.active);
         ABBA_LAUNCHED("cone_bp_k");
     }
     return ABBA_OK;

@@ -110,6 +110,10 @@ size_t cone_scratch_bytes(const abba_op *op, int batch);
 
 int op_build_tables(abba_op *op);
 
+// Cone beam and 2D fan beam run the same kernels (a fan-beam image is the
+// z = 0 plane of a cone-beam volume with one detector row).
+static inline bool cone_path(const abba_op *op) { return op->g.kind != ABBA_GEOM_PAR2D; }
+
 // Launch choices abba_autotune times (each computes the same result bits).
 int par2d_tune_candidates(const abba_op *op, TuneEntry *out, int cap);
 int cone_tune_candidates(const abba_op *op, TuneEntry *out, int cap);

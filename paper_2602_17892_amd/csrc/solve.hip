@@ -55,7 +55,7 @@ static inline int64_t round_up(int64_t v, int64_t a) { return (v + a - 1) / a * 
 static size_t op_scratch_bytes(const abba_op *A, const abba_op *B, int batch) {
     size_t b = 0;
     for (const abba_op *op : {A, B})
-        b = std::max(b, op->g.kind == ABBA_GEOM_CONE3D ? cone_scratch_bytes(op, batch) : par2d_scratch_bytes(op, batch));
+        b = std::max(b, cone_path(op) ? cone_scratch_bytes(op, batch) : par2d_scratch_bytes(op, batch));
     return b;
 }
 
@@ -194,10 +194,10 @@ __global__ void fill_k(double *__restrict__ p, int64_t n, double v) {
 static int apply_op(const abba_op *op, bool forward, VecRef in, int in_dt, VecRef out, int out_dt,
                     const SolveDims &d, const SolveWS &ws, const Launch &L) {
     if (forward) {
-        if (op->g.kind == ABBA_GEOM_CONE3D) return cone_forward(op, in, out, out_dt, d.S, ws.scratch, L);
+        if (cone_path(op)) return cone_forward(op, in, out, out_dt, d.S, ws.scratch, L);
         return par2d_forward(op, in, out, out_dt, d.S, ws.scratch, L);
     }
-    if (op->g.kind == ABBA_GEOM_CONE3D) return cone_back(op, in, in_dt, out, d.S, ws.scratch, L);
+    if (cone_path(op)) return cone_back(op, in, in_dt, out, d.S, ws.scratch, L);
     return par2d_back(op, in, in_dt, out, d.S, ws.scratch, L);
 }
 
