@@ -28,7 +28,9 @@ constexpr int NCP_FU = 4;                       // frequencies per thread: q <= 
 
 int ncp_row_chunks(int rows) { return (rows + NCP_RC - 1) / NCP_RC; }
 
-// t = beta e_1 - H_k y_k (k+1 entries), AB mode.
+// t = beta e_1 - H_k y_k (k+1 entries), AB mode.  Only the Hessenberg part of
+// H is stored (entries below the subdiagonal are never written), so row i
+// takes columns j >= i - 1.
 __global__ void ncp_coef_ab_k(const double *__restrict__ H, const double *__restrict__ y,
                               const double *__restrict__ sc, double *__restrict__ t, int K, const int *kdev,
                               const int *active) {
@@ -39,7 +41,7 @@ __global__ void ncp_coef_ab_k(const double *__restrict__ H, const double *__rest
     const double *ys = y + (int64_t)s * K;
     for (int i = threadIdx.x; i <= k; i += blockDim.x) {
         double v = i == 0 ? sc[(int64_t)s * SC_COUNT + SC_BETA] : 0.0;
-        for (int j = 0; j < k; ++j) v = fma(-Hs[(int64_t)j * (K + 1) + i], ys[j], v);
+        for (int j = i > 0 ? i - 1 : 0; j < k; ++j) v = fma(-Hs[(int64_t)j * (K + 1) + i], ys[j], v);
         t[(int64_t)s * (K + 1) + i] = v;
     }
 }
