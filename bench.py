@@ -70,10 +70,11 @@ def parse():
     p.add_argument("--roofline-reps", type=int, default=10)
     p.add_argument("--projectors-only", action="store_true",
                    help="only the projector launches (random images) and a copy of known size, for counter runs")
-    p.add_argument("--workload", choices=["slices", "cone", "learned"], default="slices",
+    p.add_argument("--workload", choices=["slices", "cone", "learned", "variants"], default="slices",
                    help="slices: the batched 2D workload (default); cone: the 3D cone-beam volume solve; "
                         "learned: train the lambda/stop network on method-generated runs, then compare it "
-                        "with GCV + DP")
+                        "with GCV + DP; variants: the benchmark batch with restarted cycles and with the NCP "
+                        "stop, and the 1024^2 fan-beam problem")
     p.add_argument("--train-runs", type=int, default=4096)
     p.add_argument("--eval-slices", type=int, default=1024)
     p.add_argument("--epochs", type=int, default=20)
@@ -495,6 +496,81 @@ def learned_workload(args):
     print(json.dumps(out), flush=True)
 
 
+def variants_workload(args):
+    """The 256 x 512^2 batch with restarted cycles of 20 (GCV, DP stop, 100
+    iterations in all) and with the NCP stop (GCV, at most 100), and one
+    1024^2 fan-beam slice (50 views, 1,024 bins of 3, SID 2048, SDD 4096,
+    1.5 % noise, AB with GCV and DP stop) beside the oracle's time for it."""
+    import numpy as np
+    import torch
+
+    import paper_2602_17892_amd as pk
+    import synth
+    torch.cuda.set_device(0)
+    S, K = args.slices, args.kmax
+    g = pk.Geometry(args.n, args.n, args.angles, args.det)
+    A, B = pk.Operator("joseph", g, "f32", "f32"), pk.Operator("pixel", g, "f32", "f32")
+    pk.autotune(A, S)
+    pk.autotune(B, S)
+    x, b, en, _ = make_inputs(args, pk, A, torch)
+    out = {"metric": "restarted / NCP / fan-beam variants", "config": {"workload": f"{S} x {args.n}^2 slices "
+           f"({args.angles} x {args.det}) and one 1024^2 fan-beam slice"}}
+
+    def rre(xr, xt):
+        n = xr.shape[0]
+        return (torch.linalg.vector_norm((xr - xt).reshape(n, -1).double(), dim=1)
+                / torch.linalg.vector_norm(xt.reshape(n, -1).double(), dim=1)).cpu().numpy()
+
+    for name, kw, p in (("plain", dict(stop="dp", noise_norm=en), 0), ("restart20", dict(stop="dp", noise_norm=en), 20),
+                        ("ncp", dict(stop="ncp"), 0)):
+        ws = torch.empty(pk.workspace_bytes(A, B, S, "AB", K, stop=kw["stop"], restart=p), dtype=torch.uint8,
+                         device="cuda")
+        run = lambda: pk.solve(A, B, b, mode="AB", k=K, reg="gcv", tau=1.01, use_graph=True, poll_every=args.poll,
+                               workspace=ws, history=False, restart=p, **kw)
+        run()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        xr, info = run()
+        torch.cuda.synchronize()
+        t = time.perf_counter() - t0
+        it = info["iters"].cpu().numpy()
+        out[name] = {"slices_per_s": round(S / t, 3), "workspace_gib": round(ws.numel() / 2 ** 30, 2),
+                     "iters_mean": float(it.mean()), "rre_median": float(np.median(rre(xr, x)))}
+        log(args, f"{name}: {S / t:.2f} slices/s, workspace {ws.numel() / 2 ** 30:.1f} GiB, iters mean "
+                  f"{it.mean():.1f}, median RRE {out[name]['rre_median']:.4f}")
+        del ws, xr
+    # the fan-beam problem (the shape of the paper's third test problem)
+    gf = pk.Geometry(1024, 1024, 50, 1024, det_pitch_u=3.0, kind="fan2d", sid=2048.0, sdd=4096.0)
+    Af, Bf = pk.Operator("joseph", gf, "f32", "f32"), pk.Operator("pixel", gf, "f32", "f32")
+    xf, bf, enf, _ = synth_batch(pk, Af, torch, 9, 0, 1, 1024, 0.015, 0.015)
+    runf = lambda: pk.solve(Af, Bf, bf, mode="AB", k=K, reg="gcv", stop="dp", tau=1.01, noise_norm=enf,
+                            history=False)
+    runf()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(5):
+        xs, info = runf()
+    torch.cuda.synchronize()
+    tf = (time.perf_counter() - t0) / 5
+    fan = {"seconds": round(tf, 4), "iters": int(info["iters"][0]), "rre": float(rre(xs, xf)[0])}
+    if not args.no_cpu_baseline:
+        import oracle
+        from oracle.geometry import FanFlat2D
+        from oracle.operators import FanFlat2DOps
+        from oracle.solver import hybrid_gmres
+        oracle.build_oracle(force=False)
+        og = FanFlat2DOps(FanFlat2D(1024, 1024, 50, 1024, 3.0, 2048.0, 4096.0))
+        t0 = time.perf_counter()
+        o = hybrid_gmres(og.A, og.B, bf[0].double().cpu().numpy().ravel(), mode="AB", K=K, rule="gcv", stop="dp",
+                         noise_norm=float(enf[0]))
+        fan["oracle_seconds"] = round(time.perf_counter() - t0, 3)
+        fan["oracle_iters"] = o.iters
+        fan["oracle_cores"] = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    out["fan_1024"] = fan
+    log(args, f"fan 1024^2 x 50 views: {tf * 1e3:.1f} ms per solve, {fan['iters']} iterations, RRE {fan['rre']:.4f}")
+    print(json.dumps(out), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -515,6 +591,9 @@ def main():
         return
     if args.workload == "learned":
         learned_workload(args)
+        return
+    if args.workload == "variants":
+        variants_workload(args)
         return
     torch.cuda.set_device(0)
     S, K = args.slices, args.kmax
