@@ -12,10 +12,9 @@
 //   3. the distance max_f |c_f - f/q| of the NCP c_f = sum_{j<=f} P_j / sum P
 //      from the straight line of white noise, which the stopping kernel
 //      compares with the 5 % Kolmogorov-Smirnov band 1.36 / sqrt(q).
-// The DFT is evaluated directly, one frequency per thread, with the twiddles
-// of the row length in LDS; the periodogram costs rows * q * det
-// multiply-adds per slice and iteration, which the rule adds only when it is
-// selected.
+// Each frequency of a row is evaluated by Goertzel's recurrence (FP64), one
+// frequency per thread; the periodogram costs rows * q * det multiply-adds per
+// slice and iteration, which the rule adds only when it is selected.
 #include <algorithm>
 #include <cmath>
 
@@ -67,7 +66,12 @@ __global__ __launch_bounds__(256) void ncp_resid_k(const TV *__restrict__ V, int
     }
 }
 
-// Periodogram partial sums over NCP_RC detector rows per workgroup.
+// Periodogram partial sums over NCP_RC detector rows per workgroup, one
+// frequency per thread, by Goertzel's recurrence in FP64:
+//   s_d = r_d + c s_{d-1} - s_{d-2}, c = 2 cos(2 pi f / det),
+//   |sum_d r_d e^{-2 pi i f d / det}|^2 = s_{N-1}^2 + s_{N-2}^2 - c s_{N-1} s_{N-2}
+// (one multiply-add per sample and frequency; the row is read from LDS by
+// all lanes at once).
 template <typename T>
 __global__ __launch_bounds__(NCP_THREADS) void ncp_spec_k(const T *__restrict__ r, int64_t ldr, int rows, int det,
                                                           int q, int nrch, float *__restrict__ spec,
@@ -75,36 +79,33 @@ __global__ __launch_bounds__(NCP_THREADS) void ncp_spec_k(const T *__restrict__ 
     const int s = blockIdx.y, ch = blockIdx.x;
     if (!active[s]) return;
     extern __shared__ __align__(16) unsigned char smem[];
-    T *twc = reinterpret_cast<T *>(smem), *tws = twc + det, *row = tws + det;
-    for (int j = threadIdx.x; j < det; j += NCP_THREADS) {
-        const double a = 2.0 * M_PI * (double)j / (double)det;
-        twc[j] = (T)cos(a);
-        tws[j] = (T)sin(a);
-    }
-    T pw[NCP_FU];
+    double *row = reinterpret_cast<double *>(smem);
+    double pw[NCP_FU], cf[NCP_FU];
 #pragma unroll
-    for (int u = 0; u < NCP_FU; ++u) pw[u] = 0;
+    for (int u = 0; u < NCP_FU; ++u) {
+        const int f = (int)threadIdx.x + 1 + u * NCP_THREADS;
+        pw[u] = 0.0;
+        cf[u] = 2.0 * cos(2.0 * M_PI * (double)f / (double)det);
+    }
     const T *rs = r + (int64_t)s * ldr;
     for (int rr = 0; rr < NCP_RC; ++rr) {
         const int a = ch * NCP_RC + rr;
         if (a >= rows) break;
         __syncthreads();   // the previous row is no longer read
-        for (int d = threadIdx.x; d < det; d += NCP_THREADS) row[d] = rs[(int64_t)a * det + d];
+        for (int d = threadIdx.x; d < det; d += NCP_THREADS) row[d] = (double)rs[(int64_t)a * det + d];
         __syncthreads();
 #pragma unroll
         for (int u = 0; u < NCP_FU; ++u) {
             const int f = (int)threadIdx.x + 1 + u * NCP_THREADS;
             if (f > q) continue;
-            T re = 0, im = 0;
-            int idx = 0;   // f d mod det
+            const double c = cf[u];
+            double s1 = 0.0, s2 = 0.0;
             for (int d = 0; d < det; ++d) {
-                const T v = row[d];
-                re = fma(v, twc[idx], re);
-                im = fma(v, tws[idx], im);
-                idx += f;
-                if (idx >= det) idx -= det;
+                const double s0 = fma(c, s1, row[d] - s2);
+                s2 = s1;
+                s1 = s0;
             }
-            pw[u] = fma(re, re, fma(im, im, pw[u]));
+            pw[u] += fma(s1, s1, fma(s2, s2, -c * s1 * s2));
         }
     }
 #pragma unroll
@@ -147,7 +148,7 @@ __global__ __launch_bounds__(256) void ncp_dist_k(const float *__restrict__ spec
 template <typename T>
 static int ncp_tail(const SolveDims &d, const SolveWS &ws, hipStream_t st) {
     const int rows = (int)(d.m / d.det), q = d.det / 2;
-    const size_t lds = (size_t)3 * d.det * sizeof(T);
+    const size_t lds = (size_t)d.det * sizeof(double);
     hipLaunchKernelGGL(ncp_spec_k<T>, dim3(d.nrch, d.S), dim3(NCP_THREADS), lds, st, (const T *)ws.rvec, d.ldm, rows,
                        d.det, q, d.nrch, ws.spec, ws.active);
     ABBA_LAUNCHED("ncp_spec_k");
