@@ -354,6 +354,7 @@ static void to_c(const TuneEntry &t, abba_tune *o) {
     o->a_jb = t.a_jb;
     o->b_g = t.b_g;
     o->czt = t.czt;
+    o->a_rb = t.a_rb;
 }
 
 static void store_tuning(abba_op *op, const TuneEntry &e) {
@@ -383,7 +384,7 @@ int abba_op_set_tuning(abba_op *op, int batch, const abba_tune *t) {
             }
         return ABBA_OK;
     }
-    store_tuning(op, TuneEntry{batch, t->a_path, t->a_jb, t->b_g, t->czt});
+    store_tuning(op, TuneEntry{batch, t->a_path, t->a_jb, t->b_g, t->czt, t->a_rb});
     return ABBA_OK;
 }
 
@@ -426,7 +427,7 @@ int abba_autotune(abba_op *op, int batch, int reps, void *stream, abba_tune *bes
     hipEvent_t e0 = nullptr, e1 = nullptr;
     int rc = ABBA_OK;
     double best_ms = 1e300, def_ms = 0.0;
-    TuneEntry win{batch, -1, 0, 0, 0};
+    TuneEntry win{batch, -1, 0, 0, 0, 0};
     auto run = [&]() {
         return fwd ? abba_project(op, in, out, batch, stream) : abba_backproject(op, in, out, batch, stream);
     };
@@ -454,7 +455,7 @@ int abba_autotune(abba_op *op, int batch, int reps, void *stream, abba_tune *bes
         e = hipGetLastError();
         if (e != hipSuccess) rc = hip_fail(e, "tune_fill_k");
     }
-    if (!rc) rc = timed(TuneEntry{batch, -1, 0, 0, 0}, &def_ms);
+    if (!rc) rc = timed(TuneEntry{batch, -1, 0, 0, 0, 0}, &def_ms);
     if (!rc) best_ms = def_ms;
     for (int i = 0; i < nc && !rc; ++i) {
         TuneEntry t = cand[i];

@@ -33,6 +33,7 @@
 namespace abba {
 
 constexpr int CPAD = 2;   // zeros on each side of a padded axis
+constexpr int CONE_RB_DEFAULT = 8;   // detector rows per band of A's work order
 
 // Per-view constants of B in the accumulation type.
 template <typename T>
@@ -246,23 +247,29 @@ __device__ __forceinline__ void plane_range(double c0, double dc, int n, int np,
 
 // A: one thread per ray; a wave is 64 consecutive detector columns of one
 // row of one view.  When all its rays share the dominant axis, the wave walks
-// the union of their plane ranges in lockstep.
+// the union of their plane ranges in lockstep.  Work order: (slice, band of
+// rb detector rows, view, row in the band, column block), dealt to the XCDs
+// in contiguous ranges, so the workgroups in flight on one XCD hold a few
+// rows of many views -- rays through a thin slab of the volume, which stays
+// in that XCD's L2.
 template <typename TI, typename TO>
 __global__ __launch_bounds__(256) void cone_fwd_k(const TI *__restrict__ vx, const TI *__restrict__ vy,
                                                   const TI *__restrict__ vz, int64_t sx, int64_t sy, int64_t szz,
                                                   VecRef yr, const ConeView *__restrict__ views, int nx, int ny,
                                                   int nz, int nviews, int nu, int nv, double pu, double pv,
-                                                  int nbu, uint32_t nxcc, int s0, const int *kdev,
-                                                  const int *active) {
+                                                  int nbu, int rb, int nrb, uint32_t nxcc, int s0,
+                                                  const int *kdev, const int *active) {
     typedef typename acc_of<TI>::type T;
-    // work order: (slice, view, detector row, column block of 256)
     const uint32_t w = cremap(blockIdx.x, gridDim.x, nxcc);
     const int cb = (int)(w % (uint32_t)nbu);
     const uint32_t w2 = w / (uint32_t)nbu;
-    const int r = (int)(w2 % (uint32_t)nv);
-    const uint32_t w3 = w2 / (uint32_t)nv;
+    const int ri = (int)(w2 % (uint32_t)rb);
+    const uint32_t w3 = w2 / (uint32_t)rb;
     const int vw = (int)(w3 % (uint32_t)nviews);
-    const int s = s0 + (int)(w3 / (uint32_t)nviews);
+    const uint32_t w4 = w3 / (uint32_t)nviews;
+    const int r = (int)(w4 % (uint32_t)nrb) * rb + ri;
+    const int s = s0 + (int)(w4 / (uint32_t)nrb);
+    if (r >= nv) return;   // the ragged last band (the whole workgroup)
     if (active && !active[s]) return;
     const int k = kdev ? *kdev : 0;
     const int c = cb * 256 + (int)threadIdx.x;
@@ -433,14 +440,19 @@ static int cone_fwd_t(const abba_op *op, VecRef x, VecRef y, int batch, void *sc
         ABBA_LAUNCHED("cone_pad_vol_k");
     }
     const int nbu = (g.det_u + 255) / 256;
-    const uint64_t per = (uint64_t)nbu * g.det_v * g.n_angles;
+    int rb = CONE_RB_DEFAULT;
+    if (const TuneEntry *t = tune_for(op, batch))
+        if (t->a_rb >= 1 && t->a_rb <= 64) rb = t->a_rb;
+    rb = std::min(rb, g.det_v);
+    const int nrb = (g.det_v + rb - 1) / rb;
+    const uint64_t per = (uint64_t)nbu * nrb * rb * g.n_angles;
     if (per > CMAX_GROUPS) return ABBA_ERR_UNSUPPORTED;
     const int ch = (int)std::min<uint64_t>((uint64_t)batch, CMAX_GROUPS / per);
     for (int s0 = 0; s0 < batch; s0 += ch) {
         const int nb = std::min(ch, batch - s0);
         hipLaunchKernelGGL((cone_fwd_k<TI, TO>), dim3((uint32_t)(per * nb)), dim3(256), 0, L.stream, vx, vy, vz,
                            (int64_t)cc.vx, (int64_t)cc.vy, (int64_t)cc.vz, y, (const ConeView *)op->tab, g.nx, g.ny,
-                           g.nz, g.n_angles, g.det_u, g.det_v, g.det_pitch_u, g.det_pitch_v, nbu,
+                           g.nz, g.n_angles, g.det_u, g.det_v, g.det_pitch_u, g.det_pitch_v, nbu, rb, nrb,
                            (uint32_t)op->nxcc, s0, L.kdev, L.active);
         ABBA_LAUNCHED("cone_fwd_k");
     }
@@ -507,7 +519,10 @@ int cone_tune_candidates(const abba_op *op, TuneEntry *out, int cap) {
     int n = 0;
     if (op->kind == ABBA_OP_PIXEL)
         for (int c : {2, 4, 8})
-            if (n < cap) out[n++] = TuneEntry{0, 0, 0, 0, c};
+            if (n < cap) out[n++] = TuneEntry{0, 0, 0, 0, c, 0};
+    if (op->kind == ABBA_OP_JOSEPH)
+        for (int r : {1, 2, 4, 8, 16, 32})
+            if (n < cap && r <= op->g.det_v) out[n++] = TuneEntry{0, 0, 0, 0, 0, r};
     return n;
 }
 

@@ -62,6 +62,7 @@ struct TuneEntry {
     int a_jb;     // 2D A, LDS kernel: bins per thread and angle (2, 3 or 4)
     int b_g;      // 2D B: angles per LDS chunk
     int czt;      // 3D B: voxels per thread along z (2, 4 or 8)
+    int a_rb;     // 3D A: detector rows per band of the work order (1 to 64)
 };
 constexpr int MAX_TUNE = 8;
 

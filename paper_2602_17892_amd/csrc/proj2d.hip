@@ -649,16 +649,16 @@ int par2d_tune_candidates(const abba_op *op, TuneEntry *out, int cap) {
         if (n < cap) out[n++] = e;
     };
     if (op->kind == ABBA_OP_JOSEPH) {
-        add(TuneEntry{0, 0, 0, 0, 0});
+        add(TuneEntry{0, 0, 0, 0, 0, 0});
         const bool fits = op->img_dtype == ABBA_F64 ? lds_fits<double>(op) : lds_fits<float>(op);
         if (fits)
-            for (int jb = 2; jb <= 4; ++jb) add(TuneEntry{0, 1, jb, 0, 0});
+            for (int jb = 2; jb <= 4; ++jb) add(TuneEntry{0, 1, jb, 0, 0, 0});
     } else if (op->kind == ABBA_OP_PIXEL) {
         int W, G;
         pixbp_window(op, &W, &G);
         const int gmax = pixbp_max_g(op, W);
         for (int g : {8, 16, 32, 64, 128})
-            if (g <= gmax) add(TuneEntry{0, 0, 0, g, 0});
+            if (g <= gmax) add(TuneEntry{0, 0, 0, g, 0, 0});
     }
     return n;
 }

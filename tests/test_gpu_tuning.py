@@ -41,7 +41,7 @@ def test_2d_launch_choices_bitwise_equal(pk, shape, dt):
     ya0, xb0 = pk.project(A, x), pk.backproject(B, y)
     for path, jb in [(0, 0), (1, 2), (1, 3), (1, 4)]:
         pk.set_tuning(A, S, a_path=path, a_jb=jb)
-        assert pk.get_tuning(A, S) == dict(a_path=path, a_jb=jb, b_g=0, czt=0)
+        assert pk.get_tuning(A, S) == dict(a_path=path, a_jb=jb, b_g=0, czt=0, a_rb=0)
         assert torch.equal(pk.project(A, x), ya0), (path, jb)
     for g in (1, 8, 16, 64, 128):
         pk.set_tuning(B, S, b_g=g)
@@ -55,12 +55,18 @@ def test_cone_launch_choices_bitwise_equal(pk):
     nx, ny, nz, nvw, nu, nv = 20, 18, 13, 16, 28, 24
     g = pk.Geometry(nx, ny, nvw, nu, det_pitch_u=1.3, kind="cone3d", nz=nz, det_v=nv, det_pitch_v=1.2,
                     sid=40.0, sdd=80.0)
+    A = pk.Operator("joseph", g, "f32", "f32")
     B = pk.Operator("pixel", g, "f32", "f32")
     y = images(2, nvw * nv, nu, 3).reshape(2, nvw, nv, nu).contiguous()
     x0 = pk.backproject(B, y)
     for c in (2, 4, 8):
         pk.set_tuning(B, 2, czt=c)
         assert torch.equal(pk.backproject(B, y), x0), c
+    x = images(2, nz * ny, nx, 5).reshape(2, nz, ny, nx).contiguous()
+    y0 = pk.project(A, x)
+    for rb in (1, 3, 5, 8, 64):          # ragged last bands included (24 rows)
+        pk.set_tuning(A, 2, a_rb=rb)
+        assert torch.equal(pk.project(A, x), y0), rb
 
 
 def test_autotune_keeps_a_choice(pk):
@@ -73,7 +79,7 @@ def test_autotune_keeps_a_choice(pk):
     print(f"A: {ta}\nB: {tb}")
     assert ta["candidates"] == 4 and tb["candidates"] >= 3
     assert ta["ms"] <= ta["default_ms"] and tb["ms"] <= tb["default_ms"]
-    assert pk.get_tuning(A, S) == {k: ta[k] for k in ("a_path", "a_jb", "b_g", "czt")}
+    assert pk.get_tuning(A, S) == {k: ta[k] for k in ("a_path", "a_jb", "b_g", "czt", "a_rb")}
     assert torch.equal(pk.project(A, x), ya0)
     # the solver uses the stored choice and returns the same bits
     og_b = pk.project(A, x).contiguous()
