@@ -129,9 +129,8 @@ typedef struct {
     int a_jb;          /* 2D A, LDS kernel: bins per thread and angle, 2..4 (0: 3)           */
     int b_g;           /* 2D B: angles per LDS chunk (0: built-in, at most 64 KB of LDS)      */
     int czt;           /* 3D B: voxels per thread along z, 2, 4 or 8 (0: 4)                   */
-    int a_rb;          /* 3D A: detector rows per band of the work order, 1..64 (0: 8); the
-                          views of a band run before the next band, so the rays in flight
-                          on one XCD touch a thin slab of the volume                        */
+    int a_rb;          /* 3D A: detector rows per band of the work order (0: all rows, the
+                          views outermost); the views of a band run before the next band  */
     double ms;         /* abba_autotune: mean time of one apply with the chosen launch       */
     double default_ms; /* abba_autotune: the same with the built-in rules                    */
     int candidates;    /* abba_autotune: launch choices timed besides the built-in rules     */

@@ -33,7 +33,6 @@
 namespace abba {
 
 constexpr int CPAD = 2;   // zeros on each side of a padded axis
-constexpr int CONE_RB_DEFAULT = 8;   // detector rows per band of A's work order
 
 // Per-view constants of B in the accumulation type.
 template <typename T>
@@ -249,9 +248,10 @@ __device__ __forceinline__ void plane_range(double c0, double dc, int n, int np,
 // row of one view.  When all its rays share the dominant axis, the wave walks
 // the union of their plane ranges in lockstep.  Work order: (slice, band of
 // rb detector rows, view, row in the band, column block), dealt to the XCDs
-// in contiguous ranges, so the workgroups in flight on one XCD hold a few
-// rows of many views -- rays through a thin slab of the volume, which stays
-// in that XCD's L2.
+// in contiguous ranges.  The built-in choice is one band of all rows (the
+// views outermost); bands of a few rows, whose rays in flight on one XCD
+// cross a thin slab of the volume, are a launch choice (measured slower on
+// the 256^3 problem: the taps are limited by the gathers, not by L2 reuse).
 template <typename TI, typename TO>
 __global__ __launch_bounds__(256) void cone_fwd_k(const TI *__restrict__ vx, const TI *__restrict__ vy,
                                                   const TI *__restrict__ vz, int64_t sx, int64_t sy, int64_t szz,
@@ -440,10 +440,9 @@ static int cone_fwd_t(const abba_op *op, VecRef x, VecRef y, int batch, void *sc
         ABBA_LAUNCHED("cone_pad_vol_k");
     }
     const int nbu = (g.det_u + 255) / 256;
-    int rb = CONE_RB_DEFAULT;
+    int rb = g.det_v;
     if (const TuneEntry *t = tune_for(op, batch))
-        if (t->a_rb >= 1 && t->a_rb <= 64) rb = t->a_rb;
-    rb = std::min(rb, g.det_v);
+        if (t->a_rb >= 1) rb = std::min(t->a_rb, g.det_v);
     const int nrb = (g.det_v + rb - 1) / rb;
     const uint64_t per = (uint64_t)nbu * nrb * rb * g.n_angles;
     if (per > CMAX_GROUPS) return ABBA_ERR_UNSUPPORTED;
@@ -521,8 +520,8 @@ int cone_tune_candidates(const abba_op *op, TuneEntry *out, int cap) {
         for (int c : {2, 4, 8})
             if (n < cap) out[n++] = TuneEntry{0, 0, 0, 0, c, 0};
     if (op->kind == ABBA_OP_JOSEPH)
-        for (int r : {1, 2, 4, 8, 16, 32})
-            if (n < cap && r <= op->g.det_v) out[n++] = TuneEntry{0, 0, 0, 0, 0, r};
+        for (int r : {2, 8, 32})
+            if (n < cap && r < op->g.det_v) out[n++] = TuneEntry{0, 0, 0, 0, 0, r};
     return n;
 }
 
