@@ -53,13 +53,6 @@ __device__ __forceinline__ uint32_t xcd_remap(uint32_t L, uint32_t total, uint32
 
 // Pointer to the element at 32-bit byte offset `off` from `base`; the two
 // taps are read as p[0], p[1] so that they form one wide load.
-// A padded image entry: the value and the difference to the next entry of its
-// row, so linear interpolation at fraction f is one fma(f, dv, v).
-template <typename T>
-struct Pair {
-    T v, dv;
-};
-
 template <typename T>
 __device__ __forceinline__ const T *at_byte(const T *base, uint32_t off) {
     return reinterpret_cast<const T *>(reinterpret_cast<const char *>(base) + off);
@@ -78,58 +71,51 @@ template <>
 __device__ __forceinline__ double fract_of<double>(double t) { return __builtin_amdgcn_fract(t); }
 
 // ------------------------------------------------------ padded copies -----
-// Image -> xp [ny][nx + 4] (row-major) and xq [nx][ny + 4] (transposed) of
-// pairs (x_c, x_{c+1} - x_c) of the row padded with PAD zeros on both sides
-// (x past the padded row is 0).  33 x 33 tiles (one halo row and column for
-// the next entry) through LDS.
+// Image -> xp [ny][nx + 4] (row-major) and xq [nx][ny + 4] (transposed), each
+// row with PAD zeros on both sides.  32 x 32 tiles through LDS.
 template <typename T>
-__global__ __launch_bounds__(256) void pad_image_k(VecRef xr, Pair<T> *__restrict__ xp, Pair<T> *__restrict__ xq,
-                                                   int nx, int ny, int s0, const int *kdev, const int *active) {
+__global__ __launch_bounds__(256) void pad_image_k(VecRef xr, T *__restrict__ xp, T *__restrict__ xq, int nx,
+                                                   int ny, int s0, const int *kdev, const int *active) {
     const int s = s0 + blockIdx.z;
     if (active && !active[s]) return;
     const int k = kdev ? *kdev : 0;
     const T *x = vec_ptr<const T>(xr, s, k);
     const int lp = nx + 2 * PAD, lq = ny + 2 * PAD;
-    Pair<T> *op = xp + (int64_t)s * round_rows(ny) * lp;
-    Pair<T> *oq = xq + (int64_t)s * round_rows(nx) * lq;
-    const Pair<T> zero{(T)0, (T)0};
+    T *op = xp + (int64_t)s * round_rows(ny) * lp;
+    T *oq = xq + (int64_t)s * round_rows(nx) * lq;
     // the zero rows that round both copies up to a multiple of RPAD rows
     if (blockIdx.x == 0 && blockIdx.y == 0) {
-        for (int e = threadIdx.x; e < (round_rows(ny) - ny) * lp; e += 256) op[(int64_t)ny * lp + e] = zero;
-        for (int e = threadIdx.x; e < (round_rows(nx) - nx) * lq; e += 256) oq[(int64_t)nx * lq + e] = zero;
+        for (int e = threadIdx.x; e < (round_rows(ny) - ny) * lp; e += 256) op[(int64_t)ny * lp + e] = (T)0;
+        for (int e = threadIdx.x; e < (round_rows(nx) - nx) * lq; e += 256) oq[(int64_t)nx * lq + e] = (T)0;
     }
-    __shared__ T tile[33][34];
-    const int j0 = blockIdx.x * 32, i0 = blockIdx.y * 32;
-    for (int e = threadIdx.x; e < 33 * 33; e += 256) {
-        const int r = e / 33, c = e % 33, i = i0 + r, j = j0 + c;
-        tile[r][c] = (i < ny && j < nx) ? x[(int64_t)i * nx + j] : (T)0;
-    }
-    __syncthreads();
+    __shared__ T tile[32][33];
     const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;   // 32 x 8
+    const int j0 = blockIdx.x * 32, i0 = blockIdx.y * 32;
 #pragma unroll
     for (int r = ty; r < 32; r += 8) {
         const int i = i0 + r, j = j0 + tx;
+        T v = (T)0;
         if (i < ny && j < nx) {
-            const T v = tile[r][tx];
-            op[(int64_t)i * lp + j + PAD] = Pair<T>{v, tile[r][tx + 1] - v};
+            v = x[(int64_t)i * nx + j];
+            op[(int64_t)i * lp + j + PAD] = v;
         }
-        const int jq = j0 + r, iq = i0 + tx;
-        if (iq < ny && jq < nx) {
-            const T v = tile[tx][r];
-            oq[(int64_t)jq * lq + iq + PAD] = Pair<T>{v, tile[tx + 1][r] - v};
-        }
+        tile[r][tx] = v;
     }
-    // the pads of rows i0..i0+31 of xp: columns 0, 1 (its next entry is the
-    // row's first value), nx+2, nx+3; the same for the rows j0..j0+31 of xq
+    // the pads of rows i0..i0+31 of xp: columns 0, 1, nx+2, nx+3
     if (blockIdx.x == 0 && threadIdx.x < 128) {
         const int i = i0 + (threadIdx.x >> 2), c = threadIdx.x & 3;
-        if (i < ny)
-            op[(int64_t)i * lp + (c < 2 ? c : nx + c)] = c == 1 ? Pair<T>{(T)0, tile[i - i0][0]} : zero;
+        if (i < ny) op[(int64_t)i * lp + (c < 2 ? c : nx + c)] = (T)0;
     }
+    __syncthreads();
+#pragma unroll
+    for (int r = ty; r < 32; r += 8) {
+        const int j = j0 + r, i = i0 + tx;
+        if (i < ny && j < nx) oq[(int64_t)j * lq + i + PAD] = tile[tx][r];
+    }
+    // the pads of rows j0..j0+31 of xq
     if (blockIdx.y == 0 && threadIdx.x < 128) {
         const int j = j0 + (threadIdx.x >> 2), c = threadIdx.x & 3;
-        if (j < nx)
-            oq[(int64_t)j * lq + (c < 2 ? c : ny + c)] = c == 1 ? Pair<T>{(T)0, tile[0][j - j0]} : zero;
+        if (j < nx) oq[(int64_t)j * lq + (c < 2 ? c : ny + c)] = (T)0;
     }
 }
 
@@ -144,7 +130,7 @@ __global__ __launch_bounds__(256) void pad_image_k(VecRef xr, Pair<T> *__restric
 // from (global memory or a band staged in LDS).
 template <typename T>
 struct JBand {
-    static constexpr int H = sizeof(T) == 8 ? 4 : 8;
+    static constexpr int H = sizeof(T) == 8 ? 8 : 16;
 };
 static_assert(RPAD % 16 == 0 && RPAD % 8 == 0, "bands must tile the padded rows");
 
@@ -178,18 +164,17 @@ __device__ __forceinline__ void wave_union(int &r0, int &r1) {
 
 // Contribution of the band whose first row is `rows` (stride L) for a ray
 // with coordinate ub = u(b0) in the band's first row.  Clamping to [0, C+2]
-// keeps the entry inside the padded row and reads zeros wherever both taps
-// are outside the image; after the clamp u >= 0, so (int) is floor.
+// keeps the tap pair inside the padded row and reads zeros wherever a tap
+// is outside the image; after the clamp u >= 0, so (int) is floor.
 template <typename T, int H>
-__device__ __forceinline__ T band_sum(const Pair<T> *rows, int L, T ub, T slope, int C) {
+__device__ __forceinline__ T band_sum(const T *rows, int L, T ub, T slope, int C) {
     T a0 = 0, a1 = 0;
 #pragma unroll
     for (int q = 0; q < H; ++q) {
         const T u = fma(-(T)q, slope, ub);
         const T f = fract_of(u);
-        const Pair<T> e =
-            *at_byte(rows + q * L, (uint32_t)(int)clampf(u, (T)0, (T)(C + 2)) * (uint32_t)sizeof(Pair<T>));
-        const T v = fma(f, e.dv, e.v);
+        const T *e = at_byte(rows + q * L, (uint32_t)(int)clampf(u, (T)0, (T)(C + 2)) * (uint32_t)sizeof(T));
+        const T v = fma(f, e[1] - e[0], e[0]);
         if (q & 1) a1 += v;
         else a0 += v;
     }
@@ -199,8 +184,7 @@ __device__ __forceinline__ T band_sum(const Pair<T> *rows, int L, T ub, T slope,
 // Gather version: one thread per ray, a wave = 64 consecutive bins of one
 // angle, the wave walks the bands that meet the union of its rays' rows.
 template <typename TI, typename TO>
-__global__ __launch_bounds__(256) void joseph2d_fwd_k(const Pair<TI> *__restrict__ xp,
-                                                      const Pair<TI> *__restrict__ xq,
+__global__ __launch_bounds__(256) void joseph2d_fwd_k(const TI *__restrict__ xp, const TI *__restrict__ xq,
                                                       VecRef yr,
                                                       const AngleTab<typename acc_of<TI>::type> *__restrict__ tab,
                                                       int nx, int ny, int nd, typename acc_of<TI>::type ds,
@@ -220,14 +204,14 @@ __global__ __launch_bounds__(256) void joseph2d_fwd_k(const Pair<TI> *__restrict
     const int d = (int)(w % (uint32_t)nbx) * 256 + threadIdx.x;
     const int k = kdev ? *kdev : 0;
     const AngleTab<T> t = tab[a];
-    const Pair<T> *P;
+    const T *P;
     int R, C;
     if (t.rowmarch) {
-        P = xp + (int64_t)s * round_rows(ny) * (nx + 2 * PAD);
+        P = (const T *)xp + (int64_t)s * round_rows(ny) * (nx + 2 * PAD);
         R = ny;
         C = nx;
     } else {
-        P = xq + (int64_t)s * round_rows(nx) * (ny + 2 * PAD);
+        P = (const T *)xq + (int64_t)s * round_rows(nx) * (ny + 2 * PAD);
         R = nx;
         C = ny;
     }
@@ -256,8 +240,7 @@ __global__ __launch_bounds__(256) void joseph2d_fwd_k(const Pair<TI> *__restrict
 constexpr int JB_DEFAULT = 3;
 
 template <typename TI, typename TO, int JB>
-__global__ __launch_bounds__(256) void joseph2d_lds_k(const Pair<TI> *__restrict__ xp,
-                                                      const Pair<TI> *__restrict__ xq,
+__global__ __launch_bounds__(256) void joseph2d_lds_k(const TI *__restrict__ xp, const TI *__restrict__ xq,
                                                       VecRef yr,
                                                       const AngleTab<typename acc_of<TI>::type> *__restrict__ tab,
                                                       const int *__restrict__ agrp, int ngroups, int nbc, int nx,
@@ -269,7 +252,7 @@ __global__ __launch_bounds__(256) void joseph2d_lds_k(const Pair<TI> *__restrict
     constexpr int H = JBand<T>::H;
     constexpr int GA = JOSEPH_GA;
     extern __shared__ __align__(16) unsigned char smem[];
-    Pair<T> *band = reinterpret_cast<Pair<T> *>(smem);   // [H][L]
+    T *band = reinterpret_cast<T *>(smem);   // [H][L]
     // work order: (slice, angle group, bin chunk of 256*JB)
     const uint32_t w = xcd_remap(blockIdx.x, gridDim.x, nxcc);
     const int bc = (int)(w % (uint32_t)nbc);
@@ -280,14 +263,14 @@ __global__ __launch_bounds__(256) void joseph2d_lds_k(const Pair<TI> *__restrict
     const int k = kdev ? *kdev : 0;
     const int g_first = agrp[4 * gi], g_count = agrp[4 * gi + 1], rowmarch = agrp[4 * gi + 2];
     const int *order = agrp + 4 * ngroups;
-    const Pair<T> *P;
+    const T *P;
     int R, C;
     if (rowmarch) {
-        P = xp + (int64_t)s * round_rows(ny) * (nx + 2 * PAD);
+        P = (const T *)xp + (int64_t)s * round_rows(ny) * (nx + 2 * PAD);
         R = ny;
         C = nx;
     } else {
-        P = xq + (int64_t)s * round_rows(nx) * (ny + 2 * PAD);
+        P = (const T *)xq + (int64_t)s * round_rows(nx) * (ny + 2 * PAD);
         R = nx;
         C = ny;
     }
@@ -316,17 +299,14 @@ __global__ __launch_bounds__(256) void joseph2d_lds_k(const Pair<TI> *__restrict
         }
     }
     const int Rr = round_rows(R);
-    // a band is H * L pairs: 16-byte copies (a pair of pairs in FP32, one pair
-    // in FP64) when they tile it
-    const bool vec4 = sizeof(T) == 8 || (L % 2) == 0;
-    const int n16 = H * L * (int)sizeof(Pair<T>) / 16;
+    const bool vec4 = (L % 4) == 0;
     for (int b0 = 0; b0 < Rr; b0 += H) {
         __syncthreads();   // the previous band is no longer read
-        const Pair<T> *src = P + (int64_t)b0 * L;
-        if (vec4) {
+        const T *src = P + (int64_t)b0 * L;
+        if (vec4 && sizeof(T) == 4) {
             const float4 *s4 = reinterpret_cast<const float4 *>(src);
             float4 *d4 = reinterpret_cast<float4 *>(band);
-            for (int c = threadIdx.x; c < n16; c += 256) d4[c] = s4[c];
+            for (int c = threadIdx.x; c < H * L / 4; c += 256) d4[c] = s4[c];
         } else {
             for (int c = threadIdx.x; c < H * L; c += 256) band[c] = src[c];
         }
@@ -506,27 +486,25 @@ __global__ __launch_bounds__(256) void josephT2d_k(VecRef yr, VecRef xr,
 
 // ------------------------------------------------------------ host side ----
 static size_t acc_size(const abba_op *op) { return op->img_dtype == ABBA_F64 ? 8 : 4; }
-// bytes of one entry of the padded copies: a (value, difference) pair
-static size_t pair_size(const abba_op *op) { return 2 * acc_size(op); }
 
 size_t par2d_scratch_bytes(const abba_op *op, int batch) {
     if (op->kind != ABBA_OP_JOSEPH) return 0;   // only A reads a padded copy
     const int64_t nx = op->g.nx, ny = op->g.ny;
     return (size_t)batch * (size_t)(round_rows(ny) * (nx + 2 * PAD) + round_rows(nx) * (ny + 2 * PAD)) *
-           pair_size(op);
+           acc_size(op);
 }
 
 // A padded slice must be addressable with 32-bit byte offsets.
 static bool offsets_fit(const abba_op *op) {
     const uint64_t nx = op->g.nx, ny = op->g.ny;
     const uint64_t lim = 1ull << 31;
-    return (uint64_t)round_rows(ny) * (nx + 2 * PAD) * pair_size(op) < lim &&
-           (uint64_t)round_rows(nx) * (ny + 2 * PAD) * pair_size(op) < lim;
+    return (uint64_t)round_rows(ny) * (nx + 2 * PAD) * acc_size(op) < lim &&
+           (uint64_t)round_rows(nx) * (ny + 2 * PAD) * acc_size(op) < lim;
 }
 
 template <typename T>
 static bool lds_fits(const abba_op *op) {
-    const size_t band_bytes = (size_t)JBand<T>::H * (std::max(op->g.nx, op->g.ny) + 2 * PAD) * sizeof(Pair<T>);
+    const size_t band_bytes = (size_t)JBand<T>::H * (std::max(op->g.nx, op->g.ny) + 2 * PAD) * sizeof(T);
     return band_bytes <= 65536 && op->agrp && std::max(op->g.nx, op->g.ny) < 65535;
 }
 
@@ -536,11 +514,10 @@ static uint64_t lds_groups(const abba_op *op, int jb) {
 }
 
 template <typename TI, typename TO, int JB>
-static int lds_launch(const abba_op *op, const Pair<TI> *xp, const Pair<TI> *xq, VecRef y, int batch,
-                      const Launch &L) {
+static int lds_launch(const abba_op *op, const TI *xp, const TI *xq, VecRef y, int batch, const Launch &L) {
     typedef typename acc_of<TI>::type T;
     const int nx = op->g.nx, ny = op->g.ny, nd = op->g.det_u;
-    const size_t band_bytes = (size_t)JBand<T>::H * (std::max(nx, ny) + 2 * PAD) * sizeof(Pair<T>);
+    const size_t band_bytes = (size_t)JBand<T>::H * (std::max(nx, ny) + 2 * PAD) * sizeof(T);
     const int nbc = (nd + 256 * JB - 1) / (256 * JB);
     const uint64_t per = lds_groups(op, JB);
     const int ch = (int)std::min<uint64_t>((uint64_t)batch, MAX_GROUPS / per);
@@ -559,8 +536,8 @@ template <typename TI, typename TO>
 static int fwd_launch(const abba_op *op, VecRef x, VecRef y, int batch, void *scratch, const Launch &L) {
     typedef typename acc_of<TI>::type T;
     const int nx = op->g.nx, ny = op->g.ny, na = op->g.n_angles, nd = op->g.det_u;
-    Pair<TI> *xp = (Pair<TI> *)scratch;
-    Pair<TI> *xq = xp + (int64_t)batch * round_rows(ny) * (nx + 2 * PAD);
+    TI *xp = (TI *)scratch;
+    TI *xq = xp + (int64_t)batch * round_rows(ny) * (nx + 2 * PAD);
     for (int s0 = 0; s0 < batch; s0 += MAX_GRID_YZ) {
         const int nb = std::min(MAX_GRID_YZ, batch - s0);
         dim3 tg((nx + 31) / 32, (ny + 31) / 32, nb);
@@ -593,7 +570,7 @@ static int fwd_launch(const abba_op *op, VecRef x, VecRef y, int batch, void *sc
     for (int s0 = 0; s0 < batch; s0 += chunk) {
         const int nb = std::min(chunk, batch - s0);
         hipLaunchKernelGGL((joseph2d_fwd_k<TI, TO>), dim3((uint32_t)(per_slice * nb)), dim3(256), 0, L.stream,
-                           (const Pair<TI> *)xp, (const Pair<TI> *)xq, y, (const AngleTab<T> *)op->tab, nx, ny, nd,
+                           (const TI *)xp, (const TI *)xq, y, (const AngleTab<T> *)op->tab, nx, ny, nd,
                            (T)op->g.det_pitch_u, (T)(0.5 * (nd - 1)), na, nbx, (uint32_t)op->nxcc, s0, L.kdev,
                            L.active);
         ABBA_LAUNCHED("joseph2d_fwd_k");
