@@ -224,6 +224,14 @@ __device__ __forceinline__ uint32_t cremap(uint32_t L, uint32_t total, uint32_t 
     return x * q + min(x, r) + slot;
 }
 
+// A pointer that is the same in every lane of the wave, made scalar.
+template <typename T>
+__device__ __forceinline__ const T *uniform_ptr(const T *p) {
+    const uint64_t v = reinterpret_cast<uint64_t>(p);
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v), hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
+    return reinterpret_cast<const T *>(((uint64_t)hi << 32) | lo);
+}
+
 __device__ __forceinline__ float cfract(float t) { return __builtin_amdgcn_fractf(t); }
 __device__ __forceinline__ double cfract(double t) { return __builtin_amdgcn_fract(t); }
 
@@ -319,32 +327,38 @@ __global__ __launch_bounds__(256) void cone_fwd_k(const TI *__restrict__ vx, con
     const int Lq = nq + 2 * CPAD, Lp = np_ + 2 * CPAD;
     const T P0 = (T)(p0 + CPAD), DP = (T)dp, Q0 = (T)(q0 + CPAD), DQ = (T)dq;
     const T pmax = (T)(np_ + CPAD), qmax = (T)(nq + CPAD);
-    T acc0 = 0, acc1 = 0;
-    int j = jlo;
-    for (; j + 1 <= jhi; j += 2) {
-        T v[2];
-#pragma unroll
-        for (int h = 0; h < 2; ++h) {
-            const T pp = fma((T)(j + h), DP, P0), qq = fma((T)(j + h), DQ, Q0);
-            const T fp = cfract(pp), fq = cfract(qq);
-            const int ipp = (int)fmin(fmax(pp, (T)0), pmax), iqq = (int)fmin(fmax(qq, (T)0), qmax);
-            const TI *e = P + ((int64_t)(j + h) * Lp + ipp) * Lq + iqq;
-            const T a00 = (T)e[0], a01 = (T)e[1], a10 = (T)e[Lq], a11 = (T)e[Lq + 1];
-            const T lo = fma(fq, a01 - a00, a00), hi = fma(fq, a11 - a10, a10);
-            v[h] = fma(fp, hi - lo, lo);
-        }
-        acc0 += v[0];
-        acc1 += v[1];
-    }
-    for (; j <= jhi; ++j) {
-        const T pp = fma((T)j, DP, P0), qq = fma((T)j, DQ, Q0);
+    // in lockstep the copy is the same for the whole wave: a scalar base with
+    // 32-bit element offsets (a padded copy of one slice has < 2^31 elements)
+    const TI *Pb = same ? uniform_ptr(P) : P;
+    auto tap = [&](int jj) -> T {
+        const T pp = fma((T)jj, DP, P0), qq = fma((T)jj, DQ, Q0);
         const T fp = cfract(pp), fq = cfract(qq);
-        const int ipp = (int)fmin(fmax(pp, (T)0), pmax), iqq = (int)fmin(fmax(qq, (T)0), qmax);
-        const TI *e = P + ((int64_t)j * Lp + ipp) * Lq + iqq;
+        const uint32_t ipp = (uint32_t)fmin(fmax(pp, (T)0), pmax), iqq = (uint32_t)fmin(fmax(qq, (T)0), qmax);
+        const TI *e = Pb + (((uint32_t)jj * (uint32_t)Lp + ipp) * (uint32_t)Lq + iqq);
         const T a00 = (T)e[0], a01 = (T)e[1], a10 = (T)e[Lq], a11 = (T)e[Lq + 1];
         const T lo = fma(fq, a01 - a00, a00), hi = fma(fq, a11 - a10, a10);
-        acc0 += fma(fp, hi - lo, lo);
+        return fma(fp, hi - lo, lo);
+    };
+    // steps alternate between two sums (even and odd steps from jlo); four
+    // steps per pass keep eight loads in flight per wave
+    T acc0 = 0, acc1 = 0;
+    int j = jlo;
+    for (; j + 3 <= jhi; j += 4) {
+        T v[4];
+#pragma unroll
+        for (int h = 0; h < 4; ++h) v[h] = tap(j + h);
+        acc0 += v[0];
+        acc1 += v[1];
+        acc0 += v[2];
+        acc1 += v[3];
     }
+    if (j + 1 <= jhi) {
+        const T v0 = tap(j), v1 = tap(j + 1);
+        acc0 += v0;
+        acc1 += v1;
+        j += 2;
+    }
+    if (j <= jhi) acc0 += tap(j);
     if (!live) return;
     const T wgt = (T)(len / fabs(d[ia]));
     store_as<TO>(vec_ptr<TO>(yr, s, k), ((int64_t)vw * nv + r) * nu + c, (acc0 + acc1) * wgt);
@@ -439,6 +453,7 @@ static int cone_fwd_t(const abba_op *op, VecRef x, VecRef y, int batch, void *sc
                            (int64_t)cc.vx, (int64_t)cc.vy, (int64_t)cc.vz, L.kdev, L.active);
         ABBA_LAUNCHED("cone_pad_vol_k");
     }
+    if (std::max({cc.vx, cc.vy, cc.vz}) >= (size_t)1 << 31) return ABBA_ERR_UNSUPPORTED;
     const int nbu = (g.det_u + 255) / 256;
     int rb = g.det_v;
     if (const TuneEntry *t = tune_for(op, batch))
