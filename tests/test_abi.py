@@ -75,3 +75,29 @@ def test_validation_before_any_device_call():
     assert pk.lib.abba_solve(None, None, None, None, 1, 0, 5, None, None, None, None, None, 0, None) == -1
     assert b"required" in pk.lib.abba_last_error()
     del keep
+
+
+def test_validation_of_the_newer_entry_points():
+    import paper_2602_17892_amd as pk
+    h = ctypes.c_void_p()
+    # fan beam: the source must lie outside the image and before the detector
+    bad = pk.Geometry(64, 64, 12, 13, kind="fan2d", sid=20.0, sdd=80.0)._c()[0]
+    assert pk.lib.abba_op_create(ctypes.byref(h), 0, ctypes.byref(bad), 1, 1) == -1
+    bad = pk.Geometry(8, 8, 12, 13, kind="fan2d", sid=60.0, sdd=30.0)._c()[0]
+    assert pk.lib.abba_op_create(ctypes.byref(h), 0, ctypes.byref(bad), 1, 1) == -1
+    fan = pk.Geometry(8, 8, 12, 13, kind="fan2d", sid=30.0, sdd=60.0)._c()[0]
+    assert pk.lib.abba_op_create(ctypes.byref(h), 2, ctypes.byref(fan), 1, 1) == -7   # no exact transpose
+    bad = pk.Geometry(8, 8, 12, 13, kind="fan2d", nz=3, sid=30.0, sdd=60.0)._c()[0]
+    assert pk.lib.abba_op_create(ctypes.byref(h), 0, ctypes.byref(bad), 1, 1) == -1
+    # learned network calls
+    assert pk.lib.abba_mlp_forward(None, None, 5, None, None) == -1
+    assert pk.lib.abba_mlp_forward(None, None, 0, None, None) == 0          # nothing to do
+    assert pk.lib.abba_mlp_forward(None, None, -1, None, None) == -1
+    assert pk.lib.abba_mlp_loss_grad(None, None, None, 4, None, 4, None, None, None) == -1
+    assert pk.lib.abba_mlp_adam(None, None, None, None, 1, 1e-3, 0.9, 0.999, 1e-8, None) == -1
+    assert pk.lib.abba_mlp_labels(None, 1, 5, None, None, None, None) == -1
+    # tuning
+    t = pk._Tune()
+    assert pk.lib.abba_autotune(None, 4, 3, None, ctypes.byref(t)) == -1
+    assert pk.lib.abba_op_set_tuning(None, 4, ctypes.byref(t)) == -1
+    assert pk.lib.abba_op_get_tuning(None, 4, ctypes.byref(t)) == -1
