@@ -233,6 +233,10 @@ __device__ __forceinline__ const T *uniform_ptr(const T *p) {
 }
 
 __device__ __forceinline__ float cfract(float t) { return __builtin_amdgcn_fractf(t); }
+
+// a / b: in FP32 through the hardware reciprocal (1 ulp), in FP64 exactly.
+__device__ __forceinline__ float cdiv(float a, float b) { return a * __builtin_amdgcn_rcpf(b); }
+__device__ __forceinline__ double cdiv(double a, double b) { return a / b; }
 __device__ __forceinline__ double cfract(double t) { return __builtin_amdgcn_fract(t); }
 
 // Planes j (of np) whose crossing lies in (-1, n) for a coordinate
@@ -405,7 +409,7 @@ __global__ __launch_bounds__(256) void cone_bp_k(const typename acc_of<TI>::type
 #pragma unroll
         for (int m = 0; m < CZT; ++m) {
             const T den = fma(Z[m], b.n[2], bn);
-            const T M = b.dist / den;
+            const T M = cdiv(b.dist, den);
             const T u = fma(M, fma(Z[m], b.eup[2], bu), b.cu) + (T)CPAD;
             const T v = fma(M, fma(Z[m], b.evp[2], bv), b.cv) + (T)CPAD;
             const T fu = cfract(u), fv = cfract(v);
