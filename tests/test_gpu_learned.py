@@ -226,57 +226,50 @@ def test_learned_stop_defers_to_dp(pk):
 
 
 def test_learned_training_end_to_end(pk):
-    # training data from the method itself: 48 runs at 32^2 with labels from
-    # the true images, then Adam on the network; evaluation on 8 fresh slices
-    n, na, nd, K = 32, 45, 47, 20
-    A, B = ops(pk, "f32")
-    S = 48
-    xs, bs, ens = [], [], []
-    for s in range(S):
-        og_x, _ = synth.phantom2d(5, s, n)
-        xs.append(og_x)
-    xt = cuda(np.stack(xs))
-    bt = pk.project(A, xt).double()
-    eta = np.array([synth.noise_level(5, s, 1e-3, 5e-2) for s in range(S)])
-    for s in range(S):
-        g = cuda(synth.noise_direction(5, s, na * nd).reshape(na, nd), torch.float64)
-        nb = torch.linalg.vector_norm(bt[s])
-        bs.append(bt[s] + eta[s] * nb / torch.linalg.vector_norm(g) * g)
-        ens.append(float(eta[s] * nb))
-    b = torch.stack(bs).to(torch.float32).contiguous()
+    """What the trained network gains: training data from the method itself
+    (256 runs at 64^2, 90 x 91, noise log-uniform in [0.1 %, 5 %], K = 60, with
+    labels from the true images), Adam on the GPU, then 32 fresh slices solved
+    with GCV + DP and with the learned lambda and stop (DP first).  The learned
+    rule must take fewer iterations at a median error no worse than 2 % above
+    GCV + DP's."""
+    n, na, nd, K = 64, 90, 91, 60
+    A, B = ops(pk, "f32", n, na, nd)
+
+    def batch(cfg, S):
+        xs = cuda(np.stack([synth.phantom2d(cfg, s, n)[0] for s in range(S)]))
+        bt = pk.project(A, xs).double()
+        rows, en = [], []
+        for s in range(S):
+            eta = synth.noise_level(cfg, s, 1e-3, 5e-2)
+            g = cuda(synth.noise_direction(cfg, s, na * nd).reshape(na, nd), torch.float64)
+            nb = torch.linalg.vector_norm(bt[s])
+            rows.append(bt[s] + eta * nb / torch.linalg.vector_norm(g) * g)
+            en.append(float(eta * nb))
+        return xs, torch.stack(rows).to(torch.float32).contiguous(), torch.tensor(en, dtype=torch.float64,
+                                                                                  device="cuda")
+
+    xt, b, _ = batch(5, 256)
     _, info = pk.solve(A, B, b, mode="AB", k=K, reg="gcv", features=True, x_true=xt)
     tg, ks = pk.mlp_labels(info["rre"], info["iters"])
-    X = info["features"].reshape(-1, 64).contiguous()
-    T = tg.reshape(-1, 2).contiguous()
+    X = info["features"].reshape(-1, 64)
+    T = tg.reshape(-1, 2)
     ok = torch.isfinite(T).all(dim=1)
     X, T = X[ok].contiguous(), T[ok].contiguous()
     theta = cuda(synth.mlp_init(9))
     l0, _ = pk.mlp_loss_grad(theta, X, T)
-    hist = pk.mlp_train(theta, X, T, epochs=60, batch=256, lr=2e-3, seed=1)
+    hist = pk.mlp_train(theta, X, T, epochs=40, batch=1024, lr=1e-3, seed=1)
     l1, _ = pk.mlp_loss_grad(theta, X, T)
-    print(f"training: {X.shape[0]} samples, loss {float(l0):.4f} -> {float(l1):.4f}; k* mean "
-          f"{ks.float().mean():.1f}")
-    assert float(l1) < 0.25 * float(l0) and hist[-1] < hist[0]
-    # the trained rule against GCV + DP on fresh slices
-    E = 8
-    xe = cuda(np.stack([synth.phantom2d(6, s, n)[0] for s in range(E)]))
-    be = pk.project(A, xe).double()
-    ene = []
-    rows = []
-    for s in range(E):
-        g = cuda(synth.noise_direction(6, s, na * nd).reshape(na, nd), torch.float64)
-        nb = torch.linalg.vector_norm(be[s])
-        rows.append(be[s] + 0.01 * nb / torch.linalg.vector_norm(g) * g)
-        ene.append(float(0.01 * nb))
-    be = torch.stack(rows).to(torch.float32).contiguous()
-    en = torch.tensor(ene, dtype=torch.float64, device="cuda")
+    xe, be, en = batch(6, 32)
     xg, ig = pk.solve(A, B, be, mode="AB", k=K, reg="gcv", stop="dp", noise_norm=en)
     xl, il = pk.solve(A, B, be, mode="AB", k=K, reg="learned", stop="learned", noise_norm=en, mlp=theta)
 
     def rre(xr):
-        return (torch.linalg.vector_norm((xr - xe).reshape(E, -1).double(), dim=1)
-                / torch.linalg.vector_norm(xe.reshape(E, -1).double(), dim=1)).cpu().numpy()
+        return (torch.linalg.vector_norm((xr - xe).reshape(32, -1).double(), dim=1)
+                / torch.linalg.vector_norm(xe.reshape(32, -1).double(), dim=1)).cpu().numpy()
     rg, rl = rre(xg), rre(xl)
-    print(f"GCV+DP: iters {ig['iters'].float().mean():.1f}, median RRE {np.median(rg):.4f}; "
-          f"learned: iters {il['iters'].float().mean():.1f}, median RRE {np.median(rl):.4f}")
-    assert np.all(np.isfinite(rl)) and int(il["iters"].min()) >= 1
+    itg, itl = ig["iters"].double().mean().item(), il["iters"].double().mean().item()
+    print(f"training: {X.shape[0]} samples, loss {float(l0):.4f} -> {float(l1):.4f}, k* mean {ks.float().mean():.1f}; "
+          f"GCV+DP: iters {itg:.1f}, median RRE {np.median(rg):.4f}; learned: iters {itl:.1f}, "
+          f"median RRE {np.median(rl):.4f}")
+    assert float(l1) < 0.25 * float(l0) and hist[-1] < hist[0]
+    assert itl < itg and np.median(rl) <= 1.02 * np.median(rg)
