@@ -251,13 +251,19 @@ def _need(t, dtype, numel, name):
     return t.numel() // numel
 
 
+def _need_exact(t, dtype, numel, name):
+    _need(t, dtype, 1, name)
+    if t.numel() != numel:
+        raise ValueError(f"{name} has {t.numel()} elements, expected {numel}")
+
+
 def project(A: Operator, x, out=None):
     """y = A x (batched over leading dimensions)."""
     import torch
     batch = _need(x, A.img_dtype, A.n, "x")
     if out is None:
         out = torch.empty((batch, *A.geom.sino_shape), dtype=A.sino_dtype, device=x.device)
-    _need(out, A.sino_dtype, A.m, "out")
+    _need_exact(out, A.sino_dtype, batch * A.m, "out")
     _check(lib.abba_project(A.handle, _ptr(x), _ptr(out), batch, _stream_ptr()), "abba_project")
     return out
 
@@ -268,7 +274,7 @@ def backproject(B: Operator, y, out=None):
     batch = _need(y, B.sino_dtype, B.m, "y")
     if out is None:
         out = torch.empty((batch, *B.geom.image_shape), dtype=B.img_dtype, device=y.device)
-    _need(out, B.img_dtype, B.n, "out")
+    _need_exact(out, B.img_dtype, batch * B.n, "out")
     _check(lib.abba_backproject(B.handle, _ptr(y), _ptr(out), batch, _stream_ptr()), "abba_backproject")
     return out
 
@@ -363,9 +369,11 @@ def solve(A: Operator, B: Operator, b, mode: str = "AB", k: int = 30, reg: str =
         x = torch.zeros((batch, *A.geom.image_shape), dtype=A.img_dtype, device=dev)
     else:
         x = x0.clone()
-    _need(x, A.img_dtype, A.n, "x0")
+    _need_exact(x, A.img_dtype, batch * A.n, "x0")
     if noise_norm is not None:
         noise_norm = noise_norm.to(device=dev, dtype=torch.float64).contiguous()
+        if noise_norm.numel() != batch:
+            raise ValueError(f"noise_norm has {noise_norm.numel()} entries, expected one per slice ({batch})")
     fbits = (FEAT_OUT if features else 0) | (FEAT_LABELS if x_true is not None else 0)
     r, s, e = _structs(reg, lam, tau, noise_norm, mlp, judge_delta, stop, tau, rns_eps, use_graph, poll_every,
                        restart, fbits, ortho)
@@ -384,19 +392,19 @@ def solve(A: Operator, B: Operator, b, mode: str = "AB", k: int = 30, reg: str =
     o.features = None if feats is None else feats.data_ptr()
     rre = None
     if x_true is not None:
-        _need(x_true, A.img_dtype, A.n, "x_true")
-        if x_true.numel() != batch * A.n:
-            raise ValueError("x_true must hold one image per slice")
+        _need_exact(x_true, A.img_dtype, batch * A.n, "x_true")
         rre = torch.full((batch, k, LABEL_GRID), float("nan"), dtype=torch.float64, device=dev)
         o.x_true = x_true.data_ptr()
         o.rre = rre.data_ptr()
     if mlp is not None:
-        _need(mlp, torch.float32, MLP_PARAMS, "mlp")
+        _need_exact(mlp, torch.float32, MLP_PARAMS, "mlp")
     nb = ctypes.c_size_t()
     _check(lib.abba_solve_workspace(A.handle, B.handle, batch, m, k, ctypes.byref(s), ctypes.byref(e),
                                     ctypes.byref(nb)), "abba_solve_workspace")
     if workspace is None:
         workspace = torch.empty(nb.value, dtype=torch.uint8, device=dev)
+    elif not workspace.is_cuda or workspace.dtype != torch.uint8 or not workspace.is_contiguous():
+        raise ValueError("workspace must be a contiguous uint8 device tensor")
     _check(lib.abba_solve(A.handle, B.handle, _ptr(b), _ptr(x), batch, m, k, ctypes.byref(r), ctypes.byref(s),
                           ctypes.byref(o), ctypes.byref(e), _ptr(workspace), workspace.numel(), _stream_ptr()),
            "abba_solve")
@@ -408,7 +416,7 @@ def mlp_forward(params, X):
     """Y [n, 2] = network(X [n, 64]) (float32 device tensors)."""
     import torch
     n = _need(X, torch.float32, MLP_FEATURES, "X")
-    _need(params, torch.float32, MLP_PARAMS, "params")
+    _need_exact(params, torch.float32, MLP_PARAMS, "params")
     Y = torch.empty((n, 2), dtype=torch.float32, device=X.device)
     _check(lib.abba_mlp_forward(_ptr(params), _ptr(X), n, _ptr(Y), _stream_ptr()), "abba_mlp_forward")
     return Y
@@ -420,12 +428,14 @@ def mlp_loss_grad(params, X, T, idx=None, grad=None, loss=None):
     nrows = _need(X, torch.float32, MLP_FEATURES, "X")
     if _need(T, torch.float32, 2, "T") != nrows:
         raise ValueError("X and T need the same number of rows")
-    _need(params, torch.float32, MLP_PARAMS, "params")
+    _need_exact(params, torch.float32, MLP_PARAMS, "params")
     n = nrows
     if idx is not None:
         n = _need(idx, torch.int32, 1, "idx")
     grad = torch.empty(MLP_PARAMS, dtype=torch.float32, device=X.device) if grad is None else grad
     loss = torch.empty(1, dtype=torch.float64, device=X.device) if loss is None else loss
+    _need_exact(grad, torch.float32, MLP_PARAMS, "grad")
+    _need_exact(loss, torch.float64, 1, "loss")
     _check(lib.abba_mlp_loss_grad(_ptr(params), _ptr(X), _ptr(T), nrows, None if idx is None else _ptr(idx), n,
                                   _ptr(grad), _ptr(loss), _stream_ptr()), "abba_mlp_loss_grad")
     return loss, grad
@@ -433,6 +443,9 @@ def mlp_loss_grad(params, X, T, idx=None, grad=None, loss=None):
 
 def mlp_adam(params, grad, m, v, step, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8):
     """One Adam step in place on params (m, v: moment buffers)."""
+    import torch
+    for t, name in ((params, "params"), (grad, "grad"), (m, "m"), (v, "v")):
+        _need_exact(t, torch.float32, MLP_PARAMS, name)
     _check(lib.abba_mlp_adam(_ptr(params), _ptr(grad), _ptr(m), _ptr(v), int(step), float(lr), float(beta1),
                              float(beta2), float(eps), _stream_ptr()), "abba_mlp_adam")
 
@@ -440,12 +453,14 @@ def mlp_adam(params, grad, m, v, step, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8
 def mlp_labels(rre, iters=None):
     """Training targets [batch, k, 2] and k* [batch] from solve(..., x_true=...)'s rre."""
     import torch
+    if rre.dim() != 3 or rre.shape[2] != LABEL_GRID:
+        raise ValueError(f"rre must be [batch, k, {LABEL_GRID}]")
     batch, k = rre.shape[0], rre.shape[1]
-    _need(rre, torch.float64, k * LABEL_GRID, "rre")
+    _need_exact(rre, torch.float64, batch * k * LABEL_GRID, "rre")
     tgt = torch.empty((batch, k, 2), dtype=torch.float32, device=rre.device)
     ks = torch.empty(batch, dtype=torch.int32, device=rre.device)
     if iters is not None:
-        _need(iters, torch.int32, batch, "iters")
+        _need_exact(iters, torch.int32, batch, "iters")
     _check(lib.abba_mlp_labels(_ptr(rre), batch, k, None if iters is None else _ptr(iters), _ptr(tgt), _ptr(ks),
                                _stream_ptr()), "abba_mlp_labels")
     return tgt, ks

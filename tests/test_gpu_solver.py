@@ -303,6 +303,35 @@ def test_argument_errors(pk):
     assert e.value.status in (-1,)
 
 
+def test_binding_rejects_wrong_buffer_sizes(pk):
+    # buffers whose size does not match the batch are refused before any launch
+    A, B, og, xt, bd, bu, ens = problem(pk, 16, 20, 23, 0.01, 3, 0, batch=3)
+    S = bd.shape[0]
+    xt = torch.as_tensor(xt).to(device="cuda", dtype=torch.float32)
+    ens = torch.as_tensor(ens, dtype=torch.float64, device="cuda")
+    with pytest.raises(ValueError):
+        pk.project(A, xt, out=torch.empty((S + 1, 20, 23), device="cuda"))
+    with pytest.raises(ValueError):
+        pk.project(A, xt, out=torch.empty((S - 1, 20, 23), device="cuda"))
+    with pytest.raises(ValueError):
+        pk.backproject(B, bd, out=torch.empty((S - 1, 16, 16), device="cuda"))
+    with pytest.raises(ValueError):
+        pk.solve(A, B, bd, k=5, x0=torch.zeros((S - 1, 16, 16), device="cuda"))
+    with pytest.raises(ValueError):
+        pk.solve(A, B, bd, k=5, reg="dp", noise_norm=ens[:-1])
+    with pytest.raises(ValueError):
+        pk.solve(A, B, bd, k=5, workspace=torch.empty(1 << 20, dtype=torch.uint8))
+    with pytest.raises(ValueError):
+        pk.solve(A, B, bd, k=5, x_true=xt[:-1].contiguous())
+    with pytest.raises(ValueError):
+        pk.solve(A, B, bd, k=5, reg="learned", mlp=torch.zeros(2 * pk.MLP_PARAMS, device="cuda"))
+    p = torch.zeros(pk.MLP_PARAMS, device="cuda")
+    with pytest.raises(ValueError):
+        pk.mlp_adam(p, p, p, torch.zeros(pk.MLP_PARAMS - 1, device="cuda"), 1)
+    with pytest.raises(ValueError):
+        pk.mlp_labels(torch.zeros((2, 3, 8), dtype=torch.float64, device="cuda"))
+
+
 def test_c2_shape_first_iterations_parity(pk):
     # 512^2 FP32, 720 x 725, 0.5% noise: a few iterations against the oracle
     A, B, og, xt, bd, bu, ens = problem(pk, 512, 720, 725, 0.005, 1, 0)
