@@ -46,9 +46,23 @@ struct SmallArgs {
     int ab_resid;            // 1: rho_k = projected residual (AB mode)
 };
 
+constexpr int SS_NR = (KMAX_SMALL + SS_GROUP - 1) / SS_GROUP;   // column entries per lane
+
+// The value of the partner lane inside a row of 16 lanes (a DPP row).
+template <int CTRL>
+__device__ __forceinline__ double dpp_peer(double v) {
+    return __builtin_amdgcn_update_dpp(0.0, v, CTRL, 0xF, 0xF, false);
+}
+
+// Sum over the 16 lanes of a Jacobi group, which is one DPP row: quad
+// swaps, then the half-row and row mirrors.  Each stage adds two values that
+// the partner lane adds as well, so every lane ends with the same bits.
 __device__ __forceinline__ double group_sum(double v) {
-#pragma unroll
-    for (int off = SS_GROUP / 2; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    static_assert(SS_GROUP == 16, "a Jacobi group is one DPP row");
+    v += dpp_peer<0xB1>(v);    // quad_perm [1,0,3,2]
+    v += dpp_peer<0x4E>(v);    // quad_perm [2,3,0,1]
+    v += dpp_peer<0x141>(v);   // row_half_mirror
+    v += dpp_peer<0x140>(v);   // row_mirror
     return v;
 }
 
@@ -219,12 +233,25 @@ __global__ __launch_bounds__(SS_THREADS) void smallsolve_k(SmallArgs a) {
                 }
                 if (p >= k || q >= k) continue;
                 double *ap = A + (size_t)p * K, *aq = A + (size_t)q * K;
+                double *vp = V + (size_t)p * K, *vq = V + (size_t)q * K;
+                // the four columns' entries of this lane, all loads in flight
+                // at once (entries past k read as zero and are not stored)
+                double xr[SS_NR], zr[SS_NR], vx[SS_NR], vz[SS_NR];
+#pragma unroll
+                for (int u = 0; u < SS_NR; ++u) {
+                    const int r = gl + u * SS_GROUP;
+                    const bool in = r < k;
+                    xr[u] = in ? ap[r] : 0.0;
+                    zr[u] = in ? aq[r] : 0.0;
+                    vx[u] = in ? vp[r] : 0.0;
+                    vz[u] = in ? vq[r] : 0.0;
+                }
                 double al = 0.0, be = 0.0, ga = 0.0;
-                for (int r = gl; r < k; r += SS_GROUP) {
-                    const double x = ap[r], z = aq[r];
-                    al = fma(x, x, al);
-                    be = fma(z, z, be);
-                    ga = fma(x, z, ga);
+#pragma unroll
+                for (int u = 0; u < SS_NR; ++u) {
+                    al = fma(xr[u], xr[u], al);
+                    be = fma(zr[u], zr[u], be);
+                    ga = fma(xr[u], zr[u], ga);
                 }
                 al = group_sum(al);
                 be = group_sum(be);
@@ -234,14 +261,15 @@ __global__ __launch_bounds__(SS_THREADS) void smallsolve_k(SmallArgs a) {
                     const double t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
                     const double c = 1.0 / sqrt(1.0 + t * t);
                     const double sn = c * t;
-                    double *vp = V + (size_t)p * K, *vq = V + (size_t)q * K;
-                    for (int r = gl; r < k; r += SS_GROUP) {
-                        const double x = ap[r], z = aq[r];
-                        ap[r] = c * x - sn * z;
-                        aq[r] = sn * x + c * z;
-                        const double vx = vp[r], vz = vq[r];
-                        vp[r] = c * vx - sn * vz;
-                        vq[r] = sn * vx + c * vz;
+#pragma unroll
+                    for (int u = 0; u < SS_NR; ++u) {
+                        const int r = gl + u * SS_GROUP;
+                        if (r < k) {
+                            ap[r] = c * xr[u] - sn * zr[u];
+                            aq[r] = sn * xr[u] + c * zr[u];
+                            vp[r] = c * vx[u] - sn * vz[u];
+                            vq[r] = sn * vx[u] + c * vz[u];
+                        }
                     }
                     if (gl == 0) s_rot = 1;
                 }

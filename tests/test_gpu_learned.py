@@ -175,8 +175,28 @@ def test_solver_label_grid(pk, ortho):
     assert e <= 1e-9
     tg, ks = pk.mlp_labels(info["rre"], info["iters"])
     To, kso = L.labels(Ro, K)
-    assert int(ks[0]) == kso
-    assert np.allclose(tg[0].cpu().numpy(), To, rtol=0, atol=1e-7)
+    check_labels(tg[0].cpu().numpy(), int(ks[0]), To, kso, Ro, K, tie=1e-9)
+
+
+def check_labels(T, ks, To, kso, Ro, K, tie):
+    """The targets are argmins over the lambda grid (per iteration) and over
+    the iterations, decided on values that agree to ~1e-11: where the oracle's
+    minimum is unique by more than `tie` (relative) the choice must be the
+    same; inside a near-tie the GPU's choice must be one of the tied values."""
+    g_gpu = np.rint((T[:, 0] / L.SCALE + 8.0) * (L.LGRID - 1) / 8.0).astype(int)
+    assert np.allclose(T[:, 0], (-8.0 + 8.0 * g_gpu / (L.LGRID - 1)) * L.SCALE, rtol=0, atol=1e-7)
+    for j in range(Ro.shape[0]):
+        row = Ro[j]
+        m = row.min()
+        tied = np.flatnonzero(row <= m * (1 + tie))
+        if tied.size == 1:
+            assert g_gpu[j] == tied[0], (j, g_gpu[j], tied)
+        else:
+            assert g_gpu[j] in tied, (j, g_gpu[j], tied)
+    best = Ro.min(axis=1)
+    tied_k = np.flatnonzero(best <= best.min() * (1 + tie)) + 1
+    assert (ks == kso) if tied_k.size == 1 else (ks in tied_k), (ks, kso, tied_k)
+    assert np.allclose(T[:, 1], ks / K, rtol=0, atol=1e-7)
 
 
 @pytest.mark.parametrize("mode", ["AB", "BA"])
