@@ -406,9 +406,10 @@ __global__ __launch_bounds__(256) void pixbp2d_k(VecRef yr, VecRef xr,
             for (int m = 0; m < 4; ++m) {
                 const T t = fma(Ym[m], sb, base);
                 const T f = fract_of(t);
-                // t >= 1 inside the window, so (int) is floor; the clamp only
-                // guards the LDS row
-                const int idx = (int)clampf(t, (T)0, (T)(W - 1));
+                // every pixel of the tile (overhang included) has
+                // 1 <= t < 2 + 31 (|cos| + |sin|)/ds <= W - 3 up to rounding of
+                // a few ulp, so (int) is floor and both taps lie in the window
+                const int idx = (int)t;
                 const T v = wrow[2 * idx], dv = wrow[2 * idx + 1];
                 acc[m] += fma(f, dv, v);
             }
