@@ -354,7 +354,7 @@ __global__ __launch_bounds__(256) void pixbp2d_k(VecRef yr, VecRef xr,
     typedef typename acc_of<TI>::type T;
     extern __shared__ __align__(16) unsigned char smem[];
     T *win = reinterpret_cast<T *>(smem);                           // [G][W][2]
-    int *wtab = reinterpret_cast<int *>(smem + (size_t)G * W * 2 * sizeof(T));   // [G]
+    T *wbase = reinterpret_cast<T *>(smem + (size_t)G * W * 2 * sizeof(T));      // [G]: cd - w0 (exact)
     // work order: (slice, tile row, tile column)
     const uint32_t w = xcd_remap(blockIdx.x, gridDim.x, nxcc);
     const uint32_t wt = w / (uint32_t)ntx;
@@ -384,7 +384,7 @@ __global__ __launch_bounds__(256) void pixbp2d_k(VecRef yr, VecRef xr,
             const T cb = tab[a].cb, sb = tab[a].sb;
             const T tmin = cd + fmin(X0 * cb, X1 * cb) + fmin(Y0 * sb, Y1 * sb);
             const int w0 = (int)floor(tmin) - 1;
-            if ((threadIdx.x & 63) == 0) wtab[al] = w0;
+            if ((threadIdx.x & 63) == 0) wbase[al] = cd - (T)w0;
             const TIN *row = y + (int64_t)a * nd;
             T *dst = win + (size_t)al * W * 2;
             for (int c = threadIdx.x & 63; c < W; c += 64) {
@@ -400,7 +400,7 @@ __global__ __launch_bounds__(256) void pixbp2d_k(VecRef yr, VecRef xr,
             const int a = a0 + al;
             const T cb = tab[a].cb, sb = tab[a].sb;
             // t relative to the window start: t - w0 = fma(Y, sb, X cb + cd - w0)
-            const T base = fma(X, cb, cd - (T)wtab[al]);
+            const T base = fma(X, cb, wbase[al]);
             const T *wrow = win + (size_t)al * W * 2;
 #pragma unroll
             for (int m = 0; m < 4; ++m) {
@@ -439,7 +439,7 @@ static void pixbp_window(const abba_op *op, int *W, int *G) {
 
 // Most angles per chunk whose windows fit in 64 KB of LDS.
 static int pixbp_max_g(const abba_op *op, int W) {
-    const size_t per = (size_t)W * 2 * (op->img_dtype == ABBA_F64 ? 8 : 4) + sizeof(int);
+    const size_t per = (size_t)(W * 2 + 1) * (op->img_dtype == ABBA_F64 ? 8 : 4);
     return (int)std::max<size_t>(1, 65536 / per);
 }
 
@@ -615,7 +615,7 @@ static int back_launch(const abba_op *op, VecRef y, VecRef x, int batch, const L
     pixbp_window(op, &W, &G);
     if (const TuneEntry *t = tune_for(op, batch))
         if (t->b_g > 0) G = std::min(t->b_g, pixbp_max_g(op, W));
-    const size_t shmem = (size_t)G * W * 2 * sizeof(T) + (size_t)G * sizeof(int);
+    const size_t shmem = (size_t)G * (W * 2 + 1) * sizeof(T);
     if ((size_t)W * 2 * sizeof(T) > 32768) return ABBA_ERR_UNSUPPORTED;
     const int btx = (nx + BT - 1) / BT, bty = (ny + BT - 1) / BT;
     const uint64_t tiles = (uint64_t)btx * bty;
