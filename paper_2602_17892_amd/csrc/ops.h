@@ -28,7 +28,7 @@ struct AngleTab {
 
 // Angles per workgroup of the LDS-band Joseph projector; its angle groups
 // hold angles of one march direction only.
-constexpr int JOSEPH_GA = 4;
+constexpr int JOSEPH_GA = 6;
 
 // Per-view constants of the 3D cone beam, FP64 (ray set-up is FP64; the
 // voxel-driven B rounds them to its accumulation type).
