@@ -162,10 +162,13 @@ def joseph_ray_steps(n, n_angles, n_det, ds=1.0):
 
 
 def kernel_source_digest():
+    """Digest of the sources that define the 2D projector kernels (their code
+    and launch constants)."""
     import hashlib
     h = hashlib.sha256()
-    with open(os.path.join(ROOT, "paper_2602_17892_amd", "csrc", "proj2d.hip"), "rb") as f:
-        h.update(f.read())
+    for name in ("proj2d.hip", "ops.h"):
+        with open(os.path.join(ROOT, "paper_2602_17892_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
     return h.hexdigest()[:16]
 
 
