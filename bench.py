@@ -582,9 +582,9 @@ def variants_workload(args):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU: the slices of the batched workload are "
-                          "independent and shard with no communication, but only the one-GPU path is "
-                          "built and measured; rerun with --gpus 1"}))
+        print(json.dumps({"error": "bench.py runs on one GPU: the slices of the batched workload are "
+                          "independent and would shard with no communication, but only the one-GPU path "
+                          "exists; rerun with --gpus 1"}))
         sys.exit(2)
     import numpy as np
     import torch

@@ -78,7 +78,7 @@ typedef enum {
     ABBA_ERR_NOMEM = -4,        /* host allocation failed or size overflow                    */
     ABBA_ERR_HIP = -5,          /* a HIP call or kernel launch failed                         */
     ABBA_ERR_NONFINITE = -6,    /* non-finite value found where a check was requested        */
-    ABBA_ERR_UNSUPPORTED = -7   /* valid request that this build does not implement          */
+    ABBA_ERR_UNSUPPORTED = -7   /* valid request that this library does not implement        */
 } abba_status;
 
 typedef enum { ABBA_F64 = 0, ABBA_F32 = 1, ABBA_BF16 = 2 } abba_dtype;

@@ -5,7 +5,7 @@ reconstruction method's arithmetic (no projector, no Krylov step, no
 regularisation), so that both sides of a parity test can take their inputs
 from here without sharing any computation.
 
-Conventions (the paper specifies none of these; they are the build's own):
+Conventions (the paper specifies none of these; they are choices of this package):
 
 * Random streams: ``numpy.random.default_rng([cfg_id, idx, stream])`` (PCG64),
   with stream 0 = phantom, 1 = noise vector, 2 = noise level.
