@@ -3,7 +3,7 @@
 The binding only marshals arguments: every step of the method runs in the
 HIP kernels of libabba.so.  PyTorch supplies device memory and the current
 HIP stream.  Importing this module fails loudly if the library is not built
-(``python -m paper_2602_17892_amd.build``).
+(``python paper_2602_17892_amd/build.py``).
 
 Low-level names mirror the C ABI (include/abba.h): abba_op_create,
 abba_project, abba_backproject, abba_solve_workspace, abba_solve, ...
@@ -79,7 +79,7 @@ class _Exec(ctypes.Structure):
 
 def _load():
     if not os.path.exists(LIB_PATH):
-        raise ImportError(f"{LIB_PATH} is not built; run `python -m paper_2602_17892_amd.build`")
+        raise ImportError(f"{LIB_PATH} is not built; run `python paper_2602_17892_amd/build.py`")
     L = ctypes.CDLL(LIB_PATH)
     vp, i = ctypes.c_void_p, ctypes.c_int
     L.abba_version.restype = ctypes.c_char_p

@@ -1,6 +1,6 @@
 """Build libabba.so (HIP, gfx950) in-tree.
 
-    python -m paper_2602_17892_amd.build
+    python paper_2602_17892_amd/build.py
 
 Each .hip source under csrc/ is compiled to an object under _build/ and the
 objects are linked into paper_2602_17892_amd/libabba.so.

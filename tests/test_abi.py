@@ -23,7 +23,7 @@ def declared_functions():
 @pytest.fixture(scope="module")
 def L():
     if not os.path.exists(LIB):
-        pytest.fail("libabba.so is not built (python -m paper_2602_17892_amd.build)")
+        pytest.fail("libabba.so is not built (python paper_2602_17892_amd/build.py)")
     return ctypes.CDLL(LIB)
 
 
