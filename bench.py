@@ -329,7 +329,7 @@ def cone_workload(args):
     A32 = pk.Operator("joseph", g, "f32", "f32")
     tune = {"A": pk.autotune(A, 1), "B": pk.autotune(B, 1)}
     log(args, "autotune: " + "; ".join(f"{k} {v['ms']:.2f} ms (built-in {v['default_ms']:.2f}), choice "
-                                       f"{ {c: v[c] for c in ('czt', 'a_rb')} }" for k, v in tune.items()))
+                                       f"{ {c: v[c] for c in ('czt', 'a_rb', 'a_occ')} }" for k, v in tune.items()))
     t0 = time.perf_counter()
     vol, _ = synth.phantom3d(4, 0, n, device=torch.device("cuda"))
     xt = vol.to(torch.float32).reshape(1, n, n, n).contiguous()
@@ -381,7 +381,7 @@ def cone_workload(args):
         "config": {"workload": f"{n}^3 cone beam, {C['views']} views x {C['nv']}x{C['nu']} detector at pitch "
                                f"{C['pitch']}, SID {C['sid']:g}, SDD {C['sdd']:g}, hybrid BA-GMRES GCV, k {K}"},
         "rre": rre,
-        "autotune": {k: {"choice": {c: v[c] for c in ("czt", "a_rb")}, "ms": round(v["ms"], 3),
+        "autotune": {k: {"choice": {c: v[c] for c in ("czt", "a_rb", "a_occ")}, "ms": round(v["ms"], 3),
                          "builtin_ms": round(v["default_ms"], 3)} for k, v in tune.items()},
         "projector": {"A_ms": round(t_A * 1e3, 3), "B_ms": round(t_B * 1e3, 3), "A_TFLOPs": round(tf_A, 3),
                       "B_TFLOPs": round(tf_B, 3), "A_plane_crossings": steps, "B_voxel_view_pairs": pairs,
@@ -718,7 +718,7 @@ def main():
                       "A_TFLOPs": round(tf_A, 3), "B_TFLOPs": round(tf_B, 3), "A_ray_steps": steps,
                       "B_pixel_angle_pairs": pairs},
         "roofline": roofline,
-        "autotune": {k: {"choice": {c: v[c] for c in ("a_path", "a_jb", "b_g", "czt", "a_rb")}, "ms": round(v["ms"], 3),
+        "autotune": {k: {"choice": {c: v[c] for c in ("a_path", "a_jb", "b_g", "czt", "a_rb", "a_occ")}, "ms": round(v["ms"], 3),
                          "builtin_ms": round(v["default_ms"], 3)} for k, v in tune.items()},
     }
     if not args.no_cpu_baseline:

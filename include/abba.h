@@ -131,6 +131,10 @@ typedef struct {
     int czt;           /* 3D B: voxels per thread along z, 2, 4 or 8 (0: 4)                   */
     int a_rb;          /* 3D A: detector rows per band of the work order (0: all rows, the
                           views outermost); the views of a band run before the next band  */
+    int a_occ;         /* 3D A: at most this many workgroups per compute unit (0: no cap),
+                          held by reserving unused LDS (at most 64 KB per workgroup, so
+                          a_occ >= 3 on 160 KB of LDS per CU; smaller values are
+                          ABBA_ERR_ARG): fewer rays in flight share the caches           */
     double ms;         /* abba_autotune: mean time of one apply with the chosen launch       */
     double default_ms; /* abba_autotune: the same with the built-in rules                    */
     int candidates;    /* abba_autotune: launch choices timed besides the built-in rules     */

@@ -253,8 +253,13 @@ int abba_op_create(abba_op **out, int kind, const abba_geometry *geom, int img_d
     if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, op->device) != hipSuccess || ncu < 1)
         ncu = 1;
     (void)hipGetLastError();
+    int lds_cu = 0;
+    if (hipDeviceGetAttribute(&lds_cu, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor, op->device) !=
+            hipSuccess || lds_cu < 1)
+        lds_cu = 65536;
     op->nxcc = nxcc;
     op->ncu = ncu;
+    op->lds_cu = lds_cu;
     rc = op_build_tables(op);
     if (rc) {
         if (op->tab) (void)hipFree(op->tab);
@@ -355,6 +360,7 @@ static void to_c(const TuneEntry &t, abba_tune *o) {
     o->b_g = t.b_g;
     o->czt = t.czt;
     o->a_rb = t.a_rb;
+    o->a_occ = t.a_occ;
 }
 
 static void store_tuning(abba_op *op, const TuneEntry &e) {
@@ -384,7 +390,12 @@ int abba_op_set_tuning(abba_op *op, int batch, const abba_tune *t) {
             }
         return ABBA_OK;
     }
-    store_tuning(op, TuneEntry{batch, t->a_path, t->a_jb, t->b_g, t->czt, t->a_rb});
+    if (t->a_occ < 0 || (t->a_occ > 0 && op->lds_cu / t->a_occ > 65536)) {
+        set_error("abba_op_set_tuning: a_occ must be 0 or at least %d (LDS per CU / 64 KB)",
+                  (op->lds_cu + 65535) / 65536);
+        return ABBA_ERR_ARG;
+    }
+    store_tuning(op, TuneEntry{batch, t->a_path, t->a_jb, t->b_g, t->czt, t->a_rb, t->a_occ});
     return ABBA_OK;
 }
 

@@ -460,15 +460,18 @@ static int cone_fwd_t(const abba_op *op, VecRef x, VecRef y, int batch, void *sc
     if (std::max({cc.vx, cc.vy, cc.vz}) >= (size_t)1 << 31) return ABBA_ERR_UNSUPPORTED;
     const int nbu = (g.det_u + 255) / 256;
     int rb = g.det_v;
-    if (const TuneEntry *t = tune_for(op, batch))
+    size_t cap_lds = 0;   // unused LDS per workgroup that caps the workgroups per CU
+    if (const TuneEntry *t = tune_for(op, batch)) {
         if (t->a_rb >= 1) rb = std::min(t->a_rb, g.det_v);
+        if (t->a_occ >= 1) cap_lds = std::min<size_t>(65536, (size_t)op->lds_cu / (size_t)t->a_occ / 512 * 512);
+    }
     const int nrb = (g.det_v + rb - 1) / rb;
     const uint64_t per = (uint64_t)nbu * nrb * rb * g.n_angles;
     if (per > CMAX_GROUPS) return ABBA_ERR_UNSUPPORTED;
     const int ch = (int)std::min<uint64_t>((uint64_t)batch, CMAX_GROUPS / per);
     for (int s0 = 0; s0 < batch; s0 += ch) {
         const int nb = std::min(ch, batch - s0);
-        hipLaunchKernelGGL((cone_fwd_k<TI, TO>), dim3((uint32_t)(per * nb)), dim3(256), 0, L.stream, vx, vy, vz,
+        hipLaunchKernelGGL((cone_fwd_k<TI, TO>), dim3((uint32_t)(per * nb)), dim3(256), cap_lds, L.stream, vx, vy, vz,
                            (int64_t)cc.vx, (int64_t)cc.vy, (int64_t)cc.vz, y, (const ConeView *)op->tab, g.nx, g.ny,
                            g.nz, g.n_angles, g.det_u, g.det_v, g.det_pitch_u, g.det_pitch_v, nbu, rb, nrb,
                            (uint32_t)op->nxcc, s0, L.kdev, L.active);
@@ -538,9 +541,12 @@ int cone_tune_candidates(const abba_op *op, TuneEntry *out, int cap) {
     if (op->kind == ABBA_OP_PIXEL)
         for (int c : {2, 4, 8})
             if (n < cap) out[n++] = TuneEntry{0, 0, 0, 0, c, 0};
-    if (op->kind == ABBA_OP_JOSEPH)
+    if (op->kind == ABBA_OP_JOSEPH) {
         for (int r : {2, 8, 32})
-            if (n < cap && r < op->g.det_v) out[n++] = TuneEntry{0, 0, 0, 0, 0, r};
+            if (n < cap && r < op->g.det_v) out[n++] = TuneEntry{0, 0, 0, 0, 0, r, 0};
+        for (int c : {5, 4})
+            if (n < cap) out[n++] = TuneEntry{0, 0, 0, 0, 0, 0, c};
+    }
     return n;
 }
 

@@ -63,6 +63,7 @@ struct TuneEntry {
     int b_g;      // 2D B: angles per LDS chunk
     int czt;      // 3D B: voxels per thread along z (2, 4 or 8)
     int a_rb;     // 3D A: detector rows per band of the work order (1 to 64)
+    int a_occ;    // 3D A: workgroups per compute unit at most (0: no cap)
 };
 constexpr int MAX_TUNE = 8;
 
@@ -83,6 +84,7 @@ struct abba_op {
     int device;
     int nxcc;              // XCDs of the device (workgroups are dealt to them round-robin)
     int ncu;               // compute units of the device
+    int lds_cu;            // LDS bytes per compute unit
     void *tab;             // AngleTab<float|double>[n_angles] or ConeView[views]
     int *agrp;             // 2D: [ngroups][4] {first, count, rowmarch, 0}, then the angle order [n_angles]
     int ngroups;

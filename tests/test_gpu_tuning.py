@@ -41,7 +41,7 @@ def test_2d_launch_choices_bitwise_equal(pk, shape, dt):
     ya0, xb0 = pk.project(A, x), pk.backproject(B, y)
     for path, jb in [(0, 0), (1, 2), (1, 3), (1, 4)]:
         pk.set_tuning(A, S, a_path=path, a_jb=jb)
-        assert pk.get_tuning(A, S) == dict(a_path=path, a_jb=jb, b_g=0, czt=0, a_rb=0)
+        assert pk.get_tuning(A, S) == dict(a_path=path, a_jb=jb, b_g=0, czt=0, a_rb=0, a_occ=0)
         assert torch.equal(pk.project(A, x), ya0), (path, jb)
     for g in (1, 8, 16, 64, 128):
         pk.set_tuning(B, S, b_g=g)
@@ -67,6 +67,10 @@ def test_cone_launch_choices_bitwise_equal(pk):
     for rb in (1, 3, 5, 8, 64):          # ragged last bands included (24 rows)
         pk.set_tuning(A, 2, a_rb=rb)
         assert torch.equal(pk.project(A, x), y0), rb
+    for occ in (5, 4, 3):                # workgroups per CU capped by reserved LDS
+        pk.set_tuning(A, 2, a_occ=occ)
+        assert pk.get_tuning(A, 2)["a_occ"] == occ
+        assert torch.equal(pk.project(A, x), y0), occ
 
 
 def test_autotune_keeps_a_choice(pk):
@@ -79,7 +83,7 @@ def test_autotune_keeps_a_choice(pk):
     print(f"A: {ta}\nB: {tb}")
     assert ta["candidates"] == 4 and tb["candidates"] >= 3
     assert ta["ms"] <= ta["default_ms"] and tb["ms"] <= tb["default_ms"]
-    assert pk.get_tuning(A, S) == {k: ta[k] for k in ("a_path", "a_jb", "b_g", "czt", "a_rb")}
+    assert pk.get_tuning(A, S) == {k: ta[k] for k in ("a_path", "a_jb", "b_g", "czt", "a_rb", "a_occ")}
     assert torch.equal(pk.project(A, x), ya0)
     # the solver uses the stored choice and returns the same bits
     og_b = pk.project(A, x).contiguous()
@@ -94,5 +98,9 @@ def test_tuning_argument_errors(pk):
     A, _ = ops2d(pk, (16, 16, 20, 23))
     with pytest.raises(pk.AbbaError):
         pk.set_tuning(A, 0, a_path=1)
+    with pytest.raises(pk.AbbaError):
+        pk.set_tuning(A, 1, a_occ=-1)
+    with pytest.raises(pk.AbbaError):
+        pk.set_tuning(A, 1, a_occ=1)          # would reserve more than 64 KB of LDS
     with pytest.raises(pk.AbbaError):
         pk.autotune(A, 0)
