@@ -40,7 +40,9 @@ struct ConeB {
     T n[3];     // detector normal
     T eup[3];   // eu / pu
     T evp[3];   // ev / pv
-    T Sn, Su, Sv, cu, cv, dist;
+    T Sn, Su, Sv;
+    T cu, cv;   // detector coordinate of the centre, plus the two leading pad entries
+    T dist;
 };
 
 // ------------------------------------------------------------ host side ----
@@ -125,8 +127,8 @@ int build_cone_tables(abba_op *op) {
             b->Sn = (T)c.Sn;
             b->Su = (T)c.Su;
             b->Sv = (T)c.Sv;
-            b->cu = (T)c.cu;
-            b->cv = (T)c.cv;
+            b->cu = (T)(c.cu + CPAD);
+            b->cv = (T)(c.cv + CPAD);
             b->dist = (T)c.dist;
         };
         if (op->img_dtype == ABBA_F64) fill(reinterpret_cast<ConeB<double> *>(host.data() + bytes_d) + v);
@@ -370,13 +372,18 @@ __global__ __launch_bounds__(256) void cone_fwd_k(const TI *__restrict__ vx, con
 
 // B: one thread per CZT voxels along z (a 16 x 16 (y, x) tile per workgroup;
 // CZT is a launch choice that leaves every sum unchanged); loop over the views.
+// MP is the power of the magnification in the weight: 2 for the cone beam
+// (two transverse detector axes), 1 for the fan beam.
 constexpr int CZT_DEFAULT = 4;
 
-template <typename TI, int CZT>
+__device__ __forceinline__ float cclamp(float x, float lo, float hi) { return __builtin_amdgcn_fmed3f(x, lo, hi); }
+__device__ __forceinline__ double cclamp(double x, double lo, double hi) { return fmin(fmax(x, lo), hi); }
+
+template <typename TI, int CZT, int MP>
 __global__ __launch_bounds__(256) void cone_bp_k(const typename acc_of<TI>::type *__restrict__ yp, int64_t ss,
                                                  VecRef xr, const ConeB<typename acc_of<TI>::type> *__restrict__ vb,
                                                  int nx, int ny, int nz, int nviews, int nu, int nv,
-                                                 typename acc_of<TI>::type ipp, int mpow, int ntx, int nty,
+                                                 typename acc_of<TI>::type ipp, int ntx, int nty,
                                                  int ntz, uint32_t nxcc, int s0, const int *kdev,
                                                  const int *active) {
     typedef typename acc_of<TI>::type T;
@@ -405,19 +412,22 @@ __global__ __launch_bounds__(256) void cone_bp_k(const typename acc_of<TI>::type
         const T bn = fma(X, b.n[0], fma(Y, b.n[1], -b.Sn));
         const T bu = fma(X, b.eup[0], fma(Y, b.eup[1], -b.Su));
         const T bv = fma(X, b.evp[0], fma(Y, b.evp[1], -b.Sv));
+        // the view is the same for the whole workgroup: 32-bit byte offsets
+        // from its base (a padded view has < 2^30 entries)
         const T *view = Ys + (int64_t)vw * Lv * Lu;
 #pragma unroll
         for (int m = 0; m < CZT; ++m) {
             const T den = fma(Z[m], b.n[2], bn);
             const T M = cdiv(b.dist, den);
-            const T u = fma(M, fma(Z[m], b.eup[2], bu), b.cu) + (T)CPAD;
-            const T v = fma(M, fma(Z[m], b.evp[2], bv), b.cv) + (T)CPAD;
+            const T u = fma(M, fma(Z[m], b.eup[2], bu), b.cu);   // padded coordinates
+            const T v = fma(M, fma(Z[m], b.evp[2], bv), b.cv);
             const T fu = cfract(u), fv = cfract(v);
-            const int iu = (int)fmin(fmax(u, (T)0), umax), iv = (int)fmin(fmax(v, (T)0), vmax);
-            const T *e = view + (int64_t)iv * Lu + iu;
+            const uint32_t iu = (uint32_t)cclamp(u, (T)0, umax), iv = (uint32_t)cclamp(v, (T)0, vmax);
+            const T *e = reinterpret_cast<const T *>(reinterpret_cast<const char *>(view) +
+                                                     (iv * (uint32_t)Lu + iu) * (uint32_t)sizeof(T));
             const T a00 = e[0], a01 = e[1], a10 = e[Lu], a11 = e[Lu + 1];
             const T lo = fma(fu, a01 - a00, a00), hi = fma(fu, a11 - a10, a10);
-            const T wgt = mpow == 2 ? M * M * ipp : M * ipp;
+            const T wgt = (MP == 2 ? M * M : M) * ipp;
             acc[m] = fma(wgt, fma(fv, hi - lo, lo), acc[m]);
         }
     }
@@ -500,15 +510,21 @@ static int cone_bp_launch(const abba_op *op, const typename acc_of<TI>::type *yp
     const int ntx = (g.nx + 15) / 16, nty = (g.ny + 15) / 16, ntz = (g.nz + CZT - 1) / CZT;
     const uint64_t per = (uint64_t)ntx * nty * ntz;
     if (per > CMAX_GROUPS) return ABBA_ERR_UNSUPPORTED;
+    if ((int64_t)(g.det_u + 2 * CPAD) * (g.det_v + 2 * CPAD) >= (int64_t)1 << 30) return ABBA_ERR_UNSUPPORTED;
     const int ch = (int)std::min<uint64_t>((uint64_t)batch, CMAX_GROUPS / per);
     const size_t bytes_d = sizeof(ConeView) * g.n_angles;
     const ConeB<T> *vb = reinterpret_cast<const ConeB<T> *>((const unsigned char *)op->tab + bytes_d);
     for (int s0 = 0; s0 < batch; s0 += ch) {
         const int nb = std::min(ch, batch - s0);
-        hipLaunchKernelGGL((cone_bp_k<TI, CZT>), dim3((uint32_t)(per * nb)), dim3(256), 0, L.stream, yp,
-                           (int64_t)cc.sino, x, vb, g.nx, g.ny, g.nz, g.n_angles, g.det_u, g.det_v,
-                           (T)(1.0 / (g.det_pitch_u * g.det_pitch_v)), g.kind == ABBA_GEOM_FAN2D ? 1 : 2, ntx, nty,
-                           ntz, (uint32_t)op->nxcc, s0, L.kdev, L.active);
+        const T ipp = (T)(1.0 / (g.det_pitch_u * g.det_pitch_v));
+        if (g.kind == ABBA_GEOM_FAN2D)
+            hipLaunchKernelGGL((cone_bp_k<TI, CZT, 1>), dim3((uint32_t)(per * nb)), dim3(256), 0, L.stream, yp,
+                               (int64_t)cc.sino, x, vb, g.nx, g.ny, g.nz, g.n_angles, g.det_u, g.det_v, ipp, ntx,
+                               nty, ntz, (uint32_t)op->nxcc, s0, L.kdev, L.active);
+        else
+            hipLaunchKernelGGL((cone_bp_k<TI, CZT, 2>), dim3((uint32_t)(per * nb)), dim3(256), 0, L.stream, yp,
+                               (int64_t)cc.sino, x, vb, g.nx, g.ny, g.nz, g.n_angles, g.det_u, g.det_v, ipp, ntx,
+                               nty, ntz, (uint32_t)op->nxcc, s0, L.kdev, L.active);
         ABBA_LAUNCHED("cone_bp_k");
     }
     return ABBA_OK;
