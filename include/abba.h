@@ -101,9 +101,12 @@ typedef struct abba_op abba_op;
 /* Create an operator on the current HIP device.  Geometry tables are built
  * in FP64 on the host and rounded to the storage type.  `img_dtype` and
  * `sino_dtype` must be one of the supported pairs.  *out receives the handle;
- * it is immutable and may be used from several streams at once. */
+ * apart from its launch tuning (abba_autotune, abba_op_set_tuning) it is
+ * immutable and may be used from several streams at once. */
 int abba_op_create(abba_op **out, int kind, const abba_geometry *geom,
                    int img_dtype, int sino_dtype);
+/* Frees the operator's device tables (hipFree, which waits for the device);
+ * no work that uses the operator may still be queued.  NULL is a no-op. */
 void abba_op_destroy(abba_op *op);
 /* Image length n and sinogram length m of one slice. */
 int abba_op_sizes(const abba_op *op, int64_t *n_img, int64_t *n_sino);
