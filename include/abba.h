@@ -121,7 +121,10 @@ int abba_op_sizes(const abba_op *op, int64_t *n_img, int64_t *n_sino);
 int abba_project(const abba_op *A, const void *x, void *y, int batch, void *stream);
 
 /* x_s = B y_s for s < batch; `B` is ABBA_OP_PIXEL (unmatched B of
- * eqs. (4)-(5)) or ABBA_OP_JOSEPH_T (exact A^T).  Asynchronous. */
+ * eqs. (4)-(5)) or ABBA_OP_JOSEPH_T (exact A^T).  y is [batch][m] in the
+ * sinogram dtype, x [batch][n] in the image dtype.  Asynchronous on `stream`.
+ * On cone and fan geometries it allocates its scratch (a zero-padded copy of
+ * the views) stream-ordered; on the 2D parallel beam it allocates nothing. */
 int abba_backproject(const abba_op *B, const void *y, void *x, int batch, void *stream);
 
 /* ---- Launch tuning (tile shapes and kernel choices of the projectors).

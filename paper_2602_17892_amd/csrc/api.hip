@@ -343,14 +343,9 @@ int abba_backproject(const abba_op *B, const void *y, void *x, int batch, void *
         if (e != hipSuccess) return hip_fail(e, "hipFreeAsync");
         return ABBA_OK;
     }
-    // the pixel-driven backprojector reads a zero-padded copy of the sinogram
-    void *scr = nullptr;
-    ABBA_HIP(hipMallocAsync(&scr, par2d_scratch_bytes(B, batch), st));
-    int rc = par2d_back(B, yr, B->sino_dtype, xr, batch, scr, L);
-    hipError_t e = hipFreeAsync(scr, st);
-    if (rc) return rc;
-    if (e != hipSuccess) return hip_fail(e, "hipFreeAsync");
-    return ABBA_OK;
+    // the pixel-driven backprojector stages sinogram windows in LDS and needs
+    // no scratch in device memory
+    return par2d_back(B, yr, B->sino_dtype, xr, batch, nullptr, L);
 }
 
 // ------------------------------------------------------------ tuning ------
