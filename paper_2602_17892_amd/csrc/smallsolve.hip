@@ -148,7 +148,7 @@ __global__ __launch_bounds__(SS_THREADS) void smallsolve_k(SmallArgs a) {
     double *col = V + (size_t)K * K;   // [K+1]
     double *red = col + (K + 1);       // [64]
     double *xtra = red + 64;           // small-K overflow area
-    __shared__ int s_rot;
+    __shared__ int s_rot, s_big;
     __shared__ int s_idx;
     __shared__ double s_val[4];
     __shared__ double s_uk1;
@@ -215,11 +215,14 @@ __global__ __launch_bounds__(SS_THREADS) void smallsolve_k(SmallArgs a) {
     // values only at O(delta^2) and the vectors at O(delta): 1e-12 is far
     // below what any consumer of y needs, and well above the rounding noise
     // of the computed inner products (which a k*eps threshold would chase).
-    const double tol = 1e-12;
+    // One-sided Jacobi converges quadratically: after a sweep in which every
+    // pair was off-orthogonal by at most sqrt(tol), what remains is O(tol),
+    // so that sweep is the last one (the confirmation sweep is skipped).
+    const double tol = 1e-12, tol_last = 1e-6;
     int sweeps = 0;
     for (int sweep = 0; sweep < MAX_SWEEPS && k > 1; ++sweep) {
         ++sweeps;
-        if (tid == 0) s_rot = 0;
+        if (tid == 0) s_rot = s_big = 0;
         __syncthreads();
         for (int rnd = 0; rnd < n - 1; ++rnd) {
             for (int pi = grp; pi < n / 2; pi += SS_PAIRS) {
@@ -271,14 +274,17 @@ __global__ __launch_bounds__(SS_THREADS) void smallsolve_k(SmallArgs a) {
                             vq[r] = sn * vx[u] + c * vz[u];
                         }
                     }
-                    if (gl == 0) s_rot = 1;
+                    if (gl == 0) {
+                        s_rot = 1;
+                        if (fabs(ga) > tol_last * sqrt(al * be)) s_big = 1;
+                    }
                 }
             }
             __syncthreads();
         }
-        const int rot = s_rot;
+        const int rot = s_rot, big = s_big;
         __syncthreads();
-        if (!rot) break;
+        if (!rot || !big) break;
     }
 
     // ---- sigma_i = ||A_i||, uhat_i = A_i . g / sigma_i; save the warm start
