@@ -101,3 +101,37 @@ def test_validation_of_the_newer_entry_points():
     assert pk.lib.abba_autotune(None, 4, 3, None, ctypes.byref(t)) == -1
     assert pk.lib.abba_op_set_tuning(None, 4, ctypes.byref(t)) == -1
     assert pk.lib.abba_op_get_tuning(None, 4, ctypes.byref(t)) == -1
+
+
+# ctypes field name -> C field name where they differ (`lambda` is a Python keyword)
+_C_NAMES = {("abba_reg", "lam"): "lambda", ("abba_out", "lam"): "lambda"}
+
+
+def test_struct_layouts_match_the_header(tmp_path):
+    """The binding's ctypes structures have the sizes and field offsets of the
+    C structures in include/abba.h (compiled here by gcc)."""
+    import shutil
+    import subprocess
+    if shutil.which("gcc") is None:
+        pytest.skip("gcc is not available")
+    if not os.path.exists(LIB):
+        pytest.fail("libabba.so is not built (python paper_2602_17892_amd/build.py)")
+    import paper_2602_17892_amd as pk
+    structs = {"abba_geometry": pk._Geometry, "abba_reg": pk._Reg, "abba_stop": pk._Stop, "abba_out": pk._Out,
+               "abba_exec": pk._Exec, "abba_tune": pk._Tune}
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "abba.h"', "int main(void) {"]
+    for cname, cls in structs.items():
+        lines.append(f'printf("{cname} size %zu\\n", sizeof({cname}));')
+        for fname, _ in cls._fields_:
+            c = _C_NAMES.get((cname, fname), fname)
+            lines.append(f'printf("{cname} {fname} %zu\\n", offsetof({cname}, {c}));')
+    lines.append("return 0; }")
+    src, exe = tmp_path / "layout.c", tmp_path / "layout"
+    src.write_text("\n".join(lines) + "\n")
+    subprocess.run(["gcc", "-std=c99", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split("\n")
+    got = {tuple(l.split()[:2]): int(l.split()[2]) for l in out if l.strip()}
+    for cname, cls in structs.items():
+        assert got[(cname, "size")] == ctypes.sizeof(cls), cname
+        for fname, _ in cls._fields_:
+            assert got[(cname, fname)] == getattr(cls, fname).offset, (cname, fname)
