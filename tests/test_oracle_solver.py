@@ -440,3 +440,21 @@ def test_ncp_stop_fires_once_the_residual_is_white(oracle_lib):
     # discrepancy principle does
     od = sv.hybrid_gmres(og.A, og.B, b, mode="AB", K=40, rule="gcv", stop="dp", noise_norm=en)
     assert od.status == sv.STATUS_STOP_DP and o.iters < od.iters
+
+
+def test_stopping_rules_order_as_the_paper_reports(oracle_lib):
+    # Sec. 5 reports that residual stagnation stops later than the discrepancy
+    # principle and the cumulative periodogram earlier; a qualitative claim,
+    # checked over four seeded problems (64^2, 1 % noise, hybrid AB with GCV)
+    ncp_first, rns_later = 0, 0
+    for idx in range(4):
+        ops, x, b, en = c1_problem(idx=idx)
+        k = {}
+        for stop in ("ncp", "dp", "rns"):
+            o = sv.hybrid_gmres(ops.A, ops.B, b, mode="AB", K=80, rule="gcv", stop=stop, noise_norm=en,
+                                rns_eps=1e-3, det=91)
+            k[stop] = o.iters
+        assert k["dp"] < 80                     # the discrepancy principle fires on every one of them
+        ncp_first += k["ncp"] < k["dp"]
+        rns_later += k["rns"] > k["dp"]
+    assert ncp_first == 4 and rns_later >= 3
