@@ -6,16 +6,18 @@
 //       B != A^T of eqs. (4)-(5)).
 //
 // Layout: one thread per ray (A) or per pixel (A^T, B).  Lanes of a wave run
-// along detector bins (A) or over a 16 x 4 pixel patch (B), so consecutive
-// lanes touch neighbouring memory.
+// along detector bins (A), over two 32-pixel rows of a tile (B) or four
+// 16-pixel rows (A^T), so consecutive lanes touch neighbouring memory.
 //
-// A and B first copy their input into scratch with two zeros on each side of
-// every row: the image row-major and transposed (rays that march over image
-// columns walk rows of the transposed copy), the sinogram row by row.  An
-// interpolation position is then clamped into [-2, len], and its two taps are
-// always one 8-byte (FP64: 16-byte) load from the padded row whose values
-// are exactly those of the zero-extended row.  There are no per-tap masks and
-// no branches in the inner loops, and each step issues a single load.
+// A first copies the image into scratch with two zeros on each side of every
+// row, row-major and transposed (rays that march over image columns walk rows
+// of the transposed copy).  An interpolation position is then clamped into
+// [-2, len], and its two taps are always one 8-byte (FP64: 16-byte) load from
+// the padded row whose values are exactly those of the zero-extended row: no
+// per-tap masks and no branches in the inner loop, one load per step.  B
+// stages, per angle, the window of sinogram bins a pixel tile projects onto
+// in LDS (zeros outside the detector), with every tap inside the window by
+// construction, so it needs neither scratch nor a clamp.
 //
 // All launches are 1D; workgroups are renumbered so that each XCD (own L2)
 // walks a contiguous range of slices (see xcd_remap).  Nothing uses atomics,
