@@ -505,8 +505,9 @@ def learned_workload(args):
 
 
 def variants_workload(args):
-    """The 256 x 512^2 batch with restarted cycles of 20 (GCV, DP stop, 100
-    iterations in all) and with the NCP stop (GCV, at most 100), and one
+    """The 256 x 512^2 batch with hybrid BA-GMRES (GCV, DP stop, at most 100),
+    with restarted cycles of 20 (AB, GCV, DP stop, 100 iterations in all) and
+    with the NCP stop (AB, GCV, at most 100), and one
     1024^2 fan-beam slice (50 views, 1,024 bins of 3, SID 2048, SDD 4096,
     1.5 % noise, AB with GCV and DP stop) beside the oracle's time for it."""
     import numpy as np
@@ -521,7 +522,7 @@ def variants_workload(args):
     pk.autotune(A, S)
     pk.autotune(B, S)
     x, b, en, _ = make_inputs(args, pk, A, torch)
-    out = {"metric": "restarted / NCP / fan-beam variants", "config": {"workload": f"{S} x {args.n}^2 slices "
+    out = {"metric": "BA / restarted / NCP / fan-beam variants", "config": {"workload": f"{S} x {args.n}^2 slices "
            f"({args.angles} x {args.det}) and one 1024^2 fan-beam slice"}}
 
     def rre(xr, xt):
@@ -529,11 +530,13 @@ def variants_workload(args):
         return (torch.linalg.vector_norm((xr - xt).reshape(n, -1).double(), dim=1)
                 / torch.linalg.vector_norm(xt.reshape(n, -1).double(), dim=1)).cpu().numpy()
 
-    for name, kw, p in (("plain", dict(stop="dp", noise_norm=en), 0), ("restart20", dict(stop="dp", noise_norm=en), 20),
-                        ("ncp", dict(stop="ncp"), 0)):
-        ws = torch.empty(pk.workspace_bytes(A, B, S, "AB", K, stop=kw["stop"], restart=p), dtype=torch.uint8,
+    for name, mode, kw, p in (("plain", "AB", dict(stop="dp", noise_norm=en), 0),
+                              ("ba", "BA", dict(stop="dp", noise_norm=en), 0),
+                              ("restart20", "AB", dict(stop="dp", noise_norm=en), 20),
+                              ("ncp", "AB", dict(stop="ncp"), 0)):
+        ws = torch.empty(pk.workspace_bytes(A, B, S, mode, K, stop=kw["stop"], restart=p), dtype=torch.uint8,
                          device="cuda")
-        run = lambda: pk.solve(A, B, b, mode="AB", k=K, reg="gcv", tau=1.01, use_graph=True, poll_every=args.poll,
+        run = lambda: pk.solve(A, B, b, mode=mode, k=K, reg="gcv", tau=1.01, use_graph=True, poll_every=args.poll,
                                workspace=ws, history=False, restart=p, **kw)
         run()
         torch.cuda.synchronize()
