@@ -443,6 +443,23 @@ def test_ncp_stop_parity(pk, mode):
     assert it == o.iters and ed <= 1e-6 and ex <= 1e-8
 
 
+@pytest.mark.parametrize("mode", ["AB", "BA"])
+@pytest.mark.parametrize("p", [2, 3])
+def test_restarted_ncp_stop_parity(pk, mode, p):
+    """Restarted cycles with the NCP stop: each cycle tests its own residuals,
+    and the run ends in the cycle where the periodogram first looks white
+    (AB: iteration 9 with p = 2, 16 with p = 3; BA: 6 and 5), FP64."""
+    A, B, og, xt, bd, bu, ens = problem(pk, 32, 45, 47, 0.02, 0, 15, dt="f64")
+    K = 40
+    x, info = pk.solve(A, B, bd, mode=mode, k=K, reg="gcv", stop="ncp", restart=p)
+    o = osv.hybrid_gmres_restarted(og.A, og.B, bu[0], p=p, mode=mode, K=K, rule="gcv", stop="ncp", det=47)
+    it = int(info["iters"][0])
+    ex = rel(x.cpu().numpy(), o.x)
+    print(f"restarted NCP {mode} p={p}: iters {it} / oracle {o.iters}, x {ex:.2e}")
+    assert o.status == osv.STATUS_STOP_NCP and int(info["status"][0]) == pk.ST_STOP_NCP
+    assert it == o.iters and o.iters > p and ex <= 1e-8
+
+
 def test_ncp_stop_batch_f32(pk):
     """FP32 path, three slices: each stops where its own per-slice run stops,
     with distances within the FP32 gate of the oracle's."""
