@@ -460,6 +460,36 @@ def test_restarted_ncp_stop_parity(pk, mode, p):
     assert it == o.iters and o.iters > p and ex <= 1e-8
 
 
+def bf16_round(a):
+    """Round to the nearest BF16 (ties to even) through FP32, returned as FP64."""
+    u = np.ascontiguousarray(np.asarray(a, dtype=np.float32)).view(np.uint32).astype(np.uint64)
+    u = ((u + 0x7FFF + ((u >> 16) & 1)) & 0xFFFF0000).astype(np.uint32)
+    return u.view(np.float32).astype(np.float64)
+
+
+@pytest.mark.parametrize("ortho", ["dcgs2", "cgs2"])
+def test_bf16_sinogram_solves(pk, ortho):
+    """2D solves with the sinogram stored in BF16.  BA mode keeps every
+    z_k = A w_k in BF16, so the oracle rounds its A output the same way and
+    runs the schedule the GPU ran (rounding makes the operator nonlinear);
+    AB mode stores only b (and A x_0 = 0) in BF16 and its basis in FP32, so
+    it is the FP32 iteration on the rounded data.  Gates: 1e-4 against the
+    oracle that models the storage, 2^-7 against the unrounded FP64 BA run."""
+    A, B, og, xt, bd, bu, ens = problem(pk, 32, 45, 47, 0.01, 0, 21, dt="f32", sino="bf16")
+    K = 8
+    xb, ib = pk.solve(A, B, bd, mode="BA", k=K, reg="gcv", ortho=ortho)
+    o16 = osv.hybrid_gmres(lambda v: bf16_round(og.A(v)), og.B, bu[0], mode="BA", K=K, rule="gcv", ortho=ortho)
+    o64 = osv.hybrid_gmres(og.A, og.B, bu[0], mode="BA", K=K, rule="gcv", ortho=ortho)
+    e16, e64 = rel(xb.double().cpu().numpy(), o16.x), rel(xb.double().cpu().numpy(), o64.x)
+    xa, ia = pk.solve(A, B, bd, mode="AB", k=K, reg="gcv", ortho=ortho)
+    oa = osv.hybrid_gmres(og.A, og.B, bu[0], mode="AB", K=K, rule="gcv", ortho=ortho)
+    ea = rel(xa.double().cpu().numpy(), oa.x)
+    print(f"BF16 sinogram ({ortho}): BA x vs oracle with BF16 stores {e16:.2e}, vs FP64 {e64:.2e}; "
+          f"AB x vs FP64 on the rounded b {ea:.2e}")
+    assert int(ib["iters"][0]) == K and int(ia["iters"][0]) == K
+    assert e16 <= 1e-4 and e64 <= 2.0 ** -7 and ea <= 1e-4
+
+
 def test_ncp_stop_batch_f32(pk):
     """FP32 path, three slices: each stops where its own per-slice run stops,
     with distances within the FP32 gate of the oracle's."""
