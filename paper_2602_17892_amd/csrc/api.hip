@@ -113,14 +113,12 @@ static void fill_tab2d(const abba_op *op, AngleTab<T> *t) {
             e.inv_c = (T)(1.0 / cs);
             e.slope = (T)(sn / cs);
             e.off = (T)(cy * (sn / cs) + cx);
-            e.off2 = (T)(cy * (sn / cs) + cx + 2.0);
             e.w = (T)(1.0 / std::fabs(cs));
             e.absc = (T)std::fabs(cs);
         } else {
             e.inv_c = (T)(1.0 / sn);
             e.slope = (T)(cs / sn);
             e.off = (T)(cx * (cs / sn) + cy);
-            e.off2 = (T)(cx * (cs / sn) + cy + 2.0);
             e.w = (T)(1.0 / std::fabs(sn));
             e.absc = (T)std::fabs(sn);
         }

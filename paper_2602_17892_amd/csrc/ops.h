@@ -21,7 +21,6 @@ struct AngleTab {
     T cb, sb;  // cos/ds, sin/ds: detector coordinate of a pixel in bins (B)
     T cs, sn;  // cos, sin (exact transpose)
     T absc;    // |dominant direction cosine|
-    T off2;    // off + 2: u_r shifted into the coordinates of a row with two zeros in front
     int rowmarch;
     int pad;
 };
@@ -29,6 +28,9 @@ struct AngleTab {
 // Angles per workgroup of the LDS-band Joseph projector; its angle groups
 // hold angles of one march direction only.
 constexpr int JOSEPH_GA = 6;
+// Zeros on each side of a row of the padded image copies read by the 2D
+// Joseph projector: at least twice the rows of its bands (8).
+constexpr int JPAD = 16;
 
 // Per-view constants of the 3D cone beam, FP64 (ray set-up is FP64; the
 // voxel-driven B rounds them to its accumulation type).

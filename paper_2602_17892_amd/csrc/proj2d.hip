@@ -9,12 +9,14 @@
 // along detector bins (A), over two 32-pixel rows of a tile (B) or four
 // 16-pixel rows (A^T), so consecutive lanes touch neighbouring memory.
 //
-// A first copies the image into scratch with two zeros on each side of every
-// row, row-major and transposed (rays that march over image columns walk rows
-// of the transposed copy).  An interpolation position is then clamped into
-// [-2, len], and its two taps are always one 8-byte (FP64: 16-byte) load from
-// the padded row whose values are exactly those of the zero-extended row: no
-// per-tap masks and no branches in the inner loop, one load per step.  B
+// A first copies the image into scratch with PAD = 16 zeros on each side of
+// every row, row-major and transposed (rays that march over image columns
+// walk rows of the transposed copy).  Rows are taken in bands of 8; one clamp
+// of a ray's position per band keeps all its taps in the band inside the
+// padded rows, whose values are exactly those of the zero-extended rows: no
+// per-tap masks, clamps or branches in the inner loop.  The batched kernel
+// stages each band in LDS as aligned pairs (x[c], x[c+1] - x[c]), so a step
+// is one 8-byte (FP64: 16-byte) LDS read.  B
 // stages, per angle, the window of sinogram bins a pixel tile projects onto
 // in LDS (zeros outside the detector), with every tap inside the window by
 // construction, so it needs neither scratch nor a clamp.
@@ -31,7 +33,7 @@
 
 namespace abba {
 
-constexpr int PAD = 2;    // zeros on each side of a padded row
+constexpr int PAD = JPAD;   // zeros on each side of a padded row
 constexpr int RPAD = 16;  // padded copies have a multiple of RPAD rows (extra rows are zero)
 
 __host__ __device__ constexpr int round_rows(int r) { return (r + RPAD - 1) / RPAD * RPAD; }
@@ -73,8 +75,9 @@ template <>
 __device__ __forceinline__ double fract_of<double>(double t) { return __builtin_amdgcn_fract(t); }
 
 // ------------------------------------------------------ padded copies -----
-// Image -> xp [ny][nx + 4] (row-major) and xq [nx][ny + 4] (transposed), each
-// row with PAD zeros on both sides.  32 x 32 tiles through LDS.
+// Image -> xp [ny][nx + 2 PAD] (row-major) and xq [nx][ny + 2 PAD]
+// (transposed), each row with PAD zeros on both sides.  32 x 32 tiles through
+// LDS.
 template <typename T>
 __global__ __launch_bounds__(256) void pad_image_k(VecRef xr, T *__restrict__ xp, T *__restrict__ xq, int nx,
                                                    int ny, int s0, const int *kdev, const int *active) {
@@ -103,10 +106,12 @@ __global__ __launch_bounds__(256) void pad_image_k(VecRef xr, T *__restrict__ xp
         }
         tile[r][tx] = v;
     }
-    // the pads of rows i0..i0+31 of xp: columns 0, 1, nx+2, nx+3
-    if (blockIdx.x == 0 && threadIdx.x < 128) {
-        const int i = i0 + (threadIdx.x >> 2), c = threadIdx.x & 3;
-        if (i < ny) op[(int64_t)i * lp + (c < 2 ? c : nx + c)] = (T)0;
+    // the pads of rows i0..i0+31 of xp: columns [0, PAD) and [nx + PAD, nx + 2 PAD)
+    if (blockIdx.x == 0) {
+        for (int e = threadIdx.x; e < 32 * 2 * PAD; e += 256) {
+            const int i = i0 + e / (2 * PAD), c = e % (2 * PAD);
+            if (i < ny) op[(int64_t)i * lp + (c < PAD ? c : nx + c)] = (T)0;
+        }
     }
     __syncthreads();
 #pragma unroll
@@ -115,26 +120,30 @@ __global__ __launch_bounds__(256) void pad_image_k(VecRef xr, T *__restrict__ xp
         if (i < ny && j < nx) oq[(int64_t)j * lq + i + PAD] = tile[tx][r];
     }
     // the pads of rows j0..j0+31 of xq
-    if (blockIdx.y == 0 && threadIdx.x < 128) {
-        const int j = j0 + (threadIdx.x >> 2), c = threadIdx.x & 3;
-        if (j < nx) oq[(int64_t)j * lq + (c < 2 ? c : ny + c)] = (T)0;
+    if (blockIdx.y == 0) {
+        for (int e = threadIdx.x; e < 32 * 2 * PAD; e += 256) {
+            const int j = j0 + e / (2 * PAD), c = e % (2 * PAD);
+            if (j < nx) oq[(int64_t)j * lq + (c < PAD ? c : ny + c)] = (T)0;
+        }
     }
 }
 
 // ---------------------------------------------------------- Joseph A -------
 // Ray (a, d) of a march direction with R rows of C pixels (padded rows of
-// L = C + 4 entries): u(r) = u0 - r*slope is the interpolation coordinate in
-// row r, shifted by the two leading pad zeros.  y = w * sum_r lerp(row r at
-// u(r)).  The rows are taken in bands of JH; a band contributes the sum over
+// L = C + 2 PAD entries): u(r) = u0 - r*slope is the interpolation coordinate
+// in row r (image column units); |slope| <= 1 (the march runs along the
+// dominant direction cosine).  y = w * sum_r lerp(row r at
+// u(r)).  The rows are taken in bands of H; a band contributes the sum over
 // its rows, accumulated at even and odd rows separately.  Both kernels below
 // compute exactly this with the same operations in the same order, so their
 // results are bitwise identical; they differ only in where the taps come
 // from (global memory or a band staged in LDS).
 template <typename T>
 struct JBand {
-    static constexpr int H = sizeof(T) == 8 ? 8 : 16;
+    static constexpr int H = 8;
 };
 static_assert(RPAD % 16 == 0 && RPAD % 8 == 0, "bands must tile the padded rows");
+static_assert(PAD >= 2 * JBand<float>::H && PAD >= 2 * JBand<double>::H, "a band's taps must stay in its pads");
 
 // Rows whose crossing lies in (-1, C), widened by one row on each side.  Both
 // ends are clamped to [-2, R+1] before the conversion to int: for a ray that
@@ -164,23 +173,78 @@ __device__ __forceinline__ void wave_union(int &r0, int &r1) {
     }
 }
 
-// Contribution of the band whose first row is `rows` (stride L) for a ray
-// with coordinate ub = u(b0) in the band's first row.  Clamping to [0, C+2]
-// keeps the tap pair inside the padded row and reads zeros wherever a tap
-// is outside the image; after the clamp u >= 0, so (int) is floor.
-template <typename T, int H>
-__device__ __forceinline__ T band_sum(const T *rows, int L, T ub, T slope, int C) {
-    T a0 = 0, a1 = 0;
+// floor(x) as an int; FP32 has a single instruction for it.
+template <typename T>
+__device__ __forceinline__ int floor_int(T x);
+template <>
+__device__ __forceinline__ int floor_int<float>(float x) {
+    int r;
+    asm("v_cvt_flr_i32_f32 %0, %1" : "=v"(r) : "v"(x));
+    return r;
+}
+template <>
+__device__ __forceinline__ int floor_int<double>(double x) { return (int)floor(x); }
+
+// The taps of entry c of padded row q of a band as (x[c], x[c+1] - x[c]):
+// read from the padded image (RowTaps) or from pairs staged in LDS with the
+// difference already formed by the same subtraction (PairTaps).
+template <typename T>
+struct pair_of;
+template <>
+struct pair_of<float> {
+    typedef float2 type;
+};
+template <>
+struct pair_of<double> {
+    typedef double2 type;
+};
+
+template <typename T>
+struct RowTaps {
+    const T *rows;
+    int L;
+    __device__ __forceinline__ void get(int q, int c, T &x0, T &dx) const {
+        const T *e = at_byte(rows + q * L, (uint32_t)c * (uint32_t)sizeof(T));
+        x0 = e[0];
+        dx = e[1] - e[0];
+    }
+};
+
+template <typename T>
+struct PairTaps {
+    const typename pair_of<T>::type *rows;
+    int L;
+    __device__ __forceinline__ void get(int q, int c, T &x0, T &dx) const {
+        const typename pair_of<T>::type e =
+            *at_byte(rows + q * L, (uint32_t)c * (uint32_t)sizeof(typename pair_of<T>::type));
+        x0 = e.x;
+        dx = e.y;
+    }
+};
+
+// Contribution of a band (padded rows of L = C + 2 PAD entries) for a ray
+// with image coordinate ub = u(b0) in the band's first row; image column c
+// is entry c + PAD of a padded row.  ub is clamped
+// once to [H-1-PAD, C+PAD-H-1]: with |slope| <= 1 every u(b0+q), q < H, then
+// lies in [-PAD, C+PAD-2], so both taps are inside the padded row.  The clamp
+// moves ub only when the ray passes the band entirely outside the image
+// (ub < H-1-PAD puts every u below 2H-2-PAD <= -2, ub > C+PAD-H-1 every u
+// above C+PAD-2H >= C), and then the clamped taps are pad zeros too: the sum
+// is exactly that of the zero-extended rows.
+template <typename T, int H, typename Taps>
+__device__ __forceinline__ T band_sum(const Taps &tp, T ub, T slope) {
+    ub = clampf(ub, (T)(H - 1 - PAD), (T)(tp.L - PAD - H - 1));
+    T a[2];
 #pragma unroll
     for (int q = 0; q < H; ++q) {
         const T u = fma(-(T)q, slope, ub);
         const T f = fract_of(u);
-        const T *e = at_byte(rows + q * L, (uint32_t)(int)clampf(u, (T)0, (T)(C + 2)) * (uint32_t)sizeof(T));
-        const T v = fma(f, e[1] - e[0], e[0]);
-        if (q & 1) a1 += v;
-        else a0 += v;
+        T x0, dx;
+        tp.get(q, floor_int(u) + PAD, x0, dx);
+        const T v = fma(f, dx, x0);
+        a[q & 1] = q < 2 ? v : a[q & 1] + v;   // even and odd rows
     }
-    return a0 + a1;
+    return a[0] + a[1];
 }
 
 // Gather version: one thread per ray, a wave = 64 consecutive bins of one
@@ -219,9 +283,9 @@ __global__ __launch_bounds__(256) void joseph2d_fwd_k(const TI *__restrict__ xp,
     }
     const int L = C + 2 * PAD;
     const T sd = ((T)d - cd) * ds;
-    const T u0 = fma(sd, t.inv_c, t.off2);
+    const T u0 = fma(sd, t.inv_c, t.off);
     int r0, r1;
-    ray_rows(fma(sd, t.inv_c, t.off), t.slope, R, C, r0, r1);
+    ray_rows(u0, t.slope, R, C, r0, r1);
     if (d >= nd) {
         r0 = R;
         r1 = -1;
@@ -230,7 +294,7 @@ __global__ __launch_bounds__(256) void joseph2d_fwd_k(const TI *__restrict__ xp,
     const int rlo = __builtin_amdgcn_readfirstlane(r0), rhi = __builtin_amdgcn_readfirstlane(r1);
     T acc = 0;
     for (int b0 = rlo / H * H; b0 <= rhi; b0 += H)
-        acc += band_sum<T, H>(P + (int64_t)b0 * L, L, fma(-(T)b0, t.slope, u0), t.slope, C);
+        acc += band_sum<T, H>(RowTaps<T>{P + (int64_t)b0 * L, L}, fma(-(T)b0, t.slope, u0), t.slope);
     if (d < nd) store_as<TO>(vec_ptr<TO>(yr, s, k), (int64_t)a * nd + d, acc * t.w);
 }
 
@@ -253,8 +317,9 @@ __global__ __launch_bounds__(256) void joseph2d_lds_k(const TI *__restrict__ xp,
     static_assert(sizeof(TI) == sizeof(T), "images are stored in the accumulation type");
     constexpr int H = JBand<T>::H;
     constexpr int GA = JOSEPH_GA;
+    typedef typename pair_of<T>::type T2;
     extern __shared__ __align__(16) unsigned char smem[];
-    T *band = reinterpret_cast<T *>(smem);   // [H][L]
+    T2 *band = reinterpret_cast<T2 *>(smem);   // [H][L] pairs (x[c], x[c+1] - x[c])
     // work order: (slice, angle group, bin chunk of 256*JB)
     const uint32_t w = xcd_remap(blockIdx.x, gridDim.x, nxcc);
     const int bc = (int)(w % (uint32_t)nbc);
@@ -288,10 +353,10 @@ __global__ __launch_bounds__(256) void joseph2d_lds_k(const TI *__restrict__ xp,
         for (int j = 0; j < JB; ++j) {
             const int d = bc * (256 * JB) + j * 256 + (int)threadIdx.x;
             const T sd = ((T)d - cd) * ds;
-            u0[ai][j] = fma(sd, t.inv_c, t.off2);
+            u0[ai][j] = fma(sd, t.inv_c, t.off);
             acc[ai][j] = 0;
             int r0, r1;
-            ray_rows(fma(sd, t.inv_c, t.off), t.slope, R, C, r0, r1);
+            ray_rows(u0[ai][j], t.slope, R, C, r0, r1);
             if (ai >= g_count || d >= nd) {
                 r0 = R;
                 r1 = -1;
@@ -304,13 +369,24 @@ __global__ __launch_bounds__(256) void joseph2d_lds_k(const TI *__restrict__ xp,
     const bool vec4 = (L % 4) == 0;
     for (int b0 = 0; b0 < Rr; b0 += H) {
         __syncthreads();   // the previous band is no longer read
+        // the pair of the band's last entry (never read) takes x[c+1] = 0
         const T *src = P + (int64_t)b0 * L;
+        const int n = H * L;
         if (vec4 && sizeof(T) == 4) {
+            const float *s1 = reinterpret_cast<const float *>(src);
             const float4 *s4 = reinterpret_cast<const float4 *>(src);
             float4 *d4 = reinterpret_cast<float4 *>(band);
-            for (int c = threadIdx.x; c < H * L / 4; c += 256) d4[c] = s4[c];
+            for (int c = threadIdx.x; c < n / 4; c += 256) {
+                const float4 v = s4[c];
+                const float x4 = 4 * c + 4 < n ? s1[4 * c + 4] : 0.0f;
+                d4[2 * c] = make_float4(v.x, v.y - v.x, v.y, v.z - v.y);
+                d4[2 * c + 1] = make_float4(v.z, v.w - v.z, v.w, x4 - v.w);
+            }
         } else {
-            for (int c = threadIdx.x; c < H * L; c += 256) band[c] = src[c];
+            for (int c = threadIdx.x; c < n; c += 256) {
+                const T x0 = src[c], x1 = c + 1 < n ? src[c + 1] : (T)0;
+                band[c] = T2{x0, x1 - x0};
+            }
         }
         __syncthreads();
 #pragma unroll
@@ -319,7 +395,7 @@ __global__ __launch_bounds__(256) void joseph2d_lds_k(const TI *__restrict__ xp,
             for (int j = 0; j < JB; ++j) {
                 const int lo = (int)(rng[ai][j] & 0xffffu), hi1 = (int)(rng[ai][j] >> 16);
                 if (lo > b0 + H - 1 || hi1 <= b0) continue;   // the same in all lanes of the wave
-                acc[ai][j] += band_sum<T, H>(band, L, fma(-(T)b0, slope[ai], u0[ai][j]), slope[ai], C);
+                acc[ai][j] += band_sum<T, H>(PairTaps<T>{band, L}, fma(-(T)b0, slope[ai], u0[ai][j]), slope[ai]);
             }
         }
     }
@@ -507,7 +583,7 @@ static bool offsets_fit(const abba_op *op) {
 
 template <typename T>
 static bool lds_fits(const abba_op *op) {
-    const size_t band_bytes = (size_t)JBand<T>::H * (std::max(op->g.nx, op->g.ny) + 2 * PAD) * sizeof(T);
+    const size_t band_bytes = (size_t)JBand<T>::H * (std::max(op->g.nx, op->g.ny) + 2 * PAD) * 2 * sizeof(T);
     return band_bytes <= 65536 && op->agrp && std::max(op->g.nx, op->g.ny) < 65535;
 }
 
@@ -520,7 +596,7 @@ template <typename TI, typename TO, int JB>
 static int lds_launch(const abba_op *op, const TI *xp, const TI *xq, VecRef y, int batch, const Launch &L) {
     typedef typename acc_of<TI>::type T;
     const int nx = op->g.nx, ny = op->g.ny, nd = op->g.det_u;
-    const size_t band_bytes = (size_t)JBand<T>::H * (std::max(nx, ny) + 2 * PAD) * sizeof(T);
+    const size_t band_bytes = (size_t)JBand<T>::H * (std::max(nx, ny) + 2 * PAD) * 2 * sizeof(T);
     const int nbc = (nd + 256 * JB - 1) / (256 * JB);
     const uint64_t per = lds_groups(op, JB);
     const int ch = (int)std::min<uint64_t>((uint64_t)batch, MAX_GROUPS / per);
