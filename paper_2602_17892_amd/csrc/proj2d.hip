@@ -234,14 +234,17 @@ struct PairTaps {
 template <typename T, int H, typename Taps>
 __device__ __forceinline__ T band_sum(const Taps &tp, T ub, T slope) {
     ub = clampf(ub, (T)(H - 1 - PAD), (T)(tp.L - PAD - H - 1));
-    T a[2];
+    T f[H], x0[H], dx[H], a[2];
+#pragma unroll
+    for (int q = 0; q < H; ++q) {   // all taps of the band first
+        const T u = fma(-(T)q, slope, ub);
+        f[q] = fract_of(u);
+        tp.get(q, floor_int(u) + PAD, x0[q], dx[q]);
+    }
+    __builtin_amdgcn_sched_barrier(0);   // keep the H loads in flight together
 #pragma unroll
     for (int q = 0; q < H; ++q) {
-        const T u = fma(-(T)q, slope, ub);
-        const T f = fract_of(u);
-        T x0, dx;
-        tp.get(q, floor_int(u) + PAD, x0, dx);
-        const T v = fma(f, dx, x0);
+        const T v = fma(f[q], dx[q], x0[q]);
         a[q & 1] = q < 2 ? v : a[q & 1] + v;   // even and odd rows
     }
     return a[0] + a[1];
