@@ -27,7 +27,7 @@ struct AngleTab {
 
 // Angles per workgroup of the LDS-band Joseph projector; its angle groups
 // hold angles of one march direction only.
-constexpr int JOSEPH_GA = 6;
+constexpr int JOSEPH_GA = 8;
 // Zeros on each side of a row of the padded image copies read by the 2D
 // Joseph projector: at least twice the rows of its bands (8).
 constexpr int JPAD = 16;

@@ -365,7 +365,7 @@ __global__ __launch_bounds__(256) void joseph2d_lds_k(const TI *__restrict__ xp,
                 r1 = -1;
             }
             wave_union(r0, r1);
-            rng[ai][j] = (uint32_t)r0 | ((uint32_t)(r1 + 1) << 16);
+            rng[ai][j] = __builtin_amdgcn_readfirstlane((uint32_t)r0 | ((uint32_t)(r1 + 1) << 16));
         }
     }
     const int Rr = round_rows(R);
