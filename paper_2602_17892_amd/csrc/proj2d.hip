@@ -434,8 +434,9 @@ __global__ __launch_bounds__(256) void pixbp2d_k(VecRef yr, VecRef xr,
                                                  uint32_t nxcc, int s0, const int *kdev, const int *active) {
     typedef typename acc_of<TI>::type T;
     extern __shared__ __align__(16) unsigned char smem[];
-    T *win = reinterpret_cast<T *>(smem);                           // [G][W][2]
-    T *wbase = reinterpret_cast<T *>(smem + (size_t)G * W * 2 * sizeof(T));      // [G]: cd - w0 (exact)
+    T *win = reinterpret_cast<T *>(smem);                                     // [G][W][2]
+    T *par = reinterpret_cast<T *>(smem + (size_t)G * W * 2 * sizeof(T));       // [G][3]: cb, sb, cd - w0
+    int *w0s = reinterpret_cast<int *>(smem + (size_t)G * (W * 2 + 3) * sizeof(T));   // [G]: w0
     // work order: (slice, tile row, tile column)
     const uint32_t w = xcd_remap(blockIdx.x, gridDim.x, nxcc);
     const uint32_t wt = w / (uint32_t)ntx;
@@ -457,31 +458,39 @@ __global__ __launch_bounds__(256) void pixbp2d_k(VecRef yr, VecRef xr,
     const T X0 = (T)(tx * BT) - cx, X1 = X0 + (T)(BT - 1);
     const T Y0 = (T)(ty * BT) - cy, Y1 = Y0 + (T)(BT - 1);
     T acc[4] = {0, 0, 0, 0};
+    const float winv = 1.0f / (float)W;
     for (int a0 = 0; a0 < na; a0 += G) {
         const int g = min(G, na - a0);
         __syncthreads();   // the previous chunk is no longer read
-        for (int al = threadIdx.x >> 6; al < g; al += 4) {
-            const int a = a0 + al;
-            const T cb = tab[a].cb, sb = tab[a].sb;
+        // window start of each angle of the chunk, one thread per angle
+        for (int al = threadIdx.x; al < g; al += 256) {
+            const T cb = tab[a0 + al].cb, sb = tab[a0 + al].sb;
             const T tmin = cd + fmin(X0 * cb, X1 * cb) + fmin(Y0 * sb, Y1 * sb);
             const int w0 = (int)floor(tmin) - 1;
-            if ((threadIdx.x & 63) == 0) wbase[al] = cd - (T)w0;
-            const TIN *row = y + (int64_t)a * nd;
-            T *dst = win + (size_t)al * W * 2;
-            for (int c = threadIdx.x & 63; c < W; c += 64) {
-                const int p = w0 + c;
-                const T v = (p >= 0 && p < nd) ? (T)load_as<TIN>(row, p) : (T)0;
-                const T vn = (p + 1 >= 0 && p + 1 < nd) ? (T)load_as<TIN>(row, p + 1) : (T)0;
-                dst[2 * c] = v;
-                dst[2 * c + 1] = vn - v;
-            }
+            par[3 * al] = cb;
+            par[3 * al + 1] = sb;
+            par[3 * al + 2] = cd - (T)w0;
+            w0s[al] = w0;
+        }
+        __syncthreads();
+        // the windows: entry e = al*W + c of the chunk, all threads over all
+        // angles.  al = floor((e + 1/2) / W) in FP32 is exact: (e + 1/2)/W is
+        // at least 1/(2W) from an integer and e < G*W <= 8192 (64 KB of LDS)
+        // keeps the rounding error far below that.
+        for (int e = threadIdx.x; e < g * W; e += 256) {
+            const int al = (int)(((float)e + 0.5f) * winv);
+            const int p = w0s[al] + (e - al * W);
+            const TIN *row = y + (int64_t)(a0 + al) * nd;
+            const T v = ((unsigned)p < (unsigned)nd) ? (T)load_as<TIN>(row, p) : (T)0;
+            const T vn = ((unsigned)(p + 1) < (unsigned)nd) ? (T)load_as<TIN>(row, p + 1) : (T)0;
+            win[2 * e] = v;
+            win[2 * e + 1] = vn - v;
         }
         __syncthreads();
         for (int al = 0; al < g; ++al) {
-            const int a = a0 + al;
-            const T cb = tab[a].cb, sb = tab[a].sb;
+            const T cb = par[3 * al], sb = par[3 * al + 1];
             // t relative to the window start: t - w0 = fma(Y, sb, X cb + cd - w0)
-            const T base = fma(X, cb, wbase[al]);
+            const T base = fma(X, cb, par[3 * al + 2]);
             const T *wrow = win + (size_t)al * W * 2;
 #pragma unroll
             for (int m = 0; m < 4; ++m) {
@@ -520,7 +529,7 @@ static void pixbp_window(const abba_op *op, int *W, int *G) {
 
 // Most angles per chunk whose windows fit in 64 KB of LDS.
 static int pixbp_max_g(const abba_op *op, int W) {
-    const size_t per = (size_t)(W * 2 + 1) * (op->img_dtype == ABBA_F64 ? 8 : 4);
+    const size_t per = (size_t)(W * 2 + 3) * (op->img_dtype == ABBA_F64 ? 8 : 4) + 4;
     return (int)std::max<size_t>(1, 65536 / per);
 }
 
@@ -696,7 +705,7 @@ static int back_launch(const abba_op *op, VecRef y, VecRef x, int batch, const L
     pixbp_window(op, &W, &G);
     if (const TuneEntry *t = tune_for(op, batch))
         if (t->b_g > 0) G = std::min(t->b_g, pixbp_max_g(op, W));
-    const size_t shmem = (size_t)G * (W * 2 + 1) * sizeof(T);
+    const size_t shmem = (size_t)G * ((W * 2 + 3) * sizeof(T) + 4);
     if ((size_t)W * 2 * sizeof(T) > 32768) return ABBA_ERR_UNSUPPORTED;
     const int btx = (nx + BT - 1) / BT, bty = (ny + BT - 1) / BT;
     const uint64_t tiles = (uint64_t)btx * bty;
