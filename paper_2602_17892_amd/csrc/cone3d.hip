@@ -336,23 +336,38 @@ __global__ __launch_bounds__(256) void cone_fwd_k(const TI *__restrict__ vx, con
     // in lockstep the copy is the same for the whole wave: a scalar base with
     // 32-bit element offsets (a padded copy of one slice has < 2^31 elements)
     const TI *Pb = same ? uniform_ptr(P) : P;
-    auto tap = [&](int jj) -> T {
+    // the four taps of plane jj and the two fractions
+    auto load = [&](int jj, T &fp, T &fq, T &a00, T &a01, T &a10, T &a11) {
         const T pp = fma((T)jj, DP, P0), qq = fma((T)jj, DQ, Q0);
-        const T fp = cfract(pp), fq = cfract(qq);
+        fp = cfract(pp);
+        fq = cfract(qq);
         const uint32_t ipp = (uint32_t)fmin(fmax(pp, (T)0), pmax), iqq = (uint32_t)fmin(fmax(qq, (T)0), qmax);
         const TI *e = Pb + (((uint32_t)jj * (uint32_t)Lp + ipp) * (uint32_t)Lq + iqq);
-        const T a00 = (T)e[0], a01 = (T)e[1], a10 = (T)e[Lq], a11 = (T)e[Lq + 1];
+        a00 = (T)e[0];
+        a01 = (T)e[1];
+        a10 = (T)e[Lq];
+        a11 = (T)e[Lq + 1];
+    };
+    auto combine = [](T fp, T fq, T a00, T a01, T a10, T a11) -> T {
         const T lo = fma(fq, a01 - a00, a00), hi = fma(fq, a11 - a10, a10);
         return fma(fp, hi - lo, lo);
     };
-    // steps alternate between two sums (even and odd steps from jlo); four
-    // steps per pass keep eight loads in flight per wave
+    auto tap = [&](int jj) -> T {
+        T fp, fq, a00, a01, a10, a11;
+        load(jj, fp, fq, a00, a01, a10, a11);
+        return combine(fp, fq, a00, a01, a10, a11);
+    };
+    // steps alternate between two sums (even and odd steps from jlo); the
+    // loads of four steps are issued before any is combined
     T acc0 = 0, acc1 = 0;
     int j = jlo;
     for (; j + 3 <= jhi; j += 4) {
-        T v[4];
+        T fp[4], fq[4], a00[4], a01[4], a10[4], a11[4], v[4];
 #pragma unroll
-        for (int h = 0; h < 4; ++h) v[h] = tap(j + h);
+        for (int h = 0; h < 4; ++h) load(j + h, fp[h], fq[h], a00[h], a01[h], a10[h], a11[h]);
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int h = 0; h < 4; ++h) v[h] = combine(fp[h], fq[h], a00[h], a01[h], a10[h], a11[h]);
         acc0 += v[0];
         acc1 += v[1];
         acc0 += v[2];
