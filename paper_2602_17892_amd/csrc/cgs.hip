@@ -19,6 +19,19 @@ __device__ __forceinline__ void unpack(const float4 &v, double *o) { o[0] = v.x;
 __device__ __forceinline__ void unpack(const double2 &v, double *o) { o[0] = v.x; o[1] = v.y; }
 __device__ __forceinline__ float4 pack_f(const double *o) { return make_float4((float)o[0], (float)o[1], (float)o[2], (float)o[3]); }
 
+// A basis column read once per sweep (the basis is far larger than the
+// caches): a load with the non-temporal hint.
+__device__ __forceinline__ float4 ld_stream(const float4 *p) {
+    typedef float f4 __attribute__((ext_vector_type(4)));
+    const f4 v = __builtin_nontemporal_load(reinterpret_cast<const f4 *>(p));
+    return make_float4(v.x, v.y, v.z, v.w);
+}
+__device__ __forceinline__ double2 ld_stream(const double2 *p) {
+    typedef double d2 __attribute__((ext_vector_type(2)));
+    const d2 v = __builtin_nontemporal_load(reinterpret_cast<const d2 *>(p));
+    return make_double2(v.x, v.y);
+}
+
 template <typename T> __device__ __forceinline__ typename vec16<T>::type pack(const double *o);
 template <> __device__ __forceinline__ float4 pack<float>(const double *o) { return pack_f(o); }
 template <> __device__ __forceinline__ double2 pack<double>(const double *o) { return make_double2(o[0], o[1]); }
@@ -357,7 +370,7 @@ __global__ __launch_bounds__(256) void ddots_k(const TW *__restrict__ W, int64_t
         for (int jj = 0; jj < DOT_JT; ++jj) {
             if (jj < jn) {
                 double wv[N];
-                unpack(reinterpret_cast<const V *>(Ws + (int64_t)(j0 + jj) * ldw)[e], wv);
+                unpack(ld_stream(reinterpret_cast<const V *>(Ws + (int64_t)(j0 + jj) * ldw) + e), wv);
 #pragma unroll
                 for (int q = 0; q < N; ++q) {
                     acc[jj] = fma(wv[q], vv[q], acc[jj]);
@@ -508,10 +521,10 @@ __global__ __launch_bounds__(256) void dupdate_k(TW *__restrict__ W, int64_t sli
         int i = 0;
         for (; i + 4 <= k; i += 4) {
             double w0[N], w1[N], w2[N], w3[N];
-            unpack(reinterpret_cast<const V *>(Ws + (int64_t)(i + 0) * ldw)[e], w0);
-            unpack(reinterpret_cast<const V *>(Ws + (int64_t)(i + 1) * ldw)[e], w1);
-            unpack(reinterpret_cast<const V *>(Ws + (int64_t)(i + 2) * ldw)[e], w2);
-            unpack(reinterpret_cast<const V *>(Ws + (int64_t)(i + 3) * ldw)[e], w3);
+            unpack(ld_stream(reinterpret_cast<const V *>(Ws + (int64_t)(i + 0) * ldw) + e), w0);
+            unpack(ld_stream(reinterpret_cast<const V *>(Ws + (int64_t)(i + 1) * ldw) + e), w1);
+            unpack(ld_stream(reinterpret_cast<const V *>(Ws + (int64_t)(i + 2) * ldw) + e), w2);
+            unpack(ld_stream(reinterpret_cast<const V *>(Ws + (int64_t)(i + 3) * ldw) + e), w3);
             const double a0 = as[i], a1 = as[i + 1], a2 = as[i + 2], a3 = as[i + 3];
             const double g0 = gs[i], g1 = gs[i + 1], g2 = gs[i + 2], g3 = gs[i + 3];
 #pragma unroll
@@ -528,7 +541,7 @@ __global__ __launch_bounds__(256) void dupdate_k(TW *__restrict__ W, int64_t sli
         }
         for (; i < k; ++i) {
             double w0[N];
-            unpack(reinterpret_cast<const V *>(Ws + (int64_t)i * ldw)[e], w0);
+            unpack(ld_stream(reinterpret_cast<const V *>(Ws + (int64_t)i * ldw) + e), w0);
             const double a0 = as[i], g0 = gs[i];
 #pragma unroll
             for (int q = 0; q < N; ++q) {
