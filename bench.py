@@ -78,6 +78,8 @@ def parse():
     p.add_argument("--train-runs", type=int, default=4096)
     p.add_argument("--eval-slices", type=int, default=1024)
     p.add_argument("--epochs", type=int, default=20)
+    p.add_argument("--no-learned", action="store_true",
+                   help="leave out the learned-rule comparison of the default run")
     p.add_argument("--quiet", action="store_true")
     return p.parse_args()
 
@@ -117,6 +119,34 @@ def synth_batch(pk, A, torch, cfg_id, first, count, n, lo, hi):
 
 def make_inputs(args, pk, A, torch):
     return synth_batch(pk, A, torch, 2, 0, args.slices, args.n, 1e-3, 5e-2)
+
+
+def rel_l2(a, b):
+    import numpy as np
+    a = np.asarray(a, dtype=np.float64).ravel()
+    b = np.asarray(b, dtype=np.float64).ravel()
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+def gcv_gap(lams, o):
+    """The largest relative excess of the GCV function (eq. (15)) at the
+    GPU's lambda_k over its value at the oracle's, both on the oracle's
+    projected problem of iteration k."""
+    from oracle import smallsolve as oss
+    gaps = [oss.gcv(float(l), *o.small[k]) / oss.gcv(float(o.lam[k]), *o.small[k]) - 1.0
+            for k, l in enumerate(lams)]
+    return float(max(gaps)) if gaps else 0.0
+
+
+def dcgs2_bytes(iters, length, elem=4):
+    """Algorithmic HBM bytes of the delayed-CGS2 sweeps of a solve: a slice
+    stopped at iteration k_s runs steps j = 0..k_s; step j reads the basis
+    vectors w_1..w_j, the vector v and M v once in the dot-product sweep
+    (j + 2 vectors) and again in the update sweep, which also writes v and M v
+    (j + 4 vectors): (2j + 6) vectors of `length` entries."""
+    import numpy as np
+    k = np.asarray(iters, dtype=np.int64)
+    return int(((k + 1) * (k + 6)).sum()) * length * elem
 
 
 def time_apply(fn, torch, reps=10):
@@ -222,8 +252,33 @@ def projectors_only(args):
                       "copy_bytes_each_way": x.numel() * 4, "source_digest": kernel_source_digest()}), flush=True)
 
 
+def cpu_model():
+    """The host CPU's model name (from /proc/cpuinfo) and the cores this
+    process may use."""
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except AttributeError:
+        usable = os.cpu_count() or 1
+    return model, usable
+
+
+def oracle_threads():
+    return int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+
+
 def cpu_baseline(args, b_slice, en_slice, k_cap):
-    """The FP64 oracle on one slice of the same workload (same rule and stop)."""
+    """The FP64 oracle on one slice of the same workload (same rule and stop).
+    Returns its time, its result (projected problems kept for the lambda
+    comparison) and the threads it used."""
     import numpy as np
 
     import oracle
@@ -235,10 +290,46 @@ def cpu_baseline(args, b_slice, en_slice, k_cap):
     bb = np.asarray(b_slice, dtype=np.float64).ravel()
     t0 = time.perf_counter()
     o = hybrid_gmres(og.A, og.B, bb, mode="AB", K=k_cap, rule="gcv", stop="dp", tau=1.01,
-                     noise_norm=float(en_slice))
+                     noise_norm=float(en_slice), keep_small=True)
     t = time.perf_counter() - t0
-    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-    return t, o.iters, threads
+    return t, o, oracle_threads()
+
+
+def cpu_thread_scaling(args):
+    """The oracle on all host threads and on one: one A and one B apply at the
+    benchmark's slice shape, and the 64^2 configuration's whole solve (90
+    angles x 91 bins, 1 % noise, hybrid AB-GMRES with GCV, 30 iterations)."""
+    import numpy as np
+    from threadpoolctl import threadpool_limits
+
+    import oracle
+    import synth
+    from oracle.geometry import Par2D
+    from oracle.operators import Par2DOps
+    from oracle.solver import hybrid_gmres
+    oracle.build_oracle(force=False)
+    og = Par2DOps(Par2D(args.n, args.n, args.angles, args.det))
+    rng = np.random.default_rng(0)
+    x = rng.uniform(size=og.n)
+    y = rng.standard_normal(og.m)
+    o64 = Par2DOps(Par2D(64, 64, 90, 91))
+    xt, _ = synth.phantom2d(0, 0, 64)
+    b64, _ = synth.add_relative_noise(o64.A(xt).reshape(-1), synth.noise_direction(0, 0, o64.m), 0.01)
+
+    def run():
+        t0 = time.perf_counter()
+        og.A(x)
+        og.B(y)
+        t_ab = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        hybrid_gmres(o64.A, o64.B, b64, mode="AB", K=30, rule="gcv")
+        return t_ab, time.perf_counter() - t0
+
+    all_ab, all_c1 = run()
+    with threadpool_limits(limits=1):
+        one_ab, one_c1 = run()
+    return {"threads": oracle_threads(), "AB_apply_pair_s": round(all_ab, 3), "AB_apply_pair_s_1thread":
+            round(one_ab, 3), "c1_solve_s": round(all_c1, 3), "c1_solve_s_1thread": round(one_c1, 3)}
 
 
 def cone_ray_steps(n, views, nu, nv, pitch, sid, sdd):
@@ -400,6 +491,10 @@ def cone_workload(args):
 
 
 def learned_workload(args):
+    print(json.dumps(learned_run(args)), flush=True)
+
+
+def learned_run(args):
     """Training: runs of hybrid AB-GMRES (K = 100, GCV) on 256^2 random-ellipse
     slices, 360 angles x 363 bins, noise log-uniform in [0.1%, 5%], with the
     features and the RRE label grids of every iteration; Adam on the network.
@@ -448,10 +543,11 @@ def learned_workload(args):
     ge = pk.Geometry(512, 512, 720, 725)
     A, B = pk.Operator("joseph", ge, "f32", "f32"), pk.Operator("pixel", ge, "f32", "f32")
     ws = torch.empty(pk.workspace_bytes(A, B, SB, "AB", K, stop="dp"), dtype=torch.uint8, device="cuda")
-    res = {"gcv": dict(t=0.0, iters=[], rre=[]), "learned": dict(t=0.0, iters=[], rre=[])}
+    res = {"gcv": dict(t=0.0, iters=[], rre=[]), "learned": dict(t=0.0, iters=[], rre=[]), "eta": []}
     for first in range(0, args.eval_slices, SB):
         cnt = min(SB, args.eval_slices - first)
-        x, b, en, _ = synth_batch(pk, A, torch, 6, first, cnt, 512, 1e-3, 5e-2)
+        x, b, en, eta = synth_batch(pk, A, torch, 6, first, cnt, 512, 1e-3, 5e-2)
+        res["eta"].append(eta)
         for name in ("gcv", "learned"):
             kw = dict(reg="gcv", stop="dp") if name == "gcv" else dict(reg="learned", stop="learned", mlp=theta,
                                                                       judge_delta=0.05)
@@ -466,12 +562,15 @@ def learned_workload(args):
             res[name]["rre"].append((torch.linalg.vector_norm((xr - x).reshape(cnt, -1).double(), dim=1)
                                      / torch.linalg.vector_norm(x.reshape(cnt, -1).double(), dim=1)).cpu().numpy())
         del x, b, en
-    for r in res.values():
-        r["iters"] = np.concatenate(r["iters"])
-        r["rre"] = np.concatenate(r["rre"])
+    res["eta"] = np.concatenate(res["eta"])
+    for name in ("gcv", "learned"):
+        res[name]["iters"] = np.concatenate(res[name]["iters"])
+        res[name]["rre"] = np.concatenate(res[name]["rre"])
     E = args.eval_slices
     ratio = res["learned"]["rre"] / res["gcv"]["rre"]
-    for name, r in res.items():
+    miss = ratio > 1.02
+    for name in ("gcv", "learned"):
+        r = res[name]
         log(args, f"{name}: {E / r['t']:.2f} slices/s, iters mean {r['iters'].mean():.1f}, "
                   f"median RRE {np.median(r['rre']):.4f}")
     log(args, f"learned RRE <= 1.02 x GCV+DP RRE on {np.mean(ratio <= 1.02) * 100:.1f}% of slices")
@@ -496,12 +595,17 @@ def learned_workload(args):
                     "iters_mean": float(res["learned"]["iters"].mean()),
                     "rre_median": float(np.median(res["learned"]["rre"])),
                     "frac_rre_within_2pct_of_gcv": float(np.mean(ratio <= 1.02)),
-                    "rre_ratio_median": float(np.median(ratio))},
+                    "rre_ratio_median": float(np.median(ratio)),
+                    "rre_ratio_p95": float(np.percentile(ratio, 95)),
+                    "rre_ratio_max": float(ratio.max()),
+                    "misses": int(miss.sum()),
+                    "miss_eta": [float(e) for e in np.sort(res["eta"][miss])[:64]]},
+        "speedup_learned_vs_gcv_dp": round(res["gcv"]["t"] / res["learned"]["t"], 3),
         "training": {"runs": args.train_runs, "samples": int(X.shape[0]), "epochs": args.epochs,
                      "loss_start": float(l0), "loss_end": hist[-1], "data_s": round(t_gen, 2),
                      "train_s": round(t_train, 2), "k_star_mean": float(kst.mean())},
     }
-    print(json.dumps(out), flush=True)
+    return out
 
 
 def variants_workload(args):
@@ -661,8 +765,30 @@ def main():
         same = same and bool(torch.equal(x1[0], xb[s]))
         plain_iters.append(int(i1["iters"][0]))
     t_plain = (time.perf_counter() - t0) / P
-    # the batched run's work on the same subset: scale by the subset's share of iterations
-    log(args, f"plain: {t_plain:.3f}s/slice on {P} slices, bitwise equal to batched: {same}")
+    # the subset's mean iteration count differs from the batch's: compare per
+    # iteration as well as per slice
+    it_plain = float(np.mean(plain_iters))
+    t_plain_iter = t_plain / it_plain
+    t_batched_iter = t_batched / (S * float(iters.mean()))
+    log(args, f"plain: {t_plain:.3f}s/slice on {P} slices ({it_plain:.1f} iterations on average), bitwise equal "
+              f"to batched: {same}")
+
+    # ---- the same batched solve once more with its phases timed by HIP
+    # events (eager launches; not part of the timed steps): the Gram-Schmidt
+    # sweeps' bandwidth over the whole solve
+    xp, ip = pk.solve(A, B, b, mode="AB", k=K, reg="gcv", tau=1.01, noise_norm=en, stop="dp", poll_every=args.poll,
+                      workspace=ws, history=False, phases=True)
+    same_p = bool(torch.equal(xp, xb))
+    phase_ms = ip["phase_ms"]
+    it_p = ip["iters"].cpu().numpy().astype(np.int64)
+    cgs_bytes = dcgs2_bytes(it_p, args.angles * args.det)
+    t_cgs = phase_ms["ortho"] / 1e3
+    cgs = {"bytes": int(cgs_bytes), "seconds": round(t_cgs, 4), "TBps": round(cgs_bytes / t_cgs / 1e12, 3),
+           "frac_hbm": round(cgs_bytes / t_cgs / 1e9 / HBM_PEAK_GBS, 4)}
+    log(args, "phases (ms): " + ", ".join(f"{k} {v:.1f}" for k, v in phase_ms.items()) +
+        f"; Gram-Schmidt sweeps {cgs_bytes / 1e12:.2f} TB in {t_cgs:.3f}s = {cgs['TBps']:.2f} TB/s; "
+        f"same x as the graph run: {same_p}")
+    del xp, ip
 
     # ---- projector launches over the whole batch, event-timed on the stream
     # they run on (the same launch shape as inside the solve)
@@ -713,7 +839,11 @@ def main():
                   "status_dp": int((status & 2 != 0).sum())},
         "rre_median": float(np.median(rre_b)),
         "plain": {"slices_per_s": round(1.0 / t_plain, 3), "subset": [int(s) for s in idx],
-                  "bitwise_equal_to_batched": same, "speedup_batched_vs_plain": round(value * t_plain, 3)},
+                  "iters_mean_subset": it_plain, "bitwise_equal_to_batched": same,
+                  "speedup_batched_vs_plain": round(value * t_plain, 3),
+                  "speedup_per_iteration": round(t_plain_iter / t_batched_iter, 3)},
+        "phases_ms": {k: round(v, 2) for k, v in phase_ms.items()},
+        "cgs2": cgs,
         "projector": {"A_GBps": round(gbs_A, 2), "A_frac_hbm": round(gbs_A / HBM_PEAK_GBS, 5),
                       "B_GBps": round(gbs_B, 2), "B_frac_hbm": round(gbs_B / HBM_PEAK_GBS, 5),
                       "A_ms_batch": round(t_A * 1e3, 3), "B_ms_batch": round(t_B * 1e3, 3),
@@ -724,13 +854,40 @@ def main():
         "autotune": {k: {"choice": {c: v[c] for c in ("a_path", "a_jb", "b_g", "czt", "a_rb", "a_occ")}, "ms": round(v["ms"], 3),
                          "builtin_ms": round(v["default_ms"], 3)} for k, v in tune.items()},
     }
+    if not args.no_learned:
+        # train the lambda/stop network on method-generated runs, then solve
+        # fresh slices with it and with GCV + DP (its own batches and
+        # workspaces; the benchmark's are released first)
+        del ws
+        torch.cuda.empty_cache()
+        lr = learned_run(args)
+        out["learned"] = {k: lr[k] for k in ("config", "gcv_dp", "learned", "speedup_learned_vs_gcv_dp", "training")}
+        out["learned"]["speedup_learned_vs_plain"] = round(lr["learned"]["slices_per_s"] * t_plain, 3)
     if not args.no_cpu_baseline:
         s0 = int(np.argsort(iters)[len(iters) // 2])
-        t_cpu, it_cpu, thr = cpu_baseline(args, b[s0].double().cpu().numpy(), float(en[s0]), K)
+        # the GPU's lambda history of that slice: the plain path gives the
+        # batched run's bits (checked above on the subset)
+        x1, i1 = pk.solve(A, B, b[s0:s0 + 1], mode="AB", k=K, reg="gcv", tau=1.01, noise_norm=en[s0:s0 + 1],
+                          stop="dp", workspace=ws1, history=True)
+        lam_gpu = i1["lam"][0].cpu().numpy()
+        same_s0 = bool(torch.equal(x1[0], xb[s0]))
+        t_cpu, o, thr = cpu_baseline(args, b[s0].double().cpu().numpy(), float(en[s0]), K)
+        model, usable = cpu_model()
         out["cpu_baseline"] = {"value": round(1.0 / t_cpu, 5), "unit": "slices/s", "cores": thr, "kind": "oracle",
                                "sample": f"1 slice (index {s0}, median GPU stop iteration {int(iters[s0])}) "
                                          f"solved to its DP stop by the FP64 oracle: {t_cpu:.1f}s, "
-                                         f"{it_cpu} iterations"}
+                                         f"{o.iters} iterations",
+                               "cpu_model": model, "usable_cores": usable}
+        out["cpu_baseline"]["thread_scaling"] = cpu_thread_scaling(args)
+        xg = xb[s0].double().cpu().numpy().ravel()
+        k_common = min(o.iters, int(iters[s0]))
+        out["parity"] = {"slice": s0, "x_rel_vs_oracle": rel_l2(xg, o.x), "gpu_iters": int(iters[s0]),
+                         "oracle_iters": o.iters, "same_stop": int(iters[s0]) == o.iters,
+                         "same_status": int(status[s0]) == o.status,
+                         "lambda_gcv_gap": gcv_gap(lam_gpu[:k_common], o), "plain_equals_batched": same_s0,
+                         "rre_gpu": float(rre_b[s0]), "rre_oracle": rel_l2(o.x, x_true[s0].double().cpu().numpy())}
+        log(args, f"parity, slice {s0}: x vs oracle {out['parity']['x_rel_vs_oracle']:.2e}, stop "
+                  f"{int(iters[s0])}/{o.iters}, GCV gap {out['parity']['lambda_gcv_gap']:.1e}")
     print(json.dumps(out), flush=True)
 
 

@@ -230,7 +230,19 @@ typedef struct {
     int features;              /* bits ABBA_FEAT_*: write the learned-rule features
                                   (out.features) and/or training labels (out.rre)          */
     int ortho;                 /* Gram-Schmidt schedule, ABBA_ORTHO_*                        */
+    double *phase_ms;          /* host [ABBA_PHASES] or NULL: add the stream time of each
+                                  phase of the solve (ms, from HIP events recorded between
+                                  the phases); the iterations then run without a graph and
+                                  the call synchronises `stream` before it returns          */
 } abba_exec;
+
+/* Phases timed by exec.phase_ms: the forward projector A (its padded input
+ * copies included), the backprojector B, the Gram-Schmidt sweeps with their
+ * reductions and per-slice algebra (eq. (8)), the small solve with the lambda
+ * rule, learned rule and stopping tests (eq. (12)), and the rest
+ * (initialisation, residual formation, assembly of x). */
+enum { ABBA_PHASE_A = 0, ABBA_PHASE_B = 1, ABBA_PHASE_ORTHO = 2, ABBA_PHASE_SMALL = 3, ABBA_PHASE_OTHER = 4,
+       ABBA_PHASES = 5 };
 
 /* exec.features bits.  Labels need AB mode, out.x_true and out.rre; they add a
  * [batch][k][k+1] FP64 Gram matrix to the workspace. */
@@ -249,6 +261,34 @@ enum { ABBA_ORTHO_DELAYED = 0, ABBA_ORTHO_CGS2 = 1 };
 /* Bytes of device workspace abba_solve needs for (A, B, batch, mode, k, stop). */
 int abba_solve_workspace(const abba_op *A, const abba_op *B, int batch, int mode, int k,
                          const abba_stop *stop, const abba_exec *exec, size_t *bytes);
+
+/* Where abba_solve keeps the Arnoldi quantities of eq. (8), M W_k = W_{k+1} H_k,
+ * inside its workspace, for callers that inspect them (the same arguments as
+ * abba_solve_workspace; `layout` is a host struct).  After abba_solve has
+ * finished on the stream, for slice s stopped at iteration k_s (the last
+ * cycle's count for restarted runs):
+ *   basis  vector j (0 <= j <= k_s) holds w_{j+1}, the orthonormal basis
+ *          vector, at byte offset basis + ((s basis_slots + j) ldw) * esize,
+ *          len entries of basis_dtype (ABBA_F64 for the F64 pair, else
+ *          ABBA_F32); when slice s ended in a breakdown, vector k_s is not a
+ *          basis vector (h_{k_s+1,k_s} = 0 and M W_k = W_k H_k(1:k, :)).
+ *   H      FP64 [batch][k][k+1] at byte offset hessenberg, column-major per
+ *          slice: entry (i, j) of H_k at ((s k + j)(k + 1) + i) * 8; columns
+ *          j < k_s are those of H_{k_s}, rows past j + 1 are not defined.
+ * Both offsets are within the workspace of abba_solve_workspace bytes. */
+typedef struct {
+    size_t bytes;              /* workspace size (as abba_solve_workspace)           */
+    size_t basis;              /* byte offset of the basis                           */
+    size_t hessenberg;         /* byte offset of H                                   */
+    int64_t ldw;               /* elements between consecutive basis vectors         */
+    int64_t len;               /* basis vector length: m (AB) or n (BA)              */
+    int basis_dtype;           /* abba_dtype of the basis                            */
+    int basis_slots;           /* basis vectors per slice                            */
+    int k;                     /* Hessenberg columns per slice (one cycle)           */
+} abba_basis_layout;
+
+int abba_solve_layout(const abba_op *A, const abba_op *B, int batch, int mode, int k,
+                      const abba_stop *stop, const abba_exec *exec, abba_basis_layout *layout);
 
 /* Hybrid AB-GMRES (mode AB, Algorithm 1) or BA-GMRES (mode BA, Algorithm 2)
  * on `batch` independent slices.

@@ -18,7 +18,7 @@ from dataclasses import dataclass
 
 __all__ = [
     "LIB_PATH", "lib", "AbbaError", "Geometry", "Operator", "project", "backproject", "solve",
-    "workspace_bytes", "ST_KMAX", "ST_STOP_DP", "ST_STOP_RNS", "ST_BREAKDOWN", "ST_NONFINITE",
+    "workspace_bytes", "solve_layout", "basis_views", "ST_KMAX", "ST_STOP_DP", "ST_STOP_RNS", "ST_BREAKDOWN", "ST_NONFINITE",
     "ST_STOP_LEARNED", "ST_STOP_NCP", "autotune", "set_tuning", "get_tuning", "mlp_forward", "mlp_loss_grad", "mlp_adam", "mlp_labels", "MLP_PARAMS",
 ]
 
@@ -72,9 +72,19 @@ class _Tune(ctypes.Structure):
                 ("candidates", ctypes.c_int)]
 
 
+class _Layout(ctypes.Structure):
+    _fields_ = [("bytes", ctypes.c_size_t), ("basis", ctypes.c_size_t), ("hessenberg", ctypes.c_size_t),
+                ("ldw", ctypes.c_int64), ("len", ctypes.c_int64), ("basis_dtype", ctypes.c_int),
+                ("basis_slots", ctypes.c_int), ("k", ctypes.c_int)]
+
+
 class _Exec(ctypes.Structure):
     _fields_ = [("use_graph", ctypes.c_int), ("poll_every", ctypes.c_int), ("restart", ctypes.c_int),
-                ("features", ctypes.c_int), ("ortho", ctypes.c_int)]
+                ("features", ctypes.c_int), ("ortho", ctypes.c_int), ("phase_ms", ctypes.c_void_p)]
+
+
+# phases timed by abba_exec.phase_ms
+PHASES = ("A", "B", "ortho", "small", "other")
 
 
 def _load():
@@ -99,6 +109,9 @@ def _load():
     L.abba_solve_workspace.argtypes = [vp, vp, i, i, i, ctypes.POINTER(_Stop), ctypes.POINTER(_Exec),
                                        ctypes.POINTER(ctypes.c_size_t)]
     L.abba_solve_workspace.restype = i
+    L.abba_solve_layout.argtypes = [vp, vp, i, i, i, ctypes.POINTER(_Stop), ctypes.POINTER(_Exec),
+                                    ctypes.POINTER(_Layout)]
+    L.abba_solve_layout.restype = i
     L.abba_solve.argtypes = [vp, vp, vp, vp, i, i, i, ctypes.POINTER(_Reg), ctypes.POINTER(_Stop),
                              ctypes.POINTER(_Out), ctypes.POINTER(_Exec), vp, ctypes.c_size_t, vp]
     L.abba_solve.restype = i
@@ -133,6 +146,7 @@ abba_project = lib.abba_project
 abba_backproject = lib.abba_backproject
 abba_solve_workspace = lib.abba_solve_workspace
 abba_solve = lib.abba_solve
+abba_solve_layout = lib.abba_solve_layout
 abba_autotune = lib.abba_autotune
 abba_op_set_tuning = lib.abba_op_set_tuning
 abba_op_get_tuning = lib.abba_op_get_tuning
@@ -345,10 +359,37 @@ def workspace_bytes(A: Operator, B: Operator, batch: int, mode: str, k: int, sto
     return nb.value
 
 
+def solve_layout(A: Operator, B: Operator, batch: int, mode: str, k: int, stop=None, labels=False,
+                 restart: int = 0) -> dict:
+    """Where abba_solve keeps the basis W and the Hessenberg matrix H inside
+    its workspace (abba_solve_layout): byte offsets and strides."""
+    _, s, e = _structs("none", 0, 0, None, None, 0, stop, 1.01, 1e-3, 0, 1, restart, FEAT_LABELS if labels else 0)
+    L = _Layout()
+    _check(lib.abba_solve_layout(A.handle, B.handle, batch, MODE_AB if mode == "AB" else MODE_BA, k,
+                                 ctypes.byref(s), ctypes.byref(e), ctypes.byref(L)), "abba_solve_layout")
+    return dict(bytes=L.bytes, basis=L.basis, hessenberg=L.hessenberg, ldw=L.ldw, len=L.len,
+                basis_dtype=L.basis_dtype, basis_slots=L.basis_slots, k=L.k)
+
+
+def basis_views(workspace, layout: dict, batch: int):
+    """(W, H) views into a solve's workspace tensor: W [batch, slots, ldw] in the
+    basis dtype, H [batch, k, k+1] float64 (column j of H_k is H[s, j])."""
+    import torch
+    dt = _torch_dtype(layout["basis_dtype"])
+    esz = torch.empty((), dtype=dt).element_size()
+    nW = batch * layout["basis_slots"] * layout["ldw"]
+    W = workspace[layout["basis"]:layout["basis"] + nW * esz].view(dt).view(batch, layout["basis_slots"],
+                                                                            layout["ldw"])
+    k = layout["k"]
+    nH = batch * k * (k + 1)
+    H = workspace[layout["hessenberg"]:layout["hessenberg"] + nH * 8].view(torch.float64).view(batch, k, k + 1)
+    return W, H
+
+
 def solve(A: Operator, B: Operator, b, mode: str = "AB", k: int = 30, reg: str = "gcv", lam: float = 0.0,
           tau: float = 1.01, noise_norm=None, stop=None, rns_eps: float = 1e-3, x0=None, use_graph=False,
           poll_every: int = 1, restart: int = 0, mlp=None, judge_delta: float = 0.05, history: bool = True,
-          workspace=None, features: bool = False, ortho: str = "dcgs2", x_true=None):
+          workspace=None, features: bool = False, ortho: str = "dcgs2", x_true=None, phases: bool = False):
     """Hybrid AB-/BA-GMRES on a batch of slices; returns (x, info).
 
     ortho: "dcgs2" (CGS2 with the second pass delayed to the next step's
@@ -360,7 +401,9 @@ def solve(A: Operator, B: Operator, b, mode: str = "AB", k: int = 30, reg: str =
     history, lam [batch, k] and resid [batch, k+1].  features=True adds the
     learned-rule features [batch, k, 64] (float32); x_true (device, image
     dtype, AB mode) adds the RRE label grid rre [batch, k, 64].  mlp: device
-    float32 [MLP_PARAMS] for reg="learned".
+    float32 [MLP_PARAMS] for reg="learned".  phases=True times the phases of
+    the solve with HIP events (the iterations then run without a graph and the
+    call waits for the stream) and adds info["phase_ms"], a dict over PHASES.
     """
     import torch
     batch = _need(b, A.sino_dtype, A.m, "b")
@@ -377,6 +420,8 @@ def solve(A: Operator, B: Operator, b, mode: str = "AB", k: int = 30, reg: str =
     fbits = (FEAT_OUT if features else 0) | (FEAT_LABELS if x_true is not None else 0)
     r, s, e = _structs(reg, lam, tau, noise_norm, mlp, judge_delta, stop, tau, rns_eps, use_graph, poll_every,
                        restart, fbits, ortho)
+    pms = (ctypes.c_double * len(PHASES))() if phases else None
+    e.phase_ms = None if pms is None else ctypes.addressof(pms)
     m = MODE_AB if mode == "AB" else MODE_BA
     iters = torch.zeros(batch, dtype=torch.int32, device=dev)
     status = torch.zeros(batch, dtype=torch.int32, device=dev)
@@ -409,6 +454,8 @@ def solve(A: Operator, B: Operator, b, mode: str = "AB", k: int = 30, reg: str =
                           ctypes.byref(o), ctypes.byref(e), _ptr(workspace), workspace.numel(), _stream_ptr()),
            "abba_solve")
     info = dict(iters=iters, status=status, lam=lamh, resid=resh, features=feats, rre=rre, ncp=ncph)
+    if pms is not None:
+        info["phase_ms"] = {name: float(pms[i]) for i, name in enumerate(PHASES)}
     return x, info
 
 

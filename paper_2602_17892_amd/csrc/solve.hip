@@ -51,6 +51,50 @@ int learned_step(const SolveDims &d, const SolveWS &ws, const abba_reg *reg, int
 
 static inline int64_t round_up(int64_t v, int64_t a) { return (v + a - 1) / a * a; }
 
+// Stream-time accounting of the phases of a solve (exec.phase_ms): an event
+// is recorded at every phase change; interval i runs from event i to event
+// i + 1 and belongs to phase ph[i].
+struct PhaseClock {
+    hipStream_t st = nullptr;
+    std::vector<hipEvent_t> ev;
+    std::vector<int> ph;
+    int mark(int phase) {
+        hipEvent_t e;
+        hipError_t r = hipEventCreate(&e);
+        if (r != hipSuccess) return hip_fail(r, "hipEventCreate");
+        ev.push_back(e);
+        ph.push_back(phase);
+        r = hipEventRecord(e, st);
+        if (r != hipSuccess) return hip_fail(r, "hipEventRecord");
+        return ABBA_OK;
+    }
+    // Synchronise and add each interval's time to ms[phase].
+    int finish(double *ms) {
+        int rc = mark(-1);
+        if (!rc) {
+            hipError_t r = hipEventSynchronize(ev.back());
+            if (r != hipSuccess) rc = hip_fail(r, "hipEventSynchronize");
+        }
+        for (size_t i = 0; !rc && i + 1 < ev.size(); ++i) {
+            if (ph[i] < 0) continue;
+            float t = 0.f;
+            hipError_t r = hipEventElapsedTime(&t, ev[i], ev[i + 1]);
+            if (r != hipSuccess) rc = hip_fail(r, "hipEventElapsedTime");
+            else ms[ph[i]] += t;
+        }
+        release();
+        return rc;
+    }
+    void release() {
+        for (hipEvent_t e : ev) (void)hipEventDestroy(e);
+        ev.clear();
+        ph.clear();
+    }
+    ~PhaseClock() { release(); }
+};
+
+static inline int clock_mark(PhaseClock *c, int phase) { return c ? c->mark(phase) : ABBA_OK; }
+
 // Scratch the operators of one solve need for `batch` slices.
 static size_t op_scratch_bytes(const abba_op *A, const abba_op *B, int batch) {
     size_t b = 0;
@@ -192,13 +236,17 @@ __global__ void fill_k(double *__restrict__ p, int64_t n, double v) {
 }
 
 static int apply_op(const abba_op *op, bool forward, VecRef in, int in_dt, VecRef out, int out_dt,
-                    const SolveDims &d, const SolveWS &ws, const Launch &L) {
-    if (forward) {
-        if (cone_path(op)) return cone_forward(op, in, out, out_dt, d.S, ws.scratch, L);
-        return par2d_forward(op, in, out, out_dt, d.S, ws.scratch, L);
-    }
-    if (cone_path(op)) return cone_back(op, in, in_dt, out, d.S, ws.scratch, L);
-    return par2d_back(op, in, in_dt, out, d.S, ws.scratch, L);
+                    const SolveDims &d, const SolveWS &ws, const Launch &L, PhaseClock *clk) {
+    int rc = clock_mark(clk, forward ? ABBA_PHASE_A : ABBA_PHASE_B);
+    if (rc) return rc;
+    if (forward)
+        rc = cone_path(op) ? cone_forward(op, in, out, out_dt, d.S, ws.scratch, L)
+                           : par2d_forward(op, in, out, out_dt, d.S, ws.scratch, L);
+    else
+        rc = cone_path(op) ? cone_back(op, in, in_dt, out, d.S, ws.scratch, L)
+                           : par2d_back(op, in, in_dt, out, d.S, ws.scratch, L);
+    if (rc) return rc;
+    return clock_mark(clk, ABBA_PHASE_OTHER);
 }
 
 struct IterCfg {
@@ -214,6 +262,7 @@ struct IterCfg {
     const abba_reg *reg;
     const abba_out *out;
     const void *x0;
+    PhaseClock *clk;     // exec.phase_ms accounting, or nullptr
 };
 
 // The operator step of iteration k: q = M (input vector) into W, keeping
@@ -229,12 +278,12 @@ static int apply_M(const SolveDims &d, const SolveWS &ws, const IterCfg &c, cons
     int rc;
     if (d.mode == ABBA_MODE_AB) {
         VecRef p{ws.P, (int64_t)d.pslots * d.ldn, d.ldn, in_off};
-        if ((rc = apply_op(c.B, false, win, d.w_dt, p, d.img_dt, d, ws, L))) return rc;
-        return apply_op(c.A, true, p, d.img_dt, wout, d.w_dt, d, ws, L);
+        if ((rc = apply_op(c.B, false, win, d.w_dt, p, d.img_dt, d, ws, L, c.clk))) return rc;
+        return apply_op(c.A, true, p, d.img_dt, wout, d.w_dt, d, ws, L, c.clk);
     }
     VecRef z{ws.Z, (int64_t)(d.keepZ ? d.pslots : 1) * d.ldm, d.keepZ ? d.ldm : 0, d.keepZ ? in_off : 0};
-    if ((rc = apply_op(c.A, true, win, d.w_dt, z, d.sino_dt, d, ws, L))) return rc;
-    return apply_op(c.B, false, z, d.sino_dt, wout, d.w_dt, d, ws, L);
+    if ((rc = apply_op(c.A, true, win, d.w_dt, z, d.sino_dt, d, ws, L, c.clk))) return rc;
+    return apply_op(c.B, false, z, d.sino_dt, wout, d.w_dt, d, ws, L, c.clk);
 }
 
 // Launch one iteration for all active slices on `st`.
@@ -243,7 +292,9 @@ static int one_iteration(const SolveDims &d, const SolveWS &ws, const IterCfg &c
     const bool delayed = d.ortho == ABBA_ORTHO_DELAYED;
     int rc;
     if ((rc = apply_M(d, ws, c, L))) return rc;
+    if ((rc = clock_mark(c.clk, ABBA_PHASE_ORTHO))) return rc;
     if ((rc = delayed ? dcgs2_step(d, ws, ws.kdev, st) : cgs2_step(d, ws, st))) return rc;
+    if ((rc = clock_mark(c.clk, ABBA_PHASE_SMALL))) return rc;
     if ((rc = launch_smallsolve(d, ws, c.rule, c.lam_fixed, c.tau, c.noise_reg, st))) return rc;
     if (c.learned || d.feat_out || d.labels) {
         if ((rc = learned_step(d, ws, c.reg, c.learned, c.x0, c.out, st))) return rc;
@@ -262,7 +313,9 @@ static int one_iteration(const SolveDims &d, const SolveWS &ws, const IterCfg &c
         if ((rc = launch_finish_resid(d, ws, nb, st))) return rc;
     }
     if (d.ncp && (rc = launch_ncp(d, ws, yk, st))) return rc;
-    return launch_stop(d, ws, c.stop_kind, c.stop_tau, c.rns_eps, c.noise_stop, c.iters, c.status, st);
+    if ((rc = launch_stop(d, ws, c.stop_kind, c.stop_tau, c.rns_eps, c.noise_stop, c.iters, c.status, st)))
+        return rc;
+    return clock_mark(c.clk, ABBA_PHASE_OTHER);
 }
 
 __global__ void cycle_begin_k(int *__restrict__ alive, int *__restrict__ iters, int *__restrict__ status, int S) {
@@ -352,7 +405,8 @@ static int run_cycle(const SolveDims &d, const SolveWS &ws, const IterCfg &cfg, 
         return rc;
     VecRef xin{x, d.n, 0, 0};
     VecRef sino{ws.sino, d.ldm, 0, 0};
-    if ((rc = apply_op(cfg.A, true, xin, d.img_dt, sino, d.sino_dt, d, ws, L0))) return rc;
+    if ((rc = clock_mark(cfg.clk, ABBA_PHASE_OTHER))) return rc;
+    if ((rc = apply_op(cfg.A, true, xin, d.img_dt, sino, d.sino_dt, d, ws, L0, cfg.clk))) return rc;
     if (d.mode == ABBA_MODE_AB) {
         // r_0 = b - A x_0 (basis storage), rho_0 = beta
         if ((rc = launch_sub(d.sino_dt, b, d.m, ws.sino, d.ldm, d.w_dt, ws.W, wsl, d.m, d.ldw, d.S, st))) return rc;
@@ -363,7 +417,7 @@ static int run_cycle(const SolveDims &d, const SolveWS &ws, const IterCfg &cfg, 
             return rc;
         if ((rc = launch_norm(d.sino_dt, ws.sino, d.ldm, d.m, d.S, ws.npart, ws.rhoh, d.K + 1, st))) return rc;
         VecRef w0{ws.W, wsl, 0, 0};
-        if ((rc = apply_op(cfg.B, false, sino, d.sino_dt, w0, d.w_dt, d, ws, L0))) return rc;
+        if ((rc = apply_op(cfg.B, false, sino, d.sino_dt, w0, d.w_dt, d, ws, L0, cfg.clk))) return rc;
     }
     if ((rc = normalize_first(d, ws, cfg.iters, cfg.status, alive, st))) return rc;
     if ((cfg.learned || d.feat_out || d.labels) && (rc = learned_prepare(d, ws, x, cfg.out, st))) return rc;
@@ -374,13 +428,15 @@ static int run_cycle(const SolveDims &d, const SolveWS &ws, const IterCfg &cfg, 
         ABBA_LAUNCHED("set_int_k");
         Launch L1{st, ws.kdev, ws.active};
         if ((rc = apply_M(d, ws, cfg, L1))) return rc;
+        if ((rc = clock_mark(cfg.clk, ABBA_PHASE_ORTHO))) return rc;
         if ((rc = dcgs2_step(d, ws, ws.kdev, st))) return rc;
+        if ((rc = clock_mark(cfg.clk, ABBA_PHASE_OTHER))) return rc;
     }
     hipLaunchKernelGGL(set_int_k, dim3(1), dim3(1), 0, st, ws.kdev, 1);
     ABBA_LAUNCHED("set_int_k");
 
     // ---- iterations
-    if (ex.use_graph && !*gexec) {
+    if (ex.use_graph && !cfg.clk && !*gexec) {
         hipStream_t cap;
         ABBA_HIP(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
         hipError_t e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
@@ -455,6 +511,37 @@ extern "C" int abba_solve_workspace(const abba_op *A, const abba_op *B, int batc
     return ABBA_OK;
 }
 
+extern "C" int abba_solve_layout(const abba_op *A, const abba_op *B, int batch, int mode, int k,
+                                 const abba_stop *stop, const abba_exec *exec, abba_basis_layout *layout) {
+    if (!layout) {
+        set_error("layout is NULL");
+        return ABBA_ERR_ARG;
+    }
+    SolveDims d;
+    abba_out dummy;
+    std::memset(&dummy, 0, sizeof(dummy));
+    dummy.resid = (double *)1;   // the carve-up abba_solve_workspace sizes
+    const int kc = exec && exec->restart > 0 && exec->restart < k ? exec->restart : k;
+    int rc = make_dims(A, B, batch, mode, kc, stop, &dummy, &d);
+    if (rc) return rc;
+    d.labels = exec && (exec->features & ABBA_FEAT_LABELS) && mode == ABBA_MODE_AB;
+    SolveWS ws;
+    // carve from a fake base address 0 + 256 so that offsets come out as
+    // pointers (a null base would leave every pointer null)
+    char *base = reinterpret_cast<char *>(256);
+    const size_t bytes = solve_workspace_bytes(d, &ws, base, op_scratch_bytes(A, B, batch));
+    std::memset(layout, 0, sizeof(*layout));
+    layout->bytes = bytes;
+    layout->basis = (size_t)((char *)ws.W - base);
+    layout->hessenberg = (size_t)((char *)ws.H - base);
+    layout->ldw = d.ldw;
+    layout->len = d.len;
+    layout->basis_dtype = d.w_dt;
+    layout->basis_slots = d.wslots;
+    layout->k = d.K;
+    return ABBA_OK;
+}
+
 extern "C" int abba_solve(const abba_op *A, const abba_op *B, const void *b, void *x, int batch, int mode, int k,
                           const abba_reg *reg, const abba_stop *stop, const abba_out *out, const abba_exec *exec,
                           void *workspace, size_t ws_bytes, void *stream) {
@@ -462,7 +549,7 @@ extern "C" int abba_solve(const abba_op *A, const abba_op *B, const void *b, voi
         set_error("abba_solve: b, x, reg, out.iters, out.status and workspace are required");
         return ABBA_ERR_ARG;
     }
-    abba_exec ex{0, 1, 0, 0, ABBA_ORTHO_DELAYED};
+    abba_exec ex{0, 1, 0, 0, ABBA_ORTHO_DELAYED, nullptr};
     if (exec) ex = *exec;
     if (ex.restart < 0) {
         set_error("restart cycle length must be >= 0");
@@ -579,11 +666,19 @@ extern "C" int abba_solve(const abba_op *A, const abba_op *B, const void *b, voi
     cfg.reg = reg;
     cfg.out = out;
     cfg.x0 = x;
+    PhaseClock clock;
+    clock.st = st;
+    cfg.clk = ex.phase_ms ? &clock : nullptr;
     hipGraphExec_t gexec = nullptr;
     hipGraph_t graph = nullptr;
     auto cleanup = [&]() {
         if (gexec) (void)hipGraphExecDestroy(gexec);
         if (graph) (void)hipGraphDestroy(graph);
+    };
+    // the phase times of a finished run (the call then waits for the stream)
+    auto timed = [&](int rc_) {
+        if (!rc_ && cfg.clk) rc_ = clock.finish(ex.phase_ms);
+        return rc_;
     };
 
     if (!restarting) {
@@ -604,7 +699,7 @@ extern "C" int abba_solve(const abba_op *A, const abba_op *B, const void *b, voi
             hipLaunchKernelGGL(copy_hist_k, dim3(d.S), dim3(128), 0, st, ws.ncph, d.K, out->ncp, d.K, d.K, d.S);
             ABBA_LAUNCHED("copy_hist_k");
         }
-        return ABBA_OK;
+        return timed(ABBA_OK);
     }
 
     // ---- restarted cycles (Sec. 3.3): x_0 <- the last cycle's iterate
@@ -645,5 +740,5 @@ extern "C" int abba_solve(const abba_op *A, const abba_op *B, const void *b, voi
         }
     }
     cleanup();
-    return rc;
+    return timed(rc);
 }

@@ -72,6 +72,9 @@ def test_validation_before_any_device_call():
     assert pk.lib.abba_backproject(None, None, None, 1, None) == -1
     nb = ctypes.c_size_t()
     assert pk.lib.abba_solve_workspace(None, None, 1, 0, 5, None, None, ctypes.byref(nb)) == -1
+    lay = pk._Layout()
+    assert pk.lib.abba_solve_layout(None, None, 1, 0, 5, None, None, ctypes.byref(lay)) == -1
+    assert pk.lib.abba_solve_layout(None, None, 1, 0, 5, None, None, None) == -1
     assert pk.lib.abba_solve(None, None, None, None, 1, 0, 5, None, None, None, None, None, 0, None) == -1
     assert b"required" in pk.lib.abba_last_error()
     del keep
@@ -118,7 +121,7 @@ def test_struct_layouts_match_the_header(tmp_path):
         pytest.fail("libabba.so is not built (python paper_2602_17892_amd/build.py)")
     import paper_2602_17892_amd as pk
     structs = {"abba_geometry": pk._Geometry, "abba_reg": pk._Reg, "abba_stop": pk._Stop, "abba_out": pk._Out,
-               "abba_exec": pk._Exec, "abba_tune": pk._Tune}
+               "abba_exec": pk._Exec, "abba_tune": pk._Tune, "abba_basis_layout": pk._Layout}
     lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "abba.h"', "int main(void) {"]
     for cname, cls in structs.items():
         lines.append(f'printf("{cname} size %zu\\n", sizeof({cname}));')

@@ -66,3 +66,14 @@ def test_cone_ray_steps_brute_force(n, views, nu, nv, pitch, sid, sdd):
                     crd = [S[o] + t * d[o] + c for o in range(3) if o != a]
                     want += all(-1 < q < n for q in crd)
     assert bench.cone_ray_steps(n, views, nu, nv, pitch, sid, sdd) == want
+
+
+def test_dcgs2_byte_count():
+    """The delayed-CGS2 byte count: steps j = 0..k_s per slice, each moving
+    (j + 2) vectors in the dot-product sweep and (j + 4) in the update sweep
+    (counted here step by step)."""
+    import bench
+    iters = [0, 1, 5, 100]
+    length = 1000
+    want = sum(sum((j + 2) + (j + 4) for j in range(k + 1)) for k in iters) * length * 4
+    assert bench.dcgs2_bytes(iters, length) == want

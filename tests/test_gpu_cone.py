@@ -35,6 +35,14 @@ def rel(a, b):
     return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
 
 
+def relp(a, b):
+    """Projector error: the larger of the relative L2 error and
+    max|a - b| / max|b| (a wrong value on a few bins shows in the second)."""
+    a = np.asarray(a, dtype=np.float64).ravel()
+    b = np.asarray(b, dtype=np.float64).ravel()
+    return float(max(rel(a, b), np.max(np.abs(a - b)) / max(np.max(np.abs(b)), 1e-300)))
+
+
 # nx, ny, nz, views, nu, nv, pu, pv, sid, sdd
 SHAPES = [
     (20, 18, 16, 24, 32, 28, 1.3, 1.1, 40.0, 80.0),   # moderate cone angle, ragged sizes
@@ -70,8 +78,8 @@ def test_cone_parity(pk, shape, dt):
     tdt = {"f64": torch.float64, "f32": torch.float32}[dt]
     xd, yd = dev(x, tdt), dev(y, tdt)
     xr, yr = xd.double().cpu().numpy(), yd.double().cpu().numpy()
-    ea = rel(pk.project(A, xd).double().cpu().numpy(), og.A(xr))
-    eb = rel(pk.backproject(B, yd).double().cpu().numpy(), og.B(yr))
+    ea = relp(pk.project(A, xd).double().cpu().numpy(), og.A(xr))
+    eb = relp(pk.backproject(B, yd).double().cpu().numpy(), og.B(yr))
     tol = 1e-12 if dt == "f64" else 1e-5
     print(f"cone {shape} {dt}: A {ea:.2e} B {eb:.2e}")
     assert ea <= tol and eb <= tol
@@ -85,8 +93,8 @@ def test_cone_user_angles(pk):
     r = np.random.default_rng(4)
     x = r.uniform(size=(10, 14, 14))
     y = r.standard_normal((9, 16, 20))
-    ea = rel(pk.project(A, dev(x, torch.float64)).cpu().numpy(), og.A(x))
-    eb = rel(pk.backproject(B, dev(y, torch.float64)).cpu().numpy(), og.B(y))
+    ea = relp(pk.project(A, dev(x, torch.float64)).cpu().numpy(), og.A(x))
+    eb = relp(pk.backproject(B, dev(y, torch.float64)).cpu().numpy(), og.B(y))
     print(f"cone user angles: A {ea:.2e} B {eb:.2e}")
     assert max(ea, eb) <= 1e-12
 
@@ -99,11 +107,11 @@ def test_cone_bf16_sinogram(pk):
     ya = pk.project(A, dev(x, torch.float32))
     assert ya.dtype == torch.bfloat16
     ref = og.A(x.astype(np.float32).astype(np.float64))
-    ea = rel(ya.double().cpu().numpy(), ref)
+    ea = relp(ya.double().cpu().numpy(), ref)
     # one BF16 rounding (2^-8 relative) on every entry at most
     step = np.abs(ya.double().cpu().numpy().ravel() - ref) / np.maximum(np.abs(ref), 1e-30)
     yb = torch.as_tensor(ref.reshape(nvw, nv, nu)).to(device="cuda", dtype=torch.bfloat16)
-    eb = rel(pk.backproject(B, yb).double().cpu().numpy(), og.B(yb.double().cpu().numpy()))
+    eb = relp(pk.backproject(B, yb).double().cpu().numpy(), og.B(yb.double().cpu().numpy()))
     print(f"cone bf16: A vs FP64 {ea:.2e} (max per entry {step[np.abs(ref) > 1e-3].max():.2e}) B {eb:.2e}")
     assert step[np.abs(ref) > 1e-3].max() <= 2.0 ** -8 and eb <= 1e-5
 
@@ -150,11 +158,11 @@ def test_cone_c4_shape_sampled(pk):
     views = [0, 45, 127, 300]
     beta = 2 * math.pi * np.array(views) / nvw
     og_v = Cone3DOps(Cone3D(nx, ny, nz, len(views), nu, nv, pu, pv, sid, sdd, beta))
-    ea = rel(yh[views], og_v.A(xr).reshape(len(views), nv, nu))
+    ea = relp(yh[views], og_v.A(xr).reshape(len(views), nv, nu))
     # sampled voxels of B y (the oracle sums over all 360 views for each)
     og = Cone3DOps(Cone3D(nx, ny, nz, nvw, nu, nv, pu, pv, sid, sdd))
     idx = r.choice(nx * ny * nz, 2000, replace=False)
-    eb = rel(xbh[idx], og.B_points(yh, idx))
+    eb = relp(xbh[idx], og.B_points(yh, idx))
     print(f"C4 256^3 x 360 x 384^2: A (4 views) {ea:.2e}  B (2000 voxels) {eb:.2e}")
     assert ea <= 1e-5 and eb <= 1e-5
 

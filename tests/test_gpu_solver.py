@@ -505,3 +505,19 @@ def test_ncp_stop_batch_f32(pk):
         assert ed <= 1e-4 and abs(it - o.iters) <= 1
         x1, i1 = pk.solve(A, B, bd[s:s + 1].contiguous(), mode="AB", k=K, reg="gcv", stop="ncp")
         assert torch.equal(x1[0], x[s]) and int(i1["iters"][0]) == it
+
+
+def test_phase_timing(pk):
+    """exec.phase_ms: every phase of a batched solve gets stream time, and
+    the eager, timed run gives the graph run's bits."""
+    A, B, og, xt, bd, bu, ens = problem(pk, 64, 90, 91, 0.02, 0, 7, batch=4)
+    noise = torch.tensor(ens, device="cuda", dtype=torch.float64)
+    kw = dict(mode="AB", k=30, reg="gcv", noise_norm=noise, stop="dp")
+    xg, ig = pk.solve(A, B, bd, use_graph=True, poll_every=4, **kw)
+    xp, ip = pk.solve(A, B, bd, phases=True, poll_every=4, **kw)
+    ph = ip["phase_ms"]
+    print("phases (ms):", {k: round(v, 3) for k, v in ph.items()})
+    assert torch.equal(xg, xp) and torch.equal(ig["iters"], ip["iters"])
+    assert set(ph) == set(pk.PHASES)
+    assert all(v > 0.0 for v in ph.values())
+    assert "phase_ms" not in ig
