@@ -241,8 +241,9 @@ def projectors_only(args):
     y = torch.empty((S, args.angles, args.det), device="cuda")
     xo = torch.empty_like(x)
     reps = 3
+    wsa = torch.empty(pk.project_workspace_bytes(A, S), dtype=torch.uint8, device="cuda")
     for _ in range(reps):
-        pk.project(A, x, out=y)
+        pk.project(A, x, out=y, workspace=wsa)
     for _ in range(reps):
         pk.backproject(B, y, out=xo)
     for _ in range(reps):
@@ -446,8 +447,10 @@ def cone_workload(args):
     log(args, f"BA K={K}: {t_solve:.3f}s/solve, RRE {rre:.4f}")
     y = torch.empty_like(b)
     xo = torch.empty_like(xt)
-    t_A = time_apply(lambda: pk.project(A, xt, out=y), torch, args.roofline_reps)
-    t_B = time_apply(lambda: pk.backproject(B, b, out=xo), torch, args.roofline_reps)
+    wsa = torch.empty(pk.project_workspace_bytes(A, 1), dtype=torch.uint8, device="cuda")
+    wsb = torch.empty(pk.backproject_workspace_bytes(B, 1), dtype=torch.uint8, device="cuda")
+    t_A = time_apply(lambda: pk.project(A, xt, out=y, workspace=wsa), torch, args.roofline_reps)
+    t_B = time_apply(lambda: pk.backproject(B, b, out=xo, workspace=wsb), torch, args.roofline_reps)
     steps = cone_ray_steps(n, C["views"], C["nu"], C["nv"], C["pitch"], C["sid"], C["sdd"])
     pairs = n ** 3 * C["views"]
     tf_A = steps * FLOPS_PER_CONE_STEP / t_A / 1e12
@@ -795,8 +798,10 @@ def main():
     xin = x_true.contiguous()
     yb = torch.empty_like(b)
     xo = torch.empty_like(xin)
-    t_A = time_apply(lambda: pk.project(A, xin, out=yb), torch, args.roofline_reps)
+    wsa = torch.empty(pk.project_workspace_bytes(A, S), dtype=torch.uint8, device="cuda")
+    t_A = time_apply(lambda: pk.project(A, xin, out=yb, workspace=wsa), torch, args.roofline_reps)
     t_B = time_apply(lambda: pk.backproject(B, b, out=xo), torch, args.roofline_reps)
+    del wsa
     n, m = args.n * args.n, args.angles * args.det
     bytes_apply = S * (n + m) * 4
     gbs_A, gbs_B = bytes_apply / t_A / 1e9, bytes_apply / t_B / 1e9

@@ -111,21 +111,35 @@ void abba_op_destroy(abba_op *op);
 /* Image length n and sinogram length m of one slice. */
 int abba_op_sizes(const abba_op *op, int64_t *n_img, int64_t *n_sino);
 
+/* Device scratch, in bytes, that abba_project (abba_backproject) needs for
+ * `batch` slices of this operator: zero-padded copies of the input that the
+ * kernels read (2D A: the image rows with pads, row-major and transposed;
+ * cone and fan A: the volume per dominant axis; cone and fan B: the views).
+ * 0 for the 2D parallel-beam B and A^T, which stage their input in LDS.
+ * `bytes` is a host pointer. */
+int abba_project_workspace(const abba_op *A, int batch, size_t *bytes);
+int abba_backproject_workspace(const abba_op *B, int batch, size_t *bytes);
+
 /* y_s = A x_s for s < batch (eq. (1)); `A` must be ABBA_OP_JOSEPH.  x is
  * [batch][n] in the image dtype, y [batch][m] in the sinogram dtype.
- * Asynchronous on `stream`; allocates its scratch (padded copies of x)
- * stream-ordered.  Two kernels compute A with identical results: one per ray
- * from global memory, and one that streams the image through LDS, used when
- * the batch is large enough to fill the device; the environment variable
+ * workspace: a caller-owned device buffer of at least abba_project_workspace
+ * bytes, 256-byte aligned (NULL when that size is 0), overwritten by the call
+ * and free again once the stream has passed it; a smaller or misaligned one
+ * is ABBA_ERR_ARG.  The call allocates nothing.  Asynchronous on `stream`.
+ * Two kernels compute A with identical results: one per ray from global
+ * memory, and one that streams the image through LDS, used when the batch is
+ * large enough to fill the device; the environment variable
  * ABBA_JOSEPH_PATH=gather|lds forces one of them. */
-int abba_project(const abba_op *A, const void *x, void *y, int batch, void *stream);
+int abba_project(const abba_op *A, const void *x, void *y, int batch, void *workspace, size_t ws_bytes,
+                 void *stream);
 
 /* x_s = B y_s for s < batch; `B` is ABBA_OP_PIXEL (unmatched B of
  * eqs. (4)-(5)) or ABBA_OP_JOSEPH_T (exact A^T).  y is [batch][m] in the
- * sinogram dtype, x [batch][n] in the image dtype.  Asynchronous on `stream`.
- * On cone and fan geometries it allocates its scratch (a zero-padded copy of
- * the views) stream-ordered; on the 2D parallel beam it allocates nothing. */
-int abba_backproject(const abba_op *B, const void *y, void *x, int batch, void *stream);
+ * sinogram dtype, x [batch][n] in the image dtype.  workspace as for
+ * abba_project, sized by abba_backproject_workspace.  The call allocates
+ * nothing.  Asynchronous on `stream`. */
+int abba_backproject(const abba_op *B, const void *y, void *x, int batch, void *workspace, size_t ws_bytes,
+                     void *stream);
 
 /* ---- Launch tuning (tile shapes and kernel choices of the projectors).
  * Every choice computes the same result bits: it changes how work is split
@@ -146,14 +160,21 @@ typedef struct {
     int candidates;    /* abba_autotune: launch choices timed besides the built-in rules     */
 } abba_tune;
 
+/* Device bytes abba_autotune needs for `batch` slices: an input and an output
+ * of the operator and the scratch of one apply. */
+int abba_autotune_workspace(const abba_op *op, int batch, size_t *bytes);
+
 /* Times the launch choices of `op` for `batch` slices (reps applies each,
- * after one warm-up; reps < 1 means 3) on a fixed input pattern in buffers
- * it allocates and frees, with HIP events on `stream`, and keeps the fastest
- * (the built-in rules included) in the operator for that batch size; later
- * calls with that batch size, abba_solve included, use it.  `best` (host) may
- * be NULL.  Synchronises `stream`.  An operator keeps 8 batch sizes (the
- * oldest is dropped); changing them while the operator runs is a race. */
-int abba_autotune(abba_op *op, int batch, int reps, void *stream, abba_tune *best);
+ * after one warm-up; reps < 1 means 3) on a fixed input pattern written into
+ * the caller's workspace (at least abba_autotune_workspace bytes, 256-byte
+ * aligned), with HIP events on `stream`, and keeps the fastest (the built-in
+ * rules included) in the operator for that batch size; later calls with that
+ * batch size, abba_solve included, use it.  `best` (host) may be NULL.
+ * Synchronises `stream`; allocates no device memory.  An operator keeps 8
+ * batch sizes (the oldest is dropped); changing them while the operator runs
+ * is a race. */
+int abba_autotune(abba_op *op, int batch, int reps, void *workspace, size_t ws_bytes, void *stream,
+                  abba_tune *best);
 
 /* Sets the launch choices of `op` for `batch` (t NULL: forget them). */
 int abba_op_set_tuning(abba_op *op, int batch, const abba_tune *t);
@@ -306,7 +327,8 @@ int abba_solve_layout(const abba_op *A, const abba_op *B, int batch, int mode, i
  *           cycle; the learned rule, features and labels need unrestarted
  *           runs (ABBA_ERR_UNSUPPORTED).
  *   reg, stop, out, exec as above; `out.iters` and `out.status` are required.
- *   workspace, ws_bytes  device buffer of at least abba_solve_workspace bytes.
+ *   workspace, ws_bytes  device buffer of at least abba_solve_workspace bytes,
+ *           256-byte aligned.
  * The Arnoldi process uses classical Gram-Schmidt with one re-orthogonalisation
  * (CGS2, schedule exec.ortho) with FP64 accumulation; H_k, its SVD and lambda
  * are FP64.  A
@@ -343,13 +365,19 @@ int abba_solve(const abba_op *A, const abba_op *B, const void *b, void *x, int b
  * abba_solve. */
 int abba_mlp_forward(const float *params, const float *X, int n, float *Y, void *stream);
 
+/* Device bytes of per-tile partial gradients abba_mlp_loss_grad needs for n
+ * samples. */
+int abba_mlp_loss_grad_workspace(int n, size_t *bytes);
+
 /* Mean squared error L = (1/n) sum_i |net(X[r_i]) - T[r_i]|^2 with r_i =
  * idx[i] (device int32 [n], or NULL for r_i = i) and its gradient `grad`
  * [ABBA_MLP_PARAMS] (device); `loss` is a device double or NULL.  X is
  * [nrows][64], T [nrows][2]; rows r_i outside [0, nrows) count as absent.
- * Allocates per-tile partial gradients stream-ordered; deterministic. */
+ * workspace: device, at least abba_mlp_loss_grad_workspace(n) bytes (the
+ * per-tile partial gradients); the call allocates nothing.  Deterministic:
+ * the partials are summed in tile order. */
 int abba_mlp_loss_grad(const float *params, const float *X, const float *T, int nrows, const int *idx, int n,
-                       float *grad, double *loss, void *stream);
+                       float *grad, double *loss, void *workspace, size_t ws_bytes, void *stream);
 
 /* One Adam step (Kingma and Ba 2015, Algorithm 1, bias-corrected), step >= 1,
  * on params with moment buffers m, v (device, ABBA_MLP_PARAMS each). */

@@ -18,7 +18,8 @@ from dataclasses import dataclass
 
 __all__ = [
     "LIB_PATH", "lib", "AbbaError", "Geometry", "Operator", "project", "backproject", "solve",
-    "workspace_bytes", "solve_layout", "basis_views", "ST_KMAX", "ST_STOP_DP", "ST_STOP_RNS", "ST_BREAKDOWN", "ST_NONFINITE",
+    "workspace_bytes", "project_workspace_bytes", "backproject_workspace_bytes",
+    "mlp_loss_grad_workspace_bytes", "solve_layout", "basis_views", "ST_KMAX", "ST_STOP_DP", "ST_STOP_RNS", "ST_BREAKDOWN", "ST_NONFINITE",
     "ST_STOP_LEARNED", "ST_STOP_NCP", "autotune", "set_tuning", "get_tuning", "mlp_forward", "mlp_loss_grad", "mlp_adam", "mlp_labels", "MLP_PARAMS",
 ]
 
@@ -102,10 +103,19 @@ def _load():
     L.abba_op_destroy.restype = None
     L.abba_op_sizes.argtypes = [vp, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64)]
     L.abba_op_sizes.restype = i
-    L.abba_project.argtypes = [vp, vp, vp, i, vp]
+    sz, szp = ctypes.c_size_t, ctypes.POINTER(ctypes.c_size_t)
+    L.abba_project_workspace.argtypes = [vp, i, szp]
+    L.abba_project_workspace.restype = i
+    L.abba_backproject_workspace.argtypes = [vp, i, szp]
+    L.abba_backproject_workspace.restype = i
+    L.abba_project.argtypes = [vp, vp, vp, i, vp, sz, vp]
     L.abba_project.restype = i
-    L.abba_backproject.argtypes = [vp, vp, vp, i, vp]
+    L.abba_backproject.argtypes = [vp, vp, vp, i, vp, sz, vp]
     L.abba_backproject.restype = i
+    L.abba_autotune_workspace.argtypes = [vp, i, szp]
+    L.abba_autotune_workspace.restype = i
+    L.abba_mlp_loss_grad_workspace.argtypes = [i, szp]
+    L.abba_mlp_loss_grad_workspace.restype = i
     L.abba_solve_workspace.argtypes = [vp, vp, i, i, i, ctypes.POINTER(_Stop), ctypes.POINTER(_Exec),
                                        ctypes.POINTER(ctypes.c_size_t)]
     L.abba_solve_workspace.restype = i
@@ -115,7 +125,7 @@ def _load():
     L.abba_solve.argtypes = [vp, vp, vp, vp, i, i, i, ctypes.POINTER(_Reg), ctypes.POINTER(_Stop),
                              ctypes.POINTER(_Out), ctypes.POINTER(_Exec), vp, ctypes.c_size_t, vp]
     L.abba_solve.restype = i
-    L.abba_autotune.argtypes = [vp, i, i, vp, ctypes.POINTER(_Tune)]
+    L.abba_autotune.argtypes = [vp, i, i, vp, sz, vp, ctypes.POINTER(_Tune)]
     L.abba_autotune.restype = i
     L.abba_op_set_tuning.argtypes = [vp, i, ctypes.POINTER(_Tune)]
     L.abba_op_set_tuning.restype = i
@@ -123,7 +133,7 @@ def _load():
     L.abba_op_get_tuning.restype = i
     L.abba_mlp_forward.argtypes = [vp, vp, i, vp, vp]
     L.abba_mlp_forward.restype = i
-    L.abba_mlp_loss_grad.argtypes = [vp, vp, vp, i, vp, i, vp, vp, vp]
+    L.abba_mlp_loss_grad.argtypes = [vp, vp, vp, i, vp, i, vp, vp, vp, sz, vp]
     L.abba_mlp_loss_grad.restype = i
     L.abba_mlp_adam.argtypes = [vp, vp, vp, vp, i, ctypes.c_double, ctypes.c_double, ctypes.c_double,
                                 ctypes.c_double, vp]
@@ -144,6 +154,10 @@ abba_op_destroy = lib.abba_op_destroy
 abba_op_sizes = lib.abba_op_sizes
 abba_project = lib.abba_project
 abba_backproject = lib.abba_backproject
+abba_project_workspace = lib.abba_project_workspace
+abba_backproject_workspace = lib.abba_backproject_workspace
+abba_autotune_workspace = lib.abba_autotune_workspace
+abba_mlp_loss_grad_workspace = lib.abba_mlp_loss_grad_workspace
 abba_solve_workspace = lib.abba_solve_workspace
 abba_solve = lib.abba_solve
 abba_solve_layout = lib.abba_solve_layout
@@ -271,25 +285,61 @@ def _need_exact(t, dtype, numel, name):
         raise ValueError(f"{name} has {t.numel()} elements, expected {numel}")
 
 
-def project(A: Operator, x, out=None):
-    """y = A x (batched over leading dimensions)."""
+def _bytes(fn, *a) -> int:
+    nb = ctypes.c_size_t()
+    _check(fn(*a, ctypes.byref(nb)), fn.__name__)
+    return nb.value
+
+
+def project_workspace_bytes(A: Operator, batch: int) -> int:
+    """Device scratch bytes abba_project needs for `batch` slices."""
+    return _bytes(lib.abba_project_workspace, A.handle, int(batch))
+
+
+def backproject_workspace_bytes(B: Operator, batch: int) -> int:
+    """Device scratch bytes abba_backproject needs for `batch` slices."""
+    return _bytes(lib.abba_backproject_workspace, B.handle, int(batch))
+
+
+def _workspace(nbytes, workspace, device):
+    """The caller's workspace tensor (checked), or a new one from torch's
+    allocator when none is given; None when nothing is needed."""
+    import torch
+    if workspace is None:
+        return torch.empty(nbytes, dtype=torch.uint8, device=device) if nbytes else None
+    if not workspace.is_cuda or workspace.dtype != torch.uint8 or not workspace.is_contiguous():
+        raise ValueError("workspace must be a contiguous uint8 device tensor")
+    return workspace
+
+
+def _wsptr(ws):
+    return (None, 0) if ws is None else (_ptr(ws), ws.numel())
+
+
+def project(A: Operator, x, out=None, workspace=None):
+    """y = A x (batched over leading dimensions).  workspace: a uint8 device
+    tensor of at least project_workspace_bytes(A, batch) bytes, or None for
+    one from torch's allocator."""
     import torch
     batch = _need(x, A.img_dtype, A.n, "x")
     if out is None:
         out = torch.empty((batch, *A.geom.sino_shape), dtype=A.sino_dtype, device=x.device)
     _need_exact(out, A.sino_dtype, batch * A.m, "out")
-    _check(lib.abba_project(A.handle, _ptr(x), _ptr(out), batch, _stream_ptr()), "abba_project")
+    ws = _workspace(project_workspace_bytes(A, batch), workspace, x.device)
+    _check(lib.abba_project(A.handle, _ptr(x), _ptr(out), batch, *_wsptr(ws), _stream_ptr()), "abba_project")
     return out
 
 
-def backproject(B: Operator, y, out=None):
-    """x = B y (batched over leading dimensions)."""
+def backproject(B: Operator, y, out=None, workspace=None):
+    """x = B y (batched over leading dimensions); workspace as for project."""
     import torch
     batch = _need(y, B.sino_dtype, B.m, "y")
     if out is None:
         out = torch.empty((batch, *B.geom.image_shape), dtype=B.img_dtype, device=y.device)
     _need_exact(out, B.img_dtype, batch * B.n, "out")
-    _check(lib.abba_backproject(B.handle, _ptr(y), _ptr(out), batch, _stream_ptr()), "abba_backproject")
+    ws = _workspace(backproject_workspace_bytes(B, batch), workspace, y.device)
+    _check(lib.abba_backproject(B.handle, _ptr(y), _ptr(out), batch, *_wsptr(ws), _stream_ptr()),
+           "abba_backproject")
     return out
 
 
@@ -297,12 +347,16 @@ def _tune_dict(t):
     return dict(a_path=t.a_path, a_jb=t.a_jb, b_g=t.b_g, czt=t.czt, a_rb=t.a_rb, a_occ=t.a_occ)
 
 
-def autotune(op: Operator, batch: int, reps: int = 3):
+def autotune(op: Operator, batch: int, reps: int = 3, workspace=None):
     """Time the launch choices of `op` at `batch` and keep the fastest for that
     batch size (abba_autotune).  Returns the choice with its time and the
     built-in rules' time in ms."""
+    import torch
     t = _Tune()
-    _check(lib.abba_autotune(op.handle, int(batch), int(reps), _stream_ptr(), ctypes.byref(t)), "abba_autotune")
+    ws = _workspace(_bytes(lib.abba_autotune_workspace, op.handle, int(batch)), workspace,
+                    torch.device("cuda", torch.cuda.current_device()))
+    _check(lib.abba_autotune(op.handle, int(batch), int(reps), *_wsptr(ws), _stream_ptr(), ctypes.byref(t)),
+           "abba_autotune")
     return dict(_tune_dict(t), ms=t.ms, default_ms=t.default_ms, candidates=t.candidates)
 
 
@@ -469,7 +523,12 @@ def mlp_forward(params, X):
     return Y
 
 
-def mlp_loss_grad(params, X, T, idx=None, grad=None, loss=None):
+def mlp_loss_grad_workspace_bytes(n: int) -> int:
+    """Device bytes of per-tile partial gradients for n samples."""
+    return _bytes(lib.abba_mlp_loss_grad_workspace, int(n))
+
+
+def mlp_loss_grad(params, X, T, idx=None, grad=None, loss=None, workspace=None):
     """(loss, grad) of the mean squared error over rows idx of (X, T) (all rows if None)."""
     import torch
     nrows = _need(X, torch.float32, MLP_FEATURES, "X")
@@ -483,8 +542,9 @@ def mlp_loss_grad(params, X, T, idx=None, grad=None, loss=None):
     loss = torch.empty(1, dtype=torch.float64, device=X.device) if loss is None else loss
     _need_exact(grad, torch.float32, MLP_PARAMS, "grad")
     _need_exact(loss, torch.float64, 1, "loss")
+    ws = _workspace(mlp_loss_grad_workspace_bytes(n), workspace, X.device)
     _check(lib.abba_mlp_loss_grad(_ptr(params), _ptr(X), _ptr(T), nrows, None if idx is None else _ptr(idx), n,
-                                  _ptr(grad), _ptr(loss), _stream_ptr()), "abba_mlp_loss_grad")
+                                  _ptr(grad), _ptr(loss), *_wsptr(ws), _stream_ptr()), "abba_mlp_loss_grad")
     return loss, grad
 
 
@@ -525,6 +585,7 @@ def mlp_train(params, X, T, epochs, batch=4096, lr=1e-3, seed=0, log=None):
     grad = torch.empty_like(m)
     loss = torch.empty(1, dtype=torch.float64, device=X.device)
     rng = np.random.default_rng(seed)
+    ws = torch.empty(mlp_loss_grad_workspace_bytes(min(batch, nrows)), dtype=torch.uint8, device=X.device)
     step, hist = 0, []
     for ep in range(epochs):
         perm = torch.as_tensor(rng.permutation(nrows).astype(np.int32), device=X.device)
@@ -532,7 +593,7 @@ def mlp_train(params, X, T, epochs, batch=4096, lr=1e-3, seed=0, log=None):
         nb = 0
         for i0 in range(0, nrows, batch):
             idx = perm[i0:i0 + batch]
-            mlp_loss_grad(params, X, T, idx=idx, grad=grad, loss=loss)
+            mlp_loss_grad(params, X, T, idx=idx, grad=grad, loss=loss, workspace=ws)
             step += 1
             mlp_adam(params, grad, m, v, step, lr)
             tot += loss

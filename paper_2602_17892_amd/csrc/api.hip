@@ -288,9 +288,52 @@ int abba_op_sizes(const abba_op *op, int64_t *n_img, int64_t *n_sino) {
     return ABBA_OK;
 }
 
-int abba_project(const abba_op *A, const void *x, void *y, int batch, void *stream) {
-    if (A && batch == 0) return ABBA_OK;
-    if (!A || !x || !y || batch < 0) {
+// Device scratch of one apply: the zero-padded copies the forward projectors
+// read (2D: the image rows with pads, row-major and transposed; 3D: the
+// volume per dominant axis), the zero-padded views the voxel- and
+// pixel-driven backprojectors of the cone and fan geometries read, and none
+// for the 2D parallel-beam backprojectors (they stage in LDS).
+static size_t apply_scratch_bytes(const abba_op *op, int batch) {
+    if (op->kind == ABBA_OP_JOSEPH_T) return 0;
+    if (cone_path(op)) return cone_scratch_bytes(op, batch);
+    return op->kind == ABBA_OP_JOSEPH ? par2d_scratch_bytes(op, batch) : 0;
+}
+
+static int check_ws(const char *who, size_t need, const void *ws, size_t ws_bytes) {
+    if (need > 0 && (!ws || ws_bytes < need)) {
+        set_error("%s: workspace of %zu bytes%s is smaller than the %zu needed", who, ws_bytes,
+                  ws ? "" : " (NULL)", need);
+        return ABBA_ERR_ARG;
+    }
+    if (need > 0 && ((uintptr_t)ws & 255)) {
+        set_error("%s: the workspace must be 256-byte aligned", who);
+        return ABBA_ERR_ARG;
+    }
+    return ABBA_OK;
+}
+
+int abba_project_workspace(const abba_op *A, int batch, size_t *bytes) {
+    if (!A || !bytes || batch < 0 || A->kind != ABBA_OP_JOSEPH) {
+        set_error("abba_project_workspace: an ABBA_OP_JOSEPH operator, batch >= 0 and bytes are required");
+        return ABBA_ERR_ARG;
+    }
+    *bytes = batch ? apply_scratch_bytes(A, batch) : 0;
+    return ABBA_OK;
+}
+
+int abba_backproject_workspace(const abba_op *B, int batch, size_t *bytes) {
+    if (!B || !bytes || batch < 0 || (B->kind != ABBA_OP_PIXEL && B->kind != ABBA_OP_JOSEPH_T)) {
+        set_error("abba_backproject_workspace: an ABBA_OP_PIXEL or ABBA_OP_JOSEPH_T operator, batch >= 0 and "
+                  "bytes are required");
+        return ABBA_ERR_ARG;
+    }
+    *bytes = batch ? apply_scratch_bytes(B, batch) : 0;
+    return ABBA_OK;
+}
+
+int abba_project(const abba_op *A, const void *x, void *y, int batch, void *workspace, size_t ws_bytes,
+                 void *stream) {
+    if (!A || batch < 0 || (batch > 0 && (!x || !y))) {
         set_error("abba_project: NULL argument or negative batch");
         return ABBA_ERR_ARG;
     }
@@ -299,25 +342,18 @@ int abba_project(const abba_op *A, const void *x, void *y, int batch, void *stre
         return ABBA_ERR_ARG;
     }
     if (batch == 0) return ABBA_OK;
-    hipStream_t st = (hipStream_t)stream;
-    Launch L{st, nullptr, nullptr};
+    int rc = check_ws("abba_project", apply_scratch_bytes(A, batch), workspace, ws_bytes);
+    if (rc) return rc;
+    Launch L{(hipStream_t)stream, nullptr, nullptr};
     VecRef xr{const_cast<void *>(x), A->n, 0, 0};
     VecRef yr{y, A->m, 0, 0};
-    const bool cone = cone_path(A);
-    // the forward projector reads zero-padded copies of the image
-    void *scr = nullptr;
-    ABBA_HIP(hipMallocAsync(&scr, cone ? cone_scratch_bytes(A, batch) : par2d_scratch_bytes(A, batch), st));
-    int rc = cone ? cone_forward(A, xr, yr, A->sino_dtype, batch, scr, L)
-                  : par2d_forward(A, xr, yr, A->sino_dtype, batch, scr, L);
-    hipError_t e = hipFreeAsync(scr, st);
-    if (rc) return rc;
-    if (e != hipSuccess) return hip_fail(e, "hipFreeAsync");
-    return ABBA_OK;
+    return cone_path(A) ? cone_forward(A, xr, yr, A->sino_dtype, batch, workspace, L)
+                        : par2d_forward(A, xr, yr, A->sino_dtype, batch, workspace, L);
 }
 
-int abba_backproject(const abba_op *B, const void *y, void *x, int batch, void *stream) {
-    if (B && batch == 0) return ABBA_OK;
-    if (!B || !x || !y || batch < 0) {
+int abba_backproject(const abba_op *B, const void *y, void *x, int batch, void *workspace, size_t ws_bytes,
+                     void *stream) {
+    if (!B || batch < 0 || (batch > 0 && (!x || !y))) {
         set_error("abba_backproject: NULL argument or negative batch");
         return ABBA_ERR_ARG;
     }
@@ -326,23 +362,12 @@ int abba_backproject(const abba_op *B, const void *y, void *x, int batch, void *
         return ABBA_ERR_ARG;
     }
     if (batch == 0) return ABBA_OK;
-    hipStream_t st = (hipStream_t)stream;
-    Launch L{st, nullptr, nullptr};
+    int rc = check_ws("abba_backproject", apply_scratch_bytes(B, batch), workspace, ws_bytes);
+    if (rc) return rc;
+    Launch L{(hipStream_t)stream, nullptr, nullptr};
     VecRef yr{const_cast<void *>(y), B->m, 0, 0};
     VecRef xr{x, B->n, 0, 0};
-    if (B->kind == ABBA_OP_JOSEPH_T) return par2d_back(B, yr, B->sino_dtype, xr, batch, nullptr, L);
-    if (cone_path(B)) {
-        // the voxel-driven backprojector reads a zero-padded copy of the views
-        void *scr = nullptr;
-        ABBA_HIP(hipMallocAsync(&scr, cone_scratch_bytes(B, batch), st));
-        int rc = cone_back(B, yr, B->sino_dtype, xr, batch, scr, L);
-        hipError_t e = hipFreeAsync(scr, st);
-        if (rc) return rc;
-        if (e != hipSuccess) return hip_fail(e, "hipFreeAsync");
-        return ABBA_OK;
-    }
-    // the pixel-driven backprojector stages sinogram windows in LDS and needs
-    // no scratch in device memory
+    if (B->kind != ABBA_OP_JOSEPH_T && cone_path(B)) return cone_back(B, yr, B->sino_dtype, xr, batch, workspace, L);
     return par2d_back(B, yr, B->sino_dtype, xr, batch, nullptr, L);
 }
 
@@ -414,26 +439,58 @@ __global__ void tune_fill_k(float *p, int64_t n, int dt) {
     }
 }
 
-int abba_autotune(abba_op *op, int batch, int reps, void *stream, abba_tune *best) {
+// The autotuner's buffers: an input and an output of `batch` slices and the
+// scratch of one apply, each 256-byte aligned.
+static size_t tune_bytes(const abba_op *op, int batch, size_t *in_b, size_t *out_b) {
+    const bool fwd = op->kind == ABBA_OP_JOSEPH;
+    const int in_dt = fwd ? op->img_dtype : op->sino_dtype, out_dt = fwd ? op->sino_dtype : op->img_dtype;
+    auto al = [](size_t v) { return (v + 255) / 256 * 256; };
+    *in_b = al((size_t)batch * (fwd ? op->n : op->m) * dtype_size(in_dt));
+    *out_b = al((size_t)batch * (fwd ? op->m : op->n) * dtype_size(out_dt));
+    return *in_b + *out_b + al(apply_scratch_bytes(op, batch));
+}
+
+int abba_autotune_workspace(const abba_op *op, int batch, size_t *bytes) {
+    if (!op || !bytes || batch < 1) {
+        set_error("abba_autotune_workspace: operator and bytes are required, batch >= 1");
+        return ABBA_ERR_ARG;
+    }
+    size_t a, b;
+    *bytes = tune_bytes(op, batch, &a, &b);
+    return ABBA_OK;
+}
+
+int abba_autotune(abba_op *op, int batch, int reps, void *workspace, size_t ws_bytes, void *stream,
+                  abba_tune *best) {
+    if (!op || batch < 1) {
+        set_error("abba_autotune: NULL operator or batch < 1");
+        return ABBA_ERR_ARG;
+    }
+    size_t in_b = 0, out_b = 0;
+    const size_t need = tune_bytes(op, batch, &in_b, &out_b);
+    if (check_ws("abba_autotune", need, workspace, ws_bytes)) return ABBA_ERR_ARG;
+
     if (!op || batch < 1) {
         set_error("abba_autotune: NULL operator or batch < 1");
         return ABBA_ERR_ARG;
     }
     if (reps < 1) reps = 3;
     const bool fwd = op->kind == ABBA_OP_JOSEPH;
-    const int in_dt = fwd ? op->img_dtype : op->sino_dtype, out_dt = fwd ? op->sino_dtype : op->img_dtype;
-    const int64_t in_len = (int64_t)batch * (fwd ? op->n : op->m), out_len = (int64_t)batch * (fwd ? op->m : op->n);
+    const int in_dt = fwd ? op->img_dtype : op->sino_dtype;
+    const int64_t in_len = (int64_t)batch * (fwd ? op->n : op->m);
     TuneEntry cand[16];
     const int nc = cone_path(op) ? cone_tune_candidates(op, cand, 16)
                                                   : par2d_tune_candidates(op, cand, 16);
     hipStream_t st = (hipStream_t)stream;
-    void *in = nullptr, *out = nullptr;
+    void *in = workspace, *out = (char *)workspace + in_b, *scr = (char *)workspace + in_b + out_b;
+    const size_t scr_b = ws_bytes - in_b - out_b;
     hipEvent_t e0 = nullptr, e1 = nullptr;
     int rc = ABBA_OK;
     double best_ms = 1e300, def_ms = 0.0;
     TuneEntry win{batch, -1, 0, 0, 0, 0};
     auto run = [&]() {
-        return fwd ? abba_project(op, in, out, batch, stream) : abba_backproject(op, in, out, batch, stream);
+        return fwd ? abba_project(op, in, out, batch, scr, scr_b, stream)
+                   : abba_backproject(op, in, out, batch, scr, scr_b, stream);
     };
     auto timed = [&](const TuneEntry &t, double *ms) -> int {
         op->trial = t;
@@ -449,9 +506,7 @@ int abba_autotune(abba_op *op, int batch, int reps, void *stream, abba_tune *bes
         *ms = (double)f / reps;
         return r;
     };
-    hipError_t e = hipMalloc(&in, (size_t)in_len * dtype_size(in_dt));
-    if (e == hipSuccess) e = hipMalloc(&out, (size_t)out_len * dtype_size(out_dt));
-    if (e == hipSuccess) e = hipEventCreate(&e0);
+    hipError_t e = hipEventCreate(&e0);
     if (e == hipSuccess) e = hipEventCreate(&e1);
     if (e != hipSuccess) rc = hip_fail(e, "abba_autotune set-up");
     if (!rc) {
@@ -474,8 +529,6 @@ int abba_autotune(abba_op *op, int batch, int reps, void *stream, abba_tune *bes
     op->trial_on = 0;
     if (e0) (void)hipEventDestroy(e0);
     if (e1) (void)hipEventDestroy(e1);
-    if (in) (void)hipFree(in);
-    if (out) (void)hipFree(out);
     if (rc) return rc;
     store_tuning(op, win);
     if (best) {

@@ -609,30 +609,46 @@ extern "C" int abba_mlp_forward(const float *params, const float *X, int n, floa
     return launch_fwd(params, X, n, nullptr, n, Y, (hipStream_t)stream);
 }
 
+// Per-tile partial gradients and losses of abba_mlp_loss_grad for n samples.
+static size_t loss_grad_bytes(int n, size_t *pbytes) {
+    const int ntiles = (n + TILE - 1) / TILE;
+    *pbytes = ((size_t)ntiles * NPARAM * sizeof(float) + 255) / 256 * 256;
+    return *pbytes + (size_t)ntiles * sizeof(double);
+}
+
+extern "C" int abba_mlp_loss_grad_workspace(int n, size_t *bytes) {
+    if (n < 1 || !bytes) {
+        set_error("abba_mlp_loss_grad_workspace: n >= 1 and bytes are required");
+        return ABBA_ERR_ARG;
+    }
+    size_t p;
+    *bytes = loss_grad_bytes(n, &p);
+    return ABBA_OK;
+}
+
 extern "C" int abba_mlp_loss_grad(const float *params, const float *X, const float *T, int nrows, const int *idx,
-                                  int n, float *grad, double *loss, void *stream) {
+                                  int n, float *grad, double *loss, void *workspace, size_t ws_bytes,
+                                  void *stream) {
     if (!params || !X || !T || !grad || n < 1 || nrows < 1 || (!idx && n > nrows)) {
         set_error("abba_mlp_loss_grad: params, X, T, grad are required, n >= 1, and n <= nrows without idx");
+        return ABBA_ERR_ARG;
+    }
+    size_t pbytes;
+    const size_t need = loss_grad_bytes(n, &pbytes);
+    if (!workspace || ws_bytes < need) {
+        set_error("abba_mlp_loss_grad: workspace of %zu bytes is smaller than the %zu needed", ws_bytes, need);
         return ABBA_ERR_ARG;
     }
     int rc;
     if ((rc = set_lds_attrs())) return rc;
     hipStream_t st = (hipStream_t)stream;
     const int ntiles = (n + TILE - 1) / TILE;
-    void *buf = nullptr;
-    const size_t pbytes = (size_t)ntiles * NPARAM * sizeof(float);
-    ABBA_HIP(hipMallocAsync(&buf, pbytes + (size_t)ntiles * sizeof(double), st));
-    float *part = (float *)buf;
-    double *lpart = (double *)((char *)buf + pbytes);
+    float *part = (float *)workspace;
+    double *lpart = (double *)((char *)workspace + pbytes);
     hipLaunchKernelGGL(mlp_bwd_k, dim3(ntiles), dim3(NT), BWD_LDS, st, params, X, T, nrows, idx, n, part, lpart);
-    hipError_t e = hipGetLastError();
-    if (e == hipSuccess) {
-        hipLaunchKernelGGL(greduce_k, dim3((NPARAM + 255) / 256), dim3(256), 0, st, part, ntiles, lpart, grad, loss);
-        e = hipGetLastError();
-    }
-    hipError_t f = hipFreeAsync(buf, st);
-    if (e != hipSuccess) return hip_fail(e, "mlp_bwd_k / greduce_k");
-    if (f != hipSuccess) return hip_fail(f, "hipFreeAsync");
+    ABBA_LAUNCHED("mlp_bwd_k");
+    hipLaunchKernelGGL(greduce_k, dim3((NPARAM + 255) / 256), dim3(256), 0, st, part, ntiles, lpart, grad, loss);
+    ABBA_LAUNCHED("greduce_k");
     return ABBA_OK;
 }
 

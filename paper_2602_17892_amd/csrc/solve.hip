@@ -645,6 +645,10 @@ extern "C" int abba_solve(const abba_op *A, const abba_op *B, const void *b, voi
         set_error("workspace of %zu bytes is smaller than the %zu needed", ws_bytes, need);
         return ABBA_ERR_ARG;
     }
+    if ((uintptr_t)workspace & 255) {
+        set_error("the workspace must be 256-byte aligned");
+        return ABBA_ERR_ARG;
+    }
     hipStream_t st = (hipStream_t)stream;
     if ((rc = smallsolve_prepare())) return rc;
 

@@ -68,8 +68,15 @@ def test_validation_before_any_device_call():
     bad = pk.Geometry(8, 8, 12, 13, kind="cone3d", nz=8, det_v=9, sid=60.0, sdd=30.0)._c()[0]
     assert pk.lib.abba_op_create(ctypes.byref(h), 0, ctypes.byref(bad), 1, 1) == -1
     # NULL handles
-    assert pk.lib.abba_project(None, None, None, 1, None) == -1
-    assert pk.lib.abba_backproject(None, None, None, 1, None) == -1
+    nb0 = ctypes.c_size_t()
+    assert pk.lib.abba_project(None, None, None, 1, None, 0, None) == -1
+    assert pk.lib.abba_backproject(None, None, None, 1, None, 0, None) == -1
+    assert pk.lib.abba_project_workspace(None, 1, ctypes.byref(nb0)) == -1
+    assert pk.lib.abba_backproject_workspace(None, 1, ctypes.byref(nb0)) == -1
+    assert pk.lib.abba_autotune_workspace(None, 1, ctypes.byref(nb0)) == -1
+    assert pk.lib.abba_mlp_loss_grad_workspace(0, ctypes.byref(nb0)) == -1
+    assert pk.lib.abba_mlp_loss_grad_workspace(64, None) == -1
+    assert pk.lib.abba_mlp_loss_grad_workspace(64, ctypes.byref(nb0)) == 0 and nb0.value > 64 * 4
     nb = ctypes.c_size_t()
     assert pk.lib.abba_solve_workspace(None, None, 1, 0, 5, None, None, ctypes.byref(nb)) == -1
     lay = pk._Layout()
@@ -96,12 +103,12 @@ def test_validation_of_the_newer_entry_points():
     assert pk.lib.abba_mlp_forward(None, None, 5, None, None) == -1
     assert pk.lib.abba_mlp_forward(None, None, 0, None, None) == 0          # nothing to do
     assert pk.lib.abba_mlp_forward(None, None, -1, None, None) == -1
-    assert pk.lib.abba_mlp_loss_grad(None, None, None, 4, None, 4, None, None, None) == -1
+    assert pk.lib.abba_mlp_loss_grad(None, None, None, 4, None, 4, None, None, None, 0, None) == -1
     assert pk.lib.abba_mlp_adam(None, None, None, None, 1, 1e-3, 0.9, 0.999, 1e-8, None) == -1
     assert pk.lib.abba_mlp_labels(None, 1, 5, None, None, None, None) == -1
     # tuning
     t = pk._Tune()
-    assert pk.lib.abba_autotune(None, 4, 3, None, ctypes.byref(t)) == -1
+    assert pk.lib.abba_autotune(None, 4, 3, None, 0, None, ctypes.byref(t)) == -1
     assert pk.lib.abba_op_set_tuning(None, 4, ctypes.byref(t)) == -1
     assert pk.lib.abba_op_get_tuning(None, 4, ctypes.byref(t)) == -1
 
