@@ -13,11 +13,13 @@ Gate on x: 1e-4 relative, or 3x the FP32 floor where that is larger.  The
 FP32 floor is the oracle's own deviation when its projector outputs carry
 the GPU's error (each output rounded to FP32, and for the single slice also
 perturbed by the measured projector error 3e-6) at the same iteration count;
-every case prints its error and its floor.  lambda_k is judged by its GCV
-value on the oracle's projected problems; the stopping iteration must be the
-oracle's, or the oracle's data residual at the GPU's stop must lie within
-FP32 rounding of the threshold tau ||e|| (a tie that the storage precision
-decides).
+every case prints its error and its floor.  rho_k and lambda_k (judged by
+its GCV value on the oracle's projected problems) are gated at 3x the same
+emulated runs' deviations.  The stopping iteration must be the oracle's, or
+differ by one with the oracle's data residual at the earlier stop within
+1e-3 of the threshold tau ||e|| (the level at which FP32 residuals agree with
+the oracle's, 2.2e-4 measured over 100 iterations): a tie that the storage
+precision decides; x is then compared at the GPU's stop.
 """
 import numpy as np
 import pytest
@@ -89,20 +91,24 @@ def test_c2_full_100_iterations(pk, mode):
     rho = info["resid"][0].cpu().numpy()
     print(f"[C2 {mode}] GPU done, running the oracle", flush=True)
     o = osv.hybrid_gmres(og.A, og.B, bu, mode=mode, K=K, rule="gcv", keep_small=True)
-    floors = []
+    floors, frho, flam = [], [], []
     for d, seed in ((0.0, 0), (3e-6, 1)):
         Ap, Bp = perturbed_ops(og, d, seed)
-        floors.append(rel(osv.hybrid_gmres(Ap, Bp, bu, mode=mode, K=K, rule="gcv").x, o.x))
-    floor = max(floors)
+        emu = osv.hybrid_gmres(Ap, Bp, bu, mode=mode, K=K, rule="gcv")
+        floors.append(rel(emu.x, o.x))
+        frho.append(rel(emu.rho, o.rho))
+        flam.append(gcv_gap(emu.lam, o))
     ex = rel(xg, o.x)
     er = rel(rho, o.rho)
     gl = gcv_gap(lam, o)
-    gate = max(1e-4, 3.0 * floor)
+    gate = max(1e-4, 3.0 * max(floors))
+    grho = max(1e-4, 3.0 * max(frho))
+    glam = max(1e-6, 3.0 * max(flam))
     print(f"C2 {mode} GCV K={K}: x {ex:.2e} (gate {gate:.1e}; FP32 floor {floors[0]:.2e} rounding, "
-          f"{floors[1]:.2e} with projector error), rho {er:.2e}, GCV-value gap {gl:.1e}, "
-          f"RRE {rel(xg, xt):.4f} (oracle {rel(o.x, xt):.4f})")
+          f"{floors[1]:.2e} with projector error), rho {er:.2e} (gate {grho:.1e}), GCV-value gap {gl:.1e} "
+          f"(gate {glam:.1e}), RRE {rel(xg, xt):.4f} (oracle {rel(o.x, xt):.4f})")
     assert int(info["iters"][0]) == K == o.iters
-    assert ex <= gate and er <= gate and gl <= max(1e-6, 3.0 * floor)
+    assert ex <= gate and er <= grho and gl <= glam
 
 
 @pytest.mark.timeout(1200)
@@ -133,19 +139,26 @@ def test_benchmark_slices_to_their_dp_stop(pk):
         print(f"[slice {s}] GPU stop {it} (status {st}), running the oracle", flush=True)
         target = 1.01 * es
         o = osv.hybrid_gmres(og.A, og.B, bs, mode="AB", K=K, rule="gcv", stop="dp", tau=1.01, noise_norm=es)
+        k0 = min(it, o.iters)
+        # relative distance of the oracle's data residual from the threshold
+        # at the earlier of the two stops
+        margin = abs(o.rho[k0] / target - 1.0)
         if it == o.iters:
             floor = rel(osv.hybrid_gmres(Ap, Bp, bs, mode="AB", K=it, rule="gcv").x, o.x)
             ex = rel(xg, o.x)
             tie = False
         else:
-            # a stop decided by FP32 rounding: the oracle's residual at the
-            # GPU's stop is at the threshold; compare the iterates there
+            # a stop decided by FP32 rounding: at the earlier stop the
+            # oracle's residual lies within the FP32 residual agreement
+            # (measured <= 2.2e-4 at 100 iterations) of the threshold;
+            # compare the iterates at the GPU's stop
             oi = osv.hybrid_gmres(og.A, og.B, bs, mode="AB", K=it, rule="gcv")
-            tie = abs(oi.rho[-1] / target - 1.0) <= 1e-5 and abs(o.iters - it) == 1
+            tie = margin <= 1e-3 and abs(o.iters - it) == 1
             floor = rel(osv.hybrid_gmres(Ap, Bp, bs, mode="AB", K=it, rule="gcv").x, oi.x)
             ex = rel(xg, oi.x)
         gate = max(1e-4, 3.0 * floor)
         print(f"slice {s}: stop GPU {it} / oracle {o.iters}{' (tie at the threshold)' if tie else ''}, "
+              f"|rho_{k0} / (tau ||e||) - 1| = {margin:.1e}, "
               f"status {st} / {o.status}, x {ex:.2e} (gate {gate:.1e}, FP32 floor {floor:.2e}), "
               f"RRE {rel(xg, xt):.4f} (oracle {rel(o.x, xt):.4f})")
         assert it == o.iters or tie
