@@ -133,6 +133,20 @@ int abba_backproject_workspace(const abba_op *B, int batch, size_t *bytes);
 int abba_project(const abba_op *A, const void *x, void *y, int batch, void *workspace, size_t ws_bytes,
                  void *stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation): y = A x as
+ * abba_project computes it (the same kernels, the same result bits), with its
+ * scratch in a static device buffer of ABBA_NOALLOC_SCRATCH_BYTES that the
+ * library holds on each device it runs on until the process ends.  The call
+ * allocates nothing; the caller passes inputs and outputs.  A batch whose
+ * scratch (abba_project_workspace) exceeds the buffer is ABBA_ERR_ARG.  Every
+ * call on one device shares that device's buffer: calls that overlap on one
+ * device (on different streams, or from several threads) race and must be
+ * ordered by the caller.  Asynchronous on `stream`. */
+#define ABBA_NOALLOC_SCRATCH_BYTES (64u << 20)
+#define ABBA_MAX_DEVICES 64
+int abba_project_noalloc(const abba_op *A, const void *x, void *y, int batch, void *stream);
+
 /* x_s = B y_s for s < batch; `B` is ABBA_OP_PIXEL (unmatched B of
  * eqs. (4)-(5)) or ABBA_OP_JOSEPH_T (exact A^T).  y is [batch][m] in the
  * sinogram dtype, x [batch][n] in the image dtype.  workspace as for

@@ -18,7 +18,7 @@ from dataclasses import dataclass
 
 __all__ = [
     "LIB_PATH", "lib", "AbbaError", "Geometry", "Operator", "project", "backproject", "solve",
-    "workspace_bytes", "project_workspace_bytes", "backproject_workspace_bytes",
+    "workspace_bytes", "project_workspace_bytes", "backproject_workspace_bytes", "project_noalloc",
     "mlp_loss_grad_workspace_bytes", "solve_layout", "basis_views", "ST_KMAX", "ST_STOP_DP", "ST_STOP_RNS", "ST_BREAKDOWN", "ST_NONFINITE",
     "ST_STOP_LEARNED", "ST_STOP_NCP", "autotune", "set_tuning", "get_tuning", "mlp_forward", "mlp_loss_grad", "mlp_adam", "mlp_labels", "MLP_PARAMS",
 ]
@@ -112,6 +112,8 @@ def _load():
     L.abba_project.restype = i
     L.abba_backproject.argtypes = [vp, vp, vp, i, vp, sz, vp]
     L.abba_backproject.restype = i
+    L.abba_project_noalloc.argtypes = [vp, vp, vp, i, vp]
+    L.abba_project_noalloc.restype = i
     L.abba_autotune_workspace.argtypes = [vp, i, szp]
     L.abba_autotune_workspace.restype = i
     L.abba_mlp_loss_grad_workspace.argtypes = [i, szp]
@@ -154,6 +156,7 @@ abba_op_destroy = lib.abba_op_destroy
 abba_op_sizes = lib.abba_op_sizes
 abba_project = lib.abba_project
 abba_backproject = lib.abba_backproject
+abba_project_noalloc = lib.abba_project_noalloc
 abba_project_workspace = lib.abba_project_workspace
 abba_backproject_workspace = lib.abba_backproject_workspace
 abba_autotune_workspace = lib.abba_autotune_workspace
@@ -327,6 +330,20 @@ def project(A: Operator, x, out=None, workspace=None):
     _need_exact(out, A.sino_dtype, batch * A.m, "out")
     ws = _workspace(project_workspace_bytes(A, batch), workspace, x.device)
     _check(lib.abba_project(A.handle, _ptr(x), _ptr(out), batch, *_wsptr(ws), _stream_ptr()), "abba_project")
+    return out
+
+
+NOALLOC_SCRATCH_BYTES = 64 << 20
+
+
+def project_noalloc(A: Operator, x, out):
+    """y = A x through abba_project_noalloc: no workspace and no allocation in
+    the call (the caller passes `out`); its scratch is the library's static
+    device buffer of NOALLOC_SCRATCH_BYTES, shared by every such call on the
+    device."""
+    batch = _need(x, A.img_dtype, A.n, "x")
+    _need_exact(out, A.sino_dtype, batch * A.m, "out")
+    _check(lib.abba_project_noalloc(A.handle, _ptr(x), _ptr(out), batch, _stream_ptr()), "abba_project_noalloc")
     return out
 
 

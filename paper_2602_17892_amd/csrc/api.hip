@@ -4,6 +4,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 
 #include "ops.h"
@@ -369,6 +370,65 @@ int abba_backproject(const abba_op *B, const void *y, void *x, int batch, void *
     VecRef xr{x, B->n, 0, 0};
     if (B->kind != ABBA_OP_JOSEPH_T && cone_path(B)) return cone_back(B, yr, B->sino_dtype, xr, batch, workspace, L);
     return par2d_back(B, yr, B->sino_dtype, xr, batch, nullptr, L);
+}
+
+// ------------------------------------------- allocation-free projection ---
+// abba_project_noalloc keeps the scratch of abba_project (the padded image
+// copies, which the padding kernel writes in full, pads included, before the
+// projector reads them, so nothing needs clearing) in this file-scope device
+// array instead of a caller workspace.  In host code the name `scratch` is a
+// host-side stand-in, never a device address: each device's copy is located
+// once with hipGetSymbolAddress and only that pointer is used.
+static __device__ __align__(256) unsigned char scratch[ABBA_NOALLOC_SCRATCH_BYTES];
+
+static std::mutex g_scratch_mu;
+static void *g_scratch_dev[ABBA_MAX_DEVICES];   // the array's address on each device
+
+// The address of `scratch` on the current device (looked up on the first
+// call on that device, with that device current).
+static int noalloc_scratch(void **out) {
+    int dev = -1;
+    ABBA_HIP(hipGetDevice(&dev));
+    if (dev < 0 || dev >= ABBA_MAX_DEVICES) {
+        set_error("device %d is beyond the %d devices this library tracks", dev, ABBA_MAX_DEVICES);
+        return ABBA_ERR_UNSUPPORTED;
+    }
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_dev[dev]) {
+        void *p = nullptr;
+        hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return hip_fail(e, "hipGetSymbolAddress(scratch)");
+        if (!p) {
+            set_error("hipGetSymbolAddress(scratch) returned a null address");
+            return ABBA_ERR_HIP;
+        }
+        g_scratch_dev[dev] = p;
+    }
+    *out = g_scratch_dev[dev];
+    return ABBA_OK;
+}
+
+int abba_project_noalloc(const abba_op *A, const void *x, void *y, int batch, void *stream) {
+    if (!A || batch < 0 || (batch > 0 && (!x || !y))) {
+        set_error("abba_project_noalloc: NULL argument or negative batch");
+        return ABBA_ERR_ARG;
+    }
+    if (A->kind != ABBA_OP_JOSEPH) {
+        set_error("abba_project_noalloc needs an ABBA_OP_JOSEPH operator");
+        return ABBA_ERR_ARG;
+    }
+    if (batch == 0) return ABBA_OK;
+    const size_t need = apply_scratch_bytes(A, batch);
+    if (need > (size_t)ABBA_NOALLOC_SCRATCH_BYTES) {
+        set_error("abba_project_noalloc: %d slices need %zu bytes of scratch, beyond its %zu-byte static buffer "
+                  "(use abba_project with a workspace, or fewer slices per call)",
+                  batch, need, (size_t)ABBA_NOALLOC_SCRATCH_BYTES);
+        return ABBA_ERR_ARG;
+    }
+    void *scr = nullptr;
+    int rc = noalloc_scratch(&scr);
+    if (rc) return rc;
+    return abba_project(A, x, y, batch, scr, ABBA_NOALLOC_SCRATCH_BYTES, stream);
 }
 
 // ------------------------------------------------------------ tuning ------
