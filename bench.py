@@ -68,6 +68,8 @@ def parse():
     p.add_argument("--plain-slices", type=int, default=8)
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--roofline-reps", type=int, default=10)
+    p.add_argument("--counter-k", type=int, default=20,
+                   help="iterations of the short solve of --projectors-only")
     p.add_argument("--projectors-only", action="store_true",
                    help="only the projector launches (random images) and a copy of known size, for counter runs")
     p.add_argument("--workload", choices=["slices", "cone", "learned", "variants"], default="slices",
@@ -223,34 +225,68 @@ def recorded_traffic(kernel):
 
 
 def projectors_only(args):
-    """Projector launches at the benchmark's batch shape on seeded random
-    images, then device copies of a known size (the counter calibration)."""
+    """The kernels whose counters the profiles record, at the benchmark's batch
+    shape: the projectors on seeded random images (and, with --workload cone,
+    the cone-beam pair at its shape instead), a short batched solve whose
+    Gram-Schmidt sweeps run eagerly (--counter-k iterations, no stop), then
+    device copies of a known size (the counter calibration).  Prints the
+    algorithmic bytes each kernel family moves."""
     import torch
 
     import paper_2602_17892_amd as pk
     torch.cuda.set_device(0)
-    S = args.slices
-    g = pk.Geometry(args.n, args.n, args.angles, args.det)
-    A = pk.Operator("joseph", g, "f32", "f32")
-    B = pk.Operator("pixel", g, "f32", "f32")
-    pk.autotune(A, S)
-    pk.autotune(B, S)
+    reps = 3
     gen = torch.Generator(device="cuda")
     gen.manual_seed(2)
-    x = torch.rand((S, args.n, args.n), generator=gen, device="cuda")
-    y = torch.empty((S, args.angles, args.det), device="cuda")
-    xo = torch.empty_like(x)
-    reps = 3
-    wsa = torch.empty(pk.project_workspace_bytes(A, S), dtype=torch.uint8, device="cuda")
-    for _ in range(reps):
-        pk.project(A, x, out=y, workspace=wsa)
-    for _ in range(reps):
-        pk.backproject(B, y, out=xo)
+    info = {"projectors_only": True, "reps": reps, "source_digest": kernel_source_digest()}
+    if args.workload == "cone":
+        C = CONE
+        n = C["n"]
+        g = pk.Geometry(n, n, C["views"], C["nu"], det_pitch_u=C["pitch"], kind="cone3d", nz=n, det_v=C["nv"],
+                        det_pitch_v=C["pitch"], sid=C["sid"], sdd=C["sdd"])
+        A = pk.Operator("joseph", g, "f32", "bf16")
+        B = pk.Operator("pixel", g, "f32", "bf16")
+        pk.autotune(A, 1)
+        pk.autotune(B, 1)
+        x = torch.rand((1, n, n, n), generator=gen, device="cuda")
+        y = torch.empty((1, C["views"], C["nv"], C["nu"]), dtype=torch.bfloat16, device="cuda")
+        xo = torch.empty_like(x)
+        wsa = torch.empty(pk.project_workspace_bytes(A, 1), dtype=torch.uint8, device="cuda")
+        wsb = torch.empty(pk.backproject_workspace_bytes(B, 1), dtype=torch.uint8, device="cuda")
+        for _ in range(reps):
+            pk.project(A, x, out=y, workspace=wsa)
+        for _ in range(reps):
+            pk.backproject(B, y, out=xo, workspace=wsb)
+        info.update(workload="cone", algorithmic_bytes_per_apply=n ** 3 * 4 + C["views"] * C["nu"] * C["nv"] * 2)
+    else:
+        S = args.slices
+        g = pk.Geometry(args.n, args.n, args.angles, args.det)
+        A = pk.Operator("joseph", g, "f32", "f32")
+        B = pk.Operator("pixel", g, "f32", "f32")
+        pk.autotune(A, S)
+        pk.autotune(B, S)
+        x = torch.rand((S, args.n, args.n), generator=gen, device="cuda")
+        y = torch.empty((S, args.angles, args.det), device="cuda")
+        xo = torch.empty_like(x)
+        wsa = torch.empty(pk.project_workspace_bytes(A, S), dtype=torch.uint8, device="cuda")
+        for _ in range(reps):
+            pk.project(A, x, out=y, workspace=wsa)
+        for _ in range(reps):
+            pk.backproject(B, y, out=xo)
+        del wsa
+        K = args.counter_k
+        ws = torch.empty(pk.workspace_bytes(A, B, S, "AB", K), dtype=torch.uint8, device="cuda")
+        pk.solve(A, B, y, mode="AB", k=K, reg="gcv", history=False, workspace=ws)
+        del ws
+        m = args.angles * args.det
+        info.update(workload="slices", slices=S, solve_k=K,
+                    algorithmic_bytes_per_apply=S * (args.n * args.n + m) * 4,
+                    dcgs2_algorithmic_bytes=dcgs2_bytes([K] * S, m))
     for _ in range(reps):
         xo.copy_(x)
     torch.cuda.synchronize()
-    print(json.dumps({"projectors_only": True, "slices": S, "reps": reps,
-                      "copy_bytes_each_way": x.numel() * 4, "source_digest": kernel_source_digest()}), flush=True)
+    info["copy_bytes_each_way"] = x.numel() * 4
+    print(json.dumps(info), flush=True)
 
 
 def cpu_model():
