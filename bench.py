@@ -80,6 +80,9 @@ def parse():
     p.add_argument("--train-runs", type=int, default=4096)
     p.add_argument("--eval-slices", type=int, default=1024)
     p.add_argument("--epochs", type=int, default=20)
+    p.add_argument("--learned-variants", default="0.05:0",
+                   help="learned-rule variants delta:c to evaluate (judge margin delta, discrepancy gate c of the "
+                        "stop; comma list, the first is reported)")
     p.add_argument("--no-learned", action="store_true",
                    help="leave out the learned-rule comparison of the default run")
     p.add_argument("--quiet", action="store_true")
@@ -457,7 +460,7 @@ def cone_workload(args):
     A32 = pk.Operator("joseph", g, "f32", "f32")
     tune = {"A": pk.autotune(A, 1), "B": pk.autotune(B, 1)}
     log(args, "autotune: " + "; ".join(f"{k} {v['ms']:.2f} ms (built-in {v['default_ms']:.2f}), choice "
-                                       f"{ {c: v[c] for c in ('czt', 'a_rb', 'a_occ')} }" for k, v in tune.items()))
+                                       f"{ {c: v[c] for c in ('czt', 'a_rb', 'a_occ', 'a_tile')} }" for k, v in tune.items()))
     t0 = time.perf_counter()
     vol, _ = synth.phantom3d(4, 0, n, device=torch.device("cuda"))
     xt = vol.to(torch.float32).reshape(1, n, n, n).contiguous()
@@ -511,7 +514,7 @@ def cone_workload(args):
         "config": {"workload": f"{n}^3 cone beam, {C['views']} views x {C['nv']}x{C['nu']} detector at pitch "
                                f"{C['pitch']}, SID {C['sid']:g}, SDD {C['sdd']:g}, hybrid BA-GMRES GCV, k {K}"},
         "rre": rre,
-        "autotune": {k: {"choice": {c: v[c] for c in ("czt", "a_rb", "a_occ")}, "ms": round(v["ms"], 3),
+        "autotune": {k: {"choice": {c: v[c] for c in ("czt", "a_rb", "a_occ", "a_tile")}, "ms": round(v["ms"], 3),
                          "builtin_ms": round(v["default_ms"], 3)} for k, v in tune.items()},
         "projector": {"A_ms": round(t_A * 1e3, 3), "B_ms": round(t_B * 1e3, 3), "A_TFLOPs": round(tf_A, 3),
                       "B_TFLOPs": round(tf_B, 3), "A_plane_crossings": steps, "B_voxel_view_pairs": pairs,
@@ -582,14 +585,24 @@ def learned_run(args):
     ge = pk.Geometry(512, 512, 720, 725)
     A, B = pk.Operator("joseph", ge, "f32", "f32"), pk.Operator("pixel", ge, "f32", "f32")
     ws = torch.empty(pk.workspace_bytes(A, B, SB, "AB", K, stop="dp"), dtype=torch.uint8, device="cuda")
-    res = {"gcv": dict(t=0.0, iters=[], rre=[]), "learned": dict(t=0.0, iters=[], rre=[]), "eta": []}
+    # the learned rule with each (judge margin delta, discrepancy gate c):
+    # lambda^ replaces GCV's lambda when GCV(lambda^) <= (1 + delta) min GCV;
+    # the stop index is accepted once rho_k <= c tau ||e|| (c = 0: no gate);
+    # the first variant is the reported one
+    variants = [tuple(float(v) for v in item.split(":")) for item in str(args.learned_variants).split(",")]
+    names = ["gcv"] + [f"learned@{d:g}:{c:g}" for d, c in variants]
+    res = {name: dict(t=0.0, iters=[], rre=[]) for name in names}
+    res["eta"] = []
     for first in range(0, args.eval_slices, SB):
         cnt = min(SB, args.eval_slices - first)
         x, b, en, eta = synth_batch(pk, A, torch, 6, first, cnt, 512, 1e-3, 5e-2)
         res["eta"].append(eta)
-        for name in ("gcv", "learned"):
-            kw = dict(reg="gcv", stop="dp") if name == "gcv" else dict(reg="learned", stop="learned", mlp=theta,
-                                                                      judge_delta=0.05)
+        for name in names:
+            if name == "gcv":
+                kw = dict(reg="gcv", stop="dp")
+            else:
+                dv, cv = (float(v) for v in name.split("@")[1].split(":"))
+                kw = dict(reg="learned", stop="learned", mlp=theta, judge_delta=dv, learned_gate=cv)
             pk.solve(A, B, b[:1].contiguous(), mode="AB", k=2, noise_norm=en[:1], history=False, **kw)
             torch.cuda.synchronize()
             t0 = time.perf_counter()
@@ -602,17 +615,26 @@ def learned_run(args):
                                      / torch.linalg.vector_norm(x.reshape(cnt, -1).double(), dim=1)).cpu().numpy())
         del x, b, en
     res["eta"] = np.concatenate(res["eta"])
-    for name in ("gcv", "learned"):
+    for name in names:
         res[name]["iters"] = np.concatenate(res[name]["iters"])
         res[name]["rre"] = np.concatenate(res[name]["rre"])
     E = args.eval_slices
+    for name in names:
+        r = res[name]
+        extra = ""
+        if name != "gcv":
+            rt = r["rre"] / res["gcv"]["rre"]
+            extra = (f", RRE <= 1.02 x GCV+DP on {np.mean(rt <= 1.02) * 100:.1f}% of slices (worst "
+                     f"{rt.max():.3f})")
+        log(args, f"{name}: {E / r['t']:.2f} slices/s, iters mean {r['iters'].mean():.1f}, "
+                  f"median RRE {np.median(r['rre']):.4f}{extra}")
+    sweep = {name: {"slices_per_s": round(E / res[name]["t"], 3), "iters_mean": float(res[name]["iters"].mean()),
+                    "frac_within_2pct": float(np.mean(res[name]["rre"] / res["gcv"]["rre"] <= 1.02)),
+                    "ratio_max": float((res[name]["rre"] / res["gcv"]["rre"]).max())}
+             for name in names[1:]}
+    res["learned"] = res[names[1]]
     ratio = res["learned"]["rre"] / res["gcv"]["rre"]
     miss = ratio > 1.02
-    for name in ("gcv", "learned"):
-        r = res[name]
-        log(args, f"{name}: {E / r['t']:.2f} slices/s, iters mean {r['iters'].mean():.1f}, "
-                  f"median RRE {np.median(r['rre']):.4f}")
-    log(args, f"learned RRE <= 1.02 x GCV+DP RRE on {np.mean(ratio <= 1.02) * 100:.1f}% of slices")
     out = {
         "metric": "reconstructed slices/sec with the learned lambda and stop index vs GCV + DP",
         "value": round(E / res["learned"]["t"], 3),
@@ -637,9 +659,12 @@ def learned_run(args):
                     "rre_ratio_median": float(np.median(ratio)),
                     "rre_ratio_p95": float(np.percentile(ratio, 95)),
                     "rre_ratio_max": float(ratio.max()),
+                    "variant_sweep": sweep if len(variants) > 1 else None,
                     "misses": int(miss.sum()),
                     "miss_eta": [float(e) for e in np.sort(res["eta"][miss])[:64]]},
         "speedup_learned_vs_gcv_dp": round(res["gcv"]["t"] / res["learned"]["t"], 3),
+        "judge_delta": variants[0][0],
+        "learned_gate": variants[0][1],
         "training": {"runs": args.train_runs, "samples": int(X.shape[0]), "epochs": args.epochs,
                      "loss_start": float(l0), "loss_end": hist[-1], "data_s": round(t_gen, 2),
                      "train_s": round(t_train, 2), "k_star_mean": float(kst.mean())},
@@ -902,7 +927,8 @@ def main():
         del ws
         torch.cuda.empty_cache()
         lr = learned_run(args)
-        out["learned"] = {k: lr[k] for k in ("config", "gcv_dp", "learned", "speedup_learned_vs_gcv_dp", "training")}
+        out["learned"] = {k: lr[k] for k in ("config", "gcv_dp", "learned", "speedup_learned_vs_gcv_dp",
+                                             "judge_delta", "learned_gate", "training")}
         out["learned"]["speedup_learned_vs_plain"] = round(lr["learned"]["slices_per_s"] * t_plain, 3)
     if not args.no_cpu_baseline:
         s0 = int(np.argsort(iters)[len(iters) // 2])

@@ -172,6 +172,8 @@ typedef struct {
     double ms;         /* abba_autotune: mean time of one apply with the chosen launch       */
     double default_ms; /* abba_autotune: the same with the built-in rules                    */
     int candidates;    /* abba_autotune: launch choices timed besides the built-in rules     */
+    int a_tile;        /* 3D A: 0 a workgroup per 256 columns of one detector row (built-in),
+                          16 a workgroup per 16 x 16 tile of detector pixels                */
 } abba_tune;
 
 /* Device bytes abba_autotune needs for `batch` slices: an input and an output
@@ -237,6 +239,9 @@ typedef struct {
     double tau;                /* DP safety factor                                         */
     double rns_eps;            /* RNS tolerance                                            */
     const double *noise_norm;  /* device [batch]: ||e|| per slice (DP)                      */
+    double learned_gate;       /* ABBA_STOP_LEARNED with noise_norm: the learned stop fires
+                                  only once rho_k <= learned_gate * tau * ||e|| as well
+                                  (<= 0: no such condition)                                 */
 } abba_stop;
 
 typedef struct {
@@ -310,11 +315,14 @@ int abba_solve_workspace(const abba_op *A, const abba_op *B, int batch, int mode
  *   H      FP64 [batch][k][k+1] at byte offset hessenberg, column-major per
  *          slice: entry (i, j) of H_k at ((s k + j)(k + 1) + i) * 8; columns
  *          j < k_s are those of H_{k_s}, rows past j + 1 are not defined.
- * Both offsets are within the workspace of abba_solve_workspace bytes. */
+ *   sigma  FP64 [batch][k] at byte offset singular_values: the singular
+ *          values of H_{k_s} in descending order (k_s entries of slice s).
+ * All offsets are within the workspace of abba_solve_workspace bytes. */
 typedef struct {
     size_t bytes;              /* workspace size (as abba_solve_workspace)           */
     size_t basis;              /* byte offset of the basis                           */
     size_t hessenberg;         /* byte offset of H                                   */
+    size_t singular_values;    /* byte offset of sigma                               */
     int64_t ldw;               /* elements between consecutive basis vectors         */
     int64_t len;               /* basis vector length: m (AB) or n (BA)              */
     int basis_dtype;           /* abba_dtype of the basis                            */
@@ -370,7 +378,9 @@ int abba_solve(const abba_op *A, const abba_op *B, const void *b, void *x, int b
  * lambda (eq. (15)); the predicted lambda^ replaces it when
  * GCV(lambda^) <= (1 + judge_delta) GCV(lambda_GCV).  ABBA_STOP_LEARNED stops
  * at the first k >= K o1 (clamped to [1, K]), after the discrepancy principle
- * when noise_norm is given.  All four calls are asynchronous on `stream`. */
+ * when noise_norm is given, and then, with stop.learned_gate = c > 0, only
+ * once the data residual is within the factor c of the discrepancy level
+ * (rho_k <= c tau ||e||).  All four calls are asynchronous on `stream`. */
 #define ABBA_MLP_FEATURES 64
 #define ABBA_MLP_PARAMS 41602
 #define ABBA_LABEL_GRID 64

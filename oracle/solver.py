@@ -113,7 +113,7 @@ def hybrid_gmres(A, B, b, mode: str = "AB", K: int = 30, rule: str = "gcv",
                  noise_norm: float | None = None, rns_eps: float = 1e-3,
                  x0=None, ortho: str = "cgs2", keep_x: bool = False,
                  keep_basis: bool = False, keep_small: bool = False, mlp=None,
-                 judge_delta: float = 0.05, det: int | None = None) -> Result:
+                 judge_delta: float = 0.05, det: int | None = None, learned_gate: float = 0.0) -> Result:
     """Run hybrid AB- or BA-GMRES for at most K iterations.
 
     A, B     -- callables on flat FP64 vectors (R^n -> R^m and R^m -> R^n)
@@ -123,7 +123,9 @@ def hybrid_gmres(A, B, b, mode: str = "AB", K: int = 30, rule: str = "gcv",
     stop     -- None (run K iterations), "dp", "rns", "ncp" (the residual,
                 read as rows of `det` bins, passes the NCP white-noise test)
                 or "learned" (the network's stop index, with the discrepancy
-                principle first when noise_norm is given)
+                principle first when noise_norm is given; with learned_gate
+                c > 0 and noise_norm the stop index is accepted only once the
+                data residual is within the factor c of tau ||e||)
     """
     b = np.asarray(b, dtype=np.float64).reshape(-1)
     if x0 is None:
@@ -269,7 +271,8 @@ def hybrid_gmres(A, B, b, mode: str = "AB", K: int = 30, rule: str = "gcv",
             if ncp_white(rk, det):
                 status = STATUS_STOP_NCP
                 break
-        if stop == "learned" and k >= k_hat:
+        if stop == "learned" and k >= k_hat and (learned_gate <= 0 or target is None
+                                                 or rho <= learned_gate * target):
             status = STATUS_STOP_LEARNED
             break
     out.x = x

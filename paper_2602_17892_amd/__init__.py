@@ -58,7 +58,7 @@ class _Reg(ctypes.Structure):
 
 class _Stop(ctypes.Structure):
     _fields_ = [("kind", ctypes.c_int), ("tau", ctypes.c_double), ("rns_eps", ctypes.c_double),
-                ("noise_norm", ctypes.c_void_p)]
+                ("noise_norm", ctypes.c_void_p), ("learned_gate", ctypes.c_double)]
 
 
 class _Out(ctypes.Structure):
@@ -70,12 +70,12 @@ class _Out(ctypes.Structure):
 class _Tune(ctypes.Structure):
     _fields_ = [("a_path", ctypes.c_int), ("a_jb", ctypes.c_int), ("b_g", ctypes.c_int), ("czt", ctypes.c_int),
                 ("a_rb", ctypes.c_int), ("a_occ", ctypes.c_int), ("ms", ctypes.c_double), ("default_ms", ctypes.c_double),
-                ("candidates", ctypes.c_int)]
+                ("candidates", ctypes.c_int), ("a_tile", ctypes.c_int)]
 
 
 class _Layout(ctypes.Structure):
     _fields_ = [("bytes", ctypes.c_size_t), ("basis", ctypes.c_size_t), ("hessenberg", ctypes.c_size_t),
-                ("ldw", ctypes.c_int64), ("len", ctypes.c_int64), ("basis_dtype", ctypes.c_int),
+                ("singular_values", ctypes.c_size_t), ("ldw", ctypes.c_int64), ("len", ctypes.c_int64), ("basis_dtype", ctypes.c_int),
                 ("basis_slots", ctypes.c_int), ("k", ctypes.c_int)]
 
 
@@ -361,7 +361,7 @@ def backproject(B: Operator, y, out=None, workspace=None):
 
 
 def _tune_dict(t):
-    return dict(a_path=t.a_path, a_jb=t.a_jb, b_g=t.b_g, czt=t.czt, a_rb=t.a_rb, a_occ=t.a_occ)
+    return dict(a_path=t.a_path, a_jb=t.a_jb, b_g=t.b_g, czt=t.czt, a_rb=t.a_rb, a_occ=t.a_occ, a_tile=t.a_tile)
 
 
 def autotune(op: Operator, batch: int, reps: int = 3, workspace=None):
@@ -377,12 +377,12 @@ def autotune(op: Operator, batch: int, reps: int = 3, workspace=None):
     return dict(_tune_dict(t), ms=t.ms, default_ms=t.default_ms, candidates=t.candidates)
 
 
-def set_tuning(op: Operator, batch: int, a_path=-1, a_jb=0, b_g=0, czt=0, a_rb=0, a_occ=0, clear=False):
+def set_tuning(op: Operator, batch: int, a_path=-1, a_jb=0, b_g=0, czt=0, a_rb=0, a_occ=0, a_tile=0, clear=False):
     """Fix the launch choices of `op` for `batch` (clear=True forgets them)."""
     if clear:
         _check(lib.abba_op_set_tuning(op.handle, int(batch), None), "abba_op_set_tuning")
         return
-    t = _Tune(a_path, a_jb, b_g, czt, a_rb, a_occ, 0.0, 0.0, 0)
+    t = _Tune(a_path, a_jb, b_g, czt, a_rb, a_occ, 0.0, 0.0, 0, a_tile)
     _check(lib.abba_op_set_tuning(op.handle, int(batch), ctypes.byref(t)), "abba_op_set_tuning")
 
 
@@ -399,7 +399,7 @@ ORTHO = {"dcgs2": 0, "cgs2": 1}
 
 
 def _structs(reg, lam, tau, noise_norm, mlp, judge_delta, stop, stop_tau, rns_eps, use_graph, poll_every,
-             restart, features, ortho="dcgs2"):
+             restart, features, ortho="dcgs2", learned_gate=0.0):
     r = _Reg()
     r.kind = REG[reg]
     r.lam = float(lam)
@@ -412,6 +412,7 @@ def _structs(reg, lam, tau, noise_norm, mlp, judge_delta, stop, stop_tau, rns_ep
     s.tau = float(stop_tau)
     s.rns_eps = float(rns_eps)
     s.noise_norm = None if noise_norm is None else noise_norm.data_ptr()
+    s.learned_gate = float(learned_gate)
     e = _Exec()
     e.use_graph = int(bool(use_graph))
     e.poll_every = int(poll_every)
@@ -438,13 +439,15 @@ def solve_layout(A: Operator, B: Operator, batch: int, mode: str, k: int, stop=N
     L = _Layout()
     _check(lib.abba_solve_layout(A.handle, B.handle, batch, MODE_AB if mode == "AB" else MODE_BA, k,
                                  ctypes.byref(s), ctypes.byref(e), ctypes.byref(L)), "abba_solve_layout")
-    return dict(bytes=L.bytes, basis=L.basis, hessenberg=L.hessenberg, ldw=L.ldw, len=L.len,
+    return dict(bytes=L.bytes, basis=L.basis, hessenberg=L.hessenberg, singular_values=L.singular_values,
+                ldw=L.ldw, len=L.len,
                 basis_dtype=L.basis_dtype, basis_slots=L.basis_slots, k=L.k)
 
 
-def basis_views(workspace, layout: dict, batch: int):
+def basis_views(workspace, layout: dict, batch: int, sigma: bool = False):
     """(W, H) views into a solve's workspace tensor: W [batch, slots, ldw] in the
-    basis dtype, H [batch, k, k+1] float64 (column j of H_k is H[s, j])."""
+    basis dtype, H [batch, k, k+1] float64 (column j of H_k is H[s, j]); with
+    sigma, also the singular values of H_k, float64 [batch, k], descending."""
     import torch
     dt = _torch_dtype(layout["basis_dtype"])
     esz = torch.empty((), dtype=dt).element_size()
@@ -454,13 +457,18 @@ def basis_views(workspace, layout: dict, batch: int):
     k = layout["k"]
     nH = batch * k * (k + 1)
     H = workspace[layout["hessenberg"]:layout["hessenberg"] + nH * 8].view(torch.float64).view(batch, k, k + 1)
-    return W, H
+    if not sigma:
+        return W, H
+    o = layout["singular_values"]
+    sv = workspace[o:o + batch * k * 8].view(torch.float64).view(batch, k)
+    return W, H, sv
 
 
 def solve(A: Operator, B: Operator, b, mode: str = "AB", k: int = 30, reg: str = "gcv", lam: float = 0.0,
           tau: float = 1.01, noise_norm=None, stop=None, rns_eps: float = 1e-3, x0=None, use_graph=False,
           poll_every: int = 1, restart: int = 0, mlp=None, judge_delta: float = 0.05, history: bool = True,
-          workspace=None, features: bool = False, ortho: str = "dcgs2", x_true=None, phases: bool = False):
+          workspace=None, features: bool = False, ortho: str = "dcgs2", x_true=None, phases: bool = False,
+          learned_gate: float = 0.0):
     """Hybrid AB-/BA-GMRES on a batch of slices; returns (x, info).
 
     ortho: "dcgs2" (CGS2 with the second pass delayed to the next step's
@@ -472,7 +480,8 @@ def solve(A: Operator, B: Operator, b, mode: str = "AB", k: int = 30, reg: str =
     history, lam [batch, k] and resid [batch, k+1].  features=True adds the
     learned-rule features [batch, k, 64] (float32); x_true (device, image
     dtype, AB mode) adds the RRE label grid rre [batch, k, 64].  mlp: device
-    float32 [MLP_PARAMS] for reg="learned".  phases=True times the phases of
+    float32 [MLP_PARAMS] for reg="learned".  learned_gate = c > 0: the learned
+    stop (with noise_norm) fires only once rho_k <= c tau ||e||.  phases=True times the phases of
     the solve with HIP events (the iterations then run without a graph and the
     call waits for the stream) and adds info["phase_ms"], a dict over PHASES.
     """
@@ -490,7 +499,7 @@ def solve(A: Operator, B: Operator, b, mode: str = "AB", k: int = 30, reg: str =
             raise ValueError(f"noise_norm has {noise_norm.numel()} entries, expected one per slice ({batch})")
     fbits = (FEAT_OUT if features else 0) | (FEAT_LABELS if x_true is not None else 0)
     r, s, e = _structs(reg, lam, tau, noise_norm, mlp, judge_delta, stop, tau, rns_eps, use_graph, poll_every,
-                       restart, fbits, ortho)
+                       restart, fbits, ortho, learned_gate)
     pms = (ctypes.c_double * len(PHASES))() if phases else None
     e.phase_ms = None if pms is None else ctypes.addressof(pms)
     m = MODE_AB if mode == "AB" else MODE_BA

@@ -439,6 +439,7 @@ static void to_c(const TuneEntry &t, abba_tune *o) {
     o->czt = t.czt;
     o->a_rb = t.a_rb;
     o->a_occ = t.a_occ;
+    o->a_tile = t.a_tile;
 }
 
 static void store_tuning(abba_op *op, const TuneEntry &e) {
@@ -473,7 +474,11 @@ int abba_op_set_tuning(abba_op *op, int batch, const abba_tune *t) {
                   (op->lds_cu + 65535) / 65536);
         return ABBA_ERR_ARG;
     }
-    store_tuning(op, TuneEntry{batch, t->a_path, t->a_jb, t->b_g, t->czt, t->a_rb, t->a_occ});
+    if (t->a_tile != 0 && t->a_tile != 16) {
+        set_error("abba_op_set_tuning: a_tile must be 0 or 16");
+        return ABBA_ERR_ARG;
+    }
+    store_tuning(op, TuneEntry{batch, t->a_path, t->a_jb, t->b_g, t->czt, t->a_rb, t->a_occ, t->a_tile});
     return ABBA_OK;
 }
 

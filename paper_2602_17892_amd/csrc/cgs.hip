@@ -584,7 +584,16 @@ static inline int nblk_for(int64_t nvec) {
     return (int)b;
 }
 
-int cgs_nblk(int64_t ldw, int w_dt) { return nblk_for(ldw / (w_dt == ABBA_F64 ? 2 : 4)); }
+// 16-byte vectors of each basis vector that one block of the Gram-Schmidt
+// sweeps handles.
+#ifndef ABBA_CGS_CHUNK
+#define ABBA_CGS_CHUNK 512
+#endif
+int cgs_nblk(int64_t ldw, int w_dt) {
+    const int64_t nvec = ldw / (w_dt == ABBA_F64 ? 2 : 4);
+    int64_t b = (nvec + ABBA_CGS_CHUNK - 1) / ABBA_CGS_CHUNK;
+    return (int)std::min<int64_t>(1024, std::max<int64_t>(1, b));
+}
 
 template <typename TW>
 static int launch_dots(TW *W, const SolveDims &d, double *part, int nblk, int extra, int jtiles,

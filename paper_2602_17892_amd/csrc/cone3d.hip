@@ -266,7 +266,13 @@ __device__ __forceinline__ void plane_range(double c0, double dc, int n, int np,
 // views outermost); bands of a few rows, whose rays in flight on one XCD
 // cross a thin slab of the volume, are a launch choice (measured slower on
 // the 256^3 problem: the taps are limited by the gathers, not by L2 reuse).
-template <typename TI, typename TO>
+// With TILE the workgroup is a 16 x 16 tile of detector pixels of one view
+// (a wave 16 columns x 4 rows; work order (slice, view, tile row, tile
+// column)), nbu and rb then being the tiles per detector row and column.
+// The even and odd steps are summed by the parity of the plane index, and
+// steps outside a ray's own range read pad zeros, so every decomposition
+// gives the same bits.
+template <typename TI, typename TO, bool TILE>
 __global__ __launch_bounds__(256) void cone_fwd_k(const TI *__restrict__ vx, const TI *__restrict__ vy,
                                                   const TI *__restrict__ vz, int64_t sx, int64_t sy, int64_t szz,
                                                   VecRef yr, const ConeView *__restrict__ views, int nx, int ny,
@@ -275,19 +281,34 @@ __global__ __launch_bounds__(256) void cone_fwd_k(const TI *__restrict__ vx, con
                                                   const int *kdev, const int *active) {
     typedef typename acc_of<TI>::type T;
     const uint32_t w = cremap(blockIdx.x, gridDim.x, nxcc);
-    const int cb = (int)(w % (uint32_t)nbu);
-    const uint32_t w2 = w / (uint32_t)nbu;
-    const int ri = (int)(w2 % (uint32_t)rb);
-    const uint32_t w3 = w2 / (uint32_t)rb;
-    const int vw = (int)(w3 % (uint32_t)nviews);
-    const uint32_t w4 = w3 / (uint32_t)nviews;
-    const int r = (int)(w4 % (uint32_t)nrb) * rb + ri;
-    const int s = s0 + (int)(w4 / (uint32_t)nrb);
-    if (r >= nv) return;   // the ragged last band (the whole workgroup)
+    int c, r, vw, s;
+    bool live;
+    if (TILE) {
+        const int tu = (int)(w % (uint32_t)nbu);
+        const uint32_t w2 = w / (uint32_t)nbu;
+        const int tv = (int)(w2 % (uint32_t)rb);
+        const uint32_t w3 = w2 / (uint32_t)rb;
+        vw = (int)(w3 % (uint32_t)nviews);
+        s = s0 + (int)(w3 / (uint32_t)nviews);
+        c = tu * 16 + (int)(threadIdx.x & 15);
+        r = tv * 16 + (int)(threadIdx.x >> 4);
+        live = c < nu && r < nv;
+        if (r >= nv) r = nv - 1;   // a dead lane of a ragged tile still computes a valid ray
+    } else {
+        const int cb = (int)(w % (uint32_t)nbu);
+        const uint32_t w2 = w / (uint32_t)nbu;
+        const int ri = (int)(w2 % (uint32_t)rb);
+        const uint32_t w3 = w2 / (uint32_t)rb;
+        vw = (int)(w3 % (uint32_t)nviews);
+        const uint32_t w4 = w3 / (uint32_t)nviews;
+        r = (int)(w4 % (uint32_t)nrb) * rb + ri;
+        s = s0 + (int)(w4 / (uint32_t)nrb);
+        if (r >= nv) return;   // the ragged last band (the whole workgroup)
+        c = cb * 256 + (int)threadIdx.x;
+        live = c < nu;
+    }
     if (active && !active[s]) return;
     const int k = kdev ? *kdev : 0;
-    const int c = cb * 256 + (int)threadIdx.x;
-    const bool live = c < nu;
     const ConeView &V = views[vw];
     // ---- ray set-up (FP64)
     const double ou = (c - 0.5 * (nu - 1)) * pu, ov = (r - 0.5 * (nv - 1)) * pv;
@@ -357,10 +378,14 @@ __global__ __launch_bounds__(256) void cone_fwd_k(const TI *__restrict__ vx, con
         load(jj, fp, fq, a00, a01, a10, a11);
         return combine(fp, fq, a00, a01, a10, a11);
     };
-    // steps alternate between two sums (even and odd steps from jlo); the
-    // loads of four steps are issued before any is combined
+    // two sums, over the even and the odd planes; the loads of four steps
+    // are issued before any is combined
     T acc0 = 0, acc1 = 0;
     int j = jlo;
+    if (j <= jhi && (j & 1)) {
+        acc1 += tap(j);
+        ++j;
+    }
     for (; j + 3 <= jhi; j += 4) {
         T fp[4], fq[4], a00[4], a01[4], a10[4], a11[4], v[4];
 #pragma unroll
@@ -483,23 +508,36 @@ static int cone_fwd_t(const abba_op *op, VecRef x, VecRef y, int batch, void *sc
         ABBA_LAUNCHED("cone_pad_vol_k");
     }
     if (std::max({cc.vx, cc.vy, cc.vz}) >= (size_t)1 << 31) return ABBA_ERR_UNSUPPORTED;
-    const int nbu = (g.det_u + 255) / 256;
+    int nbu = (g.det_u + 255) / 256;
     int rb = g.det_v;
+    bool tile = false;
     size_t cap_lds = 0;   // unused LDS per workgroup that caps the workgroups per CU
     if (const TuneEntry *t = tune_for(op, batch)) {
         if (t->a_rb >= 1) rb = std::min(t->a_rb, g.det_v);
         if (t->a_occ >= 1) cap_lds = std::min<size_t>(65536, (size_t)op->lds_cu / (size_t)t->a_occ / 512 * 512);
+        tile = t->a_tile == 16;
     }
-    const int nrb = (g.det_v + rb - 1) / rb;
+    int nrb = (g.det_v + rb - 1) / rb;
+    if (tile) {   // tiles per detector row (nbu) and per column (rb); one band
+        nbu = (g.det_u + 15) / 16;
+        rb = (g.det_v + 15) / 16;
+        nrb = 1;
+    }
     const uint64_t per = (uint64_t)nbu * nrb * rb * g.n_angles;
     if (per > CMAX_GROUPS) return ABBA_ERR_UNSUPPORTED;
     const int ch = (int)std::min<uint64_t>((uint64_t)batch, CMAX_GROUPS / per);
     for (int s0 = 0; s0 < batch; s0 += ch) {
         const int nb = std::min(ch, batch - s0);
-        hipLaunchKernelGGL((cone_fwd_k<TI, TO>), dim3((uint32_t)(per * nb)), dim3(256), cap_lds, L.stream, vx, vy, vz,
-                           (int64_t)cc.vx, (int64_t)cc.vy, (int64_t)cc.vz, y, (const ConeView *)op->tab, g.nx, g.ny,
-                           g.nz, g.n_angles, g.det_u, g.det_v, g.det_pitch_u, g.det_pitch_v, nbu, rb, nrb,
-                           (uint32_t)op->nxcc, s0, L.kdev, L.active);
+        if (tile)
+            hipLaunchKernelGGL((cone_fwd_k<TI, TO, true>), dim3((uint32_t)(per * nb)), dim3(256), cap_lds, L.stream, vx,
+                               vy, vz, (int64_t)cc.vx, (int64_t)cc.vy, (int64_t)cc.vz, y, (const ConeView *)op->tab,
+                               g.nx, g.ny, g.nz, g.n_angles, g.det_u, g.det_v, g.det_pitch_u, g.det_pitch_v, nbu, rb,
+                               nrb, (uint32_t)op->nxcc, s0, L.kdev, L.active);
+        else
+            hipLaunchKernelGGL((cone_fwd_k<TI, TO, false>), dim3((uint32_t)(per * nb)), dim3(256), cap_lds, L.stream,
+                               vx, vy, vz, (int64_t)cc.vx, (int64_t)cc.vy, (int64_t)cc.vz, y,
+                               (const ConeView *)op->tab, g.nx, g.ny, g.nz, g.n_angles, g.det_u, g.det_v,
+                               g.det_pitch_u, g.det_pitch_v, nbu, rb, nrb, (uint32_t)op->nxcc, s0, L.kdev, L.active);
         ABBA_LAUNCHED("cone_fwd_k");
     }
     return ABBA_OK;
@@ -577,6 +615,8 @@ int cone_tune_candidates(const abba_op *op, TuneEntry *out, int cap) {
             if (n < cap && r < op->g.det_v) out[n++] = TuneEntry{0, 0, 0, 0, 0, r, 0};
         for (int c : {5, 4})
             if (n < cap) out[n++] = TuneEntry{0, 0, 0, 0, 0, 0, c};
+        for (int c : {0, 5, 4})
+            if (n < cap) out[n++] = TuneEntry{0, 0, 0, 0, 0, 0, c, 16};
     }
     return n;
 }

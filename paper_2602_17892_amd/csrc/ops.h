@@ -66,6 +66,7 @@ struct TuneEntry {
     int czt;      // 3D B: voxels per thread along z (2, 4 or 8)
     int a_rb;     // 3D A: detector rows per band of the work order (1 to 64)
     int a_occ;    // 3D A: workgroups per compute unit at most (0: no cap)
+    int a_tile;   // 3D A: 0 detector rows per workgroup, 16: 16 x 16 detector tiles
 };
 constexpr int MAX_TUNE = 8;
 

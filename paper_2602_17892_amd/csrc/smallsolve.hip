@@ -4,15 +4,33 @@
 // Hessenberg matrix H_k (eq. (8)).  This kernel
 //   1. extends the Givens QR of H_k by one rotation, giving R_k and
 //      Q^T beta e_1 = (g, u_{k+1}); |u_{k+1}| is the GMRES residual (eq. (9));
-//   2. extends the SVD R_k = U S V^T by one-sided (Hestenes) Jacobi, warm
-//      started from the previous iteration: with A = R V the first k-1
-//      columns of [R_{k-1} V_{k-1}, r; 0, rho] are already orthogonal;
-//   3. forms uhat = U^T g and picks lambda (Sec. 3.1): none, fixed, GCV
-//      (eq. (15)), the discrepancy principle, or the L-curve corner (eq. (14));
+//   2. updates the SVD R_{k-1} = U S V^T to R_k: with the new column
+//      (r; rho) of R_k,
+//        R_k = diag(U, 1) N diag(V, 1)^T,   N = [S  U^T r; 0  rho],
+//      and N, with its last row and column moved first, has a full first
+//      column z = (rho, U^T r) and the diagonal (0, s): N N^T = D^2 + z z^T.
+//      Its singular values are the roots of the secular equation
+//        1 + sum_i z_i^2 / (d_i^2 - w^2) = 0,
+//      one in each gap of 0 = d_0 < d_1 <= ... < d_{k-1} and one above; its
+//      singular vectors are u_j ~ (z_i / (d_i^2 - w_j^2))_i and
+//      v_j ~ (-1, (d_i z_i / (d_i^2 - w_j^2))_{i>0}) (Gu and Eisenstat's
+//      divide-and-conquer SVD, SIAM J. Matrix Anal. Appl. 16 (1995)).
+//      Entries with z_i at rounding level, and equal d_i (after a rotation
+//      that moves their z into one of them), deflate: d_i is then a
+//      singular value with unit vectors.  Each root is found in the
+//      variable mu - d_K^2, K the nearer pole, from a rational model with
+//      the two poles of its gap (Bunch, Nielsen and Sorensen 1978) inside a
+//      shrinking bracket; z is then recomputed from the roots (Loewner's
+//      formula), which keeps the vectors orthogonal to working precision.
+//      U_k = diag(U, 1) U_N and V_k = diag(V, 1) V_N (two k x k products),
+//      uhat_k = U_N^T (uhat_{k-1}; g_k) with g = Q^T beta e_1;
+//   3. picks lambda (Sec. 3.1): none, fixed, GCV (eq. (15)), the discrepancy
+//      principle, or the L-curve corner (eq. (14));
 //   4. solves eq. (12): y = V diag(s/(s^2+lam^2)) uhat, and the projected
 //      residual rho^2 = sum (lam^2/(s^2+lam^2))^2 uhat^2 + u_{k+1}^2.
-// Both Jacobi matrices (k x k FP64) live in LDS: 2 * 100^2 * 8 B = 156 KB at
-// k = 100, within gfx950's 160 KB per workgroup.
+// U and V of the previous iteration stay in the workspace (k x k FP64,
+// column-major, columns in descending order of s); one k x k FP64 matrix of
+// the update (U_N, then V_N) lives in LDS.
 //
 // Readings where the paper is silent: GCV on a 256-point log grid over
 // [1e-8 s_1, s_1], global grid minimum (first index on ties), 60
@@ -25,16 +43,17 @@
 namespace abba {
 
 constexpr int SS_THREADS = 1024;
-constexpr int SS_GROUP = 16;                       // lanes per Jacobi pair
-constexpr int SS_PAIRS = SS_THREADS / SS_GROUP;    // pairs in flight
+constexpr int SS_ROOT_LANES = 8;                   // lanes per secular root
+constexpr int SS_ROOT_ITERS = 100;                 // bound on the root iterations
+constexpr int SS_COLS = 10;                        // output columns per thread of the updates
+constexpr double SS_EPS = 2.220446049250313e-16;   // 2^-52
 constexpr int GCV_GRID = 256;
 constexpr int GOLDEN_STEPS = 60;
 constexpr int DP_STEPS = 100;
-constexpr int MAX_SWEEPS = 30;
 
 struct SmallArgs {
     const double *H;
-    double *gc, *gs, *g, *Aj, *Vj, *y, *sig, *uh, *sc, *lamh, *rhoh;
+    double *gc, *gs, *g, *Uj, *Vj, *y, *sig, *uh, *sc, *lamh, *rhoh;
     int *flags;
     int *active;
     const int *kdev;
@@ -46,24 +65,21 @@ struct SmallArgs {
     int ab_resid;            // 1: rho_k = projected residual (AB mode)
 };
 
-constexpr int SS_NR = (KMAX_SMALL + SS_GROUP - 1) / SS_GROUP;   // column entries per lane
-
-// The value of the partner lane inside a row of 16 lanes (a DPP row).
-template <int CTRL>
-__device__ __forceinline__ double dpp_peer(double v) {
-    return __builtin_amdgcn_update_dpp(0.0, v, CTRL, 0xF, 0xF, false);
+// Sum over the 8 lanes of a root group (aligned groups of 8 lanes of a wave).
+__device__ __forceinline__ double group8_sum(double v) {
+    v += __shfl_xor(v, 1, 64);
+    v += __shfl_xor(v, 2, 64);
+    v += __shfl_xor(v, 4, 64);
+    return v;
 }
 
-// Sum over the 16 lanes of a Jacobi group, which is one DPP row: quad
-// swaps, then the half-row and row mirrors.  Each stage adds two values that
-// the partner lane adds as well, so every lane ends with the same bits.
-__device__ __forceinline__ double group_sum(double v) {
-    static_assert(SS_GROUP == 16, "a Jacobi group is one DPP row");
-    v += dpp_peer<0xB1>(v);    // quad_perm [1,0,3,2]
-    v += dpp_peer<0x4E>(v);    // quad_perm [2,3,0,1]
-    v += dpp_peer<0x141>(v);   // row_half_mirror
-    v += dpp_peer<0x140>(v);   // row_mirror
-    return v;
+// 1/x to within an ulp or two: the hardware estimate and two Newton steps.
+__device__ __forceinline__ double recip(double x) {
+    double r = __builtin_amdgcn_rcp(x);
+    double e = fma(-x, r, 1.0);
+    r = fma(r, e, r);
+    e = fma(-x, r, 1.0);
+    return fma(r, e, r);
 }
 
 __device__ __forceinline__ double grid_lambda(double s1, int gi) {
@@ -135,45 +151,81 @@ __device__ double serial_lcurve(double lam, const double *sig, const double *uh,
     return (a1 * b2 - a2 * b1) / den;
 }
 
+// LDS of one slice's small solve (doubles): the k x k update matrix, the new
+// column, reduction slots, the secular problem's vectors, and the lambda
+// search's arrays; then ints.
+struct SsLds {
+    double *M, *col, *red, *dsec, *zsec, *dk, *zk, *tau, *zh, *nu, *nv, *sgo, *gh, *rc, *rs, *rcol;
+    double *lsig, *luh, *lcf, *lgv;
+    int *keep, *basek, *pos, *roti, *rotj, *defl;
+};
+
+__device__ __forceinline__ SsLds ss_lds(double *smem, int K) {
+    SsLds L;
+    double *p = smem;
+    L.M = p; p += (size_t)K * K;
+    L.col = p; p += K + 1;
+    L.red = p; p += 64;
+    L.dsec = p; p += K;
+    L.zsec = p; p += K;
+    L.dk = p; p += K;
+    L.zk = p; p += K;
+    L.tau = p; p += K;
+    L.zh = p; p += K;
+    L.nu = p; p += K;
+    L.nv = p; p += K;
+    L.sgo = p; p += K;
+    L.gh = p; p += K;
+    L.rc = p; p += K;
+    L.rs = p; p += K;
+    L.rcol = p; p += K;
+    L.lsig = p; p += K;
+    L.luh = p; p += K;
+    L.lcf = p; p += K;
+    L.lgv = p; p += GCV_GRID;
+    int *q = reinterpret_cast<int *>(p);
+    L.keep = q; q += K;
+    L.basek = q; q += K;
+    L.pos = q; q += K;
+    L.roti = q; q += K;
+    L.rotj = q; q += K;
+    L.defl = q; q += K;
+    return L;
+}
+
+size_t smallsolve_lds_bytes(int K) {
+    return sizeof(double) * ((size_t)K * K + (K + 1) + 64 + 16 * (size_t)K + GCV_GRID) + sizeof(int) * 6 * (size_t)K;
+}
+
+// d_i^2 - w_j^2 for kept entry i and root j (w_j^2 = d_K^2 + eta_j), formed
+// as (d_i - d_K)(d_i + d_K) - eta_j so that it is accurate near the pole.
+__device__ __forceinline__ double sec_diff(const double *dk, int i, int K, double eta) {
+    return (dk[i] - dk[K]) * (dk[i] + dk[K]) - eta;
+}
+
 __global__ __launch_bounds__(SS_THREADS) void smallsolve_k(SmallArgs a) {
     const int s = blockIdx.x;
     if (!a.active[s]) return;
     const int k = *a.kdev;
     const int K = a.K;
-    const int j = k - 1;
+    const int j = k - 1;          // the new column; k - 1 old singular triplets
     const int tid = threadIdx.x;
     extern __shared__ double smem[];
-    double *A = smem;                  // [K][K] column-major, column stride K
-    double *V = smem + (size_t)K * K;  // [K][K]
-    double *col = V + (size_t)K * K;   // [K+1]
-    double *red = col + (K + 1);       // [64]
-    double *xtra = red + 64;           // small-K overflow area
-    __shared__ int s_rot, s_big;
+    const SsLds L = ss_lds(smem, K);
+    double *col = L.col;
+    __shared__ int s_m, s_nd, s_nrot, s_maxit;
     __shared__ int s_idx;
     __shared__ double s_val[4];
     __shared__ double s_uk1;
 
     double *Sc = a.sc + (size_t)s * SC_COUNT;
     const double *Hcol = a.H + ((size_t)s * K + j) * (K + 1);
-    double *Ajs = a.Aj + (size_t)s * K * K;
-    double *Vjs = a.Vj + (size_t)s * K * K;
+    double *Us = a.Uj + (size_t)s * K * K;    // U_{k-1}, column-major, stride K
+    double *Vs = a.Vj + (size_t)s * K * K;
     double *gs = a.g + (size_t)s * (K + 1);
+    double *sig = a.sig + (size_t)s * K;      // descending
+    double *uh = a.uh + (size_t)s * K;
 
-    // ---- load warm start: A = [A_prev 0; . .], V = diag(V_prev, 1); new H column
-    for (int t = tid; t < k * k; t += SS_THREADS) {
-        const int c = t / k, r = t % k;
-        double av = 0.0, vv = 0.0;
-        if (c < j) {
-            if (r < j) {
-                av = Ajs[(size_t)c * K + r];
-                vv = Vjs[(size_t)c * K + r];
-            }
-        } else {
-            vv = (r == j) ? 1.0 : 0.0;
-        }
-        A[(size_t)c * K + r] = av;
-        V[(size_t)c * K + r] = vv;
-    }
     for (int t = tid; t <= k; t += SS_THREADS) col[t] = Hcol[t];
     __syncthreads();
 
@@ -202,127 +254,271 @@ __global__ __launch_bounds__(SS_THREADS) void smallsolve_k(SmallArgs a) {
         gs[j + 1] = -sn * u;
         Sc[SC_UK1] = fabs(gs[j + 1]);
         s_uk1 = fabs(gs[j + 1]);
-        for (int i = 0; i <= j; ++i) A[(size_t)j * K + i] = col[i];
-        // col now holds g (first k entries) for the other waves
-        for (int i = 0; i < k; ++i) col[i] = gs[i];
+        // the secular problem, index 0 = the new direction, then the old
+        // singular values ascending (stored descending): i <-> p = k - 1 - i
+        L.zsec[0] = col[j];
+        L.dsec[0] = 0.0;
+        L.gh[0] = gs[j];
+        for (int i = 0; i < j; ++i) L.rcol[i] = col[i];
     }
     __syncthreads();
 
-    // ---- one-sided Jacobi on A (k x k), accumulating V
-    const int grp = tid / SS_GROUP, gl = tid % SS_GROUP;
-    const int n = k + (k & 1);           // even number of players (one dummy if k odd)
-    // A pair whose columns are off-orthogonal by delta perturbs the singular
-    // values only at O(delta^2) and the vectors at O(delta): 1e-12 is far
-    // below what any consumer of y needs, and well above the rounding noise
-    // of the computed inner products (which a k*eps threshold would chase).
-    // One-sided Jacobi converges quadratically: after a sweep in which every
-    // pair was off-orthogonal by at most sqrt(tol), what remains is O(tol),
-    // so that sweep is the last one (the confirmation sweep is skipped).
-    const double tol = 1e-12, tol_last = 1e-6;
-    int sweeps = 0;
-    for (int sweep = 0; sweep < MAX_SWEEPS && k > 1; ++sweep) {
-        ++sweeps;
-        if (tid == 0) s_rot = s_big = 0;
-        __syncthreads();
-        for (int rnd = 0; rnd < n - 1; ++rnd) {
-            for (int pi = grp; pi < n / 2; pi += SS_PAIRS) {
-                int p, q;
-                if (pi == 0) {
-                    p = n - 1;
-                    q = rnd;
+    // ---- z = U^T r for the old directions
+    for (int p = tid; p < j; p += SS_THREADS) {
+        const double *up = Us + (size_t)p * K;
+        double acc = 0.0;
+        for (int r = 0; r < j; ++r) acc = fma(up[r], L.rcol[r], acc);
+        const int i = k - 1 - p;
+        L.zsec[i] = acc;
+        L.dsec[i] = sig[p];
+        L.gh[i] = uh[p];
+    }
+    __syncthreads();
+
+    // ---- deflation (one lane): small z_i, and equal d_i rotated together
+    if (tid == 0) {
+        double zz = 0.0;
+        for (int i = 0; i < k; ++i) zz = fma(L.zsec[i], L.zsec[i], zz);
+        const double nrm = fmax(L.dsec[k - 1], sqrt(zz));
+        const double tol = 8.0 * SS_EPS * nrm;
+        int m = 0, nd = 0, nrot = 0;
+        if (!(nrm > 0.0)) {
+            // R_k = 0 (or not finite): every direction deflates
+            for (int i = 0; i < k; ++i) L.defl[nd++] = i;
+        } else {
+            if (fabs(L.zsec[0]) <= tol) L.zsec[0] = tol;
+            L.keep[m++] = 0;
+        }
+        for (int i = m > 0 ? 1 : k; i < k; ++i) {
+            if (fabs(L.zsec[i]) <= tol) {
+                L.defl[nd++] = i;
+                continue;
+            }
+            const int jj = L.keep[m - 1];
+            if (jj > 0 && L.dsec[i] - L.dsec[jj] <= tol) {
+                const double r = hypot(L.zsec[i], L.zsec[jj]);
+                L.rc[nrot] = L.zsec[jj] / r;
+                L.rs[nrot] = L.zsec[i] / r;
+                L.roti[nrot] = i;
+                L.rotj[nrot] = jj;
+                ++nrot;
+                L.zsec[jj] = r;
+                L.zsec[i] = 0.0;
+                L.defl[nd++] = i;
+                continue;
+            }
+            L.keep[m++] = i;
+        }
+        for (int i = 0; i < m; ++i) {
+            L.dk[i] = L.dsec[L.keep[i]];
+            L.zk[i] = L.zsec[L.keep[i]];
+        }
+        s_m = m;
+        s_nd = nd;
+        s_nrot = nrot;
+        s_maxit = 0;
+    }
+    __syncthreads();
+    const int m = s_m, nd = s_nd, nrot = s_nrot;
+
+    // ---- the roots w_j^2 = d_K^2 + eta_j, eight lanes per root
+    {
+        double zn2 = 0.0;
+        for (int i = 0; i < m; ++i) zn2 = fma(L.zk[i], L.zk[i], zn2);
+        const int gl = tid & (SS_ROOT_LANES - 1);
+        // the eight lanes of a root are an aligned group of a wave, so they
+        // take the same branches and exchange values only among themselves
+        for (int r0 = tid / SS_ROOT_LANES; r0 < m; r0 += SS_THREADS / SS_ROOT_LANES) {
+            const int jr = r0;
+            const bool last = jr == m - 1;
+            double lo, hi;
+            int Kb;
+            const double Dhi = last ? L.dk[m - 1] * L.dk[m - 1] + zn2 : L.dk[jr + 1] * L.dk[jr + 1];
+            if (last) {
+                Kb = jr;
+            } else {
+                // the nearer pole: the sign of f at the middle of the gap
+                const double mid = 0.5 * (L.dk[jr] * L.dk[jr] + Dhi);
+                double f = 0.0;
+                for (int i = gl; i < m; i += SS_ROOT_LANES) f += L.zk[i] * L.zk[i] / (L.dk[i] * L.dk[i] - mid);
+                f = 1.0 + group8_sum(f);
+                Kb = f > 0.0 ? jr : jr + 1;
+            }
+            const double dK = L.dk[Kb];
+            lo = (L.dk[jr] - dK) * (L.dk[jr] + dK);
+            hi = last ? (L.dk[m - 1] * L.dk[m - 1] + zn2) - dK * dK : (L.dk[jr + 1] - dK) * (L.dk[jr + 1] + dK);
+            double eta = 0.5 * (lo + hi);
+            int it = 0;
+            for (; it < SS_ROOT_ITERS; ++it) {
+                double f = 0.0, fa = 0.0, dps = 0.0, dph = 0.0;
+                for (int i = gl; i < m; i += SS_ROOT_LANES) {
+                    const double dm = sec_diff(L.dk, i, Kb, eta);
+                    const double inv = recip(dm);
+                    const double t = L.zk[i] * L.zk[i] * inv;
+                    f += t;
+                    fa += fabs(t);
+                    const double dv = t * inv;
+                    if (i <= jr) dps += dv;
+                    else dph += dv;
+                }
+                f = 1.0 + group8_sum(f);
+                fa = group8_sum(fa);
+                dps = group8_sum(dps);
+                dph = group8_sum(dph);
+                if (f > 0.0) hi = eta;
+                else lo = eta;
+                if (fabs(f) <= 8.0 * SS_EPS * (1.0 + fa)) break;
+                const double Dj = sec_diff(L.dk, jr, Kb, eta);
+                double stp;
+                if (last) {
+                    const double C = f - dps * Dj;
+                    stp = Dj + dps * Dj * Dj / C;
                 } else {
-                    p = (rnd + pi) % (n - 1);
-                    q = (rnd - pi + n - 1) % (n - 1);
-                }
-                if (p >= k || q >= k) continue;
-                double *ap = A + (size_t)p * K, *aq = A + (size_t)q * K;
-                double *vp = V + (size_t)p * K, *vq = V + (size_t)q * K;
-                // the four columns' entries of this lane, all loads in flight
-                // at once (entries past k read as zero and are not stored)
-                double xr[SS_NR], zr[SS_NR], vx[SS_NR], vz[SS_NR];
-#pragma unroll
-                for (int u = 0; u < SS_NR; ++u) {
-                    const int r = gl + u * SS_GROUP;
-                    const bool in = r < k;
-                    xr[u] = in ? ap[r] : 0.0;
-                    zr[u] = in ? aq[r] : 0.0;
-                    vx[u] = in ? vp[r] : 0.0;
-                    vz[u] = in ? vq[r] : 0.0;
-                }
-                double al = 0.0, be = 0.0, ga = 0.0;
-#pragma unroll
-                for (int u = 0; u < SS_NR; ++u) {
-                    al = fma(xr[u], xr[u], al);
-                    be = fma(zr[u], zr[u], be);
-                    ga = fma(xr[u], zr[u], ga);
-                }
-                al = group_sum(al);
-                be = group_sum(be);
-                ga = group_sum(ga);
-                if (al > 0.0 && be > 0.0 && fabs(ga) > tol * sqrt(al * be)) {
-                    const double zeta = (be - al) / (2.0 * ga);
-                    const double t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
-                    const double c = 1.0 / sqrt(1.0 + t * t);
-                    const double sn = c * t;
-#pragma unroll
-                    for (int u = 0; u < SS_NR; ++u) {
-                        const int r = gl + u * SS_GROUP;
-                        if (r < k) {
-                            ap[r] = c * xr[u] - sn * zr[u];
-                            aq[r] = sn * xr[u] + c * zr[u];
-                            vp[r] = c * vx[u] - sn * vz[u];
-                            vq[r] = sn * vx[u] + c * vz[u];
-                        }
+                    const double Dj1 = sec_diff(L.dk, jr + 1, Kb, eta);
+                    const double b = dps * Dj * Dj, e = dph * Dj1 * Dj1;
+                    const double C = f - dps * Dj - dph * Dj1;
+                    const double a1 = -(C * (Dj + Dj1) + b + e), a0 = C * Dj * Dj1 + b * Dj1 + e * Dj;
+                    if (C == 0.0) {
+                        stp = -a0 / a1;
+                    } else {
+                        const double sq = sqrt(fmax(a1 * a1 - 4.0 * C * a0, 0.0));
+                        const double q = -0.5 * (a1 + copysign(sq, a1));
+                        const double r1 = q / C, r2 = q != 0.0 ? a0 / q : INFINITY;
+                        stp = (r1 > Dj && r1 < Dj1) ? r1 : r2;
                     }
-                    if (gl == 0) {
-                        s_rot = 1;
-                        if (fabs(ga) > tol_last * sqrt(al * be)) s_big = 1;
-                    }
+                }
+                double en = eta + stp;
+                if (!(en > lo && (en < hi || (last && en == hi))) || !isfinite(en)) en = 0.5 * (lo + hi);
+                if (en == eta) break;
+                eta = en;
+            }
+            if (gl == 0) {
+                L.tau[jr] = eta;
+                L.basek[jr] = Kb;
+                atomicMax(&s_maxit, it + 1);
+            }
+        }
+    }
+    __syncthreads();
+
+    // ---- Loewner: zhat from the roots; then the vector norms
+    for (int i = tid; i < m; i += SS_THREADS) {
+        const double di = L.dk[i];
+        double p = -sec_diff(L.dk, i, L.basek[m - 1], L.tau[m - 1]);   // w_{m-1}^2 - d_i^2
+        for (int jj = 0; jj < i; ++jj)
+            p *= -sec_diff(L.dk, i, L.basek[jj], L.tau[jj]) / ((L.dk[jj] - di) * (L.dk[jj] + di));
+        for (int jj = i; jj < m - 1; ++jj)
+            p *= -sec_diff(L.dk, i, L.basek[jj], L.tau[jj]) / ((L.dk[jj + 1] - di) * (L.dk[jj + 1] + di));
+        L.zh[i] = copysign(sqrt(fmax(p, 0.0)), L.zk[i]);
+    }
+    __syncthreads();
+    for (int jr = tid; jr < m; jr += SS_THREADS) {
+        double su = 0.0, sv = 1.0;
+        for (int i = 0; i < m; ++i) {
+            const double q = L.zh[i] / sec_diff(L.dk, i, L.basek[jr], L.tau[jr]);
+            su = fma(q, q, su);
+            if (i > 0) sv = fma(L.dk[i] * q, L.dk[i] * q, sv);
+        }
+        L.nu[jr] = 1.0 / sqrt(su);
+        L.nv[jr] = 1.0 / sqrt(sv);
+        const double dK = L.dk[L.basek[jr]];
+        L.sgo[jr] = sqrt(fma(dK, dK, L.tau[jr]));
+    }
+    for (int c = tid; c < nd; c += SS_THREADS) L.sgo[m + c] = L.dsec[L.defl[c]];
+    __syncthreads();
+    // output slot c (roots, then deflated values) -> column pos[c] in
+    // descending order of the singular values (ties by slot)
+    for (int c = tid; c < k; c += SS_THREADS) {
+        const double v = L.sgo[c];
+        int r = 0;
+        for (int c2 = 0; c2 < k; ++c2) {
+            const double w = L.sgo[c2];
+            r += (w > v || (w == v && c2 < c)) ? 1 : 0;
+        }
+        L.pos[c] = r;
+    }
+    __syncthreads();
+
+    // ---- U_N then V_N into L.M (row-major [secular index][column]), each
+    // followed by its product with diag(U, 1) (diag(V, 1)) written in place
+    for (int which = 0; which < 2; ++which) {
+        const bool isu = which == 0;
+        double *M = L.M;
+        for (int t = tid; t < k * k; t += SS_THREADS) M[(t / k) * K + (t % k)] = 0.0;
+        __syncthreads();
+        for (int t = tid; t < m * m; t += SS_THREADS) {
+            const int i = t / m, jr = t % m;
+            const double q = L.zh[i] / sec_diff(L.dk, i, L.basek[jr], L.tau[jr]);
+            double v;
+            if (isu) v = q * L.nu[jr];
+            else v = (i == 0 ? -1.0 : L.dk[i] * q) * L.nv[jr];
+            M[(size_t)L.keep[i] * K + L.pos[jr]] = v;
+        }
+        for (int c = tid; c < nd; c += SS_THREADS) M[(size_t)L.defl[c] * K + L.pos[m + c]] = 1.0;
+        __syncthreads();
+        // the rotations of equal d_i, last one first, on the rows
+        if (tid < 64) {
+            for (int t = nrot - 1; t >= 0; --t) {
+                const int ri = L.roti[t], rj = L.rotj[t];
+                const double c = L.rc[t], sn = L.rs[t];
+                for (int col2 = tid; col2 < k; col2 += 64) {
+                    const double xj = M[(size_t)rj * K + col2], xi = M[(size_t)ri * K + col2];
+                    M[(size_t)rj * K + col2] = c * xj - sn * xi;
+                    M[(size_t)ri * K + col2] = sn * xj + c * xi;
                 }
             }
-            __syncthreads();
         }
-        const int rot = s_rot, big = s_big;
         __syncthreads();
-        if (!rot || !big) break;
-    }
-
-    // ---- sigma_i = ||A_i||, uhat_i = A_i . g / sigma_i; save the warm start
-    double *sig = a.sig + (size_t)s * K;
-    double *uh = a.uh + (size_t)s * K;
-    for (int i = tid; i < k; i += SS_THREADS) {
-        const double *ai = A + (size_t)i * K;
-        double n2 = 0.0, d = 0.0;
-        for (int r = 0; r < k; ++r) {
-            n2 = fma(ai[r], ai[r], n2);
-            d = fma(ai[r], col[r], d);
+        if (isu) {
+            // uhat_k = U_N^T (secular-order uhat_{k-1}; g_k), and the new sigma
+            for (int c = tid; c < k; c += SS_THREADS) {
+                double acc = 0.0;
+                for (int i = 0; i < k; ++i) acc = fma(M[(size_t)i * K + c], L.gh[i], acc);
+                L.luh[c] = acc;
+            }
+            for (int c = tid; c < k; c += SS_THREADS) L.lsig[L.pos[c]] = L.sgo[c];
         }
-        const double sgm = sqrt(n2);
-        sig[i] = sgm;
-        uh[i] = sgm > 0.0 ? d / sgm : 0.0;
-    }
-    for (int t = tid; t < k * k; t += SS_THREADS) {
-        const int c = t / k, r = t % k;
-        Ajs[(size_t)c * K + r] = A[(size_t)c * K + r];
-        Vjs[(size_t)c * K + r] = V[(size_t)c * K + r];
-    }
-    __syncthreads();
-    // reuse A's LDS for sigma / uhat / coefficients / grid values
-    double *lsig = (K * K >= 3 * K + GCV_GRID) ? A : xtra;
-    double *luh = lsig + K, *lcf = luh + K, *lgv = lcf + K;
-    for (int i = tid; i < k; i += SS_THREADS) {
-        lsig[i] = sig[i];
-        luh[i] = uh[i];
-    }
-    // sigma_1
-    double mx = 0.0;
-    for (int i = tid; i < k; i += SS_THREADS) mx = fmax(mx, sig[i]);
+        // X_new[r][c] = sum_{p<k-1} X[r][p] M[k-1-p][c] + [r == k-1] M[0][c]:
+        // thread (r, column group) keeps SS_COLS sums; all reads of X happen
+        // before the barrier, all writes of the new X after it
+        double *X = isu ? Us : Vs;
+        const int ngrp = (k + SS_COLS - 1) / SS_COLS;
+        double acc[SS_COLS];
+        const int r = tid % K, cg = tid / K;
+        const bool mine = r < k && cg < ngrp && tid < K * ngrp;
 #pragma unroll
-    for (int off = 32; off > 0; off >>= 1) mx = fmax(mx, __shfl_xor(mx, off, 64));
-    if ((tid & 63) == 0) red[tid >> 6] = mx;
-    __syncthreads();
-    double s1 = 0.0;
-    for (int w = 0; w < SS_THREADS / 64; ++w) s1 = fmax(s1, red[w]);
+        for (int u = 0; u < SS_COLS; ++u) acc[u] = 0.0;
+        if (mine) {
+            const int c0 = cg * SS_COLS;
+            for (int p = 0; p < j; ++p) {
+                const double xv = X[(size_t)p * K + r];
+                const double *mr = M + (size_t)(k - 1 - p) * K + c0;
+#pragma unroll
+                for (int u = 0; u < SS_COLS; ++u)
+                    if (c0 + u < k) acc[u] = fma(xv, mr[u], acc[u]);
+            }
+            if (r == k - 1) {
+#pragma unroll
+                for (int u = 0; u < SS_COLS; ++u)
+                    if (c0 + u < k) acc[u] = M[c0 + u];
+            }
+        }
+        __syncthreads();
+        if (mine) {
+            const int c0 = cg * SS_COLS;
+#pragma unroll
+            for (int u = 0; u < SS_COLS; ++u)
+                if (c0 + u < k) X[(size_t)(c0 + u) * K + r] = acc[u];
+        }
+        __syncthreads();
+    }
+    for (int i = tid; i < k; i += SS_THREADS) {
+        sig[i] = L.lsig[i];
+        uh[i] = L.luh[i];
+    }
+    double *lsig = L.lsig, *luh = L.luh, *lcf = L.lcf, *lgv = L.lgv;
+    // sigma_1
+    const double s1 = lsig[0];
     const double uk1 = s_uk1;
     const double beta = Sc[SC_BETA];
     __syncthreads();
@@ -439,7 +635,7 @@ __global__ __launch_bounds__(SS_THREADS) void smallsolve_k(SmallArgs a) {
     double *ys = a.y + (size_t)s * K;
     for (int r = tid; r < k; r += SS_THREADS) {
         double acc = 0.0;
-        for (int i = 0; i < k; ++i) acc = fma(V[(size_t)i * K + r], lcf[i], acc);
+        for (int i = 0; i < k; ++i) acc = fma(Vs[(size_t)i * K + r], lcf[i], acc);
         ys[r] = acc;
     }
     if (tid < 64) {
@@ -457,7 +653,7 @@ __global__ __launch_bounds__(SS_THREADS) void smallsolve_k(SmallArgs a) {
             const double rho = sqrt(part + uk1 * uk1);
             Sc[SC_LAM] = lam;
             Sc[SC_RHOHAT] = rho;
-            Sc[SC_SWEEPS] = (double)sweeps;
+            Sc[SC_SWEEPS] = (double)s_maxit;
             a.lamh[(size_t)s * K + j] = lam;
             if (a.ab_resid) a.rhoh[(size_t)s * (K + 1) + k] = rho;
             if (!isfinite(rho) || !isfinite(s1)) a.flags[s] |= FL_NONFINITE;
@@ -473,7 +669,8 @@ __global__ __launch_bounds__(1024) void stop_k(int S, int K, int stop_kind, doub
                                                int *__restrict__ iters, int *__restrict__ status,
                                                int *__restrict__ kdev, int *__restrict__ nact,
                                                const double *__restrict__ sc, int has_rho,
-                                               const double *__restrict__ ncpd, double ncp_thr) {
+                                               const double *__restrict__ ncpd, double ncp_thr,
+                                               double learned_gate) {
     const int k = *kdev;
     int cnt = 0;
     for (int s = threadIdx.x; s < S; s += blockDim.x) {
@@ -489,7 +686,8 @@ __global__ __launch_bounds__(1024) void stop_k(int S, int K, int stop_kind, doub
         else if ((stop_kind == ABBA_STOP_DP || (stop_kind == ABBA_STOP_LEARNED && noise)) && rho <= tau * noise[s])
             st = ABBA_ST_STOP_DP;
         else if (stop_kind == ABBA_STOP_RNS && fabs(rprev - rho) / rprev < rns_eps) st = ABBA_ST_STOP_RNS;
-        else if (stop_kind == ABBA_STOP_LEARNED && sc && (double)k >= sc[(size_t)s * SC_COUNT + SC_KLEARN])
+        else if (stop_kind == ABBA_STOP_LEARNED && sc && (double)k >= sc[(size_t)s * SC_COUNT + SC_KLEARN] &&
+                 (!(learned_gate > 0.0) || !noise || rho <= learned_gate * tau * noise[s]))
             st = ABBA_ST_STOP_LEARNED;
         else if (stop_kind == ABBA_STOP_NCP && ncpd && ncpd[s] <= ncp_thr)
             st = ABBA_ST_STOP_NCP;
@@ -527,10 +725,6 @@ __global__ void finish_resid_k(const double *__restrict__ npart, int nblk, doubl
     rhoh[(size_t)s * (K + 1) + k] = sqrt(t);
 }
 
-size_t smallsolve_lds_bytes(int K) {
-    size_t extra = (size_t)K * K >= (size_t)(3 * K + GCV_GRID) ? 0 : (size_t)(3 * K + GCV_GRID);
-    return sizeof(double) * (2 * (size_t)K * K + (K + 1) + 64 + extra);
-}
 
 int launch_smallsolve(const SolveDims &d, const SolveWS &ws, int rule, double lam_fixed, double tau,
                       const double *noise, hipStream_t st) {
@@ -539,7 +733,7 @@ int launch_smallsolve(const SolveDims &d, const SolveWS &ws, int rule, double la
     a.gc = ws.gc;
     a.gs = ws.gs;
     a.g = ws.g;
-    a.Aj = ws.Aj;
+    a.Uj = ws.Uj;
     a.Vj = ws.Vj;
     a.y = ws.y;
     a.sig = ws.sig;
@@ -578,11 +772,11 @@ int smallsolve_prepare() {
 }
 
 int launch_stop(const SolveDims &d, const SolveWS &ws, int stop_kind, double tau, double rns_eps,
-                const double *noise, int *iters, int *status, hipStream_t st) {
+                const double *noise, double learned_gate, int *iters, int *status, hipStream_t st) {
     hipLaunchKernelGGL(stop_k, dim3(1), dim3(1024), 0, st, d.S, d.K, stop_kind, tau, rns_eps, noise, ws.rhoh,
                        ws.active, ws.flags, iters, status, ws.kdev, ws.nact, ws.sc,
                        (d.mode == ABBA_MODE_AB || d.keepZ) ? 1 : 0, d.ncp ? ws.ncpd : nullptr,
-                       d.ncp ? 1.36 / sqrt((double)(d.det / 2)) : 0.0);
+                       d.ncp ? 1.36 / sqrt((double)(d.det / 2)) : 0.0, learned_gate);
     ABBA_LAUNCHED("stop_k");
     return ABBA_OK;
 }

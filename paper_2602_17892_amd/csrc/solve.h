@@ -30,7 +30,7 @@ enum {
     SC_RHO0 = 8,      // ||b - A x_0||
     SC_LAMLEARN = 9,  // learned log10(lambda/sigma_1) prediction
     SC_KLEARN = 10,   // learned stop index prediction
-    SC_SWEEPS = 11,   // Jacobi sweeps of the last small solve (diagnostic)
+    SC_SWEEPS = 11,   // most root iterations of the last SVD update (diagnostic)
     SC_COUNT = 16
 };
 
@@ -71,7 +71,7 @@ struct SolveWS {
     double *H;      // [S][K][K+1] column-major Hessenberg
     double *gc, *gs;// [S][K] Givens rotations
     double *g;      // [S][K+1] rotated beta e1
-    double *Aj, *Vj;// [S][K][K] Jacobi state (column-major, stride K)
+    double *Uj, *Vj;// [S][K][K] U and V of the SVD of R_k (column-major, stride K)
     double *y;      // [S][K]
     double *y2;     // [S][K]         delayed CGS2: T y
     double *T;      // [S][K][K]      delayed CGS2: W = V T (column-major, upper triangular)

@@ -41,7 +41,7 @@ int launch_resid(int s_dt, const void *r0, int64_t rstride, const void *Z, int64
 int launch_smallsolve(const SolveDims &d, const SolveWS &ws, int rule, double lam_fixed, double tau,
                       const double *noise, hipStream_t st);
 int launch_stop(const SolveDims &d, const SolveWS &ws, int stop_kind, double tau, double rns_eps,
-                const double *noise, int *iters, int *status, hipStream_t st);
+                const double *noise, double learned_gate, int *iters, int *status, hipStream_t st);
 int launch_finish_resid(const SolveDims &d, const SolveWS &ws, int nblk, hipStream_t st);
 int smallsolve_prepare();
 int learned_prepare(const SolveDims &d, const SolveWS &ws, const void *x0, const abba_out *out, hipStream_t st);
@@ -127,7 +127,7 @@ size_t solve_workspace_bytes(const SolveDims &d, SolveWS *ws, void *base, size_t
     w.gc = (double *)take(S * K * 8);
     w.gs = (double *)take(S * K * 8);
     w.g = (double *)take(S * (K + 1) * 8);
-    w.Aj = (double *)take(S * K * K * 8);
+    w.Uj = (double *)take(S * K * K * 8);
     w.Vj = (double *)take(S * K * K * 8);
     w.y = (double *)take(S * K * 8);
     w.y2 = (double *)take(S * K * 8);
@@ -257,6 +257,7 @@ struct IterCfg {
     int stop_kind;
     double stop_tau, rns_eps;
     const double *noise_stop;
+    double learned_gate;
     int *iters, *status;
     int learned;
     const abba_reg *reg;
@@ -313,7 +314,8 @@ static int one_iteration(const SolveDims &d, const SolveWS &ws, const IterCfg &c
         if ((rc = launch_finish_resid(d, ws, nb, st))) return rc;
     }
     if (d.ncp && (rc = launch_ncp(d, ws, yk, st))) return rc;
-    if ((rc = launch_stop(d, ws, c.stop_kind, c.stop_tau, c.rns_eps, c.noise_stop, c.iters, c.status, st)))
+    if ((rc = launch_stop(d, ws, c.stop_kind, c.stop_tau, c.rns_eps, c.noise_stop, c.learned_gate, c.iters,
+                          c.status, st)))
         return rc;
     return clock_mark(c.clk, ABBA_PHASE_OTHER);
 }
@@ -534,6 +536,7 @@ extern "C" int abba_solve_layout(const abba_op *A, const abba_op *B, int batch, 
     layout->bytes = bytes;
     layout->basis = (size_t)((char *)ws.W - base);
     layout->hessenberg = (size_t)((char *)ws.H - base);
+    layout->singular_values = (size_t)((char *)ws.sig - base);
     layout->ldw = d.ldw;
     layout->len = d.len;
     layout->basis_dtype = d.w_dt;
@@ -663,6 +666,7 @@ extern "C" int abba_solve(const abba_op *A, const abba_op *B, const void *b, voi
     cfg.stop_tau = stop ? stop->tau : 0.0;
     cfg.rns_eps = stop ? stop->rns_eps : 0.0;
     cfg.noise_stop = stop ? stop->noise_norm : nullptr;
+    cfg.learned_gate = stop ? stop->learned_gate : 0.0;
     // a restarted run counts iterations and status per cycle, then merges them
     cfg.iters = restarting ? ws.citers : out->iters;
     cfg.status = restarting ? ws.cstatus : out->status;

@@ -172,3 +172,55 @@ def test_breakdown_in_a_batch(pk):
         assert torch.equal(x1[0], x[s]) and int(i1["iters"][0]) == it[s] and int(i1["status"][0]) == st[s]
         o = osv.hybrid_gmres(og.A, og.B, bs, mode="AB", K=K, rule="gcv")
         assert it[s] == o.iters and o.status == osv.STATUS_BREAKDOWN and rel(x[s].cpu().numpy(), o.x) <= 1e-8
+
+
+def sigma_check(pk, ws, lay, S, iters):
+    """max over slices of max|sigma_GPU - sigma(H_GPU)| / sigma_1 against
+    LAPACK on the GPU's own Hessenberg matrix."""
+    _, H, sv = pk.basis_views(ws, lay, S, sigma=True)
+    worst = 0.0
+    for s in range(S):
+        k = int(iters[s])
+        Hk = np.triu(H[s, :k, :k + 1].double().cpu().numpy().T, -1)
+        ref = np.linalg.svd(Hk, compute_uv=False)
+        got = sv[s, :k].cpu().numpy()
+        worst = max(worst, float(np.max(np.abs(got - ref)) / ref[0]))
+    return worst
+
+
+@pytest.mark.parametrize("mode", ["AB", "BA"])
+def test_singular_values_of_h(pk, mode):
+    """The small solve's singular values (updated every iteration by the
+    secular equation) against LAPACK on the final H_k: FP64 64^2 at K = 30
+    and 60, and the 512^2 FP32-basis run at K = 100."""
+    for n, na, nd, eta, dt, K in ((64, 90, 91, 0.01, "f64", 30), (64, 90, 91, 0.001, "f64", 60),
+                                  (512, 720, 725, 0.005, "f32", 100)):
+        A, B, og, xt, bd = problem(pk, n, na, nd, eta, 0, 3, dt)
+        lay = pk.solve_layout(A, B, 1, mode, K)
+        ws = torch.zeros(lay["bytes"], dtype=torch.uint8, device="cuda")
+        x, info = pk.solve(A, B, bd, mode=mode, k=K, reg="gcv", workspace=ws)
+        torch.cuda.synchronize()
+        e = sigma_check(pk, ws, lay, 1, info["iters"].cpu().numpy())
+        print(f"{mode} {n}^2 {dt} K={K}: max |sigma - LAPACK sigma(H)| / sigma_1 = {e:.1e}")
+        assert e <= 1e-12
+
+
+def test_singular_values_in_a_batch(pk):
+    """A batch whose slices end at different iterations (breakdowns at k = 2
+    and k = 1 on the two-angle geometry): each slice's singular values
+    against LAPACK on its own H, and x against the oracle."""
+    n, K = 8, 6
+    A, B, og, b, bd = breakdown_problem(pk, n, 2, "AB", 5)
+    b1 = og.A(np.full(n * n, 0.7))
+    bb = torch.stack([bd[0], torch.as_tensor(b1, dtype=torch.float64, device="cuda").reshape(2, n)]).contiguous()
+    lay = pk.solve_layout(A, B, 2, "AB", K)
+    ws = torch.zeros(lay["bytes"], dtype=torch.uint8, device="cuda")
+    x, info = pk.solve(A, B, bb, mode="AB", k=K, reg="gcv", workspace=ws)
+    torch.cuda.synchronize()
+    it = info["iters"].cpu().numpy()
+    e = sigma_check(pk, ws, lay, 2, it)
+    print(f"iters {it.tolist()}: max |sigma - LAPACK| / sigma_1 = {e:.1e}")
+    assert it.tolist() == [2, 1] and e <= 1e-12
+    for s, bs in enumerate((b, b1)):
+        o = osv.hybrid_gmres(og.A, og.B, bs, mode="AB", K=K, rule="gcv")
+        assert int(it[s]) == o.iters and rel(x[s].cpu().numpy(), o.x) <= 1e-8

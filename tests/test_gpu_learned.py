@@ -245,6 +245,32 @@ def test_learned_stop_defers_to_dp(pk):
     assert rel(xg.cpu().numpy(), o.x) <= 1e-8
 
 
+def test_learned_stop_gated_by_the_discrepancy(pk):
+    """learned_gate = c: the stop index 6 is accepted only once rho_k <= c tau
+    ||e||; with c between rho_7 and rho_8 (relative to tau ||e||) the run stops
+    at k = 8 with the learned status, as the oracle does."""
+    og, x, b, en = problem(idx=5)
+    A, B = ops(pk, "f64")
+    theta = synth.mlp_init(8)
+    W4, b4 = L.unpack(theta)[3]
+    W4 *= 0.02
+    W4[1, :] = 0.0
+    b4[:] = [-0.3, 0.55 * 10 / 12]   # stop index ceil(12 * 0.458) = 6
+    K, noise = 12, 0.1 * en          # a small ||e||: the discrepancy principle does not fire
+    free = osv.hybrid_gmres(og.A, og.B, b, mode="AB", K=K, rule="learned", mlp=theta.astype(np.float64))
+    c = np.sqrt(free.rho[7] * free.rho[8]) / (1.01 * noise)
+    o = osv.hybrid_gmres(og.A, og.B, b, mode="AB", K=K, rule="learned", stop="learned", mlp=theta.astype(np.float64),
+                         noise_norm=noise, tau=1.01, learned_gate=c)
+    bd = cuda(b.reshape(1, 45, 47), torch.float64)
+    xg, info = pk.solve(A, B, bd, mode="AB", k=K, reg="learned", stop="learned", mlp=cuda(theta),
+                        noise_norm=torch.tensor([noise], dtype=torch.float64, device="cuda"), tau=1.01,
+                        learned_gate=c)
+    ex = rel(xg.cpu().numpy(), o.x)
+    print(f"gated learned stop: c = {c:.3f}, iters {int(info['iters'][0])} / oracle {o.iters}, x {ex:.2e}")
+    assert o.iters == 8 and o.status == osv.STATUS_STOP_LEARNED
+    assert int(info["iters"][0]) == 8 and int(info["status"][0]) == pk.ST_STOP_LEARNED and ex <= 1e-8
+
+
 def test_learned_training_end_to_end(pk):
     """What the trained network gains: training data from the method itself
     (256 runs at 64^2, 90 x 91, noise log-uniform in [0.1 %, 5 %], K = 60, with

@@ -41,7 +41,7 @@ def test_2d_launch_choices_bitwise_equal(pk, shape, dt):
     ya0, xb0 = pk.project(A, x), pk.backproject(B, y)
     for path, jb in [(0, 0), (1, 2), (1, 3), (1, 4)]:
         pk.set_tuning(A, S, a_path=path, a_jb=jb)
-        assert pk.get_tuning(A, S) == dict(a_path=path, a_jb=jb, b_g=0, czt=0, a_rb=0, a_occ=0)
+        assert pk.get_tuning(A, S) == dict(a_path=path, a_jb=jb, b_g=0, czt=0, a_rb=0, a_occ=0, a_tile=0)
         assert torch.equal(pk.project(A, x), ya0), (path, jb)
     for g in (1, 8, 16, 64, 128):
         pk.set_tuning(B, S, b_g=g)
@@ -71,6 +71,12 @@ def test_cone_launch_choices_bitwise_equal(pk):
         pk.set_tuning(A, 2, a_occ=occ)
         assert pk.get_tuning(A, 2)["a_occ"] == occ
         assert torch.equal(pk.project(A, x), y0), occ
+    for occ in (0, 4):                   # 16 x 16 detector tiles (ragged: 28 x 24 pixels)
+        pk.set_tuning(A, 2, a_occ=occ, a_tile=16)
+        assert pk.get_tuning(A, 2)["a_tile"] == 16
+        assert torch.equal(pk.project(A, x), y0), ("tile", occ)
+    with pytest.raises(pk.AbbaError):
+        pk.set_tuning(A, 2, a_tile=8)
 
 
 def test_autotune_keeps_a_choice(pk):
@@ -83,7 +89,7 @@ def test_autotune_keeps_a_choice(pk):
     print(f"A: {ta}\nB: {tb}")
     assert ta["candidates"] == 4 and tb["candidates"] >= 3
     assert ta["ms"] <= ta["default_ms"] and tb["ms"] <= tb["default_ms"]
-    assert pk.get_tuning(A, S) == {k: ta[k] for k in ("a_path", "a_jb", "b_g", "czt", "a_rb", "a_occ")}
+    assert pk.get_tuning(A, S) == {k: ta[k] for k in ("a_path", "a_jb", "b_g", "czt", "a_rb", "a_occ", "a_tile")}
     assert torch.equal(pk.project(A, x), ya0)
     # the solver uses the stored choice and returns the same bits
     og_b = pk.project(A, x).contiguous()
