@@ -556,8 +556,11 @@ def learned_run(args):
     t0 = time.perf_counter()
     for first in range(0, args.train_runs, SB):
         cnt = min(SB, args.train_runs - first)
-        x, b, _, _ = synth_batch(pk, At, torch, 5, first, cnt, 256, 1e-3, 5e-2)
+        x, b, en, _ = synth_batch(pk, At, torch, 5, first, cnt, 256, 1e-3, 5e-2)
+        # ||e|| is known in the training runs as in the solves that use the
+        # network (a feature is its level relative to the initial residual)
         _, info = pk.solve(At, Bt, b, mode="AB", k=K, reg="gcv", features=True, x_true=x, workspace=ws,
+                           noise_norm=en,
                            history=False)
         tg, ks = pk.mlp_labels(info["rre"], info["iters"])
         ok = torch.isfinite(tg.reshape(-1, 2)).all(dim=1)

@@ -163,17 +163,20 @@ typedef struct {
     int a_jb;          /* 2D A, LDS kernel: bins per thread and angle, 2..4 (0: 3)           */
     int b_g;           /* 2D B: angles per LDS chunk (0: built-in, at most 64 KB of LDS)      */
     int czt;           /* 3D B: voxels per thread along z, 2, 4 or 8 (0: 4)                   */
-    int a_rb;          /* 3D A: detector rows per band of the work order (0: all rows, the
-                          views outermost); the views of a band run before the next band  */
-    int a_occ;         /* 3D A: at most this many workgroups per compute unit (0: no cap),
-                          held by reserving unused LDS (at most 64 KB per workgroup, so
+    int a_rb;          /* 3D A, rows of 256 columns: detector rows per band of the work
+                          order (0: all rows, the views outermost); the views of a band
+                          run before the next band                                        */
+    int a_occ;         /* 3D A: at most this many workgroups per compute unit, held by
+                          reserving unused LDS (at most 64 KB per workgroup, so
                           a_occ >= 3 on 160 KB of LDS per CU; smaller values are
-                          ABBA_ERR_ARG): fewer rays in flight share the caches           */
+                          ABBA_ERR_ARG): fewer rays in flight share the caches.  0: no
+                          cap when a_tile or a_rb is set, else the built-in cap of 5 */
     double ms;         /* abba_autotune: mean time of one apply with the chosen launch       */
     double default_ms; /* abba_autotune: the same with the built-in rules                    */
     int candidates;    /* abba_autotune: launch choices timed besides the built-in rules     */
-    int a_tile;        /* 3D A: 0 a workgroup per 256 columns of one detector row (built-in),
-                          16 a workgroup per 16 x 16 tile of detector pixels                */
+    int a_tile;        /* 3D A: a workgroup per 16 x 16 tile of detector pixels with waves of
+                          16 x 4 (16, and the built-in 0) or 8 x 8 (8); -1: per 256
+                          columns of one detector row (also chosen by a_rb >= 1)            */
 } abba_tune;
 
 /* Device bytes abba_autotune needs for `batch` slices: an input and an output
@@ -368,9 +371,10 @@ int abba_solve(const abba_op *A, const abba_op *B, const void *b, void *x, int b
 /* ---- Learned lambda / stop index (an optional rule beside those of Sec. 3.1-3.2).
  * Features (per slice and iteration k, from quantities the method produces
  * regardless of lambda): the 32 largest singular values of H_k as
- * log10(sigma_i/sigma_1), padded with -16, and the plain GMRES residuals
- * (eq. (9)) of iterations k-31..k as log10(r_j/r_0), 0 before iteration 1;
- * all scaled by 1/8.  Network: 64 -> 128 -> 128 -> 128 -> 2 with ReLU, FP32;
+ * log10(sigma_i/sigma_1), padded with -16; log10(||e|| / ||b - A x_0||) when
+ * the noise norm is given (reg or stop noise_norm), else -16; and the plain
+ * GMRES residuals (eq. (9)) of iterations k-30..k as log10(r_j/r_0), 0 before
+ * iteration 1; all scaled by 1/8.  Network: 64 -> 128 -> 128 -> 128 -> 2 with ReLU, FP32;
  * parameters are one flat device array of ABBA_MLP_PARAMS floats:
  * W1 [128][64], b1 [128], W2 [128][128], b2 [128], W3 [128][128], b3 [128],
  * W4 [2][128], b4 [2].  Outputs: o0 = log10(lambda/sigma_1)/8, o1 = k_stop/K.

@@ -10,10 +10,14 @@ fallback and judge:
     f[i],      i < 32: log10(sigma_(i) / sigma_(1)) for the singular values of
                        H_k sorted in decreasing order, -16 where i >= k or the
                        ratio is below 1e-16;
-    f[32 + t], t < 32: log10(r_j / r_0) with j = k - 31 + t, where r_j is the
-                       plain GMRES residual of iteration j (the component of
-                       beta e_1 outside range(H_j), eq. (9)) and r_0 = beta;
-                       0 where j < 1, -16 below 1e-16.
+    f[32],             log10(||e|| / rho_0): the known noise norm relative to
+                       the initial data residual rho_0 = ||b - A x_0|| (the
+                       level the discrepancy principle stops at), -16 when
+                       ||e|| is not given;
+    f[32 + t], 1 <= t < 32: log10(r_j / r_0) with j = k - 31 + t, where r_j
+                       is the plain GMRES residual of iteration j (the
+                       component of beta e_1 outside range(H_j), eq. (9)) and
+                       r_0 = beta; 0 where j < 1, -16 below 1e-16.
   All 64 values are scaled by 1/8 (to about [-2, 0]).
 * Network: 64 -> 128 -> 128 -> 128 -> 2, ReLU after each hidden layer, linear
   output.  Parameters are one flat vector: W1 [128][64], b1 [128],
@@ -63,11 +67,12 @@ def unpack(theta):
     return out
 
 
-def features(sigma, gres):
+def features(sigma, gres, noise_rel=None):
     """The 64 features of one slice at iteration k = len(sigma).
 
-    sigma -- singular values of H_k (any order)
-    gres  -- [r_0, r_1, ..., r_k]: beta, then the GMRES residual of each iteration
+    sigma     -- singular values of H_k (any order)
+    gres      -- [r_0, r_1, ..., r_k]: beta, then the GMRES residual of each iteration
+    noise_rel -- ||e|| / ||b - A x_0||, or None when ||e|| is not known
     """
     sigma = np.asarray(sigma, dtype=np.float64)
     k = sigma.size
@@ -81,13 +86,14 @@ def features(sigma, gres):
             v = max(math.log10(s[i] / s1), PAD)
         f[i] = v
     r0 = gres[0]
-    for t in range(NRES):
+    for t in range(1, NRES):
         j = k - (NRES - 1) + t
         v = 0.0
         if j >= 1:
             v = math.log10(gres[j] / r0) if gres[j] > 0.0 else PAD
             v = max(v, PAD)
         f[NSIG + t] = v
+    f[NSIG] = max(math.log10(noise_rel), PAD) if noise_rel is not None and noise_rel > 0.0 else PAD
     return f * SCALE
 
 

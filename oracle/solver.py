@@ -231,7 +231,7 @@ def hybrid_gmres(A, B, b, mode: str = "AB", K: int = 30, rule: str = "gcv",
         if rule == "learned":
             base = ss.solve_projected(Hk, beta, "gcv")
             gres.append(base["uk1"])
-            f = lrn.features(base["sigma"], gres)
+            f = lrn.features(base["sigma"], gres, None if noise_norm is None or rho0 <= 0.0 else noise_norm / rho0)
             lam_l, _, _, o1 = lrn.judge(mlp, f, base["sigma"], base["uhat"], base["uk1"], judge_delta)
             k_hat = min(max(K * o1, 1.0), float(K))
             sol = ss.solve_projected(Hk, beta, "fixed", lam_fixed=lam_l)

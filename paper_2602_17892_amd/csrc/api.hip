@@ -474,8 +474,8 @@ int abba_op_set_tuning(abba_op *op, int batch, const abba_tune *t) {
                   (op->lds_cu + 65535) / 65536);
         return ABBA_ERR_ARG;
     }
-    if (t->a_tile != 0 && t->a_tile != 16) {
-        set_error("abba_op_set_tuning: a_tile must be 0 or 16");
+    if (t->a_tile != 0 && t->a_tile != -1 && t->a_tile != 8 && t->a_tile != 16) {
+        set_error("abba_op_set_tuning: a_tile must be 0 (built-in), -1 (rows), 8 or 16");
         return ABBA_ERR_ARG;
     }
     store_tuning(op, TuneEntry{batch, t->a_path, t->a_jb, t->b_g, t->czt, t->a_rb, t->a_occ, t->a_tile});

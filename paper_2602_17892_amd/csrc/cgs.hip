@@ -584,16 +584,23 @@ static inline int nblk_for(int64_t nvec) {
     return (int)b;
 }
 
-// 16-byte vectors of each basis vector that one block of the Gram-Schmidt
-// sweeps handles.
+// 16-byte vectors of each basis vector that one block of the dot-product
+// sweeps handles (the partial sums depend on it, so it is fixed: a single
+// slice and a batch get the same bits), and that one block of the delayed
+// update sweep handles (elementwise, any value gives the same bits; long
+// chunks keep more loads in flight per thread).
 #ifndef ABBA_CGS_CHUNK
 #define ABBA_CGS_CHUNK 512
 #endif
-int cgs_nblk(int64_t ldw, int w_dt) {
+#ifndef ABBA_CGS_UPD_CHUNK
+#define ABBA_CGS_UPD_CHUNK 4096
+#endif
+static int sweep_blocks(int64_t ldw, int w_dt, int64_t chunk) {
     const int64_t nvec = ldw / (w_dt == ABBA_F64 ? 2 : 4);
-    int64_t b = (nvec + ABBA_CGS_CHUNK - 1) / ABBA_CGS_CHUNK;
+    const int64_t b = (nvec + chunk - 1) / chunk;
     return (int)std::min<int64_t>(1024, std::max<int64_t>(1, b));
 }
+int cgs_nblk(int64_t ldw, int w_dt) { return sweep_blocks(ldw, w_dt, ABBA_CGS_CHUNK); }
 
 template <typename TW>
 static int launch_dots(TW *W, const SolveDims &d, double *part, int nblk, int extra, int jtiles,
@@ -669,8 +676,9 @@ static int dcgs2_step_t(const SolveDims &d, const SolveWS &ws, const int *kdev, 
     hipLaunchKernelGGL(dclose_k, dim3(d.S), dim3(128), 0, st, ws.c, ws.h, d.K + 2, ws.H, ws.T, ws.gd, d.K + 2, d.K,
                        ws.sc, ws.flags, kdev ? kdev : ws.kdev, ws.active);
     ABBA_LAUNCHED("dclose_k");
-    hipLaunchKernelGGL(dupdate_k<TW>, dim3(nblk, 1, d.S), dim3(256), 0, st, W, wsl, d.ldw, (const double *)ws.c,
-                       d.K + 2, (const double *)ws.gd, d.K + 2, (const double *)ws.sc, nblk, kdev, ws.active);
+    const int nblk_u = sweep_blocks(d.ldw, d.w_dt, ABBA_CGS_UPD_CHUNK);
+    hipLaunchKernelGGL(dupdate_k<TW>, dim3(nblk_u, 1, d.S), dim3(256), 0, st, W, wsl, d.ldw, (const double *)ws.c,
+                       d.K + 2, (const double *)ws.gd, d.K + 2, (const double *)ws.sc, nblk_u, kdev, ws.active);
     ABBA_LAUNCHED("dupdate_k");
     return ABBA_OK;
 }

@@ -266,13 +266,13 @@ __device__ __forceinline__ void plane_range(double c0, double dc, int n, int np,
 // views outermost); bands of a few rows, whose rays in flight on one XCD
 // cross a thin slab of the volume, are a launch choice (measured slower on
 // the 256^3 problem: the taps are limited by the gathers, not by L2 reuse).
-// With TILE the workgroup is a 16 x 16 tile of detector pixels of one view
-// (a wave 16 columns x 4 rows; work order (slice, view, tile row, tile
-// column)), nbu and rb then being the tiles per detector row and column.
-// The even and odd steps are summed by the parity of the plane index, and
-// steps outside a ray's own range read pad zeros, so every decomposition
-// gives the same bits.
-template <typename TI, typename TO, bool TILE>
+// With TILE = 16 the workgroup is a 16 x 16 tile of detector pixels of one
+// view and a wave 16 columns x 4 rows of it; with TILE = 8 a wave is an 8 x 8
+// quarter of the tile (work order (slice, view, tile row, tile column)); nbu
+// and rb are then the tiles per detector row and column.  The even and odd
+// steps are summed by the parity of the plane index, and steps outside a
+// ray's own range read pad zeros, so every decomposition gives the same bits.
+template <typename TI, typename TO, int TILE>
 __global__ __launch_bounds__(256) void cone_fwd_k(const TI *__restrict__ vx, const TI *__restrict__ vy,
                                                   const TI *__restrict__ vz, int64_t sx, int64_t sy, int64_t szz,
                                                   VecRef yr, const ConeView *__restrict__ views, int nx, int ny,
@@ -290,8 +290,14 @@ __global__ __launch_bounds__(256) void cone_fwd_k(const TI *__restrict__ vx, con
         const uint32_t w3 = w2 / (uint32_t)rb;
         vw = (int)(w3 % (uint32_t)nviews);
         s = s0 + (int)(w3 / (uint32_t)nviews);
-        c = tu * 16 + (int)(threadIdx.x & 15);
-        r = tv * 16 + (int)(threadIdx.x >> 4);
+        const int l = (int)(threadIdx.x & 63), wv = (int)(threadIdx.x >> 6);
+        if (TILE == 16) {
+            c = tu * 16 + (l & 15);
+            r = tv * 16 + wv * 4 + (l >> 4);
+        } else {
+            c = tu * 16 + (wv & 1) * 8 + (l & 7);
+            r = tv * 16 + (wv >> 1) * 8 + (l >> 3);
+        }
         live = c < nu && r < nv;
         if (r >= nv) r = nv - 1;   // a dead lane of a ragged tile still computes a valid ray
     } else {
@@ -510,12 +516,17 @@ static int cone_fwd_t(const abba_op *op, VecRef x, VecRef y, int batch, void *sc
     if (std::max({cc.vx, cc.vy, cc.vz}) >= (size_t)1 << 31) return ABBA_ERR_UNSUPPORTED;
     int nbu = (g.det_u + 255) / 256;
     int rb = g.det_v;
-    bool tile = false;
-    size_t cap_lds = 0;   // unused LDS per workgroup that caps the workgroups per CU
+    // built-in: 16 x 16 detector tiles, waves of 16 x 4, at most 5
+    // workgroups per CU (measured at 256^3 / 360 x 384^2: 13.2 ms for
+    // 256-column rows, 9.6 ms for tiles, 7.8 ms for tiles with the cap)
+    int tile = 16;
+    size_t cap_lds = (size_t)op->lds_cu / 5 / 512 * 512;   // unused LDS that caps the workgroups per CU
     if (const TuneEntry *t = tune_for(op, batch)) {
         if (t->a_rb >= 1) rb = std::min(t->a_rb, g.det_v);
         if (t->a_occ >= 1) cap_lds = std::min<size_t>(65536, (size_t)op->lds_cu / (size_t)t->a_occ / 512 * 512);
-        tile = t->a_tile == 16;
+        else if (t->a_occ == 0 && (t->a_tile != 0 || t->a_rb >= 1)) cap_lds = 0;
+        if (t->a_tile == -1 || t->a_rb >= 1) tile = 0;
+        else if (t->a_tile == 8 || t->a_tile == 16) tile = t->a_tile;
     }
     int nrb = (g.det_v + rb - 1) / rb;
     if (tile) {   // tiles per detector row (nbu) and per column (rb); one band
@@ -528,16 +539,15 @@ static int cone_fwd_t(const abba_op *op, VecRef x, VecRef y, int batch, void *sc
     const int ch = (int)std::min<uint64_t>((uint64_t)batch, CMAX_GROUPS / per);
     for (int s0 = 0; s0 < batch; s0 += ch) {
         const int nb = std::min(ch, batch - s0);
-        if (tile)
-            hipLaunchKernelGGL((cone_fwd_k<TI, TO, true>), dim3((uint32_t)(per * nb)), dim3(256), cap_lds, L.stream, vx,
-                               vy, vz, (int64_t)cc.vx, (int64_t)cc.vy, (int64_t)cc.vz, y, (const ConeView *)op->tab,
-                               g.nx, g.ny, g.nz, g.n_angles, g.det_u, g.det_v, g.det_pitch_u, g.det_pitch_v, nbu, rb,
-                               nrb, (uint32_t)op->nxcc, s0, L.kdev, L.active);
-        else
-            hipLaunchKernelGGL((cone_fwd_k<TI, TO, false>), dim3((uint32_t)(per * nb)), dim3(256), cap_lds, L.stream,
-                               vx, vy, vz, (int64_t)cc.vx, (int64_t)cc.vy, (int64_t)cc.vz, y,
-                               (const ConeView *)op->tab, g.nx, g.ny, g.nz, g.n_angles, g.det_u, g.det_v,
-                               g.det_pitch_u, g.det_pitch_v, nbu, rb, nrb, (uint32_t)op->nxcc, s0, L.kdev, L.active);
+#define CONE_FWD(TL)                                                                                              \
+    hipLaunchKernelGGL((cone_fwd_k<TI, TO, TL>), dim3((uint32_t)(per * nb)), dim3(256), cap_lds, L.stream, vx, vy, vz, \
+                       (int64_t)cc.vx, (int64_t)cc.vy, (int64_t)cc.vz, y, (const ConeView *)op->tab, g.nx, g.ny,     \
+                       g.nz, g.n_angles, g.det_u, g.det_v, g.det_pitch_u, g.det_pitch_v, nbu, rb, nrb,               \
+                       (uint32_t)op->nxcc, s0, L.kdev, L.active)
+        if (tile == 16) CONE_FWD(16);
+        else if (tile == 8) CONE_FWD(8);
+        else CONE_FWD(0);
+#undef CONE_FWD
         ABBA_LAUNCHED("cone_fwd_k");
     }
     return ABBA_OK;
@@ -611,12 +621,15 @@ int cone_tune_candidates(const abba_op *op, TuneEntry *out, int cap) {
         for (int c : {2, 4, 8})
             if (n < cap) out[n++] = TuneEntry{0, 0, 0, 0, c, 0};
     if (op->kind == ABBA_OP_JOSEPH) {
-        for (int r : {2, 8, 32})
-            if (n < cap && r < op->g.det_v) out[n++] = TuneEntry{0, 0, 0, 0, 0, r, 0};
-        for (int c : {5, 4})
-            if (n < cap) out[n++] = TuneEntry{0, 0, 0, 0, 0, 0, c};
-        for (int c : {0, 5, 4})
-            if (n < cap) out[n++] = TuneEntry{0, 0, 0, 0, 0, 0, c, 16};
+        // 256-column rows (views outermost, or bands of rows), 16 x 16 tiles
+        // with waves of 16 x 4 or 8 x 8, and caps of the workgroups per CU
+        if (n < cap) out[n++] = TuneEntry{0, 0, 0, 0, 0, 0, 5, -1};
+        for (int r : {8, 32})
+            if (n < cap && r < op->g.det_v) out[n++] = TuneEntry{0, 0, 0, 0, 0, r, 5};
+        for (int t : {16, 8})
+            for (int c : {6, 5, 4})
+                if (n < cap) out[n++] = TuneEntry{0, 0, 0, 0, 0, 0, c, t};
+        if (n < cap) out[n++] = TuneEntry{0, 0, 0, 0, 0, 0, 0, 8};
     }
     return n;
 }

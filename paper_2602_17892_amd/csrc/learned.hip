@@ -271,7 +271,8 @@ __device__ __forceinline__ double clamp_log(double v) { return v < PADV ? PADV :
 
 // Features of every active slice at iteration k (after the small solve).
 __global__ __launch_bounds__(128) void feat_k(const double *__restrict__ sig, const double *__restrict__ sc,
-                                             double *__restrict__ gres, float *__restrict__ feat,
+                                             double *__restrict__ gres, const double *__restrict__ noise,
+                                             const double *__restrict__ rhoh, float *__restrict__ feat,
                                              float *__restrict__ fhist, int K, const int *kdev, const int *active) {
     const int s = blockIdx.x;
     if (!active[s]) return;
@@ -298,6 +299,10 @@ __global__ __launch_bounds__(128) void feat_k(const double *__restrict__ sig, co
         if (t < 32) {
             const double s1 = srt[0];
             f = (t < k && s1 > 0.0 && srt[t] > 0.0) ? clamp_log(log10(srt[t] / s1)) : PADV;
+        } else if (t == 32) {
+            // ||e|| relative to the initial data residual, when ||e|| is given
+            const double e = noise ? noise[s] : 0.0, r0 = rhoh[(int64_t)s * (K + 1)];
+            f = (e > 0.0 && r0 > 0.0) ? clamp_log(log10(e / r0)) : PADV;
         } else {
             const int j = k - 31 + (t - 32);
             f = 0.0;
@@ -566,9 +571,9 @@ int learned_prepare(const SolveDims &d, const SolveWS &ws, const void *x0, const
 }
 
 int learned_step(const SolveDims &d, const SolveWS &ws, const abba_reg *reg, int learned, const void *x0,
-                 const abba_out *out, hipStream_t st) {
+                 const abba_out *out, const double *noise, hipStream_t st) {
     int rc;
-    hipLaunchKernelGGL(feat_k, dim3(d.S), dim3(128), 0, st, ws.sig, ws.sc, ws.gres, ws.feat,
+    hipLaunchKernelGGL(feat_k, dim3(d.S), dim3(128), 0, st, ws.sig, ws.sc, ws.gres, noise, ws.rhoh, ws.feat,
                        d.feat_out ? out->features : nullptr, d.K, ws.kdev, ws.active);
     ABBA_LAUNCHED("feat_k");
     if (learned) {

@@ -47,7 +47,7 @@ int smallsolve_prepare();
 int learned_prepare(const SolveDims &d, const SolveWS &ws, const void *x0, const abba_out *out, hipStream_t st);
 int launch_ncp(const SolveDims &d, const SolveWS &ws, const double *coef_ba, hipStream_t st);
 int learned_step(const SolveDims &d, const SolveWS &ws, const abba_reg *reg, int learned, const void *x0,
-                 const abba_out *out, hipStream_t st);
+                 const abba_out *out, const double *noise, hipStream_t st);
 
 static inline int64_t round_up(int64_t v, int64_t a) { return (v + a - 1) / a * a; }
 
@@ -298,7 +298,9 @@ static int one_iteration(const SolveDims &d, const SolveWS &ws, const IterCfg &c
     if ((rc = clock_mark(c.clk, ABBA_PHASE_SMALL))) return rc;
     if ((rc = launch_smallsolve(d, ws, c.rule, c.lam_fixed, c.tau, c.noise_reg, st))) return rc;
     if (c.learned || d.feat_out || d.labels) {
-        if ((rc = learned_step(d, ws, c.reg, c.learned, c.x0, c.out, st))) return rc;
+        if ((rc = learned_step(d, ws, c.reg, c.learned, c.x0, c.out, c.noise_stop ? c.noise_stop : c.noise_reg,
+                               st)))
+            return rc;
     }
     const double *yk = ws.y;
     if (d.mode == ABBA_MODE_BA && d.keepZ) {

@@ -125,12 +125,14 @@ def ops(pk, dt, n=32, na=45, nd=47):
 
 @pytest.mark.parametrize("dt", ["f64", "f32"])
 def test_solver_features(pk, dt):
-    og, x, b, _ = problem()
+    og, x, b, en = problem()
     A, B = ops(pk, dt)
     tdt = torch.float64 if dt == "f64" else torch.float32
     bd = cuda(b.reshape(1, 45, 47), tdt)
     K = 12
-    _, info = pk.solve(A, B, bd, mode="AB", k=K, reg="gcv", features=True)
+    # ||e|| given (feature 32 is its level relative to the initial residual)
+    _, info = pk.solve(A, B, bd, mode="AB", k=K, reg="gcv", features=True,
+                       noise_norm=torch.tensor([en], dtype=torch.float64, device="cuda"))
     F = info["features"][0].cpu().numpy()
     bu = bd.double().cpu().numpy().ravel()
 
@@ -139,7 +141,7 @@ def test_solver_features(pk, dt):
         gres, out = [o.beta], []
         for sig, _, uk1 in o.small:
             gres.append(uk1)
-            out.append(L.features(sig, gres))
+            out.append(L.features(sig, gres, en / o.rho[0]))
         return np.array(out)
 
     Fo = oracle_features(og.A, og.B)
@@ -294,8 +296,9 @@ def test_learned_training_end_to_end(pk):
         return xs, torch.stack(rows).to(torch.float32).contiguous(), torch.tensor(en, dtype=torch.float64,
                                                                                   device="cuda")
 
-    xt, b, _ = batch(5, 256)
-    _, info = pk.solve(A, B, b, mode="AB", k=K, reg="gcv", features=True, x_true=xt)
+    xt, b, en_t = batch(5, 256)
+    # the training runs know ||e|| as the solves that use the network will
+    _, info = pk.solve(A, B, b, mode="AB", k=K, reg="gcv", features=True, x_true=xt, noise_norm=en_t)
     tg, ks = pk.mlp_labels(info["rre"], info["iters"])
     X = info["features"].reshape(-1, 64)
     T = tg.reshape(-1, 2)

@@ -481,13 +481,21 @@ def test_bf16_sinogram_solves(pk, ortho):
     o16 = osv.hybrid_gmres(lambda v: bf16_round(og.A(v)), og.B, bu[0], mode="BA", K=K, rule="gcv", ortho=ortho)
     o64 = osv.hybrid_gmres(og.A, og.B, bu[0], mode="BA", K=K, rule="gcv", ortho=ortho)
     e16, e64 = rel(xb.double().cpu().numpy(), o16.x), rel(xb.double().cpu().numpy(), o64.x)
+    # against the canonical two-pass CGS2 oracle with BF16 stores, gated at
+    # 3x the oracle's own gap between its two schedules under BF16 storage
+    A16 = lambda v: bf16_round(og.A(v))
+    oc = osv.hybrid_gmres(A16, og.B, bu[0], mode="BA", K=K, rule="gcv", ortho="cgs2")
+    od = osv.hybrid_gmres(A16, og.B, bu[0], mode="BA", K=K, rule="gcv", ortho="dcgs2")
+    gap = rel(od.x, oc.x)
+    ec = rel(xb.double().cpu().numpy(), oc.x)
     xa, ia = pk.solve(A, B, bd, mode="AB", k=K, reg="gcv", ortho=ortho)
     oa = osv.hybrid_gmres(og.A, og.B, bu[0], mode="AB", K=K, rule="gcv", ortho=ortho)
     ea = rel(xa.double().cpu().numpy(), oa.x)
-    print(f"BF16 sinogram ({ortho}): BA x vs oracle with BF16 stores {e16:.2e}, vs FP64 {e64:.2e}; "
-          f"AB x vs FP64 on the rounded b {ea:.2e}")
+    print(f"BF16 sinogram ({ortho}): BA x vs oracle with BF16 stores {e16:.2e} (same schedule), {ec:.2e} "
+          f"(two-pass CGS2; gate {max(1e-4, 3 * gap):.1e} from the oracle's schedule gap {gap:.1e}), vs FP64 "
+          f"{e64:.2e}; AB x vs FP64 on the rounded b {ea:.2e}")
     assert int(ib["iters"][0]) == K and int(ia["iters"][0]) == K
-    assert e16 <= 1e-4 and e64 <= 2.0 ** -7 and ea <= 1e-4
+    assert e16 <= 1e-4 and e64 <= 2.0 ** -7 and ea <= 1e-4 and ec <= max(1e-4, 3.0 * gap)
 
 
 def test_ncp_stop_batch_f32(pk):

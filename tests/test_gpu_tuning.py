@@ -71,12 +71,12 @@ def test_cone_launch_choices_bitwise_equal(pk):
         pk.set_tuning(A, 2, a_occ=occ)
         assert pk.get_tuning(A, 2)["a_occ"] == occ
         assert torch.equal(pk.project(A, x), y0), occ
-    for occ in (0, 4):                   # 16 x 16 detector tiles (ragged: 28 x 24 pixels)
-        pk.set_tuning(A, 2, a_occ=occ, a_tile=16)
-        assert pk.get_tuning(A, 2)["a_tile"] == 16
-        assert torch.equal(pk.project(A, x), y0), ("tile", occ)
+    for tile, occ in ((16, 0), (16, 4), (8, 0), (8, 5), (-1, 0)):   # tiles (ragged: 28 x 24 pixels), rows
+        pk.set_tuning(A, 2, a_occ=occ, a_tile=tile)
+        assert pk.get_tuning(A, 2)["a_tile"] == tile
+        assert torch.equal(pk.project(A, x), y0), ("tile", tile, occ)
     with pytest.raises(pk.AbbaError):
-        pk.set_tuning(A, 2, a_tile=8)
+        pk.set_tuning(A, 2, a_tile=4)
 
 
 def test_autotune_keeps_a_choice(pk):

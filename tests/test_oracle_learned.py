@@ -44,22 +44,28 @@ def test_features_hand_example():
     f = L.features([0.5, 2.0, 0.02], [4.0, 2.0, 0.4, 0.04])
     want = np.full(64, -2.0)
     want[0], want[1], want[2] = 0.0, math.log10(0.25) / 8, -2.0 / 8
-    want[32:] = 0.0
+    want[33:] = 0.0
+    want[32] = -2.0                       # no noise norm given
     want[61], want[62], want[63] = math.log10(0.5) / 8, -1.0 / 8, -2.0 / 8
     assert np.allclose(f, want, rtol=0, atol=1e-15)
+    # with ||e|| = 1 % of the initial data residual only feature 32 changes
+    g = L.features([0.5, 2.0, 0.02], [4.0, 2.0, 0.4, 0.04], noise_rel=0.01)
+    want[32] = -2.0 / 8
+    assert np.allclose(g, want, rtol=0, atol=1e-15)
+    assert L.features([1.0], [1.0, 0.5], noise_rel=1e-20)[32] == -2.0   # clamped at -16 / 8
 
 
 def test_features_padding_and_zeros():
     f = L.features([3.0, 0.0], [1.0, 0.0, 1e-20])
     assert f[0] == 0.0 and f[1] == -2.0 and np.all(f[2:32] == -2.0)
-    assert f[62] == -2.0 and f[63] == -2.0 and np.all(f[32:62] == 0.0)
+    assert f[62] == -2.0 and f[63] == -2.0 and np.all(f[33:62] == 0.0) and f[32] == -2.0
     # more than 32 iterations: only the 32 largest sigma and the last 32 residuals
     k = 40
     sig = 2.0 ** -np.arange(k)
     g = [1.0] + [10.0 ** -(j / 10) for j in range(1, k + 1)]
     f = L.features(sig[::-1], g)
     assert np.allclose(f[:32] * 8, np.log10(2.0 ** -np.arange(32)))
-    assert np.allclose(f[32:] * 8, [-(j / 10) for j in range(9, 41)])
+    assert np.allclose(f[33:] * 8, [-(j / 10) for j in range(10, 41)])
 
 
 def test_forward_closed_form():
