@@ -590,7 +590,7 @@ static inline int nblk_for(int64_t nvec) {
 // update sweep handles (elementwise, any value gives the same bits; long
 // chunks keep more loads in flight per thread).
 #ifndef ABBA_CGS_CHUNK
-#define ABBA_CGS_CHUNK 512
+#define ABBA_CGS_CHUNK 4096
 #endif
 #ifndef ABBA_CGS_UPD_CHUNK
 #define ABBA_CGS_UPD_CHUNK 4096

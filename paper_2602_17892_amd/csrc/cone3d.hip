@@ -459,7 +459,7 @@ __global__ __launch_bounds__(256) void cone_bp_k(const typename acc_of<TI>::type
         const T bu = fma(X, b.eup[0], fma(Y, b.eup[1], -b.Su));
         const T bv = fma(X, b.evp[0], fma(Y, b.evp[1], -b.Sv));
         // the view is the same for the whole workgroup: 32-bit byte offsets
-        // from its base (a padded view has < 2^30 entries)
+        // from its base (the launcher requires a padded view of < 2^32 bytes)
         const T *view = Ys + (int64_t)vw * Lv * Lu;
 #pragma unroll
         for (int m = 0; m < CZT; ++m) {
@@ -573,7 +573,8 @@ static int cone_bp_launch(const abba_op *op, const typename acc_of<TI>::type *yp
     const int ntx = (g.nx + 15) / 16, nty = (g.ny + 15) / 16, ntz = (g.nz + CZT - 1) / CZT;
     const uint64_t per = (uint64_t)ntx * nty * ntz;
     if (per > CMAX_GROUPS) return ABBA_ERR_UNSUPPORTED;
-    if ((int64_t)(g.det_u + 2 * CPAD) * (g.det_v + 2 * CPAD) >= (int64_t)1 << 30) return ABBA_ERR_UNSUPPORTED;
+    if ((int64_t)(g.det_u + 2 * CPAD) * (g.det_v + 2 * CPAD) * (int64_t)sizeof(T) >= (int64_t)1 << 32)
+        return ABBA_ERR_UNSUPPORTED;
     const int ch = (int)std::min<uint64_t>((uint64_t)batch, CMAX_GROUPS / per);
     const size_t bytes_d = sizeof(ConeView) * g.n_angles;
     const ConeB<T> *vb = reinterpret_cast<const ConeB<T> *>((const unsigned char *)op->tab + bytes_d);
