@@ -78,6 +78,9 @@ def parse():
                         "with GCV + DP; variants: the benchmark batch with restarted cycles and with the NCP "
                         "stop, and the 1024^2 fan-beam problem")
     p.add_argument("--train-runs", type=int, default=4096)
+    p.add_argument("--train-n", type=int, default=256,
+                   help="image size of the learned rule's training runs (angles and bins scale with it: "
+                        "720 x 725 at 512)")
     p.add_argument("--eval-slices", type=int, default=1024)
     p.add_argument("--epochs", type=int, default=20)
     p.add_argument("--learned-variants", default="0.05:0",
@@ -196,20 +199,25 @@ def joseph_ray_steps(n, n_angles, n_det, ds=1.0):
     return int(cnt.sum())
 
 
-def kernel_source_digest():
-    """Digest of the sources that define the 2D projector kernels (their code
-    and launch constants)."""
+SOURCES_2D = ("proj2d.hip", "ops.h")
+SOURCES_CONE = ("cone3d.hip", "ops.h")
+
+
+def kernel_source_digest(files=SOURCES_2D):
+    """Digest of the sources that define a family of projector kernels (their
+    code and launch constants): the 2D ones by default, SOURCES_CONE for the
+    cone-beam pair."""
     import hashlib
     h = hashlib.sha256()
-    for name in ("proj2d.hip", "ops.h"):
+    for name in files:
         with open(os.path.join(ROOT, "paper_2602_17892_amd", "csrc", name), "rb") as f:
             h.update(f.read())
     return h.hexdigest()[:16]
 
 
-def recorded_traffic(kernel):
+def recorded_traffic(kernel, files=SOURCES_2D):
     """HBM bytes per launch of `kernel` from the committed counter summary, or
-    None when there is none or the projector source changed since."""
+    None when there is none or the projector source (`files`) changed since."""
     path = os.path.join(PROFILES, f"{kernel}_traffic.md")
     if not os.path.exists(path):
         return None
@@ -219,7 +227,7 @@ def recorded_traffic(kernel):
             if line.startswith("- ") and " = " in line:
                 k, v = line[2:].split(" = ", 1)
                 vals[k.strip()] = v.strip().strip("`")
-    if vals.get("source_digest") != kernel_source_digest():
+    if vals.get("source_digest") != kernel_source_digest(files):
         return None
     try:
         return float(vals["hbm_bytes_per_launch"])
@@ -241,7 +249,8 @@ def projectors_only(args):
     reps = 3
     gen = torch.Generator(device="cuda")
     gen.manual_seed(2)
-    info = {"projectors_only": True, "reps": reps, "source_digest": kernel_source_digest()}
+    info = {"projectors_only": True, "reps": reps,
+            "source_digest": kernel_source_digest(SOURCES_CONE if args.workload == "cone" else SOURCES_2D)}
     if args.workload == "cone":
         C = CONE
         n = C["n"]
@@ -460,7 +469,7 @@ def cone_workload(args):
     A32 = pk.Operator("joseph", g, "f32", "f32")
     tune = {"A": pk.autotune(A, 1), "B": pk.autotune(B, 1)}
     log(args, "autotune: " + "; ".join(f"{k} {v['ms']:.2f} ms (built-in {v['default_ms']:.2f}), choice "
-                                       f"{ {c: v[c] for c in ('czt', 'a_rb', 'a_occ', 'a_tile')} }" for k, v in tune.items()))
+                                       f"{ {c: v[c] for c in ('czt', 'a_rb', 'a_occ', 'a_tile', 'a_vg')} }" for k, v in tune.items()))
     t0 = time.perf_counter()
     vol, _ = synth.phantom3d(4, 0, n, device=torch.device("cuda"))
     xt = vol.to(torch.float32).reshape(1, n, n, n).contiguous()
@@ -514,13 +523,14 @@ def cone_workload(args):
         "config": {"workload": f"{n}^3 cone beam, {C['views']} views x {C['nv']}x{C['nu']} detector at pitch "
                                f"{C['pitch']}, SID {C['sid']:g}, SDD {C['sdd']:g}, hybrid BA-GMRES GCV, k {K}"},
         "rre": rre,
-        "autotune": {k: {"choice": {c: v[c] for c in ("czt", "a_rb", "a_occ", "a_tile")}, "ms": round(v["ms"], 3),
+        "autotune": {k: {"choice": {c: v[c] for c in ("czt", "a_rb", "a_occ", "a_tile", "a_vg")}, "ms": round(v["ms"], 3),
                          "builtin_ms": round(v["default_ms"], 3)} for k, v in tune.items()},
         "projector": {"A_ms": round(t_A * 1e3, 3), "B_ms": round(t_B * 1e3, 3), "A_TFLOPs": round(tf_A, 3),
                       "B_TFLOPs": round(tf_B, 3), "A_plane_crossings": steps, "B_voxel_view_pairs": pairs,
                       "A_GBps": round(bytes_apply / t_A / 1e9, 2), "B_GBps": round(bytes_apply / t_B / 1e9, 2)},
         "roofline": {"bound": "alu", "achieved": round(dom[1], 3), "peak": round(VALU_PEAK_TFLOPS, 1),
-                     "unit": "TFLOP/s", "frac": round(dom[1] / VALU_PEAK_TFLOPS, 4), "traffic": None,
+                     "unit": "TFLOP/s", "frac": round(dom[1] / VALU_PEAK_TFLOPS, 4),
+                     "traffic": recorded_traffic(dom[0], SOURCES_CONE),
                      "kernel": dom[0], "ms_per_launch": round(dom[2] * 1e3, 3)},
     }
     if not args.no_cpu_baseline:
@@ -538,8 +548,9 @@ def learned_workload(args):
 
 def learned_run(args):
     """Training: runs of hybrid AB-GMRES (K = 100, GCV) on 256^2 random-ellipse
-    slices, 360 angles x 363 bins, noise log-uniform in [0.1%, 5%], with the
-    features and the RRE label grids of every iteration; Adam on the network.
+    slices, 360 angles x 363 bins (--train-n scales the three), noise
+    log-uniform in [0.1%, 5%], with the features and the RRE label grids of
+    every iteration; Adam on the network.
     Evaluation: fresh 512^2 slices, 720 x 725, same noise range; GCV + DP
     against the learned lambda and stop (with DP first), batches of 256."""
     import numpy as np
@@ -549,14 +560,15 @@ def learned_run(args):
     import synth
     torch.cuda.set_device(0)
     K, SB = args.kmax, 256
-    gt = pk.Geometry(256, 256, 360, 363)
+    nt = args.train_n
+    gt = pk.Geometry(nt, nt, nt * 360 // 256, math.ceil(nt * math.sqrt(2)))   # 360 x 363 at 256
     At, Bt = pk.Operator("joseph", gt, "f32", "f32"), pk.Operator("pixel", gt, "f32", "f32")
     ws = torch.empty(pk.workspace_bytes(At, Bt, SB, "AB", K, labels=True), dtype=torch.uint8, device="cuda")
     Xs, Ts, kst = [], [], []
     t0 = time.perf_counter()
     for first in range(0, args.train_runs, SB):
         cnt = min(SB, args.train_runs - first)
-        x, b, en, _ = synth_batch(pk, At, torch, 5, first, cnt, 256, 1e-3, 5e-2)
+        x, b, en, _ = synth_batch(pk, At, torch, 5, first, cnt, nt, 1e-3, 5e-2)
         # ||e|| is known in the training runs as in the solves that use the
         # network (a feature is its level relative to the initial residual)
         _, info = pk.solve(At, Bt, b, mode="AB", k=K, reg="gcv", features=True, x_true=x, workspace=ws,
@@ -651,7 +663,7 @@ def learned_run(args):
         "vs_baseline": None,
         "dtype": "f32 projectors+basis+network, f64 reductions and small solves",
         "data": "synthetic: seeded random-ellipse phantoms; training labels from the true images",
-        "config": {"workload": f"train on {args.train_runs} runs at 256^2 (360 x 363, K {K}), evaluate on "
+        "config": {"workload": f"train on {args.train_runs} runs at {nt}^2 ({gt.n_angles} x {gt.det_u}, K {K}), evaluate on "
                                f"{E} slices at 512^2 (720 x 725), eta log-uniform [0.1%,5%]"},
         "gcv_dp": {"slices_per_s": round(E / res["gcv"]["t"], 3), "iters_mean": float(res["gcv"]["iters"].mean()),
                    "rre_median": float(np.median(res["gcv"]["rre"]))},

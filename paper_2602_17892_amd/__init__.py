@@ -70,7 +70,7 @@ class _Out(ctypes.Structure):
 class _Tune(ctypes.Structure):
     _fields_ = [("a_path", ctypes.c_int), ("a_jb", ctypes.c_int), ("b_g", ctypes.c_int), ("czt", ctypes.c_int),
                 ("a_rb", ctypes.c_int), ("a_occ", ctypes.c_int), ("ms", ctypes.c_double), ("default_ms", ctypes.c_double),
-                ("candidates", ctypes.c_int), ("a_tile", ctypes.c_int)]
+                ("candidates", ctypes.c_int), ("a_tile", ctypes.c_int), ("a_vg", ctypes.c_int)]
 
 
 class _Layout(ctypes.Structure):
@@ -361,7 +361,8 @@ def backproject(B: Operator, y, out=None, workspace=None):
 
 
 def _tune_dict(t):
-    return dict(a_path=t.a_path, a_jb=t.a_jb, b_g=t.b_g, czt=t.czt, a_rb=t.a_rb, a_occ=t.a_occ, a_tile=t.a_tile)
+    return dict(a_path=t.a_path, a_jb=t.a_jb, b_g=t.b_g, czt=t.czt, a_rb=t.a_rb, a_occ=t.a_occ, a_tile=t.a_tile,
+                a_vg=t.a_vg)
 
 
 def autotune(op: Operator, batch: int, reps: int = 3, workspace=None):
@@ -377,12 +378,13 @@ def autotune(op: Operator, batch: int, reps: int = 3, workspace=None):
     return dict(_tune_dict(t), ms=t.ms, default_ms=t.default_ms, candidates=t.candidates)
 
 
-def set_tuning(op: Operator, batch: int, a_path=-1, a_jb=0, b_g=0, czt=0, a_rb=0, a_occ=0, a_tile=0, clear=False):
+def set_tuning(op: Operator, batch: int, a_path=-1, a_jb=0, b_g=0, czt=0, a_rb=0, a_occ=0, a_tile=0, a_vg=0,
+               clear=False):
     """Fix the launch choices of `op` for `batch` (clear=True forgets them)."""
     if clear:
         _check(lib.abba_op_set_tuning(op.handle, int(batch), None), "abba_op_set_tuning")
         return
-    t = _Tune(a_path, a_jb, b_g, czt, a_rb, a_occ, 0.0, 0.0, 0, a_tile)
+    t = _Tune(a_path, a_jb, b_g, czt, a_rb, a_occ, 0.0, 0.0, 0, a_tile, a_vg)
     _check(lib.abba_op_set_tuning(op.handle, int(batch), ctypes.byref(t)), "abba_op_set_tuning")
 
 

@@ -258,38 +258,47 @@ __device__ __forceinline__ void plane_range(double c0, double dc, int n, int np,
     hi = min(hi, (int)ceil(h) + 1);
 }
 
-// A: one thread per ray; a wave is 64 consecutive detector columns of one
-// row of one view.  When all its rays share the dominant axis, the wave walks
-// the union of their plane ranges in lockstep.  Work order: (slice, band of
-// rb detector rows, view, row in the band, column block), dealt to the XCDs
-// in contiguous ranges.  The built-in choice is one band of all rows (the
-// views outermost); bands of a few rows, whose rays in flight on one XCD
-// cross a thin slab of the volume, are a launch choice (measured slower on
-// the 256^3 problem: the taps are limited by the gathers, not by L2 reuse).
-// With TILE = 16 the workgroup is a 16 x 16 tile of detector pixels of one
-// view and a wave 16 columns x 4 rows of it; with TILE = 8 a wave is an 8 x 8
-// quarter of the tile (work order (slice, view, tile row, tile column)); nbu
-// and rb are then the tiles per detector row and column.  The even and odd
+// A: one thread per ray.  When all the rays of a wave share the dominant
+// axis, the wave walks the union of their plane ranges in lockstep.  Two
+// launch shapes, dealt to the XCDs in contiguous ranges of workgroups:
+// TILE = 0: a workgroup is 256 consecutive detector columns of one row of one
+// view; work order (slice, band of rb detector rows, view, row in the band,
+// column block), one band of all rows by default (the views outermost).
+// TILE = 16: the workgroup is a 16 x 16 tile of detector pixels of one view
+// and a wave 16 columns x 4 rows of it; with TILE = 8 a wave is an 8 x 8
+// quarter of the tile; nbu and rb are then the tiles per detector row and
+// column.  Tile work order: (slice, group of vg views, tile row, tile column,
+// view in the group), ngv groups (the last may be ragged); vg = 1 puts the
+// views outermost, larger groups run neighbouring views of one tile next to
+// each other, whose rays cross nearly the same voxels.  The even and odd
 // steps are summed by the parity of the plane index, and steps outside a
 // ray's own range read pad zeros, so every decomposition gives the same bits.
+// clamp to [lo, hi] (one median-of-three instruction in FP32; equal to
+// fmin(fmax(x, lo), hi) for every finite x)
+__device__ __forceinline__ float cclamp(float x, float lo, float hi) { return __builtin_amdgcn_fmed3f(x, lo, hi); }
+__device__ __forceinline__ double cclamp(double x, double lo, double hi) { return fmin(fmax(x, lo), hi); }
+
 template <typename TI, typename TO, int TILE>
 __global__ __launch_bounds__(256) void cone_fwd_k(const TI *__restrict__ vx, const TI *__restrict__ vy,
                                                   const TI *__restrict__ vz, int64_t sx, int64_t sy, int64_t szz,
                                                   VecRef yr, const ConeView *__restrict__ views, int nx, int ny,
                                                   int nz, int nviews, int nu, int nv, double pu, double pv,
-                                                  int nbu, int rb, int nrb, uint32_t nxcc, int s0,
-                                                  const int *kdev, const int *active) {
+                                                  int nbu, int rb, int nrb, int vg, int ngv, int off32, uint32_t nxcc,
+                                                  int s0, const int *kdev, const int *active) {
     typedef typename acc_of<TI>::type T;
     const uint32_t w = cremap(blockIdx.x, gridDim.x, nxcc);
     int c, r, vw, s;
     bool live;
     if (TILE) {
-        const int tu = (int)(w % (uint32_t)nbu);
-        const uint32_t w2 = w / (uint32_t)nbu;
+        const int vi = (int)(w % (uint32_t)vg);
+        const uint32_t w1 = w / (uint32_t)vg;
+        const int tu = (int)(w1 % (uint32_t)nbu);
+        const uint32_t w2 = w1 / (uint32_t)nbu;
         const int tv = (int)(w2 % (uint32_t)rb);
         const uint32_t w3 = w2 / (uint32_t)rb;
-        vw = (int)(w3 % (uint32_t)nviews);
-        s = s0 + (int)(w3 / (uint32_t)nviews);
+        vw = (int)(w3 % (uint32_t)ngv) * vg + vi;
+        s = s0 + (int)(w3 / (uint32_t)ngv);
+        if (vw >= nviews) return;   // the ragged last group of views (the whole workgroup)
         const int l = (int)(threadIdx.x & 63), wv = (int)(threadIdx.x >> 6);
         if (TILE == 16) {
             c = tu * 16 + (l & 15);
@@ -360,57 +369,81 @@ __global__ __launch_bounds__(256) void cone_fwd_k(const TI *__restrict__ vx, con
     const int Lq = nq + 2 * CPAD, Lp = np_ + 2 * CPAD;
     const T P0 = (T)(p0 + CPAD), DP = (T)dp, Q0 = (T)(q0 + CPAD), DQ = (T)dq;
     const T pmax = (T)(np_ + CPAD), qmax = (T)(nq + CPAD);
-    // in lockstep the copy is the same for the whole wave: a scalar base with
-    // 32-bit element offsets (a padded copy of one slice has < 2^31 elements)
-    const TI *Pb = same ? uniform_ptr(P) : P;
-    // the four taps of plane jj and the two fractions
-    auto load = [&](int jj, T &fp, T &fq, T &a00, T &a01, T &a10, T &a11) {
-        const T pp = fma((T)jj, DP, P0), qq = fma((T)jj, DQ, Q0);
-        fp = cfract(pp);
-        fq = cfract(qq);
-        const uint32_t ipp = (uint32_t)fmin(fmax(pp, (T)0), pmax), iqq = (uint32_t)fmin(fmax(qq, (T)0), qmax);
-        const TI *e = Pb + (((uint32_t)jj * (uint32_t)Lp + ipp) * (uint32_t)Lq + iqq);
-        a00 = (T)e[0];
-        a01 = (T)e[1];
-        a10 = (T)e[Lq];
-        a11 = (T)e[Lq + 1];
-    };
-    auto combine = [](T fp, T fq, T a00, T a01, T a10, T a11) -> T {
-        const T lo = fma(fq, a01 - a00, a00), hi = fma(fq, a11 - a10, a10);
-        return fma(fp, hi - lo, lo);
-    };
-    auto tap = [&](int jj) -> T {
-        T fp, fq, a00, a01, a10, a11;
-        load(jj, fp, fq, a00, a01, a10, a11);
-        return combine(fp, fq, a00, a01, a10, a11);
-    };
-    // two sums, over the even and the odd planes; the loads of four steps
-    // are issued before any is combined
+    // The march over planes jlo..jhi in two sums (even and odd planes), the
+    // loads of four steps issued before any is combined.  In lockstep the copy
+    // is the same for the whole wave: a scalar base and 32-bit byte offsets
+    // (off32: a padded copy of one slice has < 2^32 bytes and its row indices
+    // fit 24 bits), else per-lane
+    // 64-bit addresses; both read the same entries.
     T acc0 = 0, acc1 = 0;
-    int j = jlo;
-    if (j <= jhi && (j & 1)) {
-        acc1 += tap(j);
-        ++j;
-    }
-    for (; j + 3 <= jhi; j += 4) {
-        T fp[4], fq[4], a00[4], a01[4], a10[4], a11[4], v[4];
+    auto march = [&](auto uni_tag) {
+        constexpr bool UNI = decltype(uni_tag)::value;
+        const TI *Pu = UNI ? uniform_ptr(P) : P;
+        // the four taps of plane jj and the two fractions
+        auto load = [&](int jj, T &fp, T &fq, T &a00, T &a01, T &a10, T &a11) {
+            const T pp = fma((T)jj, DP, P0), qq = fma((T)jj, DQ, Q0);
+            fp = cfract(pp);
+            fq = cfract(qq);
+            const uint32_t ipp = (uint32_t)cclamp(pp, (T)0, pmax), iqq = (uint32_t)cclamp(qq, (T)0, qmax);
+            if constexpr (UNI) {   // global loads: a scalar base plus a 32-bit byte offset
+                // (24-bit multiplies: the host checked that rows and row lengths fit)
+                const uint32_t ei = __umul24((uint32_t)jj * (uint32_t)Lp + ipp, (uint32_t)Lq) + iqq;
+                typedef const __attribute__((address_space(1))) char gchar;
+                typedef const __attribute__((address_space(1))) TI gTI;
+                gchar *b = (gchar *)Pu;
+                const gTI *e = (const gTI *)(b + ei * (uint32_t)sizeof(TI));
+                const gTI *e1 = (const gTI *)(b + (ei + (uint32_t)Lq) * (uint32_t)sizeof(TI));
+                a00 = (T)e[0];
+                a01 = (T)e[1];
+                a10 = (T)e1[0];
+                a11 = (T)e1[1];
+            } else {
+                const uint32_t ei = ((uint32_t)jj * (uint32_t)Lp + ipp) * (uint32_t)Lq + iqq;
+                const TI *e = Pu + ei, *e1 = e + Lq;
+                a00 = (T)e[0];
+                a01 = (T)e[1];
+                a10 = (T)e1[0];
+                a11 = (T)e1[1];
+            }
+        };
+        auto combine = [](T fp, T fq, T a00, T a01, T a10, T a11) -> T {
+            const T lo = fma(fq, a01 - a00, a00), hi = fma(fq, a11 - a10, a10);
+            return fma(fp, hi - lo, lo);
+        };
+        auto tap = [&](int jj) -> T {
+            T fp, fq, a00, a01, a10, a11;
+            load(jj, fp, fq, a00, a01, a10, a11);
+            return combine(fp, fq, a00, a01, a10, a11);
+        };
+        int j = jlo;
+        if (j <= jhi && (j & 1)) {
+            acc1 += tap(j);
+            ++j;
+        }
+        for (; j + 3 <= jhi; j += 4) {
+            T fp[4], fq[4], a00[4], a01[4], a10[4], a11[4], v[4];
 #pragma unroll
-        for (int h = 0; h < 4; ++h) load(j + h, fp[h], fq[h], a00[h], a01[h], a10[h], a11[h]);
-        __builtin_amdgcn_sched_barrier(0);
+            for (int h = 0; h < 4; ++h) load(j + h, fp[h], fq[h], a00[h], a01[h], a10[h], a11[h]);
+            __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-        for (int h = 0; h < 4; ++h) v[h] = combine(fp[h], fq[h], a00[h], a01[h], a10[h], a11[h]);
-        acc0 += v[0];
-        acc1 += v[1];
-        acc0 += v[2];
-        acc1 += v[3];
-    }
-    if (j + 1 <= jhi) {
-        const T v0 = tap(j), v1 = tap(j + 1);
-        acc0 += v0;
-        acc1 += v1;
-        j += 2;
-    }
-    if (j <= jhi) acc0 += tap(j);
+            for (int h = 0; h < 4; ++h) v[h] = combine(fp[h], fq[h], a00[h], a01[h], a10[h], a11[h]);
+            acc0 += v[0];
+            acc1 += v[1];
+            acc0 += v[2];
+            acc1 += v[3];
+        }
+        if (j + 1 <= jhi) {
+            const T v0 = tap(j), v1 = tap(j + 1);
+            acc0 += v0;
+            acc1 += v1;
+            j += 2;
+        }
+        if (j <= jhi) acc0 += tap(j);
+    };
+    if (same && off32)
+        march(std::true_type{});
+    else
+        march(std::false_type{});
     if (!live) return;
     const T wgt = (T)(len / fabs(d[ia]));
     store_as<TO>(vec_ptr<TO>(yr, s, k), ((int64_t)vw * nv + r) * nu + c, (acc0 + acc1) * wgt);
@@ -420,10 +453,8 @@ __global__ __launch_bounds__(256) void cone_fwd_k(const TI *__restrict__ vx, con
 // CZT is a launch choice that leaves every sum unchanged); loop over the views.
 // MP is the power of the magnification in the weight: 2 for the cone beam
 // (two transverse detector axes), 1 for the fan beam.
-constexpr int CZT_DEFAULT = 4;
+constexpr int CZT_DEFAULT = 2;
 
-__device__ __forceinline__ float cclamp(float x, float lo, float hi) { return __builtin_amdgcn_fmed3f(x, lo, hi); }
-__device__ __forceinline__ double cclamp(double x, double lo, double hi) { return fmin(fmax(x, lo), hi); }
 
 template <typename TI, int CZT, int MP>
 __global__ __launch_bounds__(256) void cone_bp_k(const typename acc_of<TI>::type *__restrict__ yp, int64_t ss,
@@ -514,17 +545,25 @@ static int cone_fwd_t(const abba_op *op, VecRef x, VecRef y, int batch, void *sc
         ABBA_LAUNCHED("cone_pad_vol_k");
     }
     if (std::max({cc.vx, cc.vy, cc.vz}) >= (size_t)1 << 31) return ABBA_ERR_UNSUPPORTED;
+    // 32-bit byte offsets within one slice's copy, built from 24-bit products
+    // (row index plane * rows + row, and row length, below 2^24)
+    const size_t rows = (size_t)(std::max({g.nx, g.ny, g.nz}) + 1) * (size_t)(std::max({g.nx, g.ny, g.nz}) + 2 * CPAD);
+    const int off32 = std::max({cc.vx, cc.vy, cc.vz}) * sizeof(TI) < ((size_t)1 << 32) && rows < ((size_t)1 << 24) ? 1 : 0;
     int nbu = (g.det_u + 255) / 256;
     int rb = g.det_v;
-    // built-in: 16 x 16 detector tiles, waves of 16 x 4, at most 5
-    // workgroups per CU (measured at 256^3 / 360 x 384^2: 13.2 ms for
-    // 256-column rows, 9.6 ms for tiles, 7.8 ms for tiles with the cap)
-    int tile = 16;
-    size_t cap_lds = (size_t)op->lds_cu / 5 / 512 * 512;   // unused LDS that caps the workgroups per CU
+    // built-in: 16 x 16 detector tiles with 8 x 8 waves, groups of 16 views
+    // per tile, no cap on the workgroups per CU.  Measured at 256^3 / 360 x
+    // 384^2: 256-column rows 13.2 ms; 16 x 16 waves of 16 x 4, views outermost,
+    // 9.6 ms, 7.8 with at most 5 workgroups per CU (fewer rays in flight per
+    // L2); groups of 4 views per tile 6.05 ms; 8 x 8 waves with groups of 16
+    // views 5.9 ms, where the cap no longer matters.  Detectors of fewer
+    // than 16 rows (the fan beam has one) keep the rows of 256 columns.
+    int tile = g.det_v >= 16 ? 8 : 0, vg = 16;
+    size_t cap_lds = 0;   // unused LDS that caps the workgroups per CU
     if (const TuneEntry *t = tune_for(op, batch)) {
+        if (t->a_vg >= 1) vg = t->a_vg;
         if (t->a_rb >= 1) rb = std::min(t->a_rb, g.det_v);
         if (t->a_occ >= 1) cap_lds = std::min<size_t>(65536, (size_t)op->lds_cu / (size_t)t->a_occ / 512 * 512);
-        else if (t->a_occ == 0 && (t->a_tile != 0 || t->a_rb >= 1)) cap_lds = 0;
         if (t->a_tile == -1 || t->a_rb >= 1) tile = 0;
         else if (t->a_tile == 8 || t->a_tile == 16) tile = t->a_tile;
     }
@@ -533,8 +572,12 @@ static int cone_fwd_t(const abba_op *op, VecRef x, VecRef y, int batch, void *sc
         nbu = (g.det_u + 15) / 16;
         rb = (g.det_v + 15) / 16;
         nrb = 1;
+    } else {
+        vg = 1;
     }
-    const uint64_t per = (uint64_t)nbu * nrb * rb * g.n_angles;
+    vg = std::min(vg, g.n_angles);
+    const int ngv = (g.n_angles + vg - 1) / vg;   // groups of views (the rows order keeps vg = 1)
+    const uint64_t per = (uint64_t)nbu * nrb * rb * ngv * vg;
     if (per > CMAX_GROUPS) return ABBA_ERR_UNSUPPORTED;
     const int ch = (int)std::min<uint64_t>((uint64_t)batch, CMAX_GROUPS / per);
     for (int s0 = 0; s0 < batch; s0 += ch) {
@@ -542,8 +585,8 @@ static int cone_fwd_t(const abba_op *op, VecRef x, VecRef y, int batch, void *sc
 #define CONE_FWD(TL)                                                                                              \
     hipLaunchKernelGGL((cone_fwd_k<TI, TO, TL>), dim3((uint32_t)(per * nb)), dim3(256), cap_lds, L.stream, vx, vy, vz, \
                        (int64_t)cc.vx, (int64_t)cc.vy, (int64_t)cc.vz, y, (const ConeView *)op->tab, g.nx, g.ny,     \
-                       g.nz, g.n_angles, g.det_u, g.det_v, g.det_pitch_u, g.det_pitch_v, nbu, rb, nrb,               \
-                       (uint32_t)op->nxcc, s0, L.kdev, L.active)
+                       g.nz, g.n_angles, g.det_u, g.det_v, g.det_pitch_u, g.det_pitch_v, nbu, rb, nrb, vg, ngv,      \
+                       off32, (uint32_t)op->nxcc, s0, L.kdev, L.active)
         if (tile == 16) CONE_FWD(16);
         else if (tile == 8) CONE_FWD(8);
         else CONE_FWD(0);
@@ -623,14 +666,18 @@ int cone_tune_candidates(const abba_op *op, TuneEntry *out, int cap) {
             if (n < cap) out[n++] = TuneEntry{0, 0, 0, 0, c, 0};
     if (op->kind == ABBA_OP_JOSEPH) {
         // 256-column rows (views outermost, or bands of rows), 16 x 16 tiles
-        // with waves of 16 x 4 or 8 x 8, and caps of the workgroups per CU
+        // with waves of 16 x 4 or 8 x 8, caps of the workgroups per CU, and
+        // groups of neighbouring views per tile
         if (n < cap) out[n++] = TuneEntry{0, 0, 0, 0, 0, 0, 5, -1};
         for (int r : {8, 32})
             if (n < cap && r < op->g.det_v) out[n++] = TuneEntry{0, 0, 0, 0, 0, r, 5};
-        for (int t : {16, 8})
-            for (int c : {6, 5, 4})
-                if (n < cap) out[n++] = TuneEntry{0, 0, 0, 0, 0, 0, c, t};
-        if (n < cap) out[n++] = TuneEntry{0, 0, 0, 0, 0, 0, 0, 8};
+        for (int c : {6, 5, 0})
+            if (n < cap) out[n++] = TuneEntry{0, 0, 0, 0, 0, 0, c, 16};
+        for (int c : {6, 5})
+            if (n < cap) out[n++] = TuneEntry{0, 0, 0, 0, 0, 0, c, 8};
+        for (int v : {1, 4, 8})
+            if (n < cap) out[n++] = TuneEntry{0, 0, 0, 0, 0, 0, 5, 8, v};
+        if (n < cap) out[n++] = TuneEntry{0, 0, 0, 0, 0, 0, 5, 16, 4};
     }
     return n;
 }

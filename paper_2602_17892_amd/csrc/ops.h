@@ -67,6 +67,7 @@ struct TuneEntry {
     int a_rb;     // 3D A: detector rows per band of the work order (1 to 64)
     int a_occ;    // 3D A: workgroups per compute unit at most (0: no cap)
     int a_tile;   // 3D A: 0 detector rows per workgroup, 16: 16 x 16 detector tiles
+    int a_vg;     // 3D A, tiles: views per group of the work order (0: built-in)
 };
 constexpr int MAX_TUNE = 8;
 

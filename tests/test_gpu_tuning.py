@@ -41,7 +41,7 @@ def test_2d_launch_choices_bitwise_equal(pk, shape, dt):
     ya0, xb0 = pk.project(A, x), pk.backproject(B, y)
     for path, jb in [(0, 0), (1, 2), (1, 3), (1, 4)]:
         pk.set_tuning(A, S, a_path=path, a_jb=jb)
-        assert pk.get_tuning(A, S) == dict(a_path=path, a_jb=jb, b_g=0, czt=0, a_rb=0, a_occ=0, a_tile=0)
+        assert pk.get_tuning(A, S) == dict(a_path=path, a_jb=jb, b_g=0, czt=0, a_rb=0, a_occ=0, a_tile=0, a_vg=0)
         assert torch.equal(pk.project(A, x), ya0), (path, jb)
     for g in (1, 8, 16, 64, 128):
         pk.set_tuning(B, S, b_g=g)
@@ -75,8 +75,14 @@ def test_cone_launch_choices_bitwise_equal(pk):
         pk.set_tuning(A, 2, a_occ=occ, a_tile=tile)
         assert pk.get_tuning(A, 2)["a_tile"] == tile
         assert torch.equal(pk.project(A, x), y0), ("tile", tile, occ)
+    for vg in (1, 3, 5, 16, 100):        # groups of views per tile (ragged last group: 16 views)
+        pk.set_tuning(A, 2, a_tile=16, a_vg=vg)
+        assert pk.get_tuning(A, 2)["a_vg"] == vg
+        assert torch.equal(pk.project(A, x), y0), ("views per group", vg)
     with pytest.raises(pk.AbbaError):
         pk.set_tuning(A, 2, a_tile=4)
+    with pytest.raises(pk.AbbaError):
+        pk.set_tuning(A, 2, a_vg=-1)
 
 
 def test_autotune_keeps_a_choice(pk):
@@ -89,7 +95,8 @@ def test_autotune_keeps_a_choice(pk):
     print(f"A: {ta}\nB: {tb}")
     assert ta["candidates"] == 4 and tb["candidates"] >= 3
     assert ta["ms"] <= ta["default_ms"] and tb["ms"] <= tb["default_ms"]
-    assert pk.get_tuning(A, S) == {k: ta[k] for k in ("a_path", "a_jb", "b_g", "czt", "a_rb", "a_occ", "a_tile")}
+    assert pk.get_tuning(A, S) == {k: ta[k] for k in ("a_path", "a_jb", "b_g", "czt", "a_rb", "a_occ", "a_tile",
+                                                      "a_vg")}
     assert torch.equal(pk.project(A, x), ya0)
     # the solver uses the stored choice and returns the same bits
     og_b = pk.project(A, x).contiguous()
