@@ -384,7 +384,8 @@ int abba_solve(const abba_op *A, const abba_op *B, const void *b, void *x, int b
  * In abba_solve with ABBA_REG_LEARNED the small solve first picks GCV's
  * lambda (eq. (15)); the predicted lambda^ replaces it when
  * GCV(lambda^) <= (1 + judge_delta) GCV(lambda_GCV).  ABBA_STOP_LEARNED stops
- * at the first k >= K o1 (clamped to [1, K]), after the discrepancy principle
+ * at the first k >= k^_k, where k^_k is the largest of the predictions K o1
+ * (each clamped to [1, K]) made at iterations 1..k, after the discrepancy principle
  * when noise_norm is given, and then, with stop.learned_gate = c > 0, only
  * once the data residual is within the factor c of the discrepancy level
  * (rho_k <= c tau ||e||).  All four calls are asynchronous on `stream`. */

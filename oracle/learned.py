@@ -31,8 +31,9 @@ fallback and judge:
   with y_lam the solution of eq. (12); lam*_k is the grid argmin (first index
   on ties) and k* the iteration of the smallest RRE_k(lam*_k).
 * Judge: the predicted lam^ is used when GCV(lam^) <= (1 + delta) GCV(lam_GCV),
-  else lam_GCV (eq. (15)); the run stops at the first k >= K o1 (and earlier
-  if the discrepancy principle fires).
+  else lam_GCV (eq. (15)); the run stops at the first k >= max_{j <= k} K o1(j),
+  the largest stop prediction made so far (and earlier if the discrepancy
+  principle fires).
 """
 from __future__ import annotations
 

@@ -233,7 +233,9 @@ def hybrid_gmres(A, B, b, mode: str = "AB", K: int = 30, rule: str = "gcv",
             gres.append(base["uk1"])
             f = lrn.features(base["sigma"], gres, None if noise_norm is None or rho0 <= 0.0 else noise_norm / rho0)
             lam_l, _, _, o1 = lrn.judge(mlp, f, base["sigma"], base["uhat"], base["uk1"], judge_delta)
-            k_hat = min(max(K * o1, 1.0), float(K))
+            # the stop index: the largest prediction made so far
+            k_new = min(max(K * o1, 1.0), float(K))
+            k_hat = k_new if k == 1 else max(k_hat, k_new)
             sol = ss.solve_projected(Hk, beta, "fixed", lam_fixed=lam_l)
         else:
             sol = ss.solve_projected(Hk, beta, rule, lam_fixed=lam, dp_target=target)

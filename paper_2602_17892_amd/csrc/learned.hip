@@ -356,7 +356,10 @@ __global__ __launch_bounds__(64) void judge_k(const float *__restrict__ pred, co
     const double g_gcv = wave_gcv(lam_g, sg, u, k, uk1);
     const bool ok = s1 > 0.0 && g_hat <= (1.0 + delta) * g_gcv;
     if (threadIdx.x == 0) {
-        Sc[SC_KLEARN] = fmin(fmax(o1 * (double)K, 1.0), (double)K);
+        // the stop index is the largest prediction made so far: the run stops
+        // once it has passed every estimate of the best iteration
+        const double kn = fmin(fmax(o1 * (double)K, 1.0), (double)K);
+        Sc[SC_KLEARN] = k <= 1 ? kn : fmax(Sc[SC_KLEARN], kn);
         Sc[SC_LAMLEARN] = lam;
     }
     if (!ok) return;

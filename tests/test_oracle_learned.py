@@ -195,3 +195,30 @@ def test_judge_accepts_within_margin():
     assert ok and lam == lam_hat and abs(lam_hat / lg - 10 ** 0.4) < 1e-12
     lam, lam_hat, ok, _ = L.judge(theta, np.zeros(64), sig, uh, uk1, 0.0)
     assert not ok and lam == lg
+
+
+def test_learned_stop_index_is_the_running_maximum():
+    """The learned stop fires at the first k >= max_{j <= k} K o1(j): with a
+    network whose stop prediction falls as the residual falls, the run goes on
+    past the iterations at which k >= K o1(k) alone would have stopped it."""
+    og, xt, b = small_problem(seed=3)
+    theta = np.zeros(L.N_PARAMS)
+    (W1, _), (W2, _), (W3, _), (W4, b4) = L.unpack(theta)
+    W1[0, 63] = -1.0          # h = relu(-f_63) with f_63 = log10(r_k / r_0) / 8 <= 0
+    W2[0, 0] = 1.0
+    W3[0, 0] = 1.0
+    W4[1, 0] = -4.0           # o1 = 0.6 - 4 h falls with the residual
+    b4[:] = [-0.25, 0.6]
+    K = 20
+    o = osv.hybrid_gmres(og.A, og.B, b, mode="AB", K=K, rule="learned", stop="learned", mlp=theta,
+                         judge_delta=-1.0, keep_small=True)
+    # the predictions from the run's own small-solve quantities
+    gres = [float(np.linalg.norm(b))] + [sm[2] for sm in o.small]
+    preds = []
+    for j, sm in enumerate(o.small, start=1):
+        y, _ = L.forward(theta, L.features(sm[0], gres[:j + 1])[None, :])
+        preds.append(min(max(K * float(y[0, 1]), 1.0), float(K)))
+    k_rm = next(k for k in range(1, len(preds) + 1) if k >= max(preds[:k]))
+    k_pt = next(k for k in range(1, len(preds) + 1) if k >= preds[k - 1])
+    assert o.status == osv.STATUS_STOP_LEARNED and o.iters == k_rm
+    assert k_pt < k_rm and preds[0] > preds[-1]
