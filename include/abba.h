@@ -162,7 +162,7 @@ typedef struct {
     int a_path;        /* 2D A: 0 per-ray gather kernel, 1 LDS-band kernel, -1 built-in rule */
     int a_jb;          /* 2D A, LDS kernel: bins per thread and angle, 2..4 (0: 3)           */
     int b_g;           /* 2D B: angles per LDS chunk (0: built-in, at most 64 KB of LDS)      */
-    int czt;           /* 3D B: voxels per thread along z, 2, 4 or 8 (0: 2)                   */
+    int czt;           /* 3D B: voxels per thread along z, 2, 4 or 8 (0: 4)                   */
     int a_rb;          /* 3D A, rows of 256 columns: detector rows per band of the work
                           order (0: all rows, the views outermost); the views of a band
                           run before the next band                                        */
@@ -170,15 +170,17 @@ typedef struct {
                           reserving unused LDS (at most 64 KB per workgroup, so
                           a_occ >= 3 on 160 KB of LDS per CU; smaller values are
                           ABBA_ERR_ARG): fewer rays in flight share the caches.
-                          0: no cap (the built-in)                                        */
+                          0: no cap when a_tile or a_rb is set, else the built-in cap
+                          (6 for detector tiles)                                          */
     double ms;         /* abba_autotune: mean time of one apply with the chosen launch       */
     double default_ms; /* abba_autotune: the same with the built-in rules                    */
     int candidates;    /* abba_autotune: launch choices timed besides the built-in rules     */
     int a_tile;        /* 3D A: a workgroup per 16 x 16 tile of detector pixels with waves of
-                          16 x 4 (16) or 8 x 8 (8, and the built-in 0); -1: per 256
-                          columns of one detector row (also chosen by a_rb >= 1)            */
+                          16 x 4 (16, and the built-in 0 for detectors of 16 rows or more)
+                          or 8 x 8 (8); -1: per 256 columns of one detector row (also
+                          chosen by a_rb >= 1, and the built-in for shorter detectors)     */
     int a_vg;          /* 3D A, detector tiles: views per group of the work order, 1..4096
-                          (0: built-in, 16); the views of a group run next to each other
+                          (0: built-in, 24); the views of a group run next to each other
                           for each tile, so neighbouring views share the voxels in cache  */
 } abba_tune;
 

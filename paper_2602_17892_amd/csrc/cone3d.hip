@@ -141,18 +141,22 @@ int build_cone_tables(abba_op *op) {
 }
 
 // Padded-copy sizes (elements per slice).
+// The padded volume copies hold, at every (plane, p, q), the pair
+// (x[plane][p][q], x[plane][p + 1][q]): A's four bilinear taps of a position
+// are then the 16 contiguous bytes of two neighbouring pairs, one load.
 struct ConeCopies {
-    size_t vx, vy, vz;   // [nx][nz+4][ny+4], [ny][nz+4][nx+4], [nz][ny+4][nx+4]; 0 if the axis never leads
-    size_t sino;         // [views][nv+4][nu+4]
+    size_t vx, vy, vz;   // pairs over [nx][nz+4][ny+4], [ny][nz+4][nx+4], [nz][ny+4][nx+4] (elements, two
+                         // per pair); 0 if the axis never leads
+    size_t sino;         // pairs (y[v][u], y[v + 1][u]) over [views][nv+4][nu+4] (elements, two per pair)
 };
 
 static ConeCopies cone_copies(const abba_op *op) {
     const size_t nx = op->g.nx, ny = op->g.ny, nz = op->g.nz;
     ConeCopies c;
-    c.vx = (op->cone_axes & 1) ? nx * (nz + 2 * CPAD) * (ny + 2 * CPAD) : 0;
-    c.vy = (op->cone_axes & 2) ? ny * (nz + 2 * CPAD) * (nx + 2 * CPAD) : 0;
-    c.vz = (op->cone_axes & 4) ? nz * (ny + 2 * CPAD) * (nx + 2 * CPAD) : 0;
-    c.sino = (size_t)op->g.n_angles * (op->g.det_v + 2 * CPAD) * (op->g.det_u + 2 * CPAD);
+    c.vx = (op->cone_axes & 1) ? 2 * nx * (nz + 2 * CPAD) * (ny + 2 * CPAD) : 0;
+    c.vy = (op->cone_axes & 2) ? 2 * ny * (nz + 2 * CPAD) * (nx + 2 * CPAD) : 0;
+    c.vz = (op->cone_axes & 4) ? 2 * nz * (ny + 2 * CPAD) * (nx + 2 * CPAD) : 0;
+    c.sino = (size_t)2 * op->g.n_angles * (op->g.det_v + 2 * CPAD) * (op->g.det_u + 2 * CPAD);
     return c;
 }
 
@@ -170,9 +174,10 @@ __global__ __launch_bounds__(256) void cfill_k(T *__restrict__ p, int64_t n) {
         p[i] = (T)0;
 }
 
-// Volume -> the padded copies of the axes that lead some ray.  One workgroup
-// per 32 x 32 (y, x) tile of one z slice of one volume (blockIdx.z = slice in
-// the batch * nz + z).
+// Volume -> the padded pair copies of the axes that lead some ray (zeroed
+// before): each voxel is the first entry of its own pair and the second
+// entry of the pair one row (p) before.  One workgroup per 32 x 32 (y, x)
+// tile of one z slice of one volume (blockIdx.z = slice in the batch * nz + z).
 template <typename T>
 __global__ __launch_bounds__(256) void cone_pad_vol_k(VecRef xr, T *__restrict__ vx, T *__restrict__ vy,
                                                       T *__restrict__ vz, int nx, int ny, int nz, int s0,
@@ -192,8 +197,16 @@ __global__ __launch_bounds__(256) void cone_pad_vol_k(VecRef xr, T *__restrict__
         T v = (T)0;
         if (i < ny && j < nx) {
             v = x[(int64_t)i * nx + j];
-            if (vz) vz[(int64_t)s * szz + ((int64_t)z * Ly + i + CPAD) * Lx + j + CPAD] = v;
-            if (vy) vy[(int64_t)s * sy + ((int64_t)i * Lz + z + CPAD) * Lx + j + CPAD] = v;
+            if (vz) {
+                T *q = vz + (int64_t)s * szz + 2 * (((int64_t)z * Ly + i + CPAD) * Lx + j + CPAD);
+                q[0] = v;
+                q[1 - 2 * Lx] = v;
+            }
+            if (vy) {
+                T *q = vy + (int64_t)s * sy + 2 * (((int64_t)i * Lz + z + CPAD) * Lx + j + CPAD);
+                q[0] = v;
+                q[1 - 2 * Lx] = v;
+            }
         }
         tile[r][tx] = v;
     }
@@ -202,7 +215,11 @@ __global__ __launch_bounds__(256) void cone_pad_vol_k(VecRef xr, T *__restrict__
 #pragma unroll
     for (int r = ty; r < 32; r += 8) {
         const int j = j0 + r, i = i0 + tx;
-        if (i < ny && j < nx) vx[(int64_t)s * sx + ((int64_t)j * Lz + z + CPAD) * Ly + i + CPAD] = tile[tx][r];
+        if (i < ny && j < nx) {
+            T *q = vx + (int64_t)s * sx + 2 * (((int64_t)j * Lz + z + CPAD) * Ly + i + CPAD);
+            q[0] = tile[tx][r];
+            q[1 - 2 * Ly] = tile[tx][r];
+        }
     }
 }
 
@@ -216,8 +233,14 @@ __global__ __launch_bounds__(256) void cone_pad_sino_k(VecRef yr, T *__restrict_
     const int k = kdev ? *kdev : 0;
     const int w = blockIdx.x / nv, r = blockIdx.x % nv;
     const TIN *y = vec_ptr<const TIN>(yr, s, k) + ((int64_t)w * nv + r) * nu;
-    T *o = yp + (int64_t)s * ss + ((int64_t)w * (nv + 2 * CPAD) + r + CPAD) * (nu + 2 * CPAD) + CPAD;
-    for (int c = threadIdx.x; c < nu; c += 256) o[c] = (T)load_as<TIN>(y, c);
+    // pair (r, c) holds the entry first, pair (r - 1, c) second
+    const int Lu = nu + 2 * CPAD;
+    T *o = yp + (int64_t)s * ss + 2 * (((int64_t)w * (nv + 2 * CPAD) + r + CPAD) * Lu + CPAD);
+    for (int c = threadIdx.x; c < nu; c += 256) {
+        const T v = (T)load_as<TIN>(y, c);
+        o[2 * c] = v;
+        o[2 * c + 1 - 2 * Lu] = v;
+    }
 }
 
 __device__ __forceinline__ uint32_t cremap(uint32_t L, uint32_t total, uint32_t nxcc) {
@@ -372,8 +395,8 @@ __global__ __launch_bounds__(256) void cone_fwd_k(const TI *__restrict__ vx, con
     // The march over planes jlo..jhi in two sums (even and odd planes), the
     // loads of four steps issued before any is combined.  In lockstep the copy
     // is the same for the whole wave: a scalar base and 32-bit byte offsets
-    // (off32: a padded copy of one slice has < 2^32 bytes and its row indices
-    // fit 24 bits), else per-lane
+    // (off32: a padded pair copy of one slice has < 2^32 bytes and its row
+    // indices fit 24 bits), else per-lane
     // 64-bit addresses; both read the same entries.
     T acc0 = 0, acc1 = 0;
     auto march = [&](auto uni_tag) {
@@ -385,25 +408,25 @@ __global__ __launch_bounds__(256) void cone_fwd_k(const TI *__restrict__ vx, con
             fp = cfract(pp);
             fq = cfract(qq);
             const uint32_t ipp = (uint32_t)cclamp(pp, (T)0, pmax), iqq = (uint32_t)cclamp(qq, (T)0, qmax);
+            // pairs (p, q) and (p, q + 1): x[p][q], x[p+1][q], x[p][q+1], x[p+1][q+1]
             if constexpr (UNI) {   // global loads: a scalar base plus a 32-bit byte offset
                 // (24-bit multiplies: the host checked that rows and row lengths fit)
                 const uint32_t ei = __umul24((uint32_t)jj * (uint32_t)Lp + ipp, (uint32_t)Lq) + iqq;
                 typedef const __attribute__((address_space(1))) char gchar;
                 typedef const __attribute__((address_space(1))) TI gTI;
                 gchar *b = (gchar *)Pu;
-                const gTI *e = (const gTI *)(b + ei * (uint32_t)sizeof(TI));
-                const gTI *e1 = (const gTI *)(b + (ei + (uint32_t)Lq) * (uint32_t)sizeof(TI));
+                const gTI *e = (const gTI *)(b + ei * (uint32_t)(2 * sizeof(TI)));
                 a00 = (T)e[0];
-                a01 = (T)e[1];
-                a10 = (T)e1[0];
-                a11 = (T)e1[1];
+                a10 = (T)e[1];
+                a01 = (T)e[2];
+                a11 = (T)e[3];
             } else {
                 const uint32_t ei = ((uint32_t)jj * (uint32_t)Lp + ipp) * (uint32_t)Lq + iqq;
-                const TI *e = Pu + ei, *e1 = e + Lq;
+                const TI *e = Pu + 2 * (int64_t)ei;
                 a00 = (T)e[0];
-                a01 = (T)e[1];
-                a10 = (T)e1[0];
-                a11 = (T)e1[1];
+                a10 = (T)e[1];
+                a01 = (T)e[2];
+                a11 = (T)e[3];
             }
         };
         auto combine = [](T fp, T fq, T a00, T a01, T a10, T a11) -> T {
@@ -453,7 +476,7 @@ __global__ __launch_bounds__(256) void cone_fwd_k(const TI *__restrict__ vx, con
 // CZT is a launch choice that leaves every sum unchanged); loop over the views.
 // MP is the power of the magnification in the weight: 2 for the cone beam
 // (two transverse detector axes), 1 for the fan beam.
-constexpr int CZT_DEFAULT = 2;
+constexpr int CZT_DEFAULT = 4;
 
 
 template <typename TI, int CZT, int MP>
@@ -490,8 +513,9 @@ __global__ __launch_bounds__(256) void cone_bp_k(const typename acc_of<TI>::type
         const T bu = fma(X, b.eup[0], fma(Y, b.eup[1], -b.Su));
         const T bv = fma(X, b.evp[0], fma(Y, b.evp[1], -b.Sv));
         // the view is the same for the whole workgroup: 32-bit byte offsets
-        // from its base (the launcher requires a padded view of < 2^32 bytes)
-        const T *view = Ys + (int64_t)vw * Lv * Lu;
+        // from its base (the launcher requires a padded pair view of < 2^32
+        // bytes); the pairs (v, u) and (v, u + 1) are the four taps
+        const T *view = Ys + 2 * (int64_t)vw * Lv * Lu;
 #pragma unroll
         for (int m = 0; m < CZT; ++m) {
             const T den = fma(Z[m], b.n[2], bn);
@@ -501,8 +525,8 @@ __global__ __launch_bounds__(256) void cone_bp_k(const typename acc_of<TI>::type
             const T fu = cfract(u), fv = cfract(v);
             const uint32_t iu = (uint32_t)cclamp(u, (T)0, umax), iv = (uint32_t)cclamp(v, (T)0, vmax);
             const T *e = reinterpret_cast<const T *>(reinterpret_cast<const char *>(view) +
-                                                     (iv * (uint32_t)Lu + iu) * (uint32_t)sizeof(T));
-            const T a00 = e[0], a01 = e[1], a10 = e[Lu], a11 = e[Lu + 1];
+                                                     (iv * (uint32_t)Lu + iu) * (uint32_t)(2 * sizeof(T)));
+            const T a00 = e[0], a10 = e[1], a01 = e[2], a11 = e[3];
             const T lo = fma(fu, a01 - a00, a00), hi = fma(fu, a11 - a10, a10);
             const T wgt = (MP == 2 ? M * M : M) * ipp;
             acc[m] = fma(wgt, fma(fv, hi - lo, lo), acc[m]);
@@ -551,19 +575,19 @@ static int cone_fwd_t(const abba_op *op, VecRef x, VecRef y, int batch, void *sc
     const int off32 = std::max({cc.vx, cc.vy, cc.vz}) * sizeof(TI) < ((size_t)1 << 32) && rows < ((size_t)1 << 24) ? 1 : 0;
     int nbu = (g.det_u + 255) / 256;
     int rb = g.det_v;
-    // built-in: 16 x 16 detector tiles with 8 x 8 waves, groups of 16 views
-    // per tile, no cap on the workgroups per CU.  Measured at 256^3 / 360 x
-    // 384^2: 256-column rows 13.2 ms; 16 x 16 waves of 16 x 4, views outermost,
-    // 9.6 ms, 7.8 with at most 5 workgroups per CU (fewer rays in flight per
-    // L2); groups of 4 views per tile 6.05 ms; 8 x 8 waves with groups of 16
-    // views 5.9 ms, where the cap no longer matters.  Detectors of fewer
-    // than 16 rows (the fan beam has one) keep the rows of 256 columns.
-    int tile = g.det_v >= 16 ? 8 : 0, vg = 16;
-    size_t cap_lds = 0;   // unused LDS that caps the workgroups per CU
+    // built-in: 16 x 16 detector tiles with waves of 16 x 4, groups of 24
+    // views per tile, at most 6 workgroups per CU.  Measured at 256^3 / 360 x
+    // 384^2 (pair copies): 256-column rows 14.7 ms; tiles with groups of 8 /
+    // 16 / 24 / 32 / 48 / 64 views 4.84 / 4.56 / 4.37 / 4.52 / 4.40 / 5.17 ms
+    // (8 x 8 waves 0.4-0.6 ms slower).  Detectors of fewer than 16 rows (the
+    // fan beam has one) keep the rows of 256 columns.
+    int tile = g.det_v >= 16 ? 16 : 0, vg = 24;
+    size_t cap_lds = tile ? (size_t)op->lds_cu / 6 / 512 * 512 : 0;   // unused LDS that caps the workgroups per CU
     if (const TuneEntry *t = tune_for(op, batch)) {
         if (t->a_vg >= 1) vg = t->a_vg;
         if (t->a_rb >= 1) rb = std::min(t->a_rb, g.det_v);
         if (t->a_occ >= 1) cap_lds = std::min<size_t>(65536, (size_t)op->lds_cu / (size_t)t->a_occ / 512 * 512);
+        else if (t->a_tile != 0 || t->a_rb >= 1) cap_lds = 0;
         if (t->a_tile == -1 || t->a_rb >= 1) tile = 0;
         else if (t->a_tile == 8 || t->a_tile == 16) tile = t->a_tile;
     }
@@ -616,7 +640,7 @@ static int cone_bp_launch(const abba_op *op, const typename acc_of<TI>::type *yp
     const int ntx = (g.nx + 15) / 16, nty = (g.ny + 15) / 16, ntz = (g.nz + CZT - 1) / CZT;
     const uint64_t per = (uint64_t)ntx * nty * ntz;
     if (per > CMAX_GROUPS) return ABBA_ERR_UNSUPPORTED;
-    if ((int64_t)(g.det_u + 2 * CPAD) * (g.det_v + 2 * CPAD) * (int64_t)sizeof(T) >= (int64_t)1 << 32)
+    if ((int64_t)(g.det_u + 2 * CPAD) * (g.det_v + 2 * CPAD) * (int64_t)(2 * sizeof(T)) >= (int64_t)1 << 32)
         return ABBA_ERR_UNSUPPORTED;
     const int ch = (int)std::min<uint64_t>((uint64_t)batch, CMAX_GROUPS / per);
     const size_t bytes_d = sizeof(ConeView) * g.n_angles;
@@ -671,13 +695,13 @@ int cone_tune_candidates(const abba_op *op, TuneEntry *out, int cap) {
         if (n < cap) out[n++] = TuneEntry{0, 0, 0, 0, 0, 0, 5, -1};
         for (int r : {8, 32})
             if (n < cap && r < op->g.det_v) out[n++] = TuneEntry{0, 0, 0, 0, 0, r, 5};
-        for (int c : {6, 5, 0})
+        for (int c : {5, 0})
             if (n < cap) out[n++] = TuneEntry{0, 0, 0, 0, 0, 0, c, 16};
-        for (int c : {6, 5})
+        for (int v : {16, 48})
+            if (n < cap) out[n++] = TuneEntry{0, 0, 0, 0, 0, 0, 6, 16, v};
+        for (int c : {5, 0})
             if (n < cap) out[n++] = TuneEntry{0, 0, 0, 0, 0, 0, c, 8};
-        for (int v : {1, 4, 8})
-            if (n < cap) out[n++] = TuneEntry{0, 0, 0, 0, 0, 0, 5, 8, v};
-        if (n < cap) out[n++] = TuneEntry{0, 0, 0, 0, 0, 0, 5, 16, 4};
+        if (n < cap) out[n++] = TuneEntry{0, 0, 0, 0, 0, 0, 5, 8, 48};
     }
     return n;
 }
