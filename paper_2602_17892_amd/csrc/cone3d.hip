@@ -223,23 +223,29 @@ __global__ __launch_bounds__(256) void cone_pad_vol_k(VecRef xr, T *__restrict__
     }
 }
 
-// Sinogram rows -> [views][nv+4][nu+4] in the accumulation type.  One
-// workgroup per detector row (view, r) of one slice.
+// Sinogram -> the padded pair view [views][nv+4][nu+4] in the accumulation
+// type: pair (v, u) = (y[v][u], y[v + 1][u]), zeros outside the detector.
+// One workgroup per padded row of pairs (view, v) of one slice; every pair,
+// pads included, is written, so the buffer needs no clearing before.
 template <typename TIN, typename T>
 __global__ __launch_bounds__(256) void cone_pad_sino_k(VecRef yr, T *__restrict__ yp, int nviews, int nu, int nv,
                                                        int s0, int64_t ss, const int *kdev, const int *active) {
     const int s = s0 + blockIdx.y;
     if (active && !active[s]) return;
     const int k = kdev ? *kdev : 0;
-    const int w = blockIdx.x / nv, r = blockIdx.x % nv;
-    const TIN *y = vec_ptr<const TIN>(yr, s, k) + ((int64_t)w * nv + r) * nu;
-    // pair (r, c) holds the entry first, pair (r - 1, c) second
-    const int Lu = nu + 2 * CPAD;
-    T *o = yp + (int64_t)s * ss + 2 * (((int64_t)w * (nv + 2 * CPAD) + r + CPAD) * Lu + CPAD);
-    for (int c = threadIdx.x; c < nu; c += 256) {
-        const T v = (T)load_as<TIN>(y, c);
-        o[2 * c] = v;
-        o[2 * c + 1 - 2 * Lu] = v;
+    const int Lv = nv + 2 * CPAD, Lu = nu + 2 * CPAD;
+    const int w = blockIdx.x / Lv, pr = blockIdx.x % Lv;
+    const int r0 = pr - CPAD, r1 = r0 + 1;   // the detector rows of the pair
+    const bool ok0 = r0 >= 0 && r0 < nv, ok1 = r1 >= 0 && r1 < nv;
+    const TIN *y = vec_ptr<const TIN>(yr, s, k) + (int64_t)w * nv * nu;
+    T *o = yp + (int64_t)s * ss + 2 * ((int64_t)w * Lv + pr) * Lu;
+    for (int pc = threadIdx.x; pc < Lu; pc += 256) {
+        const int c = pc - CPAD;
+        const bool okc = c >= 0 && c < nu;
+        const T v0 = ok0 && okc ? (T)load_as<TIN>(y, (int64_t)r0 * nu + c) : (T)0;
+        const T v1 = ok1 && okc ? (T)load_as<TIN>(y, (int64_t)r1 * nu + c) : (T)0;
+        o[2 * pc] = v0;
+        o[2 * pc + 1] = v1;
     }
 }
 
@@ -666,12 +672,12 @@ static int cone_bp_t(const abba_op *op, VecRef y, VecRef x, int batch, void *scr
     typedef typename acc_of<TI>::type T;
     const abba_geometry &g = op->g;
     const ConeCopies cc = cone_copies(op);
-    T *yp = (T *)scratch;
-    int rc;
-    if ((rc = fill<T>(yp, (int64_t)batch * cc.sino, L.stream))) return rc;
+    T *yp = (T *)scratch;   // every pair is written by the padding kernel
+    if ((uint64_t)g.n_angles * (g.det_v + 2 * CPAD) > 0x7fffffffull) return ABBA_ERR_UNSUPPORTED;
     for (int s0 = 0; s0 < batch; s0 += 65535) {
         const int nb = std::min(65535, batch - s0);
-        hipLaunchKernelGGL((cone_pad_sino_k<TIN, T>), dim3(g.n_angles * g.det_v, nb), dim3(256), 0, L.stream, y, yp,
+        hipLaunchKernelGGL((cone_pad_sino_k<TIN, T>), dim3(g.n_angles * (g.det_v + 2 * CPAD), nb), dim3(256), 0,
+                           L.stream, y, yp,
                            g.n_angles, g.det_u, g.det_v, s0, (int64_t)cc.sino, L.kdev, L.active);
         ABBA_LAUNCHED("cone_pad_sino_k");
     }
