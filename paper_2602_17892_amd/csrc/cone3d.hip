@@ -402,8 +402,8 @@ __global__ __launch_bounds__(256) void cone_fwd_k(const TI *__restrict__ vx, con
     // loads of four steps issued before any is combined.  In lockstep the copy
     // is the same for the whole wave: a scalar base and 32-bit byte offsets
     // (off32: a padded pair copy of one slice has < 2^32 bytes and its row
-    // indices fit 24 bits), else per-lane
-    // 64-bit addresses; both read the same entries.
+    // indices fit 24 bits), else per-lane 64-bit addresses; both read the same
+    // entries.
     T acc0 = 0, acc1 = 0;
     auto march = [&](auto uni_tag) {
         constexpr bool UNI = decltype(uni_tag)::value;
@@ -574,7 +574,8 @@ static int cone_fwd_t(const abba_op *op, VecRef x, VecRef y, int batch, void *sc
                            (int64_t)cc.vx, (int64_t)cc.vy, (int64_t)cc.vz, L.kdev, L.active);
         ABBA_LAUNCHED("cone_pad_vol_k");
     }
-    if (std::max({cc.vx, cc.vy, cc.vz}) >= (size_t)1 << 31) return ABBA_ERR_UNSUPPORTED;
+    // pair indices within one slice's copy in 32 bits (two elements per pair)
+    if (std::max({cc.vx, cc.vy, cc.vz}) >= (size_t)1 << 33) return ABBA_ERR_UNSUPPORTED;
     // 32-bit byte offsets within one slice's copy, built from 24-bit products
     // (row index plane * rows + row, and row length, below 2^24)
     const size_t rows = (size_t)(std::max({g.nx, g.ny, g.nz}) + 1) * (size_t)(std::max({g.nx, g.ny, g.nz}) + 2 * CPAD);
