@@ -5,8 +5,10 @@ phantoms, 720 angles on [0, pi) x 725 unit bins, per-slice noise level drawn
 log-uniform in [0.1%, 5%]; hybrid AB-GMRES with the GCV lambda rule and the
 discrepancy-principle stop (tau = 1.01, known ||e||), at most 100 iterations,
 FP32 projectors and FP64 small solves, all slices in one batched solve whose
-per-iteration launch sequence is a replayed hipGraph.  One step = one such
-solve of the whole batch, inputs already resident in HBM.
+per-iteration launch sequence is a replayed hipGraph; the library splits the
+batch into --streams concurrent sub-batches (default 3), each on a stream of
+its own.  One step = one such solve of the whole batch, inputs already
+resident in HBM.
 
 The JSON line also carries: the plain per-slice path (one slice per call,
 eager launches, host stop check every iteration) on a subset of the same
@@ -65,6 +67,9 @@ def parse():
     p.add_argument("--angles", type=int, default=720)
     p.add_argument("--det", type=int, default=725)
     p.add_argument("--poll", type=int, default=4)
+    p.add_argument("--streams", type=int, default=3,
+                   help="the batched solve runs as this many concurrent sub-batches of consecutive slices, each on "
+                        "a stream and host thread of its own (bitwise the same results as one)")
     p.add_argument("--plain-slices", type=int, default=8)
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--roofline-reps", type=int, default=10)
@@ -799,15 +804,23 @@ def main():
     # slices (the plain path), timed before anything is measured
     t0 = time.perf_counter()
     tune = {"A": pk.autotune(A, S), "B": pk.autotune(B, S), "A_plain": pk.autotune(A, 1), "B_plain": pk.autotune(B, 1)}
+    # the sub-batches' projector launches run at their own batch sizes
+    P_st = max(1, min(args.streams, S))
+    for sz in sorted({S // P_st + (1 if i < S % P_st else 0) for i in range(P_st)} - {S, 1}):
+        tune[f"A_sub{sz}"] = pk.autotune(A, sz)
+        tune[f"B_sub{sz}"] = pk.autotune(B, sz)
     log(args, f"autotune ({time.perf_counter() - t0:.1f}s): " + "; ".join(
         f"{k} {v['ms']:.3f} ms (built-in {v['default_ms']:.3f})" for k, v in tune.items()))
-    ws_bytes = pk.workspace_bytes(A, B, S, "AB", K, stop="dp")
+    # one workspace serves the sub-batched timed solve and the one-stream
+    # phase-timed solve below
+    ws_bytes = max(pk.workspace_bytes(A, B, S, "AB", K, stop="dp", streams=args.streams),
+                   pk.workspace_bytes(A, B, S, "AB", K, stop="dp"))
     ws = torch.empty(ws_bytes, dtype=torch.uint8, device="cuda")
-    log(args, f"workspace {ws_bytes / 2**30:.1f} GiB")
+    log(args, f"workspace {ws_bytes / 2**30:.1f} GiB, {P_st} sub-batch stream(s)")
 
     def step():
         return pk.solve(A, B, b, mode="AB", k=K, reg="gcv", tau=1.01, noise_norm=en, stop="dp",
-                        use_graph=True, poll_every=args.poll, workspace=ws, history=False)
+                        use_graph=True, poll_every=args.poll, workspace=ws, history=False, streams=args.streams)
 
     for _ in range(args.warmup):
         step()
@@ -850,8 +863,8 @@ def main():
               f"to batched: {same}")
 
     # ---- the same batched solve once more with its phases timed by HIP
-    # events (eager launches; not part of the timed steps): the Gram-Schmidt
-    # sweeps' bandwidth over the whole solve
+    # events (eager launches, one stream; not part of the timed steps): the
+    # Gram-Schmidt sweeps' bandwidth over the whole solve
     xp, ip = pk.solve(A, B, b, mode="AB", k=K, reg="gcv", tau=1.01, noise_norm=en, stop="dp", poll_every=args.poll,
                       workspace=ws, history=False, phases=True)
     same_p = bool(torch.equal(xp, xb))
@@ -912,7 +925,7 @@ def main():
         "data": "synthetic: seeded random-ellipse phantoms, b = A x + relative Gaussian noise",
         "config": {"workload": f"{S} x {args.n}^2 slices, {args.angles} angles x {args.det} bins, "
                                f"eta log-uniform [0.1%,5%], hybrid AB-GMRES GCV + DP stop, kmax {K}",
-                   "slices": S, "kmax": K, "poll_every": args.poll},
+                   "slices": S, "kmax": K, "poll_every": args.poll, "streams": P_st},
         "iters": {"mean": float(iters.mean()), "min": int(iters.min()), "max": int(iters.max()),
                   "status_dp": int((status & 2 != 0).sum())},
         "rre_median": float(np.median(rre_b)),

@@ -282,6 +282,14 @@ typedef struct {
                                   phase of the solve (ms, from HIP events recorded between
                                   the phases); the iterations then run without a graph and
                                   the call synchronises `stream` before it returns          */
+    int streams;               /* run the batch as this many sub-batches of consecutive
+                                  slices (sizes differing by at most one), each on a stream
+                                  of its own and driven by a host thread of its own, the
+                                  library's streams waiting on `stream` and `stream` on
+                                  them; every slice gets the bits it gets alone.  0 or 1:
+                                  one.  The workspace is the sub-batches' workspaces one
+                                  after another (abba_solve_workspace with the same exec);
+                                  not with phase_ms or abba_solve_layout                    */
 } abba_exec;
 
 /* Phases timed by exec.phase_ms: the forward projector A (its padded input

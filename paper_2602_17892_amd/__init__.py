@@ -81,7 +81,8 @@ class _Layout(ctypes.Structure):
 
 class _Exec(ctypes.Structure):
     _fields_ = [("use_graph", ctypes.c_int), ("poll_every", ctypes.c_int), ("restart", ctypes.c_int),
-                ("features", ctypes.c_int), ("ortho", ctypes.c_int), ("phase_ms", ctypes.c_void_p)]
+                ("features", ctypes.c_int), ("ortho", ctypes.c_int), ("phase_ms", ctypes.c_void_p),
+                ("streams", ctypes.c_int)]
 
 
 # phases timed by abba_exec.phase_ms
@@ -401,7 +402,7 @@ ORTHO = {"dcgs2": 0, "cgs2": 1}
 
 
 def _structs(reg, lam, tau, noise_norm, mlp, judge_delta, stop, stop_tau, rns_eps, use_graph, poll_every,
-             restart, features, ortho="dcgs2", learned_gate=0.0):
+             restart, features, ortho="dcgs2", learned_gate=0.0, streams=1):
     r = _Reg()
     r.kind = REG[reg]
     r.lam = float(lam)
@@ -421,12 +422,14 @@ def _structs(reg, lam, tau, noise_norm, mlp, judge_delta, stop, stop_tau, rns_ep
     e.restart = int(restart)
     e.features = int(features)
     e.ortho = ORTHO[ortho]
+    e.streams = int(streams)
     return r, s, e
 
 
 def workspace_bytes(A: Operator, B: Operator, batch: int, mode: str, k: int, stop=None, labels=False,
-                    restart: int = 0) -> int:
-    _, s, e = _structs("none", 0, 0, None, None, 0, stop, 1.01, 1e-3, 0, 1, restart, FEAT_LABELS if labels else 0)
+                    restart: int = 0, streams: int = 1) -> int:
+    _, s, e = _structs("none", 0, 0, None, None, 0, stop, 1.01, 1e-3, 0, 1, restart, FEAT_LABELS if labels else 0,
+                       streams=streams)
     nb = ctypes.c_size_t()
     _check(lib.abba_solve_workspace(A.handle, B.handle, batch, MODE_AB if mode == "AB" else MODE_BA, k,
                                     ctypes.byref(s), ctypes.byref(e), ctypes.byref(nb)), "abba_solve_workspace")
@@ -470,8 +473,13 @@ def solve(A: Operator, B: Operator, b, mode: str = "AB", k: int = 30, reg: str =
           tau: float = 1.01, noise_norm=None, stop=None, rns_eps: float = 1e-3, x0=None, use_graph=False,
           poll_every: int = 1, restart: int = 0, mlp=None, judge_delta: float = 0.05, history: bool = True,
           workspace=None, features: bool = False, ortho: str = "dcgs2", x_true=None, phases: bool = False,
-          learned_gate: float = 0.0):
+          learned_gate: float = 0.0, streams: int = 1):
     """Hybrid AB-/BA-GMRES on a batch of slices; returns (x, info).
+
+    streams > 1 runs the batch as that many sub-batches of consecutive slices
+    concurrently, each on a stream and host thread of its own inside the
+    library (the same bits per slice; the workspace is workspace_bytes(...,
+    streams=streams)).
 
     ortho: "dcgs2" (CGS2 with the second pass delayed to the next step's
     sweep, the default) or "cgs2" (both passes in each step).
@@ -501,7 +509,7 @@ def solve(A: Operator, B: Operator, b, mode: str = "AB", k: int = 30, reg: str =
             raise ValueError(f"noise_norm has {noise_norm.numel()} entries, expected one per slice ({batch})")
     fbits = (FEAT_OUT if features else 0) | (FEAT_LABELS if x_true is not None else 0)
     r, s, e = _structs(reg, lam, tau, noise_norm, mlp, judge_delta, stop, tau, rns_eps, use_graph, poll_every,
-                       restart, fbits, ortho, learned_gate)
+                       restart, fbits, ortho, learned_gate, streams)
     pms = (ctypes.c_double * len(PHASES))() if phases else None
     e.phase_ms = None if pms is None else ctypes.addressof(pms)
     m = MODE_AB if mode == "AB" else MODE_BA

@@ -19,6 +19,7 @@
 // The network kernels take 64 samples per workgroup with all activations in
 // LDS; every sum runs in a fixed order, so results are bitwise reproducible.
 // Per-tile weight gradients are reduced over tiles in FP64, in tile order.
+#include <atomic>
 #include <cmath>
 
 #include "solve.h"
@@ -538,13 +539,15 @@ __global__ __launch_bounds__(128) void labels_k(const double *__restrict__ rre, 
 
 // ------------------------------------------------------------ launchers ---
 static int set_lds_attrs() {
-    static int done = -1;
+    // host threads driving sub-batches may get here together; setting the
+    // attribute twice is harmless
+    static std::atomic<int> done{-1};
     int dev = 0;
     ABBA_HIP(hipGetDevice(&dev));
-    if (done == dev) return ABBA_OK;
+    if (done.load() == dev) return ABBA_OK;
     ABBA_HIP(hipFuncSetAttribute((const void *)mlp_fwd_k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)FWD_LDS));
     ABBA_HIP(hipFuncSetAttribute((const void *)mlp_bwd_k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)BWD_LDS));
-    done = dev;
+    done.store(dev);
     return ABBA_OK;
 }
 

@@ -38,6 +38,8 @@
 // refined point kept unless it is worse; discrepancy principle by 100
 // bisection steps in log(lambda) on [1e-12 s_1, 1e8 s_1]; lambda = 0 drops
 // singular values below 1e-14 s_1.
+#include <atomic>
+
 #include "solve.h"
 
 namespace abba {
@@ -762,7 +764,7 @@ int smallsolve_prepare() {
     int dev = 0;
     hipError_t e = hipGetDevice(&dev);
     if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
-    static bool done[64] = {false};
+    static std::atomic<bool> done[64];
     if (dev >= 0 && dev < 64 && done[dev]) return ABBA_OK;
     e = hipFuncSetAttribute((const void *)smallsolve_k, hipFuncAttributeMaxDynamicSharedMemorySize,
                             (int)smallsolve_lds_bytes(KMAX_SMALL));

@@ -16,6 +16,9 @@
 // number of active slices only every `poll_every` iterations.
 #include <algorithm>
 #include <cstring>
+#include <string>
+#include <thread>
+#include <vector>
 
 #include "solve.h"
 
@@ -497,22 +500,62 @@ static int assemble_cycle(const SolveDims &d, const SolveWS &ws, void *x, const 
 
 using namespace abba;
 
+// Sub-batches of exec.streams: part i holds slices [first[i], first[i] + count[i]).
+static int split_parts(int batch, const abba_exec *exec, std::vector<int> &first, std::vector<int> &count) {
+    const int p = exec && exec->streams > 1 ? std::min(exec->streams, batch) : 1;
+    first.assign(p, 0);
+    count.assign(p, 0);
+    for (int i = 0, s0 = 0; i < p; ++i) {
+        count[i] = batch / p + (i < batch % p ? 1 : 0);
+        first[i] = s0;
+        s0 += count[i];
+    }
+    return p;
+}
+
+static size_t solve_one_bytes(const abba_op *A, const abba_op *B, int batch, int mode, int k, const abba_stop *stop,
+                              const abba_exec *exec, int *rc);
+
 extern "C" int abba_solve_workspace(const abba_op *A, const abba_op *B, int batch, int mode, int k,
                                     const abba_stop *stop, const abba_exec *exec, size_t *bytes) {
     if (!bytes) {
         set_error("bytes is NULL");
         return ABBA_ERR_ARG;
     }
+    if (exec && exec->streams < 0) {
+        set_error("exec.streams must be >= 0");
+        return ABBA_ERR_ARG;
+    }
+    std::vector<int> first, count;
+    const int p = split_parts(batch, exec, first, count);
+    if (p > 1) {   // the sub-batches' workspaces one after another, each 256-byte aligned
+        size_t total = 0;
+        for (int i = 0; i < p; ++i) {
+            int rc = ABBA_OK;
+            const size_t b = solve_one_bytes(A, B, count[i], mode, k, stop, exec, &rc);
+            if (rc) return rc;
+            total += (b + 255) / 256 * 256;
+        }
+        *bytes = total;
+        return ABBA_OK;
+    }
+    int rc = ABBA_OK;
+    *bytes = solve_one_bytes(A, B, batch, mode, k, stop, exec, &rc);
+    return rc;
+}
+
+static size_t solve_one_bytes(const abba_op *A, const abba_op *B, int batch, int mode, int k, const abba_stop *stop,
+                              const abba_exec *exec, int *rcp) {
     SolveDims d;
     abba_out dummy;
     std::memset(&dummy, 0, sizeof(dummy));
     dummy.resid = (double *)1;   // size for the worst case (Z kept in BA mode)
     const int kc = exec && exec->restart > 0 && exec->restart < k ? exec->restart : k;
     int rc = make_dims(A, B, batch, mode, kc, stop, &dummy, &d);
-    if (rc) return rc;
+    *rcp = rc;
+    if (rc) return 0;
     d.labels = exec && (exec->features & ABBA_FEAT_LABELS) && mode == ABBA_MODE_AB;
-    *bytes = solve_workspace_bytes(d, nullptr, nullptr, op_scratch_bytes(A, B, batch));
-    return ABBA_OK;
+    return solve_workspace_bytes(d, nullptr, nullptr, op_scratch_bytes(A, B, batch));
 }
 
 extern "C" int abba_solve_layout(const abba_op *A, const abba_op *B, int batch, int mode, int k,
@@ -520,6 +563,10 @@ extern "C" int abba_solve_layout(const abba_op *A, const abba_op *B, int batch, 
     if (!layout) {
         set_error("layout is NULL");
         return ABBA_ERR_ARG;
+    }
+    if (exec && exec->streams > 1) {
+        set_error("abba_solve_layout describes the workspace of one stream (exec.streams <= 1)");
+        return ABBA_ERR_UNSUPPORTED;
     }
     SolveDims d;
     abba_out dummy;
@@ -547,14 +594,14 @@ extern "C" int abba_solve_layout(const abba_op *A, const abba_op *B, int batch, 
     return ABBA_OK;
 }
 
-extern "C" int abba_solve(const abba_op *A, const abba_op *B, const void *b, void *x, int batch, int mode, int k,
-                          const abba_reg *reg, const abba_stop *stop, const abba_out *out, const abba_exec *exec,
-                          void *workspace, size_t ws_bytes, void *stream) {
+static int solve_one(const abba_op *A, const abba_op *B, const void *b, void *x, int batch, int mode, int k,
+                     const abba_reg *reg, const abba_stop *stop, const abba_out *out, const abba_exec *exec,
+                     void *workspace, size_t ws_bytes, void *stream) {
     if (!b || !x || !reg || !out || !out->iters || !out->status || !workspace) {
         set_error("abba_solve: b, x, reg, out.iters, out.status and workspace are required");
         return ABBA_ERR_ARG;
     }
-    abba_exec ex{0, 1, 0, 0, ABBA_ORTHO_DELAYED, nullptr};
+    abba_exec ex{0, 1, 0, 0, ABBA_ORTHO_DELAYED, nullptr, 1};
     if (exec) ex = *exec;
     if (ex.restart < 0) {
         set_error("restart cycle length must be >= 0");
@@ -751,4 +798,143 @@ extern "C" int abba_solve(const abba_op *A, const abba_op *B, const void *b, voi
     }
     cleanup();
     return timed(rc);
+}
+
+// ------------------------------------------------ concurrent sub-batches --
+// exec.streams > 1: the slices are independent, so the batch splits into
+// sub-batches of consecutive slices, each solved by solve_one on a stream of
+// its own from a host thread of its own (a thread drives its sub-batch's
+// launches and active-slice polls); projector launches, sweeps and small
+// solves of the sub-batches then overlap on the device.
+extern "C" int abba_solve(const abba_op *A, const abba_op *B, const void *b, void *x, int batch, int mode, int k,
+                          const abba_reg *reg, const abba_stop *stop, const abba_out *out, const abba_exec *exec,
+                          void *workspace, size_t ws_bytes, void *stream) {
+    if (exec && exec->streams < 0) {
+        set_error("exec.streams must be >= 0");
+        return ABBA_ERR_ARG;
+    }
+    std::vector<int> first, count;
+    const int p = batch > 0 ? split_parts(batch, exec, first, count) : 1;
+    if (p <= 1) return solve_one(A, B, b, x, batch, mode, k, reg, stop, out, exec, workspace, ws_bytes, stream);
+    if (!A || !B || !b || !x || !reg || !out || !out->iters || !out->status || !workspace) {
+        set_error("abba_solve: A, B, b, x, reg, out.iters, out.status and workspace are required");
+        return ABBA_ERR_ARG;
+    }
+    if (exec->phase_ms) {
+        set_error("exec.phase_ms times one stream (exec.streams <= 1)");
+        return ABBA_ERR_UNSUPPORTED;
+    }
+    size_t need = 0;
+    int rc = abba_solve_workspace(A, B, batch, mode, k, stop, exec, &need);
+    if (rc) return rc;
+    if (ws_bytes < need) {
+        set_error("workspace of %zu bytes is smaller than the %zu needed", ws_bytes, need);
+        return ABBA_ERR_ARG;
+    }
+    if ((uintptr_t)workspace & 255) {
+        set_error("the workspace must be 256-byte aligned");
+        return ABBA_ERR_ARG;
+    }
+    if ((rc = smallsolve_prepare())) return rc;
+    int dev = 0;
+    ABBA_HIP(hipGetDevice(&dev));
+    const size_t bsz = dtype_size(A->sino_dtype), xsz = dtype_size(A->img_dtype);
+    const size_t kk = (size_t)k;
+    abba_exec ex1 = *exec;
+    ex1.streams = 1;
+    struct Part {
+        abba_reg reg;
+        abba_stop stop;
+        abba_out out;
+        void *ws;
+        size_t ws_bytes;
+        hipStream_t st;
+        hipEvent_t done;
+        int rc;
+        std::string err;
+    };
+    std::vector<Part> parts(p);
+    char *wp = (char *)workspace;
+    for (int i = 0; i < p; ++i) {
+        Part &q = parts[i];
+        const size_t s0 = (size_t)first[i];
+        q.reg = *reg;
+        if (reg->noise_norm) q.reg.noise_norm = reg->noise_norm + s0;
+        if (stop) {
+            q.stop = *stop;
+            if (stop->noise_norm) q.stop.noise_norm = stop->noise_norm + s0;
+        }
+        q.out = *out;
+        q.out.iters = out->iters + s0;
+        q.out.status = out->status + s0;
+        if (out->lambda) q.out.lambda = out->lambda + s0 * kk;
+        if (out->resid) q.out.resid = out->resid + s0 * (kk + 1);
+        if (out->features) q.out.features = out->features + s0 * kk * ABBA_MLP_FEATURES;
+        if (out->x_true) q.out.x_true = (const char *)out->x_true + s0 * (size_t)A->n * xsz;
+        if (out->ncp) q.out.ncp = out->ncp + s0 * kk;
+        if (out->rre) q.out.rre = out->rre + s0 * kk * ABBA_LABEL_GRID;
+        size_t wb = 0;
+        if ((rc = abba_solve_workspace(A, B, count[i], mode, k, stop, &ex1, &wb))) return rc;
+        q.ws = wp;
+        q.ws_bytes = wb;
+        wp += (wb + 255) / 256 * 256;
+        q.st = nullptr;
+        q.done = nullptr;
+        q.rc = ABBA_OK;
+    }
+    // the library's streams start after the work already on `stream`
+    hipStream_t cst = (hipStream_t)stream;
+    hipEvent_t start = nullptr;
+    auto release = [&]() {
+        for (Part &q : parts) {
+            if (q.done) (void)hipEventDestroy(q.done);
+            if (q.st) (void)hipStreamDestroy(q.st);
+        }
+        if (start) (void)hipEventDestroy(start);
+    };
+    hipError_t e = hipEventCreateWithFlags(&start, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventRecord(start, cst);
+    for (int i = 0; i < p && e == hipSuccess; ++i) {
+        e = hipStreamCreateWithFlags(&parts[i].st, hipStreamNonBlocking);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&parts[i].done, hipEventDisableTiming);
+        if (e == hipSuccess) e = hipStreamWaitEvent(parts[i].st, start, 0);
+    }
+    if (e != hipSuccess) {
+        rc = hip_fail(e, "abba_solve: sub-batch streams");
+        release();
+        return rc;
+    }
+    std::vector<std::thread> threads;
+    threads.reserve(p);
+    for (int i = 0; i < p; ++i) {
+        threads.emplace_back([&, i]() {
+            Part &q = parts[i];
+            const hipError_t se = hipSetDevice(dev);
+            if (se != hipSuccess) {
+                q.rc = hip_fail(se, "hipSetDevice");
+            } else {
+                const size_t s0 = (size_t)first[i];
+                q.rc = solve_one(A, B, (const char *)b + s0 * (size_t)A->m * bsz, (char *)x + s0 * (size_t)A->n * xsz,
+                                 count[i], mode, k, &q.reg, stop ? &q.stop : nullptr, &q.out, &ex1, q.ws,
+                                 q.ws_bytes, q.st);
+            }
+            if (q.rc) q.err = abba_last_error();
+        });
+    }
+    for (std::thread &t : threads) t.join();
+    // `stream` waits for every sub-batch
+    for (int i = 0; i < p; ++i) {
+        e = hipEventRecord(parts[i].done, parts[i].st);
+        if (e == hipSuccess) e = hipStreamWaitEvent(cst, parts[i].done, 0);
+        if (e != hipSuccess) break;
+    }
+    for (int i = 0; i < p; ++i)
+        if (parts[i].rc) {
+            rc = parts[i].rc;
+            set_error("sub-batch %d (slices %d..%d): %s", i, first[i], first[i] + count[i] - 1, parts[i].err.c_str());
+            break;
+        }
+    if (!rc && e != hipSuccess) rc = hip_fail(e, "abba_solve: joining the sub-batch streams");
+    release();
+    return rc;
 }

@@ -84,6 +84,20 @@ def test_validation_before_any_device_call():
     assert pk.lib.abba_solve_layout(None, None, 1, 0, 5, None, None, None) == -1
     assert pk.lib.abba_solve(None, None, None, None, 1, 0, 5, None, None, None, None, None, 0, None) == -1
     assert b"required" in pk.lib.abba_last_error()
+    # concurrent sub-batches: a negative count is an argument error, and the
+    # layout query covers one stream's workspace only
+    ex = pk._Exec()
+    ex.streams = -1
+    assert pk.lib.abba_solve_workspace(None, None, 4, 0, 5, None, ctypes.byref(ex), ctypes.byref(nb)) == -1
+    assert b"streams" in pk.lib.abba_last_error()
+    assert pk.lib.abba_solve(None, None, None, None, 4, 0, 5, None, None, None, ctypes.byref(ex), None, 0,
+                             None) == -1
+    ex.streams = 2
+    assert pk.lib.abba_solve_layout(None, None, 4, 0, 5, None, ctypes.byref(ex), ctypes.byref(lay)) == -7
+    assert b"one stream" in pk.lib.abba_last_error()
+    assert pk.lib.abba_solve(None, None, None, None, 4, 0, 5, None, None, None, ctypes.byref(ex), None, 0,
+                             None) == -1
+    assert b"required" in pk.lib.abba_last_error()
     del keep
 
 
