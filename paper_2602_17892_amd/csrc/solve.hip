@@ -17,6 +17,7 @@
 #include <algorithm>
 #include <cstring>
 #include <string>
+#include <system_error>
 #include <thread>
 #include <vector>
 
@@ -904,22 +905,28 @@ extern "C" int abba_solve(const abba_op *A, const abba_op *B, const void *b, voi
         release();
         return rc;
     }
+    auto run_part = [&](int i) {
+        Part &q = parts[i];
+        const hipError_t se = hipSetDevice(dev);
+        if (se != hipSuccess) {
+            q.rc = hip_fail(se, "hipSetDevice");
+        } else {
+            const size_t s0 = (size_t)first[i];
+            q.rc = solve_one(A, B, (const char *)b + s0 * (size_t)A->m * bsz, (char *)x + s0 * (size_t)A->n * xsz,
+                             count[i], mode, k, &q.reg, stop ? &q.stop : nullptr, &q.out, &ex1, q.ws, q.ws_bytes,
+                             q.st);
+        }
+        if (q.rc) q.err = abba_last_error();
+    };
     std::vector<std::thread> threads;
     threads.reserve(p);
     for (int i = 0; i < p; ++i) {
-        threads.emplace_back([&, i]() {
-            Part &q = parts[i];
-            const hipError_t se = hipSetDevice(dev);
-            if (se != hipSuccess) {
-                q.rc = hip_fail(se, "hipSetDevice");
-            } else {
-                const size_t s0 = (size_t)first[i];
-                q.rc = solve_one(A, B, (const char *)b + s0 * (size_t)A->m * bsz, (char *)x + s0 * (size_t)A->n * xsz,
-                                 count[i], mode, k, &q.reg, stop ? &q.stop : nullptr, &q.out, &ex1, q.ws,
-                                 q.ws_bytes, q.st);
-            }
-            if (q.rc) q.err = abba_last_error();
-        });
+        // a thread that cannot be started: its sub-batch runs on this one
+        try {
+            threads.emplace_back(run_part, i);
+        } catch (const std::system_error &) {
+            run_part(i);
+        }
     }
     for (std::thread &t : threads) t.join();
     // `stream` waits for every sub-batch
