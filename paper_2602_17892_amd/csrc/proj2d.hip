@@ -418,15 +418,17 @@ __global__ __launch_bounds__(256) void joseph2d_lds_k(const TI *__restrict__ xp,
 
 // ------------------------------------------------------- pixel-driven B -----
 // x[i][j] = wb * sum_a lerp(row a of the sinogram at t = X cos/ds + Y sin/ds + cd).
-// A workgroup owns a BT x BT pixel tile.  For a chunk of angles it stages in
-// LDS, per angle, the window of detector bins the tile projects onto, as
-// pairs (y[p], y[p+1] - y[p]) with zeros outside the detector; a pixel-angle
-// pair is then one LDS read, lerp = v + f*dv.  The window of angle a starts at
-// w0 = floor(t_min) - 1 (t_min over the tile's corners) and holds W entries,
-// W >= 31*(|cos| + |sin|)/ds + 5, so every tap of the tile lies inside it.
-constexpr int BT = 32;   // pixel tile edge
+// A workgroup owns a tile of 32 columns x 64 rows (8 rows per thread).  For a
+// chunk of angles it stages in LDS, per angle, the window of detector bins the
+// tile projects onto, as pairs (y[p], y[p+1] - y[p]) with zeros outside the
+// detector; a pixel-angle pair is then one LDS read, lerp = v + f*dv.  The
+// window of angle a starts at w0 = floor(t_min) - 1 (t_min over the tile's
+// corners) and holds W entries, W >= (31 |cos| + 63 |sin|)/ds + 5 over all
+// angles, so every tap of the tile lies inside it.
+constexpr int BT = 32;         // pixel tile width (columns)
+constexpr int PIXBP_RM = 8;    // rows per thread: the tile has 8 * PIXBP_RM rows
 
-template <typename TIN, typename TI>
+template <typename TIN, typename TI, int RM>
 __global__ __launch_bounds__(256) void pixbp2d_k(VecRef yr, VecRef xr,
                                                  const AngleTab<typename acc_of<TI>::type> *__restrict__ tab,
                                                  int nx, int ny, int na, int nd, typename acc_of<TI>::type cd,
@@ -447,17 +449,20 @@ __global__ __launch_bounds__(256) void pixbp2d_k(VecRef yr, VecRef xr,
     const int k = kdev ? *kdev : 0;
     const TIN *y = vec_ptr<const TIN>(yr, s, k);
     const T cx = (T)0.5 * (T)(nx - 1), cy = (T)0.5 * (T)(ny - 1);
-    // this thread: column j, rows i0 + 8m (m = 0..3)
+    // this thread: column j, rows i0 + 8m (m < RM)
+    constexpr int BTY = 8 * RM;
     const int j = tx * BT + (threadIdx.x & 31);
-    const int i0 = ty * BT + (threadIdx.x >> 5);
+    const int i0 = ty * BTY + (threadIdx.x >> 5);
     const T X = (T)j - cx;
-    T Ym[4];
+    T Ym[RM], acc[RM];
 #pragma unroll
-    for (int m = 0; m < 4; ++m) Ym[m] = (T)(i0 + 8 * m) - cy;
+    for (int m = 0; m < RM; ++m) {
+        Ym[m] = (T)(i0 + 8 * m) - cy;
+        acc[m] = 0;
+    }
     // tile corners (the whole tile, also where it overhangs the image)
     const T X0 = (T)(tx * BT) - cx, X1 = X0 + (T)(BT - 1);
-    const T Y0 = (T)(ty * BT) - cy, Y1 = Y0 + (T)(BT - 1);
-    T acc[4] = {0, 0, 0, 0};
+    const T Y0 = (T)(ty * BTY) - cy, Y1 = Y0 + (T)(BTY - 1);
     const float winv = 1.0f / (float)W;
     for (int a0 = 0; a0 < na; a0 += G) {
         const int g = min(G, na - a0);
@@ -493,12 +498,13 @@ __global__ __launch_bounds__(256) void pixbp2d_k(VecRef yr, VecRef xr,
             const T base = fma(X, cb, par[3 * al + 2]);
             const T *wrow = win + (size_t)al * W * 2;
 #pragma unroll
-            for (int m = 0; m < 4; ++m) {
+            for (int m = 0; m < RM; ++m) {
                 const T t = fma(Ym[m], sb, base);
                 const T f = fract_of(t);
                 // every pixel of the tile (overhang included) has
-                // 1 <= t < 2 + 31 (|cos| + |sin|)/ds <= W - 3 up to rounding of
-                // a few ulp, so (int) is floor and both taps lie in the window
+                // 1 <= t < 2 + (31 |cos| + (BTY - 1) |sin|)/ds <= W - 3 up to
+                // rounding of a few ulp, so (int) is floor and both taps lie in
+                // the window
                 const int idx = (int)t;
                 const T v = wrow[2 * idx], dv = wrow[2 * idx + 1];
                 acc[m] += fma(f, dv, v);
@@ -508,7 +514,7 @@ __global__ __launch_bounds__(256) void pixbp2d_k(VecRef yr, VecRef xr,
     if (j < nx) {
         TI *xo = vec_ptr<TI>(xr, s, k);
 #pragma unroll
-        for (int m = 0; m < 4; ++m) {
+        for (int m = 0; m < RM; ++m) {
             const int i = i0 + 8 * m;
             if (i < ny) xo[(int64_t)i * nx + j] = (TI)(acc[m] * wb);
         }
@@ -520,9 +526,9 @@ static void pixbp_window(const abba_op *op, int *W, int *G) {
     double m = 0;
     for (int a = 0; a < op->g.n_angles; ++a) {
         const double th = op->g.angles ? op->g.angles[a] : a * M_PI / op->g.n_angles;
-        m = std::max(m, std::fabs(std::cos(th)) + std::fabs(std::sin(th)));
+        m = std::max(m, (BT - 1) * std::fabs(std::cos(th)) + (8 * PIXBP_RM - 1) * std::fabs(std::sin(th)));
     }
-    *W = (int)std::ceil((BT - 1) * m / op->g.det_pitch_u) + 5;
+    *W = (int)std::ceil(m / op->g.det_pitch_u) + 5;
     const size_t per = (size_t)*W * 2 * (op->img_dtype == ABBA_F64 ? 8 : 4);
     *G = (int)std::max<size_t>(1, std::min<size_t>(32, 32768 / per));
 }
@@ -707,12 +713,12 @@ static int back_launch(const abba_op *op, VecRef y, VecRef x, int batch, const L
         if (t->b_g > 0) G = std::min(t->b_g, pixbp_max_g(op, W));
     const size_t shmem = (size_t)G * ((W * 2 + 3) * sizeof(T) + 4);
     if ((size_t)W * 2 * sizeof(T) > 32768) return ABBA_ERR_UNSUPPORTED;
-    const int btx = (nx + BT - 1) / BT, bty = (ny + BT - 1) / BT;
+    const int btx = (nx + BT - 1) / BT, bty = (ny + 8 * PIXBP_RM - 1) / (8 * PIXBP_RM);
     const uint64_t tiles = (uint64_t)btx * bty;
     const int bchunk = (int)std::min<uint64_t>((uint64_t)batch, MAX_GROUPS / tiles);
     for (int s0 = 0; s0 < batch; s0 += bchunk) {
         const int nb = std::min(bchunk, batch - s0);
-        hipLaunchKernelGGL((pixbp2d_k<TIN, TI>), dim3((uint32_t)(tiles * nb)), dim3(256), shmem, L.stream, y, x,
+        hipLaunchKernelGGL((pixbp2d_k<TIN, TI, PIXBP_RM>), dim3((uint32_t)(tiles * nb)), dim3(256), shmem, L.stream, y, x,
                            (const AngleTab<T> *)op->tab, nx, ny, na, nd, (T)(0.5 * (nd - 1)), (T)(1.0 / ds), W, G,
                            btx, bty, (uint32_t)op->nxcc, s0, L.kdev, L.active);
         ABBA_LAUNCHED("pixbp2d_k");

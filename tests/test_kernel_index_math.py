@@ -65,3 +65,66 @@ def test_one_clamp_per_band_keeps_taps_in_the_padded_row(C):
             touched = in_image(i) | in_image(i + 1)
             assert not np.any(touched & moved)
     assert moved.any() and (~moved).any()
+
+
+# B's tile: 32 columns x 8*RM rows (the library's constants)
+BT, RM = 32, 8
+
+
+def window_extremes(nx, ny, na, nd, ds=1.0, angles=None):
+    """For every tile and angle of B's launch, the smallest t - w0 and the
+    largest floor(t - w0) over the tile's pixels, in the kernel's FP32
+    arithmetic, and the window length W the host picks.  t - w0 is monotone in
+    each pixel coordinate (fma is monotone in its operands), so the extremes lie
+    at the tile's corner pixels."""
+    th = np.asarray(angles, dtype=np.float64) if angles is not None else np.arange(na) * np.pi / na
+    cs, sn = np.cos(th), np.sin(th)
+    BTY = 8 * RM
+    W = int(np.ceil(np.max((BT - 1) * np.abs(cs) + (BTY - 1) * np.abs(sn)) / ds)) + 5
+    cb = (cs / ds).astype(np.float32)[None, :]
+    sb = (sn / ds).astype(np.float32)[None, :]
+    f = np.float32
+    cx, cy, cd = f(0.5) * f(nx - 1), f(0.5) * f(ny - 1), f(0.5 * (nd - 1))
+    btx, bty = -(-nx // BT), -(-ny // BTY)
+    tx, ty = np.meshgrid(np.arange(btx), np.arange(bty), indexing="ij")
+    X0 = ((tx * BT).astype(np.float32) - cx).reshape(-1, 1)
+    Y0 = ((ty * BTY).astype(np.float32) - cy).reshape(-1, 1)
+    X1, Y1 = X0 + f(BT - 1), Y0 + f(BTY - 1)
+    tmin = (cd + np.minimum(X0 * cb, X1 * cb)) + np.minimum(Y0 * sb, Y1 * sb)
+    w0 = np.floor(tmin).astype(np.int64) - 1
+    par2 = cd - w0.astype(np.float32)
+    lo, hi = None, None
+    for X in (X0, X1):
+        base = fma32(np.broadcast_to(X, par2.shape), cb.astype(np.float64), par2)
+        for Y in (Y0, Y1):
+            t = fma32(np.broadcast_to(Y, par2.shape), sb.astype(np.float64), base)
+            lo = t if lo is None else np.minimum(lo, t)
+            hi = t if hi is None else np.maximum(hi, t)
+    return float(lo.min()), int(np.floor(hi).max()), W
+
+
+@pytest.mark.parametrize("geom", [
+    (512, 512, 720, 725, 1.0), (256, 256, 360, 363, 1.0), (96, 96, 60, 137, 1.0), (64, 64, 90, 91, 1.0),
+    (128, 128, 180, 183, 1.0), (37, 50, 33, 71, 1.0), (30, 30, 40, 61, 0.7), (8, 8, 12, 13, 1.0),
+    (512, 512, 720, 1024, 0.7), (1024, 1024, 900, 1449, 1.0)])
+def test_backprojector_window_holds_every_tap(geom):
+    """B reads entry floor(t - w0) of the window (the pair of taps
+    floor(t - w0) and the next one) without a clamp: every pixel of a tile,
+    its overhang included, must have t - w0 >= 0 (truncation is floor) and
+    floor(t - w0) <= W - 1.  Checked with margins: t - w0 >= 0.99 and
+    floor(t - w0) <= W - 4."""
+    nx, ny, na, nd, ds = geom
+    lo, hi, W = window_extremes(nx, ny, na, nd, ds)
+    assert lo >= 0.99 and hi <= W - 4, (lo, hi, W)
+
+
+def test_backprojector_window_holds_every_tap_at_uneven_angles():
+    rng = np.random.default_rng(5)
+    for _ in range(20):
+        na = int(rng.integers(3, 200))
+        angles = np.sort(rng.uniform(-np.pi, 2 * np.pi, na))
+        nx, ny = (int(v) for v in rng.integers(5, 300, 2))
+        nd = int(rng.integers(8, 500))
+        ds = float(rng.uniform(0.4, 2.5))
+        lo, hi, W = window_extremes(nx, ny, na, nd, ds, angles)
+        assert lo >= 0.99 and hi <= W - 4, (nx, ny, na, nd, ds, lo, hi, W)
