@@ -565,7 +565,9 @@ def learned_run(args):
     nt = args.train_n
     gt = pk.Geometry(nt, nt, nt * 360 // 256, math.ceil(nt * math.sqrt(2)))   # 360 x 363 at 256
     At, Bt = pk.Operator("joseph", gt, "f32", "f32"), pk.Operator("pixel", gt, "f32", "f32")
-    ws = torch.empty(pk.workspace_bytes(At, Bt, SB, "AB", K, labels=True), dtype=torch.uint8, device="cuda")
+    st = args.streams
+    ws = torch.empty(pk.workspace_bytes(At, Bt, SB, "AB", K, labels=True, streams=st), dtype=torch.uint8,
+                     device="cuda")
     Xs, Ts, kst = [], [], []
     t0 = time.perf_counter()
     for first in range(0, args.train_runs, SB):
@@ -574,8 +576,7 @@ def learned_run(args):
         # ||e|| is known in the training runs as in the solves that use the
         # network (a feature is its level relative to the initial residual)
         _, info = pk.solve(At, Bt, b, mode="AB", k=K, reg="gcv", features=True, x_true=x, workspace=ws,
-                           noise_norm=en,
-                           history=False)
+                           noise_norm=en, history=False, streams=st)
         tg, ks = pk.mlp_labels(info["rre"], info["iters"])
         ok = torch.isfinite(tg.reshape(-1, 2)).all(dim=1)
         Xs.append(info["features"].reshape(-1, 64)[ok])
@@ -601,7 +602,7 @@ def learned_run(args):
 
     ge = pk.Geometry(512, 512, 720, 725)
     A, B = pk.Operator("joseph", ge, "f32", "f32"), pk.Operator("pixel", ge, "f32", "f32")
-    ws = torch.empty(pk.workspace_bytes(A, B, SB, "AB", K, stop="dp"), dtype=torch.uint8, device="cuda")
+    ws = torch.empty(pk.workspace_bytes(A, B, SB, "AB", K, stop="dp", streams=st), dtype=torch.uint8, device="cuda")
     # the learned rule with each (judge margin delta, discrepancy gate c):
     # lambda^ replaces GCV's lambda when GCV(lambda^) <= (1 + delta) min GCV;
     # the stop index is accepted once rho_k <= c tau ||e|| (c = 0: no gate);
@@ -624,7 +625,7 @@ def learned_run(args):
             torch.cuda.synchronize()
             t0 = time.perf_counter()
             xr, info = pk.solve(A, B, b, mode="AB", k=K, tau=1.01, noise_norm=en, use_graph=True,
-                                poll_every=args.poll, workspace=ws, history=False, **kw)
+                                poll_every=args.poll, workspace=ws, history=False, streams=st, **kw)
             torch.cuda.synchronize()
             res[name]["t"] += time.perf_counter() - t0
             res[name]["iters"].append(info["iters"].cpu().numpy())
@@ -666,7 +667,8 @@ def learned_run(args):
         "dtype": "f32 projectors+basis+network, f64 reductions and small solves",
         "data": "synthetic: seeded random-ellipse phantoms; training labels from the true images",
         "config": {"workload": f"train on {args.train_runs} runs at {nt}^2 ({gt.n_angles} x {gt.det_u}, K {K}), evaluate on "
-                               f"{E} slices at 512^2 (720 x 725), eta log-uniform [0.1%,5%]"},
+                               f"{E} slices at 512^2 (720 x 725), eta log-uniform [0.1%,5%]",
+                   "streams": st},
         "gcv_dp": {"slices_per_s": round(E / res["gcv"]["t"], 3), "iters_mean": float(res["gcv"]["iters"].mean()),
                    "rre_median": float(np.median(res["gcv"]["rre"]))},
         "learned": {"slices_per_s": round(E / res["learned"]["t"], 3),
