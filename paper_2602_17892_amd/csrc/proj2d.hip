@@ -418,15 +418,19 @@ __global__ __launch_bounds__(256) void joseph2d_lds_k(const TI *__restrict__ xp,
 
 // ------------------------------------------------------- pixel-driven B -----
 // x[i][j] = wb * sum_a lerp(row a of the sinogram at t = X cos/ds + Y sin/ds + cd).
-// A workgroup owns a tile of 32 columns x 64 rows (8 rows per thread).  For a
-// chunk of angles it stages in LDS, per angle, the window of detector bins the
-// tile projects onto, as pairs (y[p], y[p+1] - y[p]) with zeros outside the
+// The image is cut into tiles of 32 columns x 64 rows.  For a chunk of angles
+// a workgroup stages in LDS, per angle, the window of detector bins its tile
+// projects onto, as pairs (y[p], y[p+1] - y[p]) with zeros outside the
 // detector; a pixel-angle pair is then one LDS read, lerp = v + f*dv.  The
 // window of angle a starts at w0 = floor(t_min) - 1 (t_min over the tile's
 // corners) and holds W entries, W >= (31 |cos| + 63 |sin|)/ds + 5 over all
-// angles, so every tap of the tile lies inside it.
-constexpr int BT = 32;         // pixel tile width (columns)
-constexpr int PIXBP_RM = 8;    // rows per thread: the tile has 8 * PIXBP_RM rows
+// angles, so every tap of the tile lies inside it.  A workgroup takes the
+// whole tile (RM = 8 rows per thread) or one half of it (RM = 4, two
+// workgroups per tile, for batches too small to fill the device); both stage
+// the tile's window and compute t relative to the tile's w0, so a pixel gets
+// the same bits either way.
+constexpr int BT = 32;    // tile width (columns)
+constexpr int BTH = 64;   // tile height (rows)
 
 template <typename TIN, typename TI, int RM>
 __global__ __launch_bounds__(256) void pixbp2d_k(VecRef yr, VecRef xr,
@@ -439,8 +443,12 @@ __global__ __launch_bounds__(256) void pixbp2d_k(VecRef yr, VecRef xr,
     T *win = reinterpret_cast<T *>(smem);                                     // [G][W][2]
     T *par = reinterpret_cast<T *>(smem + (size_t)G * W * 2 * sizeof(T));       // [G][3]: cb, sb, cd - w0
     int *w0s = reinterpret_cast<int *>(smem + (size_t)G * (W * 2 + 3) * sizeof(T));   // [G]: w0
-    // work order: (slice, tile row, tile column)
-    const uint32_t w = xcd_remap(blockIdx.x, gridDim.x, nxcc);
+    static_assert(RM == 4 || RM == 8, "a workgroup takes a whole tile or one half");
+    constexpr int NH = BTH / (8 * RM);   // workgroups per tile
+    // work order: (slice, tile row, tile column, half)
+    const uint32_t w0i = xcd_remap(blockIdx.x, gridDim.x, nxcc);
+    const int half = NH > 1 ? (int)(w0i % (uint32_t)NH) : 0;
+    const uint32_t w = w0i / (uint32_t)NH;
     const uint32_t wt = w / (uint32_t)ntx;
     const int ty = (int)(wt % (uint32_t)nty);
     const int tx = (int)(w % (uint32_t)ntx);
@@ -450,9 +458,8 @@ __global__ __launch_bounds__(256) void pixbp2d_k(VecRef yr, VecRef xr,
     const TIN *y = vec_ptr<const TIN>(yr, s, k);
     const T cx = (T)0.5 * (T)(nx - 1), cy = (T)0.5 * (T)(ny - 1);
     // this thread: column j, rows i0 + 8m (m < RM)
-    constexpr int BTY = 8 * RM;
     const int j = tx * BT + (threadIdx.x & 31);
-    const int i0 = ty * BTY + (threadIdx.x >> 5);
+    const int i0 = ty * BTH + half * (8 * RM) + (threadIdx.x >> 5);
     const T X = (T)j - cx;
     T Ym[RM], acc[RM];
 #pragma unroll
@@ -462,7 +469,7 @@ __global__ __launch_bounds__(256) void pixbp2d_k(VecRef yr, VecRef xr,
     }
     // tile corners (the whole tile, also where it overhangs the image)
     const T X0 = (T)(tx * BT) - cx, X1 = X0 + (T)(BT - 1);
-    const T Y0 = (T)(ty * BTY) - cy, Y1 = Y0 + (T)(BTY - 1);
+    const T Y0 = (T)(ty * BTH) - cy, Y1 = Y0 + (T)(BTH - 1);
     const float winv = 1.0f / (float)W;
     for (int a0 = 0; a0 < na; a0 += G) {
         const int g = min(G, na - a0);
@@ -502,9 +509,9 @@ __global__ __launch_bounds__(256) void pixbp2d_k(VecRef yr, VecRef xr,
                 const T t = fma(Ym[m], sb, base);
                 const T f = fract_of(t);
                 // every pixel of the tile (overhang included) has
-                // 1 <= t < 2 + (31 |cos| + (BTY - 1) |sin|)/ds <= W - 3 up to
-                // rounding of a few ulp, so (int) is floor and both taps lie in
-                // the window
+                // 1 <= t < 2 + (31 |cos| + 63 |sin|)/ds <= W - 3 up to rounding
+                // of a few ulp, so (int) is floor and both taps lie in the
+                // window
                 const int idx = (int)t;
                 const T v = wrow[2 * idx], dv = wrow[2 * idx + 1];
                 acc[m] += fma(f, dv, v);
@@ -526,7 +533,7 @@ static void pixbp_window(const abba_op *op, int *W, int *G) {
     double m = 0;
     for (int a = 0; a < op->g.n_angles; ++a) {
         const double th = op->g.angles ? op->g.angles[a] : a * M_PI / op->g.n_angles;
-        m = std::max(m, (BT - 1) * std::fabs(std::cos(th)) + (8 * PIXBP_RM - 1) * std::fabs(std::sin(th)));
+        m = std::max(m, (BT - 1) * std::fabs(std::cos(th)) + (BTH - 1) * std::fabs(std::sin(th)));
     }
     *W = (int)std::ceil(m / op->g.det_pitch_u) + 5;
     const size_t per = (size_t)*W * 2 * (op->img_dtype == ABBA_F64 ? 8 : 4);
@@ -713,14 +720,21 @@ static int back_launch(const abba_op *op, VecRef y, VecRef x, int batch, const L
         if (t->b_g > 0) G = std::min(t->b_g, pixbp_max_g(op, W));
     const size_t shmem = (size_t)G * ((W * 2 + 3) * sizeof(T) + 4);
     if ((size_t)W * 2 * sizeof(T) > 32768) return ABBA_ERR_UNSUPPORTED;
-    const int btx = (nx + BT - 1) / BT, bty = (ny + 8 * PIXBP_RM - 1) / (8 * PIXBP_RM);
-    const uint64_t tiles = (uint64_t)btx * bty;
+    const int btx = (nx + BT - 1) / BT, bty = (ny + BTH - 1) / BTH;
+    // half tiles where whole ones would leave CUs idle (fewer than four
+    // workgroups per CU); the same bits either way
+    const bool halves = (uint64_t)btx * bty * batch < 4 * 256;
+    const uint64_t tiles = (uint64_t)btx * bty * (halves ? 2 : 1);
     const int bchunk = (int)std::min<uint64_t>((uint64_t)batch, MAX_GROUPS / tiles);
     for (int s0 = 0; s0 < batch; s0 += bchunk) {
         const int nb = std::min(bchunk, batch - s0);
-        hipLaunchKernelGGL((pixbp2d_k<TIN, TI, PIXBP_RM>), dim3((uint32_t)(tiles * nb)), dim3(256), shmem, L.stream, y, x,
-                           (const AngleTab<T> *)op->tab, nx, ny, na, nd, (T)(0.5 * (nd - 1)), (T)(1.0 / ds), W, G,
-                           btx, bty, (uint32_t)op->nxcc, s0, L.kdev, L.active);
+#define PIXBP(RM)                                                                                                  \
+    hipLaunchKernelGGL((pixbp2d_k<TIN, TI, RM>), dim3((uint32_t)(tiles * nb)), dim3(256), shmem, L.stream, y, x,     \
+                       (const AngleTab<T> *)op->tab, nx, ny, na, nd, (T)(0.5 * (nd - 1)), (T)(1.0 / ds), W, G, btx, \
+                       bty, (uint32_t)op->nxcc, s0, L.kdev, L.active)
+        if (halves) PIXBP(4);
+        else PIXBP(8);
+#undef PIXBP
         ABBA_LAUNCHED("pixbp2d_k");
     }
     return ABBA_OK;

@@ -167,6 +167,28 @@ def test_joseph_gather_and_lds_paths_are_bitwise_equal(pk, shape, dt, monkeypatc
     assert torch.equal(yg, yl)
 
 
+@pytest.mark.parametrize("shape,dt,batch", [((128, 128, 180, 183), "f32", 128), ((37, 50, 33, 71), "f64", 512),
+                                             ((512, 512, 720, 725), "f32", 8)])
+def test_backprojector_whole_and_half_tiles_are_bitwise_equal(pk, shape, dt, batch):
+    """B takes 32 x 64 pixel tiles, a whole tile per workgroup in batches
+    that fill the device and half a tile per workgroup below that (one slice
+    of 512^2 is 128 tiles for 256 CUs).  Both stage the tile's window and
+    compute positions relative to its start, so a slice backprojected in a
+    batch (whole tiles) and alone (halves) must give the same bits."""
+    nx, ny, na, nd = shape
+    g = pk.Geometry(nx, ny, na, nd)
+    B = pk.Operator("pixel", g, dt, dt)
+    tdt = {"f64": torch.float64, "f32": torch.float32}[dt]
+    assert (-(-nx // 32)) * (-(-ny // 64)) * batch >= 1024 > (-(-nx // 32)) * (-(-ny // 64))
+    y = torch.as_tensor(np.random.default_rng(8).standard_normal((batch, na, nd))).to(device="cuda", dtype=tdt)
+    xb = pk.backproject(B, y)
+    for s in (0, batch // 3, batch - 1):
+        x1 = pk.backproject(B, y[s:s + 1].contiguous())
+        torch.cuda.synchronize()
+        print(f"{shape} {dt} slice {s}: max |batch - alone| = {(xb[s] - x1[0]).abs().max().item():.3e}")
+        assert torch.equal(xb[s], x1[0])
+
+
 def test_adjoint_identity_gpu(pk):
     g = pk.Geometry(64, 64, 90, 91)
     A, At = pk.Operator("joseph", g), pk.Operator("joseph_t", g)
