@@ -691,10 +691,23 @@ def learned_run(args):
     return out
 
 
+def tune_sub_batches(pk, A, B, S, streams):
+    """Launch choices of A and B at the sub-batch sizes of a batch of S slices
+    split into `streams` concurrent sub-batches (their projector launches run
+    at those batch sizes)."""
+    p = max(1, min(streams, S))
+    out = {}
+    for sz in sorted({S // p + (1 if i < S % p else 0) for i in range(p)} - {S, 1}):
+        out[f"A_sub{sz}"] = pk.autotune(A, sz)
+        out[f"B_sub{sz}"] = pk.autotune(B, sz)
+    return out
+
+
 def variants_workload(args):
-    """The 256 x 512^2 batch with hybrid BA-GMRES (GCV, DP stop, at most 100),
-    with restarted cycles of 20 (AB, GCV, DP stop, 100 iterations in all) and
-    with the NCP stop (AB, GCV, at most 100), and one
+    """The 256 x 512^2 batch (in --streams concurrent sub-batches) with
+    hybrid BA-GMRES (GCV, DP stop, at most 100), with restarted cycles of 20
+    (AB, GCV, DP stop, 100 iterations in all) and with the NCP stop (AB, GCV,
+    at most 100), and one
     1024^2 fan-beam slice (50 views, 1,024 bins of 3, SID 2048, SDD 4096,
     1.5 % noise, AB with GCV and DP stop) beside the oracle's time for it."""
     import numpy as np
@@ -708,9 +721,11 @@ def variants_workload(args):
     A, B = pk.Operator("joseph", g, "f32", "f32"), pk.Operator("pixel", g, "f32", "f32")
     pk.autotune(A, S)
     pk.autotune(B, S)
+    tune_sub_batches(pk, A, B, S, args.streams)
+    st = args.streams
     x, b, en, _ = make_inputs(args, pk, A, torch)
     out = {"metric": "BA / restarted / NCP / fan-beam variants", "config": {"workload": f"{S} x {args.n}^2 slices "
-           f"({args.angles} x {args.det}) and one 1024^2 fan-beam slice"}}
+           f"({args.angles} x {args.det}) and one 1024^2 fan-beam slice", "streams": st}}
 
     def rre(xr, xt):
         n = xr.shape[0]
@@ -721,10 +736,10 @@ def variants_workload(args):
                               ("ba", "BA", dict(stop="dp", noise_norm=en), 0),
                               ("restart20", "AB", dict(stop="dp", noise_norm=en), 20),
                               ("ncp", "AB", dict(stop="ncp"), 0)):
-        ws = torch.empty(pk.workspace_bytes(A, B, S, mode, K, stop=kw["stop"], restart=p), dtype=torch.uint8,
-                         device="cuda")
+        ws = torch.empty(pk.workspace_bytes(A, B, S, mode, K, stop=kw["stop"], restart=p, streams=st),
+                         dtype=torch.uint8, device="cuda")
         run = lambda: pk.solve(A, B, b, mode=mode, k=K, reg="gcv", tau=1.01, use_graph=True, poll_every=args.poll,
-                               workspace=ws, history=False, restart=p, **kw)
+                               workspace=ws, history=False, restart=p, streams=st, **kw)
         run()
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -806,11 +821,8 @@ def main():
     # slices (the plain path), timed before anything is measured
     t0 = time.perf_counter()
     tune = {"A": pk.autotune(A, S), "B": pk.autotune(B, S), "A_plain": pk.autotune(A, 1), "B_plain": pk.autotune(B, 1)}
-    # the sub-batches' projector launches run at their own batch sizes
     P_st = max(1, min(args.streams, S))
-    for sz in sorted({S // P_st + (1 if i < S % P_st else 0) for i in range(P_st)} - {S, 1}):
-        tune[f"A_sub{sz}"] = pk.autotune(A, sz)
-        tune[f"B_sub{sz}"] = pk.autotune(B, sz)
+    tune.update(tune_sub_batches(pk, A, B, S, args.streams))
     log(args, f"autotune ({time.perf_counter() - t0:.1f}s): " + "; ".join(
         f"{k} {v['ms']:.3f} ms (built-in {v['default_ms']:.3f})" for k, v in tune.items()))
     # one workspace serves the sub-batched timed solve and the one-stream
