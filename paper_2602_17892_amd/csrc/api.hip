@@ -173,7 +173,7 @@ int op_build_tables(abba_op *op) {
     e = hipMalloc(&op->agrp, grp.size() * sizeof(int));
     if (e == hipSuccess) e = hipMemcpy(op->agrp, grp.data(), grp.size() * sizeof(int), hipMemcpyHostToDevice);
     if (e != hipSuccess) return hip_fail(e, "angle group upload");
-    return ABBA_OK;
+    return op->kind == ABBA_OP_PIXEL ? pixbp_build_table(op) : ABBA_OK;
 }
 
 }  // namespace abba
@@ -234,7 +234,7 @@ int abba_op_create(abba_op **out, int kind, const abba_geometry *geom, int img_d
     op->n = (int64_t)op->g.nx * op->g.ny * op->g.nz;
     op->m = (int64_t)op->g.n_angles * op->g.det_u * op->g.det_v;
     op->tab = nullptr;
-    op->major = nullptr;
+    op->bpw = nullptr;
     op->agrp = nullptr;
     op->ngroups = 0;
     op->cone_axes = 0;
@@ -262,7 +262,7 @@ int abba_op_create(abba_op **out, int kind, const abba_geometry *geom, int img_d
     rc = op_build_tables(op);
     if (rc) {
         if (op->tab) (void)hipFree(op->tab);
-        if (op->major) (void)hipFree(op->major);
+        if (op->bpw) (void)hipFree(op->bpw);
         if (op->agrp) (void)hipFree(op->agrp);
         delete op;
         return rc;
@@ -274,7 +274,7 @@ int abba_op_create(abba_op **out, int kind, const abba_geometry *geom, int img_d
 void abba_op_destroy(abba_op *op) {
     if (!op) return;
     if (op->tab) (void)hipFree(op->tab);
-    if (op->major) (void)hipFree(op->major);
+    if (op->bpw) (void)hipFree(op->bpw);
     if (op->agrp) (void)hipFree(op->agrp);
     delete op;
 }

@@ -92,7 +92,7 @@ struct abba_op {
     void *tab;             // AngleTab<float|double>[n_angles] or ConeView[views]
     int *agrp;             // 2D: [ngroups][4] {first, count, rowmarch, 0}, then the angle order [n_angles]
     int ngroups;
-    unsigned char *major;  // unused
+    void *bpw;             // 2D B: per (tile of 32 x 64 pixels, angle), the window start (pixbp_build_table)
     int cone_axes;         // 3D: bit a set if some ray has dominant axis a (0 x, 1 y, 2 z)
     abba::TuneEntry tune[abba::MAX_TUNE];   // per batch size (not thread-safe to change
     int ntune;                              // while the operator is in use)
@@ -109,6 +109,7 @@ int par2d_forward(const abba_op *op, VecRef x, VecRef y, int y_dtype, int batch,
                   const Launch &L);
 int par2d_back(const abba_op *op, VecRef y, int y_dtype, VecRef x, int batch, void *scratch, const Launch &L);
 size_t par2d_scratch_bytes(const abba_op *op, int batch);
+int pixbp_build_table(abba_op *op);
 
 // 3D cone beam (cone3d.hip).
 int cone_forward(const abba_op *op, VecRef x, VecRef y, int y_dtype, int batch, void *scratch, const Launch &L);

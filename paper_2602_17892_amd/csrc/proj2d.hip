@@ -432,17 +432,26 @@ __global__ __launch_bounds__(256) void joseph2d_lds_k(const TI *__restrict__ xp,
 constexpr int BT = 32;    // tile width (columns)
 constexpr int BTH = 64;   // tile height (rows)
 
+// Window of B for one (tile, angle), from the operator's table (built once
+// when the operator is created): its start w0 and cd - w0 in the
+// accumulation type, the addend that makes t relative to the window.
+template <typename T>
+struct BpWin {
+    T par;
+    int w0;
+};
+
 template <typename TIN, typename TI, int RM>
 __global__ __launch_bounds__(256) void pixbp2d_k(VecRef yr, VecRef xr,
                                                  const AngleTab<typename acc_of<TI>::type> *__restrict__ tab,
-                                                 int nx, int ny, int na, int nd, typename acc_of<TI>::type cd,
-                                                 typename acc_of<TI>::type wb, int W, int G, int ntx, int nty,
-                                                 uint32_t nxcc, int s0, const int *kdev, const int *active) {
+                                                 const BpWin<typename acc_of<TI>::type> *__restrict__ bpw,
+                                                 int nx, int ny, int na, int nd, typename acc_of<TI>::type wb,
+                                                 int W, int G, int ntx, int nty, uint32_t nxcc, int s0,
+                                                 const int *kdev, const int *active) {
     typedef typename acc_of<TI>::type T;
     extern __shared__ __align__(16) unsigned char smem[];
-    T *win = reinterpret_cast<T *>(smem);                                     // [G][W][2]
-    T *par = reinterpret_cast<T *>(smem + (size_t)G * W * 2 * sizeof(T));       // [G][3]: cb, sb, cd - w0
-    int *w0s = reinterpret_cast<int *>(smem + (size_t)G * (W * 2 + 3) * sizeof(T));   // [G]: w0
+    T *win = reinterpret_cast<T *>(smem);                                      // [G][W][2]
+    int *w0s = reinterpret_cast<int *>(smem + (size_t)G * W * 2 * sizeof(T));   // [G]: w0
     static_assert(RM == 4 || RM == 8, "a workgroup takes a whole tile or one half");
     constexpr int NH = BTH / (8 * RM);   // workgroups per tile
     // work order: (slice, tile row, tile column, half)
@@ -467,23 +476,14 @@ __global__ __launch_bounds__(256) void pixbp2d_k(VecRef yr, VecRef xr,
         Ym[m] = (T)(i0 + 8 * m) - cy;
         acc[m] = 0;
     }
-    // tile corners (the whole tile, also where it overhangs the image)
-    const T X0 = (T)(tx * BT) - cx, X1 = X0 + (T)(BT - 1);
-    const T Y0 = (T)(ty * BTH) - cy, Y1 = Y0 + (T)(BTH - 1);
+    // this tile's windows; the per-angle values of the loop below are
+    // wave-uniform loads (scalar memory), not LDS reads
+    const BpWin<T> *bw = bpw + ((int64_t)ty * ntx + tx) * na;
     const float winv = 1.0f / (float)W;
     for (int a0 = 0; a0 < na; a0 += G) {
         const int g = min(G, na - a0);
         __syncthreads();   // the previous chunk is no longer read
-        // window start of each angle of the chunk, one thread per angle
-        for (int al = threadIdx.x; al < g; al += 256) {
-            const T cb = tab[a0 + al].cb, sb = tab[a0 + al].sb;
-            const T tmin = cd + fmin(X0 * cb, X1 * cb) + fmin(Y0 * sb, Y1 * sb);
-            const int w0 = (int)floor(tmin) - 1;
-            par[3 * al] = cb;
-            par[3 * al + 1] = sb;
-            par[3 * al + 2] = cd - (T)w0;
-            w0s[al] = w0;
-        }
+        for (int al = threadIdx.x; al < g; al += 256) w0s[al] = bw[a0 + al].w0;
         __syncthreads();
         // the windows: entry e = al*W + c of the chunk, all threads over all
         // angles.  al = floor((e + 1/2) / W) in FP32 is exact: (e + 1/2)/W is
@@ -500,9 +500,9 @@ __global__ __launch_bounds__(256) void pixbp2d_k(VecRef yr, VecRef xr,
         }
         __syncthreads();
         for (int al = 0; al < g; ++al) {
-            const T cb = par[3 * al], sb = par[3 * al + 1];
+            const T cb = tab[a0 + al].cb, sb = tab[a0 + al].sb;
             // t relative to the window start: t - w0 = fma(Y, sb, X cb + cd - w0)
-            const T base = fma(X, cb, par[3 * al + 2]);
+            const T base = fma(X, cb, bw[a0 + al].par);
             const T *wrow = win + (size_t)al * W * 2;
 #pragma unroll
             for (int m = 0; m < RM; ++m) {
@@ -542,8 +542,52 @@ static void pixbp_window(const abba_op *op, int *W, int *G) {
 
 // Most angles per chunk whose windows fit in 64 KB of LDS.
 static int pixbp_max_g(const abba_op *op, int W) {
-    const size_t per = (size_t)(W * 2 + 3) * (op->img_dtype == ABBA_F64 ? 8 : 4) + 4;
+    const size_t per = (size_t)W * 2 * (op->img_dtype == ABBA_F64 ? 8 : 4) + 4;
     return (int)std::max<size_t>(1, 65536 / per);
+}
+
+// The window of every (tile, angle): w0 = floor(t_min) - 1 with t_min the
+// smallest detector coordinate (in bins, centre cd) of the tile's corners,
+// computed in FP64 from the FP32 (or FP64) cos/ds and sin/ds the kernel uses.
+template <typename T>
+static void pixbp_fill_table(const abba_op *op, BpWin<T> *out) {
+    const abba_geometry &g = op->g;
+    const int btx = (g.nx + BT - 1) / BT, bty = (g.ny + BTH - 1) / BTH, na = g.n_angles;
+    const double ds = g.det_pitch_u, cx = 0.5 * (g.nx - 1), cy = 0.5 * (g.ny - 1), cd = 0.5 * (g.det_u - 1);
+    for (int a = 0; a < na; ++a) {
+        const double th = g.angles ? g.angles[a] : a * M_PI / na;
+        const double cb = (double)(T)(std::cos(th) / ds), sb = (double)(T)(std::sin(th) / ds);
+        for (int ty = 0; ty < bty; ++ty)
+            for (int tx = 0; tx < btx; ++tx) {
+                const double X0 = tx * BT - cx, X1 = X0 + (BT - 1), Y0 = ty * BTH - cy, Y1 = Y0 + (BTH - 1);
+                const double tmin = cd + std::min(X0 * cb, X1 * cb) + std::min(Y0 * sb, Y1 * sb);
+                const int w0 = (int)std::floor(tmin) - 1;
+                BpWin<T> &e = out[((int64_t)ty * btx + tx) * na + a];
+                e.par = (T)(cd - w0);
+                e.w0 = w0;
+            }
+    }
+}
+
+int pixbp_build_table(abba_op *op) {
+    if (op->g.kind != ABBA_GEOM_PAR2D) return ABBA_OK;
+    const int btx = (op->g.nx + BT - 1) / BT, bty = (op->g.ny + BTH - 1) / BTH;
+    const size_t n = (size_t)btx * bty * op->g.n_angles;
+    std::vector<unsigned char> host;
+    size_t bytes;
+    if (op->img_dtype == ABBA_F64) {
+        bytes = n * sizeof(BpWin<double>);
+        host.resize(bytes);
+        pixbp_fill_table(op, reinterpret_cast<BpWin<double> *>(host.data()));
+    } else {
+        bytes = n * sizeof(BpWin<float>);
+        host.resize(bytes);
+        pixbp_fill_table(op, reinterpret_cast<BpWin<float> *>(host.data()));
+    }
+    hipError_t e = hipMalloc(&op->bpw, bytes);
+    if (e == hipSuccess) e = hipMemcpy(op->bpw, host.data(), bytes, hipMemcpyHostToDevice);
+    if (e != hipSuccess) return hip_fail(e, "backprojector window table upload");
+    return ABBA_OK;
 }
 
 
@@ -718,7 +762,7 @@ static int back_launch(const abba_op *op, VecRef y, VecRef x, int batch, const L
     pixbp_window(op, &W, &G);
     if (const TuneEntry *t = tune_for(op, batch))
         if (t->b_g > 0) G = std::min(t->b_g, pixbp_max_g(op, W));
-    const size_t shmem = (size_t)G * ((W * 2 + 3) * sizeof(T) + 4);
+    const size_t shmem = (size_t)G * (W * 2 * sizeof(T) + 4);
     if ((size_t)W * 2 * sizeof(T) > 32768) return ABBA_ERR_UNSUPPORTED;
     const int btx = (nx + BT - 1) / BT, bty = (ny + BTH - 1) / BTH;
     // half tiles where whole ones would leave CUs idle (fewer than four
@@ -730,8 +774,8 @@ static int back_launch(const abba_op *op, VecRef y, VecRef x, int batch, const L
         const int nb = std::min(bchunk, batch - s0);
 #define PIXBP(RM)                                                                                                  \
     hipLaunchKernelGGL((pixbp2d_k<TIN, TI, RM>), dim3((uint32_t)(tiles * nb)), dim3(256), shmem, L.stream, y, x,     \
-                       (const AngleTab<T> *)op->tab, nx, ny, na, nd, (T)(0.5 * (nd - 1)), (T)(1.0 / ds), W, G, btx, \
-                       bty, (uint32_t)op->nxcc, s0, L.kdev, L.active)
+                       (const AngleTab<T> *)op->tab, (const BpWin<T> *)op->bpw, nx, ny, na, nd, (T)(1.0 / ds), W, G, \
+                       btx, bty, (uint32_t)op->nxcc, s0, L.kdev, L.active)
         if (halves) PIXBP(4);
         else PIXBP(8);
 #undef PIXBP

@@ -73,10 +73,12 @@ BT, RM = 32, 8
 
 def window_extremes(nx, ny, na, nd, ds=1.0, angles=None):
     """For every tile and angle of B's launch, the smallest t - w0 and the
-    largest floor(t - w0) over the tile's pixels, in the kernel's FP32
-    arithmetic, and the window length W the host picks.  t - w0 is monotone in
-    each pixel coordinate (fma is monotone in its operands), so the extremes lie
-    at the tile's corner pixels."""
+    largest floor(t - w0) over the tile's pixels, and the window length W the
+    host picks.  The window start w0 comes from the operator's table (FP64
+    from the FP32 cos/ds and sin/ds at the tile's corners); t - w0 is the
+    kernel's FP32 arithmetic, monotone in each pixel coordinate (fma is
+    monotone in its operands), so its extremes lie at the tile's corner
+    pixels."""
     th = np.asarray(angles, dtype=np.float64) if angles is not None else np.arange(na) * np.pi / na
     cs, sn = np.cos(th), np.sin(th)
     BTY = 8 * RM
@@ -90,7 +92,9 @@ def window_extremes(nx, ny, na, nd, ds=1.0, angles=None):
     X0 = ((tx * BT).astype(np.float32) - cx).reshape(-1, 1)
     Y0 = ((ty * BTY).astype(np.float32) - cy).reshape(-1, 1)
     X1, Y1 = X0 + f(BT - 1), Y0 + f(BTY - 1)
-    tmin = (cd + np.minimum(X0 * cb, X1 * cb)) + np.minimum(Y0 * sb, Y1 * sb)
+    X0d, X1d, Y0d, Y1d = (v.astype(np.float64) for v in (X0, X1, Y0, Y1))
+    cbd, sbd = cb.astype(np.float64), sb.astype(np.float64)
+    tmin = (0.5 * (nd - 1) + np.minimum(X0d * cbd, X1d * cbd)) + np.minimum(Y0d * sbd, Y1d * sbd)
     w0 = np.floor(tmin).astype(np.int64) - 1
     par2 = cd - w0.astype(np.float32)
     lo, hi = None, None
