@@ -111,6 +111,14 @@ int build_cone_tables(abba_op *op) {
             }
     }
     op->cone_axes = axes;
+    // B takes a voxel's magnification and detector column once per column of
+    // voxels along z: the orbit lies in the plane z = 0 and the detector rows
+    // run along z, so the detector normal and the column axis have no z part
+    for (int v = 0; v < nv; ++v)
+        if (tab[v].n[2] != 0.0 || tab[v].eu[2] != 0.0) {
+            set_error("cone view %d: the detector normal or column axis leaves the orbit plane", v);
+            return ABBA_ERR_UNSUPPORTED;
+        }
     const size_t bytes_d = sizeof(ConeView) * nv;
     const size_t bytes_b = op->img_dtype == ABBA_F64 ? sizeof(ConeB<double>) * nv : sizeof(ConeB<float>) * nv;
     std::vector<unsigned char> host(bytes_d + bytes_b);
@@ -513,28 +521,33 @@ __global__ __launch_bounds__(256) void cone_bp_k(const typename acc_of<TI>::type
     const int Lu = nu + 2 * CPAD, Lv = nv + 2 * CPAD;
     const T umax = (T)(nu + CPAD), vmax = (T)(nv + CPAD);
     const T *Ys = yp + (int64_t)s * ss;
+    const uint32_t rowb = (uint32_t)Lu * (uint32_t)(2 * sizeof(T));   // bytes per padded row of pairs
     for (int vw = 0; vw < nviews; ++vw) {
         const ConeB<T> b = vb[vw];
-        const T bn = fma(X, b.n[0], fma(Y, b.n[1], -b.Sn));
+        // the detector normal and column axis have no z part (checked when
+        // the operator is built), so the magnification M, the column u and
+        // the weight are those of the whole column of voxels
+        const T den = fma(X, b.n[0], fma(Y, b.n[1], -b.Sn));
         const T bu = fma(X, b.eup[0], fma(Y, b.eup[1], -b.Su));
         const T bv = fma(X, b.evp[0], fma(Y, b.evp[1], -b.Sv));
+        const T M = cdiv(b.dist, den);
+        const T u = fma(M, bu, b.cu);   // padded coordinates
+        const T fu = cfract(u);
+        const uint32_t ub = (uint32_t)cclamp(u, (T)0, umax) * (uint32_t)(2 * sizeof(T));
+        const T wgt = (MP == 2 ? M * M : M) * ipp;
         // the view is the same for the whole workgroup: 32-bit byte offsets
         // from its base (the launcher requires a padded pair view of < 2^32
-        // bytes); the pairs (v, u) and (v, u + 1) are the four taps
+        // bytes and rows of < 2^24 bytes); the pairs (v, u) and (v, u + 1)
+        // are the four taps
         const T *view = Ys + 2 * (int64_t)vw * Lv * Lu;
 #pragma unroll
         for (int m = 0; m < CZT; ++m) {
-            const T den = fma(Z[m], b.n[2], bn);
-            const T M = cdiv(b.dist, den);
-            const T u = fma(M, fma(Z[m], b.eup[2], bu), b.cu);   // padded coordinates
             const T v = fma(M, fma(Z[m], b.evp[2], bv), b.cv);
-            const T fu = cfract(u), fv = cfract(v);
-            const uint32_t iu = (uint32_t)cclamp(u, (T)0, umax), iv = (uint32_t)cclamp(v, (T)0, vmax);
-            const T *e = reinterpret_cast<const T *>(reinterpret_cast<const char *>(view) +
-                                                     (iv * (uint32_t)Lu + iu) * (uint32_t)(2 * sizeof(T)));
+            const T fv = cfract(v);
+            const uint32_t iv = (uint32_t)cclamp(v, (T)0, vmax);
+            const T *e = reinterpret_cast<const T *>(reinterpret_cast<const char *>(view) + __umul24(iv, rowb) + ub);
             const T a00 = e[0], a10 = e[1], a01 = e[2], a11 = e[3];
             const T lo = fma(fu, a01 - a00, a00), hi = fma(fu, a11 - a10, a10);
-            const T wgt = (MP == 2 ? M * M : M) * ipp;
             acc[m] = fma(wgt, fma(fv, hi - lo, lo), acc[m]);
         }
     }
@@ -647,7 +660,11 @@ static int cone_bp_launch(const abba_op *op, const typename acc_of<TI>::type *yp
     const int ntx = (g.nx + 15) / 16, nty = (g.ny + 15) / 16, ntz = (g.nz + CZT - 1) / CZT;
     const uint64_t per = (uint64_t)ntx * nty * ntz;
     if (per > CMAX_GROUPS) return ABBA_ERR_UNSUPPORTED;
-    if ((int64_t)(g.det_u + 2 * CPAD) * (g.det_v + 2 * CPAD) * (int64_t)(2 * sizeof(T)) >= (int64_t)1 << 32)
+    // byte offsets within one padded view in 32 bits, its rows (and row
+    // indices) within the 24 bits of one multiply
+    if ((int64_t)(g.det_u + 2 * CPAD) * (g.det_v + 2 * CPAD) * (int64_t)(2 * sizeof(T)) >= (int64_t)1 << 32 ||
+        (int64_t)(g.det_u + 2 * CPAD) * (int64_t)(2 * sizeof(T)) >= (int64_t)1 << 24 ||
+        g.det_v + 2 * CPAD >= (1 << 24))
         return ABBA_ERR_UNSUPPORTED;
     const int ch = (int)std::min<uint64_t>((uint64_t)batch, CMAX_GROUPS / per);
     const size_t bytes_d = sizeof(ConeView) * g.n_angles;
