@@ -767,7 +767,7 @@ static int back_launch(const abba_op *op, VecRef y, VecRef x, int batch, const L
     const int btx = (nx + BT - 1) / BT, bty = (ny + BTH - 1) / BTH;
     // half tiles where whole ones would leave CUs idle (fewer than four
     // workgroups per CU); the same bits either way
-    const bool halves = (uint64_t)btx * bty * batch < 4 * 256;
+    const bool halves = (uint64_t)btx * bty * batch < 4ull * (uint64_t)op->ncu;
     const uint64_t tiles = (uint64_t)btx * bty * (halves ? 2 : 1);
     const int bchunk = (int)std::min<uint64_t>((uint64_t)batch, MAX_GROUPS / tiles);
     for (int s0 = 0; s0 < batch; s0 += bchunk) {
