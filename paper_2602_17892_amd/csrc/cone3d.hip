@@ -416,6 +416,13 @@ __global__ __launch_bounds__(256) void cone_fwd_k(const TI *__restrict__ vx, con
     auto march = [&](auto uni_tag) {
         constexpr bool UNI = decltype(uni_tag)::value;
         const TI *Pu = UNI ? uniform_ptr(P) : P;
+        // in lockstep the plane range and the copy's row lengths are the
+        // wave's (scalar registers): the plane counter and the plane's offset
+        // are scalar work
+        const int jl = UNI ? __builtin_amdgcn_readfirstlane(jlo) : jlo;
+        const int jh = UNI ? __builtin_amdgcn_readfirstlane(jhi) : jhi;
+        const uint32_t Lqw = UNI ? (uint32_t)__builtin_amdgcn_readfirstlane(Lq) : (uint32_t)Lq;
+        const uint32_t Lpq = UNI ? (uint32_t)__builtin_amdgcn_readfirstlane(Lp * Lq) : (uint32_t)(Lp * Lq);
         // the four taps of plane jj and the two fractions
         auto load = [&](int jj, T &fp, T &fq, T &a00, T &a01, T &a10, T &a11) {
             const T pp = fma((T)jj, DP, P0), qq = fma((T)jj, DQ, Q0);
@@ -424,8 +431,9 @@ __global__ __launch_bounds__(256) void cone_fwd_k(const TI *__restrict__ vx, con
             const uint32_t ipp = (uint32_t)cclamp(pp, (T)0, pmax), iqq = (uint32_t)cclamp(qq, (T)0, qmax);
             // pairs (p, q) and (p, q + 1): x[p][q], x[p+1][q], x[p][q+1], x[p+1][q+1]
             if constexpr (UNI) {   // global loads: a scalar base plus a 32-bit byte offset
-                // (24-bit multiplies: the host checked that rows and row lengths fit)
-                const uint32_t ei = __umul24((uint32_t)jj * (uint32_t)Lp + ipp, (uint32_t)Lq) + iqq;
+                // (the copy of one slice has < 2^32 bytes, and its rows and row
+                // lengths fit a 24-bit multiply: checked by the host)
+                const uint32_t ei = (uint32_t)jj * Lpq + __umul24(ipp, Lqw) + iqq;
                 typedef const __attribute__((address_space(1))) char gchar;
                 typedef const __attribute__((address_space(1))) TI gTI;
                 gchar *b = (gchar *)Pu;
@@ -452,12 +460,12 @@ __global__ __launch_bounds__(256) void cone_fwd_k(const TI *__restrict__ vx, con
             load(jj, fp, fq, a00, a01, a10, a11);
             return combine(fp, fq, a00, a01, a10, a11);
         };
-        int j = jlo;
-        if (j <= jhi && (j & 1)) {
+        int j = jl;
+        if (j <= jh && (j & 1)) {
             acc1 += tap(j);
             ++j;
         }
-        for (; j + 3 <= jhi; j += 4) {
+        for (; j + 3 <= jh; j += 4) {
             T fp[4], fq[4], a00[4], a01[4], a10[4], a11[4], v[4];
 #pragma unroll
             for (int h = 0; h < 4; ++h) load(j + h, fp[h], fq[h], a00[h], a01[h], a10[h], a11[h]);
@@ -469,13 +477,13 @@ __global__ __launch_bounds__(256) void cone_fwd_k(const TI *__restrict__ vx, con
             acc0 += v[2];
             acc1 += v[3];
         }
-        if (j + 1 <= jhi) {
+        if (j + 1 <= jh) {
             const T v0 = tap(j), v1 = tap(j + 1);
             acc0 += v0;
             acc1 += v1;
             j += 2;
         }
-        if (j <= jhi) acc0 += tap(j);
+        if (j <= jh) acc0 += tap(j);
     };
     if (same && off32)
         march(std::true_type{});
