@@ -676,7 +676,14 @@ static int dcgs2_step_t(const SolveDims &d, const SolveWS &ws, const int *kdev, 
     hipLaunchKernelGGL(dclose_k, dim3(d.S), dim3(128), 0, st, ws.c, ws.h, d.K + 2, ws.H, ws.T, ws.gd, d.K + 2, d.K,
                        ws.sc, ws.flags, kdev ? kdev : ws.kdev, ws.active);
     ABBA_LAUNCHED("dclose_k");
-    const int nblk_u = sweep_blocks(d.ldw, d.w_dt, ABBA_CGS_UPD_CHUNK);
+    // the update has no sums across elements, so its blocks per slice may
+    // follow the batch (the same bits): at least 1,024 blocks in all where the
+    // vectors allow, one slice alone would otherwise have 32 (one 16-byte
+    // vector per thread at most)
+    const int64_t nvec = d.ldw / (d.w_dt == ABBA_F64 ? 2 : 4);
+    const int nblk_u = (int)std::min<int64_t>(
+        std::max<int64_t>(sweep_blocks(d.ldw, d.w_dt, ABBA_CGS_UPD_CHUNK), (1024 + d.S - 1) / d.S),
+        std::max<int64_t>(1, std::min<int64_t>(1024, nvec / 256)));
     hipLaunchKernelGGL(dupdate_k<TW>, dim3(nblk_u, 1, d.S), dim3(256), 0, st, W, wsl, d.ldw, (const double *)ws.c,
                        d.K + 2, (const double *)ws.gd, d.K + 2, (const double *)ws.sc, nblk_u, kdev, ws.active);
     ABBA_LAUNCHED("dupdate_k");
