@@ -220,12 +220,13 @@ def kernel_source_digest(files=SOURCES_2D):
     return h.hexdigest()[:16]
 
 
-def recorded_traffic(kernel, files=SOURCES_2D):
-    """HBM bytes per launch of `kernel` from the committed counter summary, or
-    None when there is none or the projector source (`files`) changed since."""
+def recorded_counters(kernel, files=SOURCES_2D):
+    """The per-launch counter values of `kernel` in its committed summary
+    (profiles/<kernel>_traffic.md), or {} when there is none or the projector
+    source (`files`) changed since."""
     path = os.path.join(PROFILES, f"{kernel}_traffic.md")
     if not os.path.exists(path):
-        return None
+        return {}
     vals = {}
     with open(path) as f:
         for line in f:
@@ -233,11 +234,34 @@ def recorded_traffic(kernel, files=SOURCES_2D):
                 k, v = line[2:].split(" = ", 1)
                 vals[k.strip()] = v.strip().strip("`")
     if vals.get("source_digest") != kernel_source_digest(files):
-        return None
+        return {}
+    return vals
+
+
+def recorded_traffic(kernel, files=SOURCES_2D):
+    """HBM bytes per launch of `kernel` from the committed counter summary, or
+    None when there is none or the projector source (`files`) changed since."""
     try:
-        return float(vals["hbm_bytes_per_launch"])
+        return float(recorded_counters(kernel, files)["hbm_bytes_per_launch"])
     except (KeyError, ValueError):
         return None
+
+
+def recorded_issue(kernel, files=SOURCES_2D):
+    """VALU issue of one launch of `kernel` from the committed counter summary
+    (SQ_INSTS_VALU and SQ_BUSY_CU_CYCLES), or None: the cycles a CU is busy per
+    wave-level VALU instruction issued on one of its 4 SIMDs (256 CUs, 1,024
+    SIMDs).  A wave64 VALU instruction occupies its SIMD for 4 cycles, so a
+    kernel near 4 (or below, where instructions co-issue) is bound by issue."""
+    vals = recorded_counters(kernel, files)
+    try:
+        ins, busy = float(vals["valu_instructions_per_launch"]), float(vals["busy_cu_cycles_per_launch"])
+    except (KeyError, ValueError):
+        return None
+    if ins <= 0:
+        return None
+    return {"valu_instructions": ins, "busy_cu_cycles": busy,
+            "cycles_per_valu_per_simd": round((busy / 256) / (ins / 1024), 3)}
 
 
 def projectors_only(args):
@@ -533,6 +557,7 @@ def cone_workload(args):
         "roofline": {"bound": "alu", "achieved": round(dom[1], 3), "peak": round(VALU_PEAK_TFLOPS, 1),
                      "unit": "TFLOP/s", "frac": round(dom[1] / VALU_PEAK_TFLOPS, 4),
                      "traffic": recorded_traffic(dom[0], SOURCES_CONE),
+                     "valu_issue": recorded_issue(dom[0], SOURCES_CONE),
                      "kernel": dom[0], "ms_per_launch": round(dom[2] * 1e3, 3)},
     }
     if not args.no_cpu_baseline:
@@ -920,7 +945,7 @@ def main():
         dom_name, dom_tf, dom_t = "pixbp2d_k", tf_B, t_B
     roofline = {"bound": "alu", "achieved": round(dom_tf, 3), "peak": round(VALU_PEAK_TFLOPS, 1),
                 "unit": "TFLOP/s", "frac": round(dom_tf / VALU_PEAK_TFLOPS, 4),
-                "traffic": recorded_traffic(dom_name), "kernel": dom_name,
+                "traffic": recorded_traffic(dom_name), "valu_issue": recorded_issue(dom_name), "kernel": dom_name,
                 "ms_per_launch": round(dom_t * 1e3, 3)}
 
     value = S / t_batched

@@ -41,7 +41,15 @@ def test_recorded_traffic_ignores_stale_summaries(tmp_path, monkeypatch):
     assert bench.recorded_traffic("k") is None
     f.write_text(f"- source_digest = `{bench.kernel_source_digest()}`\n- hbm_bytes_per_launch = 123.0\n")
     assert bench.recorded_traffic("k") == 123.0
+    assert bench.recorded_issue("k") is None
     assert bench.recorded_traffic("absent") is None
+    f.write_text(f"- source_digest = `{bench.kernel_source_digest()}`\n- hbm_bytes_per_launch = 123.0\n"
+                 "- valu_instructions_per_launch = 2048\n- busy_cu_cycles_per_launch = 1024\n")
+    assert bench.recorded_issue("k") == {"valu_instructions": 2048.0, "busy_cu_cycles": 1024.0,
+                                         "cycles_per_valu_per_simd": 2.0}
+    f.write_text("- source_digest = `deadbeef`\n- valu_instructions_per_launch = 2048\n"
+                 "- busy_cu_cycles_per_launch = 1024\n")
+    assert bench.recorded_issue("k") is None
 
 
 @pytest.mark.parametrize("n,views,nu,nv,pitch,sid,sdd", [(8, 6, 12, 10, 1.0, 30.0, 60.0),
