@@ -85,3 +85,23 @@ def test_dcgs2_byte_count():
     length = 1000
     want = sum(sum((j + 2) + (j + 4) for j in range(k + 1)) for k in iters) * length * 4
     assert bench.dcgs2_bytes(iters, length) == want
+
+
+def test_sub_batch_tuning_covers_every_sub_batch_size():
+    """The sub-batches of S slices in p parts differ in size by at most one
+    (the library's split); their projector launches are tuned at exactly
+    those sizes, besides the whole batch and single slices."""
+    calls = []
+
+    class Stub:
+        @staticmethod
+        def autotune(op, batch):
+            calls.append((op, batch))
+            return {"batch": batch}
+
+    for S, p, sizes in ((256, 3, {85, 86}), (256, 2, {128}), (7, 3, {2, 3}), (5, 9, set()), (256, 1, set()),
+                        (4, 2, {2})):
+        calls.clear()
+        out = bench.tune_sub_batches(Stub, "A", "B", S, p)
+        assert {b for _, b in calls} == sizes, (S, p)
+        assert sorted(out) == sorted([f"A_sub{z}" for z in sizes] + [f"B_sub{z}" for z in sizes])
