@@ -132,3 +132,23 @@ def test_backprojector_window_holds_every_tap_at_uneven_angles():
         ds = float(rng.uniform(0.4, 2.5))
         lo, hi, W = window_extremes(nx, ny, na, nd, ds, angles)
         assert lo >= 0.99 and hi <= W - 4, (nx, ny, na, nd, ds, lo, hi, W)
+
+
+@pytest.mark.parametrize("ny", [1, 37, 64, 65, 512, 1000])
+def test_backprojector_tile_rows_are_covered_once(ny):
+    """B's workgroups over a tile of BTH = 64 rows: a whole tile (RM = 8 rows
+    per thread, rows r + 8m for thread row r < 8) or one of two halves (RM = 4,
+    rows 32 h + r + 8m).  Either way every image row is written by exactly one
+    (workgroup, thread row, m), and by the same row index, so the two launch
+    forms write the same pixels."""
+    BTH = 64
+    bty = -(-ny // BTH)
+    for RM in (8, 4):
+        NH = BTH // (8 * RM)
+        rows = []
+        for ty in range(bty):
+            for half in range(NH):
+                for r in range(8):
+                    i0 = ty * BTH + half * (8 * RM) + r
+                    rows += [i0 + 8 * m for m in range(RM) if i0 + 8 * m < ny]
+        assert sorted(rows) == list(range(ny)), RM
