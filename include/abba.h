@@ -99,7 +99,9 @@ typedef struct {
 typedef struct abba_op abba_op;
 
 /* Create an operator on the current HIP device.  Geometry tables are built
- * in FP64 on the host and rounded to the storage type.  `img_dtype` and
+ * in FP64 on the host and rounded to the storage type (for the 2D
+ * pixel-driven B also the detector-window start of every 32 x 64 pixel tile
+ * and angle); they are the only device memory the library allocates itself.  `img_dtype` and
  * `sino_dtype` must be one of the supported pairs.  *out receives the handle;
  * apart from its launch tuning (abba_autotune, abba_op_set_tuning) it is
  * immutable and may be used from several streams at once. */
