@@ -77,11 +77,13 @@ def parse():
                    help="iterations of the short solve of --projectors-only")
     p.add_argument("--projectors-only", action="store_true",
                    help="only the projector launches (random images) and a copy of known size, for counter runs")
-    p.add_argument("--workload", choices=["slices", "cone", "learned", "variants"], default="slices",
+    p.add_argument("--workload", choices=["slices", "cone", "learned", "variants", "paper"], default="slices",
                    help="slices: the batched 2D workload (default); cone: the 3D cone-beam volume solve; "
                         "learned: train the lambda/stop network on method-generated runs, then compare it "
                         "with GCV + DP; variants: the benchmark batch with restarted cycles and with the NCP "
-                        "stop, and the 1024^2 fan-beam problem")
+                        "stop, and the 1024^2 fan-beam problem; paper: single solves at the shapes of the "
+                        "paper's Test Problems 2 and 3, every method/rule/restart of its Tables 2-3, k "
+                        "iterations each")
     p.add_argument("--train-runs", type=int, default=4096)
     p.add_argument("--train-n", type=int, default=256,
                    help="image size of the learned rule's training runs (angles and bins scale with it: "
@@ -809,6 +811,51 @@ def variants_workload(args):
     print(json.dumps(out), flush=True)
 
 
+def paper_workload(args):
+    """One slice per solve at the shapes of the paper's Test Problem 2 (128^2,
+    parallel beam, 50 angles x 128 bins, 2.5 % noise) and Test Problem 3
+    (1024^2, fan beam with a flat detector, 50 views x 1,024 bins of 3, SID
+    2048, SDD 4096, 1.5 % noise), seeded random-ellipse phantoms in place of
+    the paper's; hybrid AB- and BA-GMRES with no lambda, the L-curve and GCV,
+    without restarts and with cycles of 10, each run for --kmax iterations
+    with no stopping rule.  Seconds per solve (mean of 3 after one warm-up),
+    to set beside the paper's Tables 2-3 (another machine and an iteration
+    count the paper does not state: context, not a comparison of equals)."""
+    import numpy as np
+    import torch
+
+    import paper_2602_17892_amd as pk
+    torch.cuda.set_device(0)
+    K = args.kmax
+    probs = {"tp2": (pk.Geometry(128, 128, 50, 128), 128, 0.025),
+             "tp3": (pk.Geometry(1024, 1024, 50, 1024, det_pitch_u=3.0, kind="fan2d", sid=2048.0, sdd=4096.0),
+                     1024, 0.015)}
+    out = {"metric": "seconds per single-slice solve at the shapes of the paper's Test Problems 2-3",
+           "config": {"k": K, "stop": "none (k iterations)", "data": "synthetic random-ellipse phantoms",
+                      "dtype": "f32 projectors+basis, f64 reductions and small solves"}}
+    for name, (g, n, eta) in probs.items():
+        A, B = pk.Operator("joseph", g, "f32", "f32"), pk.Operator("pixel", g, "f32", "f32")
+        x, b, en, _ = synth_batch(pk, A, torch, 11, 0, 1, n, eta, eta)
+        res = {}
+        for mode in ("AB", "BA"):
+            for rule in ("none", "lcurve", "gcv"):
+                for restart in (0, 10):
+                    run = lambda: pk.solve(A, B, b, mode=mode, k=K, reg=rule, restart=restart, history=False)
+                    run()
+                    torch.cuda.synchronize()
+                    t0 = time.perf_counter()
+                    for _ in range(3):
+                        xr, info = run()
+                    torch.cuda.synchronize()
+                    t = (time.perf_counter() - t0) / 3
+                    rre = float(torch.linalg.vector_norm((xr - x).double()) / torch.linalg.vector_norm(x.double()))
+                    key = f"{mode}_{rule}_r{restart}"
+                    res[key] = {"seconds": round(t, 5), "iters": int(info["iters"][0]), "rre": round(rre, 4)}
+                    log(args, f"{name} {key}: {t * 1e3:.2f} ms, {int(info['iters'][0])} iterations, RRE {rre:.4f}")
+        out[name] = res
+    print(json.dumps(out), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -832,6 +879,9 @@ def main():
         return
     if args.workload == "variants":
         variants_workload(args)
+        return
+    if args.workload == "paper":
+        paper_workload(args)
         return
     torch.cuda.set_device(0)
     S, K = args.slices, args.kmax
