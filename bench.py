@@ -14,9 +14,16 @@ The JSON line also carries: the plain per-slice path (one slice per call,
 eager launches, host stop check every iteration) on a subset of the same
 slices, with the check that it returns bitwise the same reconstructions; the
 projector throughput (compulsory bytes per apply / kernel time); the roofline
-of the dominant kernel; and the CPU oracle timed on a bounded sample.
+of the dominant kernel (with its recorded HBM traffic and VALU issue); the
+learned lambda/stop rule against GCV + DP; and the CPU oracle timed on a
+bounded sample.
 
-    python bench.py [--steps K] [--warmup W] [--slices S] [--kmax K]
+    python bench.py [--steps K] [--warmup W] [--slices S] [--kmax K] [--streams P]
+
+Other workloads print a JSON line of their own (--workload): cone (the 256^3
+cone-beam volume), learned (the learned-rule comparison alone), variants (BA,
+restarted cycles, the NCP stop, the 1024^2 fan beam) and paper (single solves
+at the shapes of the paper's Test Problems 2-3).
 """
 from __future__ import annotations
 
